@@ -1,0 +1,197 @@
+"""FP64 CPU oracle for the CNN-VMC J1-J2 hot path (arxiv 2204.07816).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The GPU library never imports,
+links or calls anything here, and nothing here imports the GPU library.
+
+The arithmetic lives in ``nqs_oracle.c`` (plain C, FP64); this module only
+marshals numpy arrays through ctypes.  ``ed.py`` holds the exact-diagonalisation
+test support (Hamiltonian built from spin operators by bit manipulation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nqs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU involved)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-D_GNU_SOURCE", "-o", _LIB_PATH, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    d, i8, i32, i64 = ctypes.c_double, ctypes.c_int8, ctypes.c_int32, ctypes.c_int64
+    ci = ctypes.c_int
+    sig = {
+        "oracle_num_params": (i64, [ci, ci]),
+        "oracle_marshall_sign": (ci, [ci, P(i8)]),
+        "oracle_bond_sites": (ci, [ci, ci, P(ci), P(ci)]),
+        "oracle_connected": (None, [ci, d, d, P(i8), P(i32), P(i32), P(i8), P(d)]),
+        "oracle_log_psi": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), P(i8), ci]),
+        "oracle_local_energy": (None, [ci, d, d, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_local_energy_table": (None, [ci, d, d, P(d), P(i8), P(i8), i64, P(d), ci]),
+        "oracle_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_energy_stats": (None, [P(d), i64, P(d)]),
+        "oracle_sr_cg": (None, [P(d), P(d), i64, i64, d, ci, P(d), P(d)]),
+        "oracle_sr_dense": (ci, [P(d), P(d), i64, i64, d, P(d)]),
+        "oracle_sr_apply": (None, [P(d), i64, i64, d, P(d), P(d)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _spins(spins, L):
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1, L * L)
+    return s
+
+
+def num_params(K: int, C: int) -> int:
+    return int(_load().oracle_num_params(K, C))
+
+
+def marshall_sign(L: int, spins) -> int:
+    s = _spins(spins, L)[0]
+    return int(_load().oracle_marshall_sign(L, _p(s, ctypes.c_int8)))
+
+
+def bond_sites(L: int, b: int):
+    i, j = ctypes.c_int(), ctypes.c_int()
+    cls = _load().oracle_bond_sites(L, b, ctypes.byref(i), ctypes.byref(j))
+    return i.value, j.value, int(cls)
+
+
+def connected(L: int, J1: float, J2: float, spins):
+    """Per-sample connected list: (counts[B], list of bond-id arrays, list of mu arrays, e_diag[B])."""
+    s = _spins(spins, L)
+    B, N = s.shape
+    lib = _load()
+    counts = np.zeros(B, np.int32)
+    ediag = np.zeros(B, np.float64)
+    bonds, mus = [], []
+    bid = np.zeros(4 * N, np.int32)
+    mu = np.zeros(4 * N, np.int8)
+    for b in range(B):
+        c = ctypes.c_int32()
+        e = ctypes.c_double()
+        row = np.ascontiguousarray(s[b])
+        lib.oracle_connected(L, J1, J2, _p(row, ctypes.c_int8), ctypes.byref(c),
+                             _p(bid, ctypes.c_int32), _p(mu, ctypes.c_int8), ctypes.byref(e))
+        counts[b] = c.value
+        ediag[b] = e.value
+        bonds.append(bid[:c.value].copy())
+        mus.append(mu[:c.value].copy())
+    return counts, bonds, mus, ediag
+
+
+def log_psi(L: int, K: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    la = np.zeros(B, np.float64)
+    sg = np.zeros(B, np.int8)
+    _load().oracle_log_psi(L, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
+                           _p(la, ctypes.c_double), _p(sg, ctypes.c_int8), nthreads)
+    return la, sg
+
+
+def local_energy(L: int, J1: float, J2: float, K: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_local_energy(L, J1, J2, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8),
+                                B, _p(e, ctypes.c_double), nthreads)
+    return e
+
+
+def local_energy_table(L: int, J1: float, J2: float, log_abs_tab, sign_tab, spins,
+                       nthreads: int = 0):
+    s = _spins(spins, L)
+    la = np.ascontiguousarray(log_abs_tab, np.float64)
+    sg = np.ascontiguousarray(sign_tab, np.int8)
+    assert la.shape[0] == (1 << (L * L)) and sg.shape[0] == la.shape[0]
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_local_energy_table(L, J1, J2, _p(la, ctypes.c_double), _p(sg, ctypes.c_int8),
+                                      _p(s, ctypes.c_int8), B, _p(e, ctypes.c_double), nthreads)
+    return e
+
+
+def log_deriv(L: int, K: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    P = num_params(K, C)
+    assert w.shape[0] == P
+    O = np.zeros((B, P), np.float64)
+    _load().oracle_log_deriv(L, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
+                             _p(O, ctypes.c_double), nthreads)
+    return O
+
+
+def energy_stats(e):
+    e = np.ascontiguousarray(e, np.float64)
+    st = np.zeros(2, np.float64)
+    _load().oracle_energy_stats(_p(e, ctypes.c_double), e.shape[0], _p(st, ctypes.c_double))
+    return float(st[0]), float(st[1])
+
+
+def sr_cg(O, e, lam: float = 1e-4, n_iter: int = 100):
+    O = np.ascontiguousarray(O, np.float64)
+    e = np.ascontiguousarray(e, np.float64)
+    B, P = O.shape
+    x = np.zeros(P, np.float64)
+    st = np.zeros(2, np.float64)
+    _load().oracle_sr_cg(_p(O, ctypes.c_double), _p(e, ctypes.c_double), B, P, lam, n_iter,
+                         _p(x, ctypes.c_double), _p(st, ctypes.c_double))
+    return x, float(st[0]), int(st[1])
+
+
+def sr_dense(O, e, lam: float = 1e-4):
+    O = np.ascontiguousarray(O, np.float64)
+    e = np.ascontiguousarray(e, np.float64)
+    B, P = O.shape
+    x = np.zeros(P, np.float64)
+    rc = _load().oracle_sr_dense(_p(O, ctypes.c_double), _p(e, ctypes.c_double), B, P, lam,
+                                 _p(x, ctypes.c_double))
+    if rc != 0:
+        raise np.linalg.LinAlgError("S + lambda I not positive definite")
+    return x
+
+
+def sr_apply(O, v, lam: float = 1e-4):
+    O = np.ascontiguousarray(O, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    B, P = O.shape
+    y = np.zeros(P, np.float64)
+    _load().oracle_sr_apply(_p(O, ctypes.c_double), B, P, lam, _p(v, ctypes.c_double),
+                            _p(y, ctypes.c_double))
+    return y

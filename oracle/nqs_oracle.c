@@ -1,0 +1,545 @@
+/*
+ * nqs_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see
+ * nqs_oracle.h).  Loaded only by tests/, the smoke check and the benchmark's
+ * CPU-baseline leg.
+ *
+ * Each function below follows a passage of arxiv 2204.07816:
+ *   - Hamiltonian: Sec. 6.1, Eq. (J1J2), J1 = 1, J2 = 0.5; spin operators
+ *     S = sigma/2 (reading: per-site energies near -0.50 printed in Sec. 7.3-7.4
+ *     fix the spin-1/2 normalisation).
+ *   - wave function |Psi> = sum_S W(S)|S>: Sec. 3.2, Eq. (psi); sign rule of
+ *     Table 1, read as the Marshall sign on sublattice (x+y) even.
+ *   - local energy E_loc(S) = sum_S' W(S')/W(S) <S'|H|S>, S' = S with one
+ *     antiparallel nearest or next-nearest pair exchanged: Sec. 5.4.1
+ *     ("Hotspot energy calculation").
+ *   - CNN with periodic (PBC) padding and a product of neurons as output:
+ *     Sec. 5.2; the layer shape (3x3 conv, ln cosh, sum pool) is the
+ *     configuration this library is checked on.
+ *   - O_loc = per-sample log-derivative and the SR update: Sec. 3.2 and
+ *     Sec. 5.4.1 ("Distributed SR computation"), solved here by CG with an
+ *     absolute diagonal shift, 1/Ns normalisation, x0 = 0.
+ *
+ * Pins (tests/test_oracle_*.py): closed forms of the Neel / stripe /
+ * ferromagnet connected lists and diagonal energies; Marshall theorem on the
+ * exact 4x4 J2 = 0 ground state; exhaustive <psi|H|psi>/<psi|psi> on 4x4;
+ * zero variance of E_loc for the exact eigenvector; translation and spin-flip
+ * invariance; torch-CPU circular conv2d for the forward; central finite
+ * differences and torch autograd for O; numpy dense solve for SR.
+ */
+#include "nqs_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* lattice                                                              */
+/* ------------------------------------------------------------------ */
+
+static int wrap(int a, int L) { return ((a % L) + L) % L; }
+
+int64_t oracle_num_params(int K, int C)
+{
+    if (K < 1 || C < 1) return 0;
+    int64_t p = (int64_t)C * 1 * 9 + C;                     /* layer 1: 1 -> C */
+    p += (int64_t)(K - 1) * ((int64_t)C * C * 9 + C);       /* layers 2..K     */
+    return p;
+}
+
+int oracle_marshall_sign(int L, const int8_t *spins)
+{
+    int ups_on_a = 0;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x)
+            if (((x + y) % 2 == 0) && spins[y * L + x] > 0) ++ups_on_a;
+    return (ups_on_a % 2 == 0) ? 1 : -1;
+}
+
+int oracle_bond_sites(int L, int b, int *site_i, int *site_j)
+{
+    int i = b / 4, t = b % 4;
+    int x = i % L, y = i / L;
+    int dx = 0, dy = 0, cls = 1;
+    switch (t) {
+    case 0: dx = 1; dy = 0; cls = 1; break;   /* nearest, +x        */
+    case 1: dx = 0; dy = 1; cls = 1; break;   /* nearest, +y        */
+    case 2: dx = 1; dy = 1; cls = 2; break;   /* next-nearest, +x+y */
+    default: dx = 1; dy = -1; cls = 2; break; /* next-nearest, +x-y */
+    }
+    *site_i = i;
+    *site_j = wrap(y + dy, L) * L + wrap(x + dx, L);
+    return cls;
+}
+
+/* ------------------------------------------------------------------ */
+/* Hamiltonian: connected configurations and diagonal part              */
+/* ------------------------------------------------------------------ */
+
+void oracle_connected(int L, double J1, double J2, const int8_t *spins,
+                      int32_t *count, int32_t *bond_ids, int8_t *mu,
+                      double *e_diag)
+{
+    const int N = L * L;
+    int8_t *flipped = (int8_t *)malloc((size_t)N);
+    int n = 0;
+    double diag = 0.0;
+    int m0 = oracle_marshall_sign(L, spins);
+    for (int b = 0; b < 4 * N; ++b) {
+        int si, sj;
+        int cls = oracle_bond_sites(L, b, &si, &sj);
+        double J = (cls == 1) ? J1 : J2;
+        /* diagonal: J S^z_i S^z_j = J s_i s_j / 4 */
+        diag += J * (double)spins[si] * (double)spins[sj] / 4.0;
+        if (J != 0.0 && spins[si] != spins[sj]) {
+            memcpy(flipped, spins, (size_t)N);
+            flipped[si] = spins[sj];
+            flipped[sj] = spins[si];
+            bond_ids[n] = b;
+            mu[n] = (int8_t)(oracle_marshall_sign(L, flipped) * m0);
+            ++n;
+        }
+    }
+    *count = n;
+    *e_diag = diag;
+    free(flipped);
+}
+
+/* ------------------------------------------------------------------ */
+/* CNN forward: plain loops, channel-major activations                  */
+/* ------------------------------------------------------------------ */
+
+/* ln cosh z.  Near 0 use cosh z - 1 = 2 sinh^2(z/2), which keeps full relative
+ * precision of the z^2/2 leading term; for |z| > 1 use
+ * |z| + log1p(exp(-2|z|)) - ln 2, which cannot overflow.                   */
+static double ln_cosh(double z)
+{
+    double a = fabs(z);
+    if (a <= 1.0) {
+        double sh = sinh(0.5 * a);
+        return log1p(2.0 * sh * sh);
+    }
+    return a + log1p(exp(-2.0 * a)) - M_LN2;
+}
+
+/* offsets of layer k's weights and biases in the canonical vector */
+static void layer_offsets(int K, int C, int k, int64_t *w_off, int64_t *b_off,
+                          int *cin)
+{
+    int64_t off = 0;
+    for (int l = 0; l < k; ++l) {
+        int ci = (l == 0) ? 1 : C;
+        off += (int64_t)C * ci * 9 + C;
+    }
+    *cin = (k == 0) ? 1 : C;
+    *w_off = off;
+    *b_off = off + (int64_t)C * (*cin) * 9;
+}
+
+/* one circular 3x3 cross-correlation layer: z[co][y][x] */
+static void conv_layer(int L, int cin, int cout, const double *W, const double *bias,
+                       const double *h_in, double *z_out)
+{
+    for (int co = 0; co < cout; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = bias[co];
+                for (int ci = 0; ci < cin; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx) {
+                            int yy = wrap(y + ky - 1, L), xx = wrap(x + kx - 1, L);
+                            acc += W[((co * cin + ci) * 3 + ky) * 3 + kx] *
+                                   h_in[(ci * L + yy) * L + xx];
+                        }
+                z_out[(co * L + y) * L + x] = acc;
+            }
+}
+
+/* forward pass; if zs != NULL, stores every pre-activation z_k (k = 1..K)
+ * as zs[(k-1)*C*N ...] for the backward pass.  Returns f = sum h_K.        */
+static double cnn_forward(int L, int K, int C, const double *w, const int8_t *spins,
+                          double *h_a, double *h_b, double *zs)
+{
+    const int N = L * L;
+    for (int i = 0; i < N; ++i) h_a[i] = (double)spins[i];
+    double *h_in = h_a, *h_out = h_b;
+    for (int k = 0; k < K; ++k) {
+        int64_t wo, bo;
+        int cin;
+        layer_offsets(K, C, k, &wo, &bo, &cin);
+        conv_layer(L, cin, C, w + wo, w + bo, h_in, h_out);
+        if (zs) memcpy(zs + (size_t)k * C * N, h_out, sizeof(double) * (size_t)C * N);
+        for (int q = 0; q < C * N; ++q) h_out[q] = ln_cosh(h_out[q]);
+        double *t = h_in; h_in = h_out; h_out = t;
+    }
+    double f = 0.0;                        /* sum pool: c, then y, then x */
+    for (int q = 0; q < C * N; ++q) f += h_in[q];
+    return f;
+}
+
+static int threads_or_default(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+void oracle_log_psi(int L, int K, int C, const double *w, const int8_t *spins,
+                    int64_t B, double *log_abs, int8_t *sign, int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        double *ha = (double *)malloc(sizeof(double) * (size_t)C * N);
+        double *hb = (double *)malloc(sizeof(double) * (size_t)C * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            const int8_t *sp = spins + s * N;
+            log_abs[s] = cnn_forward(L, K, C, w, sp, ha, hb, NULL);
+            if (sign) sign[s] = (int8_t)oracle_marshall_sign(L, sp);
+        }
+        free(ha);
+        free(hb);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Local energy                                                         */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int L, K, C;
+    const double *w;
+    const double *log_abs_tab;
+    const int8_t *sign_tab;
+} amp_src;
+
+/* amplitude of a configuration: log|psi| and sign */
+static void amplitude(const amp_src *a, const int8_t *spins, double *h_a, double *h_b,
+                      double *log_abs, int *sign)
+{
+    if (a->w) {
+        *log_abs = cnn_forward(a->L, a->K, a->C, a->w, spins, h_a, h_b, NULL);
+        *sign = oracle_marshall_sign(a->L, spins);
+    } else {
+        int64_t idx = 0;
+        const int N = a->L * a->L;
+        for (int i = 0; i < N; ++i)
+            if (spins[i] > 0) idx |= ((int64_t)1 << i);
+        *log_abs = a->log_abs_tab[idx];
+        *sign = a->sign_tab[idx];
+    }
+}
+
+static double local_energy_one(const amp_src *a, double J1, double J2,
+                               const int8_t *spins, int8_t *work, double *h_a, double *h_b)
+{
+    const int L = a->L, N = L * L;
+    double f0;
+    int m0;
+    amplitude(a, spins, h_a, h_b, &f0, &m0);
+    double e = 0.0;
+    for (int b = 0; b < 4 * N; ++b) {
+        int si, sj;
+        int cls = oracle_bond_sites(L, b, &si, &sj);
+        double J = (cls == 1) ? J1 : J2;
+        e += J * (double)spins[si] * (double)spins[sj] / 4.0;    /* <S|H|S>     */
+        if (J == 0.0 || spins[si] == spins[sj]) continue;
+        memcpy(work, spins, (size_t)N);                         /* S' = S^b    */
+        work[si] = spins[sj];
+        work[sj] = spins[si];
+        double f1;
+        int m1;
+        amplitude(a, work, h_a, h_b, &f1, &m1);
+        /* <S'|H|S> = J/2 for the exchanged pair; W(S')/W(S) */
+        e += (J / 2.0) * (double)(m1 * m0) * exp(f1 - f0);
+    }
+    return e;
+}
+
+static void local_energy_batch(const amp_src *a, double J1, double J2,
+                               const int8_t *spins, int64_t B, double *e_loc, int nthreads)
+{
+    const int N = a->L * a->L;
+    const int C = a->C > 0 ? a->C : 1;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        int8_t *work = (int8_t *)malloc((size_t)N);
+        double *ha = (double *)malloc(sizeof(double) * (size_t)C * N);
+        double *hb = (double *)malloc(sizeof(double) * (size_t)C * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s)
+            e_loc[s] = local_energy_one(a, J1, J2, spins + s * N, work, ha, hb);
+        free(work);
+        free(ha);
+        free(hb);
+    }
+}
+
+void oracle_local_energy(int L, double J1, double J2, int K, int C,
+                         const double *w, const int8_t *spins, int64_t B,
+                         double *e_loc, int nthreads)
+{
+    amp_src a = {L, K, C, w, NULL, NULL};
+    local_energy_batch(&a, J1, J2, spins, B, e_loc, nthreads);
+}
+
+void oracle_local_energy_table(int L, double J1, double J2,
+                               const double *log_abs_tab, const int8_t *sign_tab,
+                               const int8_t *spins, int64_t B, double *e_loc,
+                               int nthreads)
+{
+    amp_src a = {L, 0, 0, NULL, log_abs_tab, sign_tab};
+    local_energy_batch(&a, J1, J2, spins, B, e_loc, nthreads);
+}
+
+/* ------------------------------------------------------------------ */
+/* Log-derivatives by reverse-mode chain rule                           */
+/* ------------------------------------------------------------------ */
+
+static void log_deriv_one(int L, int K, int C, const double *w, const int8_t *spins,
+                          double *O, double *zs, double *h_a, double *h_b,
+                          double *delta, double *grad_in)
+{
+    const int N = L * L;
+    cnn_forward(L, K, C, w, spins, h_a, h_b, zs);
+    /* dF/dh_K = 1, dh/dz = tanh z */
+    const double *zK = zs + (size_t)(K - 1) * C * N;
+    for (int q = 0; q < C * N; ++q) delta[q] = tanh(zK[q]);
+    for (int k = K - 1; k >= 0; --k) {
+        int64_t wo, bo;
+        int cin;
+        layer_offsets(K, C, k, &wo, &bo, &cin);
+        const double *W = w + wo;
+        /* input activations of layer k: spins, or ln cosh of z_{k-1} */
+        double *h_prev = h_a;
+        if (k == 0) {
+            for (int i = 0; i < N; ++i) h_prev[i] = (double)spins[i];
+        } else {
+            const double *zp = zs + (size_t)(k - 1) * C * N;
+            for (int q = 0; q < C * N; ++q) h_prev[q] = ln_cosh(zp[q]);
+        }
+        /* weight and bias gradients */
+        for (int co = 0; co < C; ++co) {
+            double db = 0.0;
+            for (int p = 0; p < N; ++p) db += delta[co * N + p];
+            O[bo + co] = db;
+            for (int ci = 0; ci < cin; ++ci)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double g = 0.0;
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x) {
+                                int yy = wrap(y + ky - 1, L), xx = wrap(x + kx - 1, L);
+                                g += delta[(co * L + y) * L + x] *
+                                     h_prev[(ci * L + yy) * L + xx];
+                            }
+                        O[wo + ((co * cin + ci) * 3 + ky) * 3 + kx] = g;
+                    }
+        }
+        if (k == 0) break;
+        /* gradient w.r.t. the layer input (transposed circular conv) */
+        memset(grad_in, 0, sizeof(double) * (size_t)cin * N);
+        for (int co = 0; co < C; ++co)
+            for (int ci = 0; ci < cin; ++ci)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double wv = W[((co * cin + ci) * 3 + ky) * 3 + kx];
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x) {
+                                int yy = wrap(y + ky - 1, L), xx = wrap(x + kx - 1, L);
+                                grad_in[(ci * L + yy) * L + xx] +=
+                                    wv * delta[(co * L + y) * L + x];
+                            }
+                    }
+        const double *zp = zs + (size_t)(k - 1) * C * N;
+        for (int q = 0; q < cin * N; ++q) delta[q] = grad_in[q] * tanh(zp[q]);
+    }
+}
+
+void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,
+                      int64_t B, double *O, int nthreads)
+{
+    const int N = L * L;
+    const int64_t P = oracle_num_params(K, C);
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        double *zs = (double *)malloc(sizeof(double) * (size_t)K * C * N);
+        double *ha = (double *)malloc(sizeof(double) * (size_t)C * N);
+        double *hb = (double *)malloc(sizeof(double) * (size_t)C * N);
+        double *dl = (double *)malloc(sizeof(double) * (size_t)C * N);
+        double *gi = (double *)malloc(sizeof(double) * (size_t)C * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s)
+            log_deriv_one(L, K, C, w, spins + s * N, O + s * P, zs, ha, hb, dl, gi);
+        free(zs);
+        free(ha);
+        free(hb);
+        free(dl);
+        free(gi);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Statistics and stochastic reconfiguration                            */
+/* ------------------------------------------------------------------ */
+
+void oracle_energy_stats(const double *e_loc, int64_t B, double *stats)
+{
+    double m = 0.0;
+    for (int64_t s = 0; s < B; ++s) m += e_loc[s];
+    m /= (double)B;
+    double v = 0.0;
+    for (int64_t s = 0; s < B; ++s) v += (e_loc[s] - m) * (e_loc[s] - m);
+    stats[0] = m;
+    stats[1] = v / (double)B;
+}
+
+static double dot(const double *a, const double *b, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* column means of O */
+static void col_mean(const double *O, int64_t B, int64_t P, double *obar)
+{
+    for (int64_t p = 0; p < P; ++p) obar[p] = 0.0;
+    for (int64_t s = 0; s < B; ++s)
+        for (int64_t p = 0; p < P; ++p) obar[p] += O[s * P + p];
+    for (int64_t p = 0; p < P; ++p) obar[p] /= (double)B;
+}
+
+/* y = (Obar^T Obar / B + lambda) v, Obar = O - obar, applied without forming S */
+static void apply_s(const double *O, const double *obar, int64_t B, int64_t P,
+                    double lambda, const double *v, double *y, double *u)
+{
+    for (int64_t s = 0; s < B; ++s) {
+        double acc = 0.0;
+        for (int64_t p = 0; p < P; ++p) acc += (O[s * P + p] - obar[p]) * v[p];
+        u[s] = acc;
+    }
+    for (int64_t p = 0; p < P; ++p) y[p] = 0.0;
+    for (int64_t s = 0; s < B; ++s)
+        for (int64_t p = 0; p < P; ++p) y[p] += (O[s * P + p] - obar[p]) * u[s];
+    for (int64_t p = 0; p < P; ++p) y[p] = y[p] / (double)B + lambda * v[p];
+}
+
+static void force_vector(const double *O, const double *obar, const double *e, int64_t B,
+                         int64_t P, double *F)
+{
+    double m = 0.0;
+    for (int64_t s = 0; s < B; ++s) m += e[s];
+    m /= (double)B;
+    for (int64_t p = 0; p < P; ++p) F[p] = 0.0;
+    for (int64_t s = 0; s < B; ++s)
+        for (int64_t p = 0; p < P; ++p) F[p] += (O[s * P + p] - obar[p]) * (e[s] - m);
+    for (int64_t p = 0; p < P; ++p) F[p] /= (double)B;
+}
+
+void oracle_sr_apply(const double *O, int64_t B, int64_t P, double lambda,
+                     const double *v, double *y)
+{
+    double *obar = (double *)malloc(sizeof(double) * (size_t)P);
+    double *u = (double *)malloc(sizeof(double) * (size_t)B);
+    col_mean(O, B, P, obar);
+    apply_s(O, obar, B, P, lambda, v, y, u);
+    free(obar);
+    free(u);
+}
+
+void oracle_sr_cg(const double *O, const double *e_loc, int64_t B, int64_t P,
+                  double lambda, int n_iter, double *x, double *stats)
+{
+    double *obar = (double *)malloc(sizeof(double) * (size_t)P);
+    double *F = (double *)malloc(sizeof(double) * (size_t)P);
+    double *r = (double *)malloc(sizeof(double) * (size_t)P);
+    double *p = (double *)malloc(sizeof(double) * (size_t)P);
+    double *Ap = (double *)malloc(sizeof(double) * (size_t)P);
+    double *u = (double *)malloc(sizeof(double) * (size_t)B);
+    col_mean(O, B, P, obar);
+    force_vector(O, obar, e_loc, B, P, F);
+    for (int64_t i = 0; i < P; ++i) { x[i] = 0.0; r[i] = F[i]; p[i] = F[i]; }
+    double rr = dot(r, r, P);
+    const double ff = rr;
+    int it = 0;
+    /* Early exit only once the recursive residual is 1e-30 of ||F|| (far below
+     * FP64 resolution of x): past that point r.r and p.Ap underflow.        */
+    const double stop = ff * 1e-60;
+    for (; it < n_iter && rr > stop; ++it) {
+        apply_s(O, obar, B, P, lambda, p, Ap, u);
+        double pap = dot(p, Ap, P);
+        if (!(pap > 0.0)) break;
+        double alpha = rr / pap;
+        for (int64_t i = 0; i < P; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * Ap[i]; }
+        double rr_new = dot(r, r, P);
+        double beta = rr_new / rr;
+        for (int64_t i = 0; i < P; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+    }
+    stats[0] = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    stats[1] = (double)it;
+    free(obar); free(F); free(r); free(p); free(Ap); free(u);
+}
+
+int oracle_sr_dense(const double *O, const double *e_loc, int64_t B, int64_t P,
+                    double lambda, double *x)
+{
+    double *obar = (double *)malloc(sizeof(double) * (size_t)P);
+    double *F = (double *)malloc(sizeof(double) * (size_t)P);
+    double *A = (double *)malloc(sizeof(double) * (size_t)P * P);
+    col_mean(O, B, P, obar);
+    force_vector(O, obar, e_loc, B, P, F);
+    /* A = Obar^T Obar / B + lambda I */
+    for (int64_t i = 0; i < P; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double acc = 0.0;
+            for (int64_t s = 0; s < B; ++s)
+                acc += (O[s * P + i] - obar[i]) * (O[s * P + j] - obar[j]);
+            acc /= (double)B;
+            if (i == j) acc += lambda;
+            A[i * P + j] = acc;
+            A[j * P + i] = acc;
+        }
+    /* Cholesky A = G G^T, lower triangle in place */
+    int ok = 0;
+    for (int64_t j = 0; j < P && ok == 0; ++j) {
+        double d = A[j * P + j];
+        for (int64_t k = 0; k < j; ++k) d -= A[j * P + k] * A[j * P + k];
+        if (d <= 0.0) { ok = -1; break; }
+        d = sqrt(d);
+        A[j * P + j] = d;
+        for (int64_t i = j + 1; i < P; ++i) {
+            double v = A[i * P + j];
+            for (int64_t k = 0; k < j; ++k) v -= A[i * P + k] * A[j * P + k];
+            A[i * P + j] = v / d;
+        }
+    }
+    if (ok == 0) {
+        /* forward then backward substitution */
+        for (int64_t i = 0; i < P; ++i) {
+            double v = F[i];
+            for (int64_t k = 0; k < i; ++k) v -= A[i * P + k] * x[k];
+            x[i] = v / A[i * P + i];
+        }
+        for (int64_t i = P - 1; i >= 0; --i) {
+            double v = x[i];
+            for (int64_t k = i + 1; k < P; ++k) v -= A[k * P + i] * x[k];
+            x[i] = v / A[i * P + i];
+        }
+    }
+    free(obar); free(F); free(A);
+    return ok;
+}

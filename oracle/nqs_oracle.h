@@ -1,0 +1,104 @@
+/*
+ * nqs_oracle.h -- plain FP64 CPU oracle for CNN variational Monte Carlo of the
+ * spin-1/2 J1-J2 Heisenberg model on an L x L periodic square lattice
+ * (arxiv 2204.07816).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no source, header, table or helper with the GPU
+ * path under paper_2204_07816_amd/.
+ *
+ * Everything is written from the definitions in the paper, in the plainest
+ * form: no blocking, no incremental updates, full recomputation of every
+ * connected configuration, channel-major [C][L][L] activations, FP64 only.
+ *
+ * Conventions (shared *interface* with the GPU library, independent code):
+ *   - spins: int8, +1/-1, layout [y][x], site i = y*L + x            (Sec. 5.4.1, spin image)
+ *   - H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j,  S = sigma/2   (Sec. 6.1, Eq. J1J2)
+ *   - psi(s) = M(s) * exp(f(s)),  M = Marshall sign (-1)^{#up spins on sublattice A},
+ *     A = {(x+y) even}; f = CNN log-amplitude                         (Sec. 3.2 Eq. psi, Table 1 "sign rule")
+ *   - CNN: K layers of 3x3 circular cross-correlation, bias, ln cosh after
+ *     every layer, sum over sites and channels.                       (Sec. 5.2, product of neurons)
+ *   - weights: FP64, canonical order, layer by layer W_k[co][ci][ky][kx]
+ *     then b_k[co]; layer 1 has ci = 1, the others ci = C.
+ *
+ * The pins that check every function are listed at the top of nqs_oracle.c
+ * and exercised by tests/test_oracle_*.py.
+ */
+#ifndef NQS_ORACLE_H
+#define NQS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* number of CNN parameters for K layers of C channels (layer 1: 1 -> C). */
+int64_t oracle_num_params(int K, int C);
+
+/* Marshall sign of one configuration: +1 or -1.                 */
+int oracle_marshall_sign(int L, const int8_t *spins);
+
+/* The two sites of canonical bond b = 4*i + t (t: 0 (x+1,y), 1 (x,y+1),
+ * 2 (x+1,y+1), 3 (x+1,y-1), all mod L).  Returns the coupling class:
+ * 1 for a nearest-neighbour pair, 2 for a next-nearest pair.            */
+int oracle_bond_sites(int L, int b, int *site_i, int *site_j);
+
+/* Connected configurations of one sample: for every bond with J_b != 0 and
+ * antiparallel spins, in increasing bond id.  Writes count, bond ids,
+ * the Marshall ratio M(s^b)/M(s) (computed from the two full configurations)
+ * and the diagonal energy sum_b J_b s_i s_j / 4.  bond_ids and mu must hold
+ * 4*L*L entries.                                                        */
+void oracle_connected(int L, double J1, double J2, const int8_t *spins,
+                      int32_t *count, int32_t *bond_ids, int8_t *mu,
+                      double *e_diag);
+
+/* CNN log-amplitude f(s) for B samples; nthreads <= 0 means all.        */
+void oracle_log_psi(int L, int K, int C, const double *w, const int8_t *spins,
+                    int64_t B, double *log_abs, int8_t *sign, int nthreads);
+
+/* Local energy E_loc(s) = sum_b J_b s_i s_j/4
+ *   + sum_{b antiparallel, J_b != 0} (J_b/2) psi(s^b)/psi(s),
+ * psi(s^b) by full recomputation of the network.                         */
+void oracle_local_energy(int L, double J1, double J2, int K, int C,
+                         const double *w, const int8_t *spins, int64_t B,
+                         double *e_loc, int nthreads);
+
+/* Same local energy with an arbitrary tabulated wave function: the amplitude
+ * of configuration s is sign_tab[idx] * exp(log_abs_tab[idx]), idx = sum_i
+ * [s_i = +1] 2^i.  Only for N = L*L <= 24.                              */
+void oracle_local_energy_table(int L, double J1, double J2,
+                               const double *log_abs_tab, const int8_t *sign_tab,
+                               const int8_t *spins, int64_t B, double *e_loc,
+                               int nthreads);
+
+/* Per-sample log-derivatives O[s][p] = d f(s) / d theta_p, FP64, by the
+ * reverse-mode chain rule through the network.                          */
+void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,
+                      int64_t B, double *O, int nthreads);
+
+/* Energy statistics: stats[0] = mean, stats[1] = variance (1/Ns).      */
+void oracle_energy_stats(const double *e_loc, int64_t B, double *stats);
+
+/* Stochastic reconfiguration, matrix-free conjugate gradient on
+ * (S + lambda I) x = F,  S = Obar^T Obar / Ns,  F = Obar^T (E - Ebar) / Ns,
+ * Obar = O - mean(O).  x0 = 0; exactly n_iter iterations (stops early only
+ * when r.r <= 1e-60 F.F, i.e. converged far beyond FP64 resolution).
+ * stats[0] = recursive ||r|| / ||F|| at exit, stats[1] = iterations run.  */
+void oracle_sr_cg(const double *O, const double *e_loc, int64_t B, int64_t P,
+                  double lambda, int n_iter, double *x, double *stats);
+
+/* Same system solved densely: build S + lambda I and factor it by Cholesky.
+ * Returns 0 on success, -1 when the matrix is not positive definite.     */
+int oracle_sr_dense(const double *O, const double *e_loc, int64_t B, int64_t P,
+                    double lambda, double *x);
+
+/* Apply the SR matrix once: y = (S + lambda I) v (for operator tests).     */
+void oracle_sr_apply(const double *O, int64_t B, int64_t P, double lambda,
+                     const double *v, double *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

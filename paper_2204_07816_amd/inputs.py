@@ -1,0 +1,101 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module holds no arithmetic of the method: it only draws random numbers.
+The paper's inputs are MCMC samples of trained networks, which do not exist
+here; they are replaced by
+
+* spin configurations drawn uniformly from the Sz = 0 sector (each sample is a
+  random permutation of N/2 up and N/2 down spins), and
+* CNN weights and biases drawn i.i.d. from N(0, sigma^2) in canonical
+  parameter order (layer by layer: W_k[co][ci][ky][kx], then b_k[co]).
+
+Both come from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def num_params(K: int, C: int) -> int:
+    """Parameter count of K 3x3 layers with C channels (layer 1 has one input channel)."""
+    return (C * 9 + C) + (K - 1) * (C * C * 9 + C)
+
+
+def weights(K: int, C: int, sigma: float, seed: int) -> np.ndarray:
+    """FP64 canonical weight vector, i.i.d. N(0, sigma^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(0.0, sigma, size=num_params(K, C)).astype(np.float64)
+
+
+def stress_weights(K: int, C: int, gain: float, seed: int, sigma1: float = 0.5) -> np.ndarray:
+    """Larger-signal weights: layer 1 ~ N(0, sigma1^2), layer k > 1 ~ N(0, gain^2/(9 C)),
+    zero biases.  Used to make the connected-configuration ratios differ from 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(K):
+        cin = 1 if k == 0 else C
+        sd = sigma1 if k == 0 else gain / np.sqrt(9.0 * cin)
+        out.append(rng.normal(0.0, sd, size=C * cin * 9))
+        out.append(np.zeros(C))
+    return np.concatenate(out).astype(np.float64)
+
+
+def spins_sz0(L: int, B: int, seed: int) -> np.ndarray:
+    """int8 [B, L, L] configurations, uniform over the Sz = 0 sector."""
+    N = L * L
+    assert N % 2 == 0
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = np.concatenate([np.ones(N // 2, np.int8), -np.ones(N // 2, np.int8)])
+    out = np.empty((B, N), np.int8)
+    for b in range(B):
+        out[b] = rng.permutation(base)
+    return out.reshape(B, L, L)
+
+
+def spins_any(L: int, B: int, seed: int) -> np.ndarray:
+    """int8 [B, L, L] configurations with i.i.d. +-1 spins (any magnetisation)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.where(rng.random((B, L, L)) < 0.5, 1, -1).astype(np.int8)
+
+
+def neel(L: int) -> np.ndarray:
+    y, x = np.mgrid[0:L, 0:L]
+    return np.where((x + y) % 2 == 0, 1, -1).astype(np.int8)
+
+
+def column_stripe(L: int) -> np.ndarray:
+    y, x = np.mgrid[0:L, 0:L]
+    return np.where(x % 2 == 0, 1, -1).astype(np.int8)
+
+
+def ferro(L: int) -> np.ndarray:
+    return np.ones((L, L), np.int8)
+
+
+# The workloads this library is checked and measured on (J1 = 1 throughout).
+# "sigma" is the weight scale; seeds follow weights_seed = 1000 + index,
+# spins_seed = 2000 + index.
+CONFIGS = {
+    "plain4": dict(index=0, L=4, J2=0.5, K=2, C=4, sigma=0.05, B=1024),
+    "cmp10": dict(index=1, L=10, J2=0.5, K=4, C=16, sigma=0.02, B=8192),
+    "mixed": dict(index=2, lattices=((12, 0.0), (16, 0.5), (20, 0.55)), K=6, C=32,
+                  sigma=0.02, B=4096),
+    "sr24": dict(index=3, L=24, J2=0.5, K=6, C=32, sigma=0.02, B=4096),
+    "full36": dict(index=4, L=36, J2=0.5, K=8, C=32, sigma=0.02, B=1024),
+}
+
+
+def config_inputs(name: str, B: int | None = None, lattice: int = 0):
+    """(L, J2, K, C, weights, spins) of a named workload; B overrides the batch."""
+    cfg = CONFIGS[name]
+    idx = cfg["index"]
+    if "lattices" in cfg:
+        L, J2 = cfg["lattices"][lattice]
+        sseed = 2000 + idx + 100 * (lattice + 1)
+    else:
+        L, J2 = cfg["L"], cfg["J2"]
+        sseed = 2000 + idx
+    nb = cfg["B"] if B is None else B
+    w = weights(cfg["K"], cfg["C"], cfg["sigma"], 1000 + idx)
+    s = spins_sz0(L, nb, sseed)
+    return L, J2, cfg["K"], cfg["C"], w, s
