@@ -75,12 +75,12 @@ def test_sr_cg_small_system_exact():
     """CG in exact arithmetic solves an n x n SPD system in n steps: 2x2 by hand."""
     import oracle
     # columns have zero mean, so Obar = O and S = O^T O / 4 = diag(0.5, 2);
-    # F = O^T (e - mean e) / 4 = (0.5, 1); with lambda = 0.5, x = F / diag(S + lambda)
+    # F = O^T (e - mean e) / 4 = (0.5, 2); with lambda = 0.5, x = F / diag(S + lambda)
     O = np.array([[1.0, 0.0], [-1.0, 0.0], [0.0, 2.0], [0.0, -2.0]])
     e = np.array([2.0, 0.0, 5.0, 1.0])
     x, rel, it = oracle.sr_cg(O, e, 0.5, n_iter=2)
     S = np.diag([0.5, 2.0]) + 0.5 * np.eye(2)
     F = O.T @ (e - e.mean()) / 4
-    np.testing.assert_allclose(F, [0.5, 1.0])
-    np.testing.assert_allclose(x, [0.5, 0.4], rtol=1e-14)
+    np.testing.assert_allclose(F, [0.5, 2.0])
+    np.testing.assert_allclose(x, [0.5, 0.8], rtol=1e-14)
     assert it <= 2
