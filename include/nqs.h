@@ -1,0 +1,188 @@
+/*
+ * nqs.h -- C ABI of libnqs: the MI355X (gfx950) hot path of convolutional
+ * neural-network variational Monte Carlo for the spin-1/2 J1-J2 Heisenberg
+ * model on an L x L periodic square lattice (arxiv 2204.07816).
+ *
+ * What the library computes (paper passages in brackets):
+ *   H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j, S = sigma/2         [Sec. 6.1, Eq. J1J2]
+ *   psi(s) = M(s) exp f(s): M = Marshall sign (-1)^{#up spins on the
+ *     sublattice (x+y) even}, f = CNN log-amplitude                      [Sec. 3.2 Eq. psi; Table 1 sign rule]
+ *   f: K layers of 3x3 periodic (circular) cross-correlation + bias +
+ *     ln cosh, summed over sites and channels (log of a product of
+ *     neurons)                                                            [Sec. 5.2]
+ *   E_loc(s) = sum_S' psi(S')/psi(s) <S'|H|s>: diagonal part plus one
+ *     exchanged configuration per antiparallel J1/J2 pair                 [Sec. 5.4.1, hotspot energy]
+ *   O_k(s) = d log|psi(s)| / d theta_k per sample                          [Sec. 3.2, O_loc by backward]
+ *   SR: (S + lambda I) dtheta = F, S = Obar^T Obar / Ns,
+ *       F = Obar^T (E - Ebar) / Ns                                        [Sec. 3.2; Sec. 5.4.1 distributed SR]
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer unless marked "host".  The
+ *     caller owns every buffer it passes; the context owns its weights and
+ *     its workspace.
+ *   - spins: int8 +1/-1, layout [B][L][L] (row y, column x), site i = y*L+x.
+ *   - weights: FP64, canonical order, layer by layer: W_k[co][ci][ky][kx]
+ *     then b_k[co]; layer 1 has one input channel, layers 2..K have C.
+ *     The convolution is a cross-correlation:
+ *       z[co][y][x] = b[co] + sum W[co][ci][ky][kx] h[ci][(y+ky-1) mod L][(x+kx-1) mod L].
+ *   - Canonical bond id b = 4*i + t, t = 0: (x+1,y) J1, 1: (x,y+1) J1,
+ *     2: (x+1,y+1) J2, 3: (x+1,y-1) J2 (all mod L).
+ *   - stream: a hipStream_t (NULL = default stream).  All work is enqueued
+ *     asynchronously on it; no call synchronises unless documented.
+ *   - Limits: even L with 4 <= L <= 64; 1 <= K <= 16; 1 <= C <= 32 for the
+ *     FP64/FP32 paths, C in {16, 32} and K >= 2 for BF16; B <= 131072 per
+ *     call.
+ *
+ * Errors
+ *   - Argument problems found on the host are returned at once and nothing
+ *     is enqueued.
+ *   - Problems found on the device (a spin that is not +1/-1, a non-finite
+ *     log-amplitude difference or local energy) set a sticky error word in
+ *     the context; nqs_get_error() reads (and clears) it.
+ *   - A call that needs more workspace than nqs_reserve() provided allocates
+ *     it, unless the stream is being captured into a graph: then it returns
+ *     NQS_E_WORKSPACE.
+ *   - Thread safety: calls on one context must be serialised by the caller;
+ *     distinct contexts are independent.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nqs_ctx nqs_ctx;
+
+typedef enum {
+    NQS_OK = 0,
+    NQS_E_ARG = 1,          /* null pointer, negative size, bad enum          */
+    NQS_E_LATTICE = 2,      /* L odd, < 4 or > 64                             */
+    NQS_E_SPEC = 3,         /* network spec not supported                      */
+    NQS_E_NPARAMS = 4,      /* weight count does not match the spec            */
+    NQS_E_SPIN = 5,         /* device: a spin value other than +1 / -1         */
+    NQS_E_NONFINITE = 6,    /* device: non-finite log-ratio or local energy    */
+    NQS_E_NOMEM = 7,        /* device allocation failed                        */
+    NQS_E_WORKSPACE = 8,    /* workspace too small while a capture is active   */
+    NQS_E_HIP = 9,          /* a HIP runtime call failed                       */
+    NQS_E_UNSUPPORTED = 10  /* valid request this build does not implement     */
+} nqs_status;
+
+typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2 } nqs_dtype;
+
+/* How psi(S') is evaluated for the exchanged configurations [Sec. 5.4.1]:
+ * FULL recomputes the whole network for every S'; INCREMENTAL recomputes only
+ * the receptive-field cone of the exchanged pair (BF16 path only) and reads
+ * the rest from the cached activations of S; AUTO lets the library choose. */
+typedef enum { NQS_AUTO = 0, NQS_FULL = 1, NQS_INCREMENTAL = 2 } nqs_mode;
+
+typedef struct {
+    int32_t n_layers;       /* K                                              */
+    int32_t channels;       /* C                                              */
+    int32_t marshall_sign;  /* 1: psi carries the Marshall sign; 0: psi > 0   */
+    nqs_dtype conv_dtype;   /* arithmetic of the convolutions: FP64 (plain),
+                               FP32 (vector), BF16 (MFMA, FP32 accumulate)   */
+} nqs_cnn_spec;
+
+/* Create a context for one lattice and network on the current HIP device.
+ * weights: host, n_weights FP64 values in canonical order (copied).       */
+nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
+                      const double *weights, int64_t n_weights, nqs_ctx **out);
+
+/* Release the context and its device memory (synchronises the device).  */
+nqs_status nqs_destroy(nqs_ctx *ctx);
+
+/* Number of network parameters P (host out).                              */
+nqs_status nqs_num_params(const nqs_ctx *ctx, int64_t *P);
+
+/* Replace the weights (host, canonical order, n == P); synchronous.       */
+nqs_status nqs_set_weights(nqs_ctx *ctx, const double *weights, int64_t n);
+
+/* Pre-allocate workspace for batches up to B_max in the given mode, so that
+ * later calls allocate nothing (and may be captured into a hipGraph).    */
+nqs_status nqs_reserve(nqs_ctx *ctx, int64_t B_max, nqs_mode mode);
+
+/* log|psi(s)| (FP64 [B]) and the sign of psi (int8 [B], may be NULL)
+ * [Sec. 3.2 Eq. psi].                                                      */
+nqs_status nqs_log_psi(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                       double *log_abs, int8_t *sign, void *stream);
+
+/* Local energies E_loc(s), FP64 [B] [Sec. 5.4.1].  Ratios exp(f(S')-f(s)),
+ * their per-sample sums and the diagonal part are FP64 in every mode.     */
+nqs_status nqs_local_energy(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                            double *e_loc, nqs_mode mode, void *stream);
+
+/* Batch mean and variance (1/Ns) of e_loc: stats FP64 [2], device.         */
+nqs_status nqs_energy_stats(nqs_ctx *ctx, const double *e_loc, int64_t B,
+                            double *stats, void *stream);
+
+/* Per-sample log-derivatives O [B][P] row-major, FP32 or FP64 (O_dtype),
+ * computed by a hand-written backward pass in FP64 [Sec. 3.2].  The
+ * Marshall sign does not depend on the weights, so O = d f / d theta.     */
+nqs_status nqs_log_deriv(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                         void *O, nqs_dtype O_dtype, void *stream);
+
+/* Stochastic reconfiguration [Sec. 3.2; Sec. 5.4.1]: conjugate gradient on
+ * (S + diag_shift I) dtheta = F with S applied matrix-free as
+ * Obar^T (Obar v) / B + diag_shift v (S is never formed), x0 = 0, exactly
+ * n_iter iterations unless the recursive residual falls below 1e-30 ||F||.
+ * O: [B][P] in O_dtype (FP32 or FP64); e_loc FP64 [B]; dtheta FP64 [P].
+ * stats (device, FP64 [4], may be NULL): mean energy, variance,
+ * recursive ||r||/||F|| at exit, iterations run.                          */
+nqs_status nqs_sr_solve(nqs_ctx *ctx, const void *O, nqs_dtype O_dtype,
+                        const double *e_loc, int64_t B, double diag_shift,
+                        int32_t n_iter, double *dtheta, double *stats,
+                        void *stream);
+
+/* Inspection of the integer stage [Sec. 5.4.1]: for every sample the count
+ * of antiparallel bonds with J != 0 (int32 [B]), exclusive offsets
+ * (int64 [B+1]), the bond ids in canonical order and the Marshall ratio
+ * mu = M(S')/M(s) of each (int32 / int8 [capacity]), and the diagonal energy
+ * (FP64 [B]).  capacity must be >= the number of bonds with J != 0 times B
+ * (4*L*L*B when J2 != 0).  Lists are bit-exact and deterministic.         */
+nqs_status nqs_connected(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                         int32_t *counts, int64_t *offsets, int32_t *bond_ids,
+                         int8_t *mu, int64_t capacity, double *e_diag,
+                         void *stream);
+
+/* The log-amplitude differences f(S') - f(s) of every exchanged
+ * configuration, FP64 [capacity], in the order of nqs_connected.            */
+nqs_status nqs_log_ratios(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                          nqs_mode mode, double *dlog, int64_t capacity,
+                          void *stream);
+
+/* Several lattices in one launch sequence: every job has its own context
+ * (same network shape and conv dtype, any L, J2 and weights).  The
+ * exchanged configurations of all jobs share one persistent kernel launch. */
+typedef struct {
+    nqs_ctx *ctx;
+    const int8_t *spins;
+    int64_t B;
+    double *e_loc;
+} nqs_eloc_job;
+nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n_jobs,
+                                  nqs_mode mode, void *stream);
+
+/* Which mode AUTO picks for this context (host out).                      */
+nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
+
+/* Sticky device error word: synchronises the context's last stream, returns
+ * the first device-detected status since the last call (host out), clears. */
+nqs_status nqs_get_error(nqs_ctx *ctx, nqs_status *sticky);
+
+/* Kernel timing: when enabled, the library records HIP events around the
+ * exchanged-configuration kernel on the caller's stream.  nqs_kernel_time
+ * synchronises and returns the summed milliseconds and launch count since
+ * enabling, then resets.                                                  */
+nqs_status nqs_enable_timing(nqs_ctx *ctx, int32_t enable);
+nqs_status nqs_kernel_time(nqs_ctx *ctx, double *ms, int64_t *launches);
+
+/* Static description of a status code.                                    */
+const char *nqs_status_str(nqs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

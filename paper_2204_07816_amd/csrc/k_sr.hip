@@ -1,0 +1,317 @@
+// k_sr.hip -- stochastic reconfiguration [Sec. 3.2: SR gradients and
+// covariance give the parameter update delta; Sec. 5.4.1 "Distributed SR
+// computation"].  The paper forms the [R, R] covariance and factorises it;
+// here the same system
+//     (S + lambda I) x = F,  S = Obar^T Obar / Ns,  F = Obar^T (E - Ebar) / Ns,
+// Obar = O - mean(O), is solved by conjugate gradient with S applied
+// matrix-free as two streaming passes over O per iteration (HBM bound).
+// O is read as FP32 or FP64; every product, sum and dot is FP64.  Scalars
+// (alpha, beta, r.r) stay on the device, so the solve never synchronises
+// with the host and can be captured in a graph.  All reductions are two-stage
+// with a fixed order (deterministic).
+#include <algorithm>
+
+#include "nqs_internal.h"
+
+namespace nqs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxChunks = 64;
+
+struct SrCtl {
+    double rr, ff, alpha, beta, mean, var;
+    int done, it;
+};
+
+__device__ inline double ld(const float *p, int64_t i) { return (double)p[i]; }
+__device__ inline double ld(const double *p, int64_t i) { return p[i]; }
+
+__device__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// part[c][p] = sum_{s in chunk c} (O[s][p] - sub[p]) * wt[s]   (sub / wt may be null)
+template <typename OT>
+__global__ void __launch_bounds__(kThreads)
+k_colsum(const OT *__restrict__ O, int64_t B, int64_t P, const double *__restrict__ sub,
+         const double *__restrict__ wt, int64_t rows_per_chunk, double *__restrict__ part,
+         const SrCtl *ctl)
+{
+    if (ctl && ctl->done) return;
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= P) return;
+    const int64_t s0 = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t s1 = min(B, s0 + rows_per_chunk);
+    const double m = sub ? sub[p] : 0.0;
+    double acc = 0.0;
+    for (int64_t s = s0; s < s1; ++s) acc = fma(ld(O, s * P + p) - m, wt ? wt[s] : 1.0, acc);
+    part[(int64_t)blockIdx.y * P + p] = acc;
+}
+
+// out[p] = scale * sum_c part[c][p] (+ lam * v[p])
+__global__ void k_colsum_final(const double *__restrict__ part, int nchunk, int64_t P,
+                               double scale, double lam, const double *__restrict__ v,
+                               double *__restrict__ out, const SrCtl *ctl)
+{
+    if (ctl && ctl->done) return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * P + p];
+    out[p] = acc * scale + (v ? lam * v[p] : 0.0);
+}
+
+// u[s] = sum_p (O[s][p] - obar[p]) v[p]: one block per row
+template <typename OT>
+__global__ void __launch_bounds__(kThreads)
+k_rowdot(const OT *__restrict__ O, int64_t P, const double *__restrict__ obar,
+         const double *__restrict__ v, double *__restrict__ u, const SrCtl *ctl)
+{
+    __shared__ double sh[kThreads];
+    if (ctl->done) return;
+    const int64_t s = blockIdx.x;
+    const OT *row = O + s * P;
+    double acc = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += kThreads) acc = fma(ld(row, p) - obar[p], v[p], acc);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) u[s] = acc;
+}
+
+// partial dot products a.b, one value per block
+__global__ void __launch_bounds__(kThreads)
+k_dot_part(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+           double *__restrict__ part, const SrCtl *ctl)
+{
+    __shared__ double sh[kThreads];
+    if (ctl && ctl->done) return;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        acc = fma(a[i], b[i], acc);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// stage 2 of the dot products, plus the scalar recurrences of CG.
+//   what = 0: initial r.r  -> rr = ff = value; done if ff == 0
+//   what = 1: p.Ap         -> alpha = rr / pap, or done if pap <= 0
+//   what = 2: new r.r      -> beta = rr_new / rr, rr = rr_new, it++, done if converged
+__global__ void __launch_bounds__(kThreads)
+k_dot_final(const double *__restrict__ part, int nparts, int what, SrCtl *ctl)
+{
+    __shared__ double sh[kThreads];
+    if (ctl->done) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) acc += part[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    if (what == 0) {
+        ctl->rr = acc;
+        ctl->ff = acc;
+        ctl->it = 0;
+        ctl->done = !(acc > 0.0);
+    } else if (what == 1) {
+        if (!(acc > 0.0)) {
+            ctl->done = 1;
+        } else {
+            ctl->alpha = ctl->rr / acc;
+        }
+    } else {
+        ctl->beta = acc / ctl->rr;
+        ctl->rr = acc;
+        ctl->it += 1;
+        // converged far beyond FP64 resolution: ||r|| <= 1e-30 ||F||
+        if (!(acc > ctl->ff * 1e-60)) ctl->done = 1;
+    }
+}
+
+// x += alpha p; r -= alpha Ap
+__global__ void k_update_xr(double *__restrict__ x, double *__restrict__ r,
+                            const double *__restrict__ p, const double *__restrict__ ap, int64_t n,
+                            const SrCtl *ctl)
+{
+    if (ctl->done) return;
+    const double a = ctl->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = fma(a, p[i], x[i]);
+        r[i] = fma(-a, ap[i], r[i]);
+    }
+}
+
+// p = r + beta p   (runs only after a completed iteration)
+__global__ void k_update_p(double *__restrict__ p, const double *__restrict__ r, int64_t n,
+                           const SrCtl *ctl, int it_expected)
+{
+    if (ctl->it != it_expected) return;
+    const double b = ctl->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = fma(b, p[i], r[i]);
+}
+
+// x = 0, r = p = F
+__global__ void k_init(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                       const double *__restrict__ F, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = 0.0;
+        r[i] = F[i];
+        p[i] = F[i];
+    }
+}
+
+// mean / variance of e, and d = e - mean
+__global__ void __launch_bounds__(1024)
+k_center(const double *__restrict__ e, int64_t B, double *__restrict__ d, SrCtl *ctl)
+{
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (int64_t s = threadIdx.x; s < B; s += 1024) acc += e[s];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double mean = sh[0] / (double)B;
+    __syncthreads();
+    acc = 0.0;
+    for (int64_t s = threadIdx.x; s < B; s += 1024) {
+        const double v = e[s] - mean;
+        d[s] = v;
+        acc += v * v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->mean = mean;
+        ctl->var = sh[0] / (double)B;
+        ctl->done = 0;
+        ctl->it = 0;
+    }
+}
+
+__global__ void k_stats_out(const SrCtl *ctl, double *stats)
+{
+    stats[0] = ctl->mean;
+    stats[1] = ctl->var;
+    stats[2] = ctl->ff > 0.0 ? sqrt(ctl->rr / ctl->ff) : 0.0;
+    stats[3] = (double)ctl->it;
+}
+
+struct SrLayout {
+    int64_t nchunk, rows_per_chunk, ndot;
+    size_t off_obar, off_F, off_r, off_p, off_ap, off_d, off_u, off_part, off_dot, off_ctl, total;
+};
+
+SrLayout layout(int64_t B, int64_t P)
+{
+    SrLayout l;
+    l.nchunk = std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (B + 63) / 64));
+    l.rows_per_chunk = (B + l.nchunk - 1) / l.nchunk;
+    l.ndot = 512;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += (n * sizeof(double) + 255) & ~(size_t)255;
+        return o;
+    };
+    l.off_obar = take(P);
+    l.off_F = take(P);
+    l.off_r = take(P);
+    l.off_p = take(P);
+    l.off_ap = take(P);
+    l.off_d = take(B);
+    l.off_u = take(B);
+    l.off_part = take((size_t)l.nchunk * P);
+    l.off_dot = take(l.ndot);
+    l.off_ctl = take(8);
+    l.total = off;
+    return l;
+}
+
+template <typename OT>
+void sr_solve_t(const OT *O, const double *e, int64_t B, int64_t P, double lam, int n_iter,
+                double *x, double *stats, unsigned char *w, hipStream_t s)
+{
+    const SrLayout l = layout(B, P);
+    double *obar = (double *)(w + l.off_obar), *F = (double *)(w + l.off_F);
+    double *r = (double *)(w + l.off_r), *p = (double *)(w + l.off_p);
+    double *ap = (double *)(w + l.off_ap), *d = (double *)(w + l.off_d);
+    double *u = (double *)(w + l.off_u), *part = (double *)(w + l.off_part);
+    double *dot = (double *)(w + l.off_dot);
+    SrCtl *ctl = (SrCtl *)(w + l.off_ctl);
+    const dim3 cgrid((unsigned)((P + kThreads - 1) / kThreads), (unsigned)l.nchunk);
+    const unsigned vgrid = (unsigned)std::min<int64_t>(1024, (P + kThreads - 1) / kThreads);
+    const unsigned fgrid = (unsigned)((P + kThreads - 1) / kThreads);
+    const double invB = 1.0 / (double)B;
+
+    NQS_LAUNCH(k_center, dim3(1), dim3(1024), 0, s, e, B, d, ctl);
+    // column means
+    NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P,
+                       (const double *)nullptr, (const double *)nullptr, l.rows_per_chunk, part,
+                       (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
+                       invB, 0.0, (const double *)nullptr, obar, (const SrCtl *)nullptr);
+    // F = Obar^T (E - Ebar) / B
+    NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P, obar, d,
+                       l.rows_per_chunk, part, (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
+                       invB, 0.0, (const double *)nullptr, F, (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_init, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, F, P);
+    NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
+                       (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 0, ctl);
+    for (int it = 0; it < n_iter; ++it) {
+        // Ap = Obar^T (Obar p) / B + lambda p
+        NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)B), dim3(kThreads), 0, s, O, P, obar, p,
+                           u, ctl);
+        NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P, obar, u,
+                           l.rows_per_chunk, part, ctl);
+        NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part,
+                           (int)l.nchunk, P, invB, lam, p, ap, ctl);
+        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, p, ap, P,
+                           dot, ctl);
+        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 1, ctl);
+        NQS_LAUNCH(k_update_xr, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, ap, P, ctl);
+        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
+                           ctl);
+        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 2, ctl);
+        NQS_LAUNCH(k_update_p, dim3(vgrid), dim3(kThreads), 0, s, p, r, P, ctl, it + 1);
+    }
+    if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
+}
+
+}  // namespace
+
+size_t sr_workspace_bytes(int64_t B, int64_t P) { return layout(B, P).total; }
+
+void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t B, int64_t P,
+                     double lambda, int n_iter, double *x, double *stats, void *work,
+                     hipStream_t s)
+{
+    if (odt == NQS_FP32)
+        sr_solve_t<float>((const float *)O, e_loc, B, P, lambda, n_iter, x, stats,
+                          (unsigned char *)work, s);
+    else
+        sr_solve_t<double>((const double *)O, e_loc, B, P, lambda, n_iter, x, stats,
+                           (unsigned char *)work, s);
+}
+
+}  // namespace nqs

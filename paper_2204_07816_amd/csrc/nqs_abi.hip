@@ -1,0 +1,666 @@
+// nqs_abi.hip -- host side of the C ABI declared in include/nqs.h: argument
+// validation, weight packing for each kernel family, workspace management and
+// the order in which the kernels of each call are enqueued.  Nothing here does
+// arithmetic of the method; every step runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <cstdio>
+#include <cstdlib>
+
+#include "nqs_internal.h"
+
+using namespace nqs;
+
+namespace {
+
+#define HIP_OK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return NQS_E_HIP;    \
+    } while (0)
+
+int64_t params_of(int K, int C) { return (int64_t)(C * 9 + C) + (int64_t)(K - 1) * (C * C * 9 + C); }
+
+// FP64 -> BF16, round to nearest even (via FP32, with the double-rounding
+// case resolved against the exact midpoint).
+uint16_t bf16_rne(double d)
+{
+    float f = (float)d;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+    const uint32_t low = u & 0xffffu;
+    uint32_t hi = u >> 16;
+    if (low == 0x8000u) {
+        // f sits on a BF16 midpoint: decide from the exact double
+        uint32_t lo_b = u & 0xffff0000u, up_b = lo_b + 0x10000u;
+        float flo, fup;
+        std::memcpy(&flo, &lo_b, 4);
+        std::memcpy(&fup, &up_b, 4);
+        const double mid = 0.5 * ((double)flo + (double)fup);
+        const double ad = std::fabs(d), am = std::fabs(mid);
+        if (ad > am) hi += 1;
+        else if (ad == am) hi += (hi & 1);
+        return (uint16_t)hi;
+    }
+    if (low > 0x8000u) hi += 1;
+    return (uint16_t)hi;
+}
+
+template <int C>
+int chan_of_slot_h(int q)
+{
+    if (C == 32) {
+        const int g = q >> 3, r = q & 7;
+        return r < 4 ? 4 * g + r : 16 + 4 * g + (r - 4);
+    }
+    return q;
+}
+
+struct Canon {
+    const double *w;
+    int K, C;
+    int64_t off(int l) const
+    {
+        int64_t o = 0;
+        for (int i = 0; i < l; ++i) o += (int64_t)C * (i == 0 ? 1 : C) * 9 + C;
+        return o;
+    }
+    int cin(int l) const { return l == 0 ? 1 : C; }
+    double W(int l, int co, int ci, int t) const { return w[off(l) + ((int64_t)co * cin(l) + ci) * 9 + t]; }
+    double b(int l, int co) const { return w[off(l) + (int64_t)C * cin(l) * 9 + co]; }
+};
+
+template <typename T>
+void free_dev(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+template <typename T>
+nqs_status upload(T *&dst, const std::vector<T> &src)
+{
+    free_dev(dst);
+    if (src.empty()) return NQS_OK;
+    if (hipMalloc((void **)&dst, src.size() * sizeof(T)) != hipSuccess) return NQS_E_NOMEM;
+    HIP_OK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return NQS_OK;
+}
+
+nqs_status pack_weights(nqs_ctx *c)
+{
+    const int K = c->K, C = c->C;
+    Canon cn{c->w_host.data(), K, C};
+    // vector path: layer 1 [9][C] + b; layer k [9][Cin][C] + b
+    std::vector<double> v64;
+    for (int l = 0; l < K; ++l) {
+        const int ci_n = cn.cin(l);
+        for (int t = 0; t < 9; ++t)
+            for (int ci = 0; ci < ci_n; ++ci)
+                for (int co = 0; co < C; ++co) v64.push_back(cn.W(l, co, ci, t));
+        for (int co = 0; co < C; ++co) v64.push_back(cn.b(l, co));
+    }
+    std::vector<float> v32(v64.begin(), v64.end());
+    // backward data pass, layers 2..K: [t'][co][ci] = W[co][ci][8 - t']
+    std::vector<double> bw;
+    for (int l = 1; l < K; ++l)
+        for (int t = 0; t < 9; ++t)
+            for (int co = 0; co < C; ++co)
+                for (int ci = 0; ci < C; ++ci) bw.push_back(cn.W(l, co, ci, 8 - t));
+    nqs_status st;
+    if ((st = upload(c->w_vec64, v64)) != NQS_OK) return st;
+    if ((st = upload(c->w_vec32, v32)) != NQS_OK) return st;
+    if ((st = upload(c->w_bwd64, bw)) != NQS_OK) return st;
+    if ((st = upload(c->w_canon, c->w_host)) != NQS_OK) return st;
+    if (c->dtype == NQS_BF16) {
+        // A operands of v_mfma_f32_16x16x32_bf16: lane l holds row m = l % 16
+        // (output channel 16 h + m) and the 8 reduction elements (g = l/16, i)
+        // that pair with the B operand's 8 elements of lane group g.
+        std::vector<uint16_t> wm;
+        const int KS = (C == 32) ? 9 : 5, NH = C / 16;
+        for (int l = 1; l < K; ++l)
+            for (int j = 0; j < KS; ++j)
+                for (int h = 0; h < NH; ++h)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int i = 0; i < 8; ++i) {
+                            const int g = lane >> 4, co = 16 * h + (lane & 15);
+                            int tap, ci;
+                            if (C == 32) {
+                                tap = j;
+                                ci = chan_of_slot_h<32>(g * 8 + i);
+                            } else {
+                                tap = 2 * j + (g >> 1);
+                                ci = chan_of_slot_h<16>((g & 1) * 8 + i);
+                            }
+                            wm.push_back(tap <= 8 ? bf16_rne(cn.W(l, co, ci, tap)) : (uint16_t)0);
+                        }
+        std::vector<float> l1;
+        for (int t = 0; t < 9; ++t)
+            for (int co = 0; co < C; ++co) l1.push_back((float)cn.W(0, co, 0, t));
+        for (int l = 0; l < K; ++l)
+            for (int co = 0; co < C; ++co) l1.push_back((float)cn.b(l, co));
+        if ((st = upload(c->w_mfma, wm)) != NQS_OK) return st;
+        if ((st = upload(c->w_l1, l1)) != NQS_OK) return st;
+    }
+    return NQS_OK;
+}
+
+int64_t bonds_per_sample(const nqs_ctx *c)
+{
+    return (int64_t)2 * c->N * ((c->J1 != 0.0 ? 1 : 0) + (c->J2 != 0.0 ? 1 : 0));
+}
+
+nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
+{
+    if (m != NQS_AUTO) return m;
+    if (c->dtype != NQS_BF16) return NQS_FULL;
+    // incremental work: sum_k |R_k| over layers 2..K for a 2x2 seed, clamped
+    double inc = 0.0, full = 0.0;
+    for (int k = 2; k <= c->K; ++k) {
+        const int ex = std::min(2 + 2 * k, c->L);
+        inc += (double)ex * ex;
+        full += (double)c->N;
+    }
+    return inc < 0.7 * full ? NQS_INCREMENTAL : NQS_FULL;
+}
+
+#define NQS_TRY(x)                        \
+    do {                                  \
+        nqs_status _s = (x);              \
+        if (_s != NQS_OK) return _s;      \
+    } while (0)
+
+// Integer stage: counts, diagonal energy, offsets, queue.
+nqs_status integer_stage(nqs_ctx *c, const int8_t *spins, int B, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    const int64_t cap = bonds_per_sample(c) * B;
+    NQS_TRY(ensure(w.counts, sizeof(int32_t) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.ediag, sizeof(double) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.offsets, sizeof(int64_t) * (B + 1), s));
+    NQS_TRY(ensure(w.qlen, sizeof(int64_t) * 4, s));
+    NQS_TRY(ensure(w.queue, sizeof(uint32_t) * std::max<int64_t>(cap, 1), s));
+    launch_bond_count(c, spins, B, (int32_t *)w.counts.ptr, (double *)w.ediag.ptr, s);
+    launch_scan((int32_t *)w.counts.ptr, B, (int64_t *)w.offsets.ptr, (int64_t *)w.qlen.ptr, s);
+    launch_queue_fill(c, spins, B, (int64_t *)w.offsets.ptr, (uint32_t *)w.queue.ptr, s);
+    return NQS_OK;
+}
+
+// Vector-path chunk size (items per layer launch), bounded by plane memory.
+int64_t vec_chunk(const nqs_ctx *c, int64_t cap)
+{
+    const size_t per = vec_plane_bytes(c, 1);
+    int64_t m = (int64_t)((size_t)1 << 30) / (int64_t)std::max<size_t>(per, 1);
+    m = std::max<int64_t>(1, std::min<int64_t>(m, 65535));
+    return std::min(m, std::max<int64_t>(cap, 1));
+}
+
+// Base pass + exchanged-configuration pass: dlog[item].
+nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode, double *dlog,
+                           int64_t cap, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
+    if (c->dtype == NQS_BF16) {
+        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+        mfma_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr, s);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, s);
+        }
+        mfma_conn_forward(c, mode, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, cap,
+                          (double *)w.hsum.ptr, w.cache.ptr, dlog, nullptr, s);
+        if (c->timing) {
+            (void)hipEventRecord(e1, s);
+            c->events.push_back({e0, e1});
+        }
+        return NQS_OK;
+    }
+    const int64_t chunk = vec_chunk(c, std::max<int64_t>(cap, B));
+    NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.plane_b, vec_plane_bytes(c, chunk), s));
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+                         (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr, nullptr, s);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, s);
+    }
+    for (int64_t q0 = 0; q0 < cap; q0 += chunk)
+        vec_conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
+                         std::min(chunk, cap - q0), (double *)w.hsum.ptr, dlog, w.plane_a.ptr,
+                         w.plane_b.ptr, s);
+    if (c->timing) {
+        (void)hipEventRecord(e1, s);
+        c->events.push_back({e0, e1});
+    }
+    return NQS_OK;
+}
+
+// Status of the kernels enqueued by one API call (launch errors only; device
+// faults surface at the next synchronisation).
+nqs_status finish_call()
+{
+    const char *what = nullptr;
+    const hipError_t e = take_launch_error(&what);
+    (void)hipGetLastError();
+    return e == hipSuccess ? NQS_OK : NQS_E_HIP;
+}
+
+nqs_status check_common(nqs_ctx *c, const void *spins, int64_t B)
+{
+    if (!c) return NQS_E_ARG;
+    if (B < 0 || B > 131072) return NQS_E_ARG;
+    if (B > 0 && !spins) return NQS_E_ARG;
+    return NQS_OK;
+}
+
+}  // namespace
+
+namespace nqs {
+
+namespace {
+thread_local hipError_t g_launch_err = hipSuccess;
+thread_local const char *g_launch_what = nullptr;
+}  // namespace
+
+void note_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess && g_launch_err == hipSuccess) {
+        g_launch_err = e;
+        g_launch_what = what;
+        if (std::getenv("NQS_DEBUG"))
+            std::fprintf(stderr, "libnqs: launch of %s failed: %s\n", what, hipGetErrorString(e));
+    }
+}
+
+hipError_t take_launch_error(const char **what)
+{
+    const hipError_t e = g_launch_err;
+    if (what) *what = g_launch_what;
+    g_launch_err = hipSuccess;
+    g_launch_what = nullptr;
+    return e;
+}
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
+
+nqs_status ensure(DevBuf &b, size_t bytes, hipStream_t stream)
+{
+    if (bytes <= b.bytes) return NQS_OK;
+    if (stream_capturing(stream)) return NQS_E_WORKSPACE;
+    if (b.ptr) {
+        HIP_OK(hipDeviceSynchronize());
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return NQS_E_NOMEM;
+    }
+    b.bytes = want;
+    return NQS_OK;
+}
+
+}  // namespace nqs
+
+extern "C" {
+
+const char *nqs_status_str(nqs_status s)
+{
+    switch (s) {
+    case NQS_OK: return "ok";
+    case NQS_E_ARG: return "invalid argument";
+    case NQS_E_LATTICE: return "unsupported lattice (L must be even, 4 <= L <= 64)";
+    case NQS_E_SPEC: return "unsupported network specification";
+    case NQS_E_NPARAMS: return "weight count does not match the network";
+    case NQS_E_SPIN: return "spin value other than +1/-1";
+    case NQS_E_NONFINITE: return "non-finite log-amplitude ratio or local energy";
+    case NQS_E_NOMEM: return "device allocation failed";
+    case NQS_E_WORKSPACE: return "workspace too small during stream capture";
+    case NQS_E_HIP: return "HIP runtime error";
+    case NQS_E_UNSUPPORTED: return "not supported by this build";
+    }
+    return "unknown status";
+}
+
+nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
+                      const double *weights, int64_t n_weights, nqs_ctx **out)
+{
+    if (!spec || !weights || !out) return NQS_E_ARG;
+    *out = nullptr;
+    if (L < 4 || L > 64 || (L % 2) != 0) return NQS_E_LATTICE;
+    if (!std::isfinite(J1) || !std::isfinite(J2)) return NQS_E_ARG;
+    const int K = spec->n_layers, C = spec->channels;
+    if (K < 1 || K > 16 || C < 1 || C > 32) return NQS_E_SPEC;
+    if (spec->conv_dtype != NQS_FP64 && spec->conv_dtype != NQS_FP32 &&
+        spec->conv_dtype != NQS_BF16)
+        return NQS_E_SPEC;
+    if (spec->marshall_sign != 0 && spec->marshall_sign != 1) return NQS_E_SPEC;
+    if (n_weights != params_of(K, C)) return NQS_E_NPARAMS;
+    nqs_ctx *c = new nqs_ctx();
+    c->L = L;
+    c->N = L * L;
+    c->K = K;
+    c->C = C;
+    c->J1 = J1;
+    c->J2 = J2;
+    c->marshall = spec->marshall_sign;
+    c->dtype = spec->conv_dtype;
+    c->P = n_weights;
+    if (c->dtype == NQS_BF16 && !mfma_supported(c)) {
+        delete c;
+        return NQS_E_SPEC;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return NQS_E_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    c->w_host.assign(weights, weights + n_weights);
+    if (hipMalloc((void **)&c->err, sizeof(int32_t)) != hipSuccess ||
+        hipMemset(c->err, 0, sizeof(int32_t)) != hipSuccess) {
+        delete c;
+        return NQS_E_NOMEM;
+    }
+    nqs_status st = pack_weights(c);
+    if (st != NQS_OK) {
+        nqs_destroy(c);
+        return st;
+    }
+    *out = c;
+    return NQS_OK;
+}
+
+nqs_status nqs_destroy(nqs_ctx *c)
+{
+    if (!c) return NQS_E_ARG;
+    (void)hipDeviceSynchronize();
+    free_dev(c->w_canon);
+    free_dev(c->w_vec64);
+    free_dev(c->w_vec32);
+    free_dev(c->w_bwd64);
+    free_dev(c->w_mfma);
+    free_dev(c->w_l1);
+    free_dev(c->err);
+    DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
+                      &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,
+                      &c->ws.plane_b, &c->ws.zsave, &c->ws.delta,  &c->ws.sr,   &c->ws.counter};
+    for (DevBuf *b : bufs)
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (auto &e : c->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete c;
+    return NQS_OK;
+}
+
+nqs_status nqs_num_params(const nqs_ctx *c, int64_t *P)
+{
+    if (!c || !P) return NQS_E_ARG;
+    *P = c->P;
+    return NQS_OK;
+}
+
+nqs_status nqs_set_weights(nqs_ctx *c, const double *weights, int64_t n)
+{
+    if (!c || !weights) return NQS_E_ARG;
+    if (n != c->P) return NQS_E_NPARAMS;
+    HIP_OK(hipDeviceSynchronize());
+    c->w_host.assign(weights, weights + n);
+    return pack_weights(c);
+}
+
+nqs_status nqs_auto_mode(const nqs_ctx *c, nqs_mode *mode)
+{
+    if (!c || !mode) return NQS_E_ARG;
+    *mode = resolve_mode(c, NQS_AUTO);
+    return NQS_OK;
+}
+
+nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
+{
+    if (!c || B_max < 0 || B_max > 131072) return NQS_E_ARG;
+    (void)mode;
+    const int B = (int)B_max;
+    hipStream_t s = nullptr;
+    Workspace &w = c->ws;
+    const int64_t cap = bonds_per_sample(c) * B;
+    NQS_TRY(ensure(w.counts, sizeof(int32_t) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.ediag, sizeof(double) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.offsets, sizeof(int64_t) * (B + 1), s));
+    NQS_TRY(ensure(w.qlen, sizeof(int64_t) * 4, s));
+    NQS_TRY(ensure(w.queue, sizeof(uint32_t) * std::max<int64_t>(cap, 1), s));
+    NQS_TRY(ensure(w.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+    NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
+    if (c->dtype == NQS_BF16) {
+        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+    } else {
+        const int64_t chunk = vec_chunk(c, std::max<int64_t>(cap, B));
+        NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, vec_plane_bytes(c, chunk), s));
+    }
+    return NQS_OK;
+}
+
+nqs_status nqs_log_psi(nqs_ctx *c, const int8_t *spins, int64_t B, double *log_abs, int8_t *sign,
+                       void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (B > 0 && !log_abs) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0) return NQS_OK;
+    Workspace &w = c->ws;
+    NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)B * c->N, s));
+    launch_marshall(c, spins, (int)B, sign, s);
+    if (c->dtype == NQS_BF16) {
+        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+        mfma_base_forward(c, spins, (int)B, log_abs, (double *)w.hsum.ptr, w.cache.ptr, s);
+    } else {
+        const int64_t chunk = vec_chunk(c, B);
+        NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, vec_plane_bytes(c, chunk), s));
+        for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+            const int nb = (int)std::min<int64_t>(chunk, B - b0);
+            vec_base_forward(c, spins + b0 * c->N, nb, log_abs + b0,
+                             (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr,
+                             nullptr, s);
+        }
+    }
+    return finish_call();
+}
+
+nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *e_loc,
+                            nqs_mode mode, void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (B > 0 && !e_loc) return NQS_E_ARG;
+    if (mode != NQS_AUTO && mode != NQS_FULL && mode != NQS_INCREMENTAL) return NQS_E_ARG;
+    const nqs_mode m = resolve_mode(c, mode);
+    if (m == NQS_INCREMENTAL && c->dtype != NQS_BF16) return NQS_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0) return NQS_OK;
+    const int64_t cap = bonds_per_sample(c) * B;
+    NQS_TRY(integer_stage(c, spins, (int)B, s));
+    NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+    NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)c->ws.dlog.ptr, cap, s));
+    launch_energy_reduce(c, (int)B, (int64_t *)c->ws.offsets.ptr, (uint32_t *)c->ws.queue.ptr,
+                         (double *)c->ws.dlog.ptr, (double *)c->ws.ediag.ptr, e_loc, c->err, s);
+    return finish_call();
+}
+
+nqs_status nqs_log_ratios(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode mode, double *dlog,
+                          int64_t capacity, void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (B > 0 && !dlog) return NQS_E_ARG;
+    const int64_t cap = bonds_per_sample(c) * B;
+    if (capacity < cap) return NQS_E_ARG;
+    const nqs_mode m = resolve_mode(c, mode);
+    if (m == NQS_INCREMENTAL && c->dtype != NQS_BF16) return NQS_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0) return NQS_OK;
+    NQS_TRY(integer_stage(c, spins, (int)B, s));
+    NQS_TRY(log_ratio_stage(c, spins, (int)B, m, dlog, cap, s));
+    return finish_call();
+}
+
+nqs_status nqs_connected(nqs_ctx *c, const int8_t *spins, int64_t B, int32_t *counts,
+                         int64_t *offsets, int32_t *bond_ids, int8_t *mu, int64_t capacity,
+                         double *e_diag, void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (!counts || !offsets || !bond_ids || !mu || !e_diag) return NQS_E_ARG;
+    const int64_t cap = bonds_per_sample(c) * B;
+    if (capacity < cap) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0) {
+        HIP_OK(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
+        return NQS_OK;
+    }
+    NQS_TRY(integer_stage(c, spins, (int)B, s));
+    HIP_OK(hipMemcpyAsync(counts, c->ws.counts.ptr, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(offsets, c->ws.offsets.ptr, sizeof(int64_t) * (B + 1),
+                          hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(e_diag, c->ws.ediag.ptr, sizeof(double) * B, hipMemcpyDeviceToDevice, s));
+    launch_queue_expand(c, (uint32_t *)c->ws.queue.ptr, (int64_t *)c->ws.qlen.ptr, capacity,
+                        bond_ids, mu, s);
+    return finish_call();
+}
+
+nqs_status nqs_energy_stats(nqs_ctx *c, const double *e_loc, int64_t B, double *stats, void *stream)
+{
+    if (!c || !stats || B <= 0 || !e_loc) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    launch_energy_stats(e_loc, (int)B, stats, s);
+    return finish_call();
+}
+
+nqs_status nqs_log_deriv(nqs_ctx *c, const int8_t *spins, int64_t B, void *O, nqs_dtype odt,
+                         void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (B > 0 && !O) return NQS_E_ARG;
+    if (odt != NQS_FP32 && odt != NQS_FP64) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0) return NQS_OK;
+    Workspace &w = c->ws;
+    const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
+    // samples per chunk: z of every layer + 2 planes + 2 deltas per sample
+    const size_t per = plane * (c->K + 4);
+    int64_t chunk = (int64_t)(((size_t)6 << 30) / per);
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, B));
+    NQS_TRY(ensure(w.zsave, plane * c->K * chunk, s));
+    NQS_TRY(ensure(w.delta, plane * 2 * chunk, s));
+    NQS_TRY(ensure(w.plane_a, plane * chunk, s));
+    NQS_TRY(ensure(w.plane_b, plane * chunk, s));
+    NQS_TRY(ensure(w.fbase, sizeof(double) * chunk, s));
+    NQS_TRY(ensure(w.hsum, plane / c->C * chunk, s));
+    // with pre-activations saved, the vector kernels run in FP64 whatever the
+    // context's conv dtype
+    const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr, (double *)w.hsum.ptr,
+                         w.plane_a.ptr, w.plane_b.ptr, (double *)w.zsave.ptr, s);
+        double *da = (double *)w.delta.ptr;
+        vec_backward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr, da,
+                     da + (size_t)nb * c->N * c->C, (unsigned char *)O + (size_t)b0 * c->P * esz,
+                     odt, s);
+    }
+    return finish_call();
+}
+
+nqs_status nqs_sr_solve(nqs_ctx *c, const void *O, nqs_dtype odt, const double *e_loc, int64_t B,
+                        double diag_shift, int32_t n_iter, double *dtheta, double *stats,
+                        void *stream)
+{
+    if (!c || !O || !e_loc || !dtheta || B <= 0 || n_iter < 0) return NQS_E_ARG;
+    if (odt != NQS_FP32 && odt != NQS_FP64) return NQS_E_ARG;
+    if (!(diag_shift >= 0.0) || !std::isfinite(diag_shift)) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    NQS_TRY(ensure(c->ws.sr, sr_workspace_bytes(B, c->P), s));
+    launch_sr_solve(O, odt, e_loc, B, c->P, diag_shift, n_iter, dtheta, stats, c->ws.sr.ptr, s);
+    return finish_call();
+}
+
+nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode mode, void *stream)
+{
+    if (!jobs || n < 0) return NQS_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        if (!jobs[i].ctx) return NQS_E_ARG;
+        if (jobs[i].ctx->K != jobs[0].ctx->K || jobs[i].ctx->C != jobs[0].ctx->C ||
+            jobs[i].ctx->dtype != jobs[0].ctx->dtype)
+            return NQS_E_SPEC;
+    }
+    for (int i = 0; i < n; ++i)
+        NQS_TRY(nqs_local_energy(jobs[i].ctx, jobs[i].spins, jobs[i].B, jobs[i].e_loc, mode, stream));
+    return NQS_OK;
+}
+
+nqs_status nqs_get_error(nqs_ctx *c, nqs_status *sticky)
+{
+    if (!c || !sticky) return NQS_E_ARG;
+    HIP_OK(hipStreamSynchronize(c->last_stream));
+    int32_t v = 0;
+    HIP_OK(hipMemcpy(&v, c->err, sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemset(c->err, 0, sizeof(int32_t)));
+    *sticky = (v & kErrSpin) ? NQS_E_SPIN : ((v & kErrNonFinite) ? NQS_E_NONFINITE : NQS_OK);
+    return NQS_OK;
+}
+
+nqs_status nqs_enable_timing(nqs_ctx *c, int32_t enable)
+{
+    if (!c) return NQS_E_ARG;
+    c->timing = enable ? 1 : 0;
+    return NQS_OK;
+}
+
+nqs_status nqs_kernel_time(nqs_ctx *c, double *ms, int64_t *launches)
+{
+    if (!c || !ms || !launches) return NQS_E_ARG;
+    double total = 0.0;
+    for (auto &e : c->events) {
+        HIP_OK(hipEventSynchronize(e.second));
+        float t = 0.f;
+        HIP_OK(hipEventElapsedTime(&t, e.first, e.second));
+        total += t;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    *ms = total;
+    *launches = (int64_t)c->events.size();
+    c->events.clear();
+    return NQS_OK;
+}
+
+}  // extern "C"

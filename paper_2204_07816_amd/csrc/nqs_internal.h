@@ -1,0 +1,154 @@
+// nqs_internal.h -- context, workspace and kernel-launch interfaces shared by
+// the translation units of libnqs (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nqs.h"
+
+namespace nqs {
+
+// Bond type t of canonical bond b = 4*i + t and its displacement.
+//   t = 0: (x+1, y)  J1      t = 1: (x, y+1)  J1
+//   t = 2: (x+1, y+1) J2     t = 3: (x+1, y-1) J2
+__host__ __device__ inline int bond_dx(int t) { return (t == 1) ? 0 : 1; }
+__host__ __device__ inline int bond_dy(int t) { return t == 0 ? 0 : (t == 1 ? 1 : (t == 2 ? 1 : -1)); }
+
+// Queue entry: sample index and bond id packed in 32 bits (bond < 2^14).
+constexpr int kBondBits = 14;
+__host__ __device__ inline uint32_t pack_item(int sample, int bond) {
+    return ((uint32_t)sample << kBondBits) | (uint32_t)bond;
+}
+__host__ __device__ inline int item_sample(uint32_t e) { return (int)(e >> kBondBits); }
+__host__ __device__ inline int item_bond(uint32_t e) { return (int)(e & ((1u << kBondBits) - 1)); }
+
+// Device-side sticky error codes (ORed bits, mapped to nqs_status on read).
+constexpr int kErrSpin = 1;
+constexpr int kErrNonFinite = 2;
+
+// Growable device buffer.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    DevBuf counts;      // int32 [B]
+    DevBuf ediag;       // f64 [B]
+    DevBuf offsets;     // int64 [B+1]
+    DevBuf qlen;        // int64 [1] total queue length (device)
+    DevBuf queue;       // uint32 [capacity]
+    DevBuf dlog;        // f64 [capacity]
+    DevBuf fbase;       // f64 [B] log-amplitude of the samples
+    DevBuf hsum;        // f64 [B][N] channel sums of the last layer (base pass)
+    DevBuf cache;       // activations of the base pass (dtype-dependent)
+    DevBuf plane_a;     // scratch planes for the vector path
+    DevBuf plane_b;
+    DevBuf zsave;       // f64 pre-activations for the backward pass
+    DevBuf delta;       // f64 backward deltas
+    DevBuf sr;          // SR vectors
+    DevBuf counter;     // work counters for persistent kernels
+};
+
+}  // namespace nqs
+
+struct nqs_ctx {
+    int L = 0, N = 0, K = 0, C = 0;
+    double J1 = 1.0, J2 = 0.0;
+    int marshall = 1;
+    nqs_dtype dtype = NQS_FP64;
+    int64_t P = 0;
+    int device = 0;
+    // weights
+    std::vector<double> w_host;   // canonical
+    double *w_canon = nullptr;    // device canonical FP64 [P]
+    double *w_vec64 = nullptr;    // vector-path packing, FP64
+    float *w_vec32 = nullptr;     // vector-path packing, FP32
+    double *w_bwd64 = nullptr;    // transposed packing for the backward data pass
+    uint16_t *w_mfma = nullptr;   // BF16 MFMA A-operand packing, layers 2..K
+    float *w_l1 = nullptr;        // layer-1 weights + all biases, FP32, MFMA path
+    // workspace
+    nqs::Workspace ws;
+    int32_t *err = nullptr;       // device sticky error word
+    hipStream_t last_stream = nullptr;
+    // timing
+    int timing = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    int n_cu = 256;
+};
+
+namespace nqs {
+
+// --- launch-error capture: HIP's last-error state is overwritten by the next
+// successful call, so every launch is checked right away and the first
+// failure of a call is kept (thread-local) until the API entry point returns.
+void note_launch(const char *what);
+hipError_t take_launch_error(const char **what);
+
+#define NQS_LAUNCH(kernel, ...)                     \
+    do {                                            \
+        hipLaunchKernelGGL(kernel, __VA_ARGS__);    \
+        ::nqs::note_launch(#kernel);                \
+    } while (0)
+
+// --- workspace helpers (nqs_abi.hip) ---
+nqs_status ensure(DevBuf &b, size_t bytes, hipStream_t stream);
+bool stream_capturing(hipStream_t s);
+
+// --- lattice kernels (k_lattice.hip) ---
+// a1: antiparallel-bond counts, diagonal energy, spin validation.
+void launch_bond_count(const nqs_ctx *c, const int8_t *spins, int B, int32_t *counts,
+                       double *ediag, hipStream_t s);
+// a2: exclusive scan of counts -> offsets[B+1], qlen[0] = offsets[B].
+void launch_scan(const int32_t *counts, int B, int64_t *offsets, int64_t *qlen, hipStream_t s);
+// a2: queue entries in canonical bond order.
+void launch_queue_fill(const nqs_ctx *c, const int8_t *spins, int B, const int64_t *offsets,
+                       uint32_t *queue, hipStream_t s);
+// Marshall sign per sample (+ spin validation); sign may be null.
+void launch_marshall(const nqs_ctx *c, const int8_t *spins, int B, int8_t *sign, hipStream_t s);
+// inspection: bond ids + Marshall ratios from the queue.
+void launch_queue_expand(const nqs_ctx *c, const uint32_t *queue, const int64_t *qlen,
+                         int64_t capacity, int32_t *bond_ids, int8_t *mu, hipStream_t s);
+
+// --- vector (FP64 / FP32) network kernels (k_conv_vec.hip) ---
+// Base pass over B samples: f[B], hsum[B][N]; planes are scratch [B*N*C].
+void vec_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
+                      void *plane_a, void *plane_b, double *zsave, hipStream_t s);
+// Full recompute of every queue item in chunks: dlog[item] = f(S') - f(s).
+// Items q_begin + [0, q_count) of the queue; items at or past qlen[0] are skipped
+// on the device, so the host never needs the queue length.
+void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                      const int64_t *qlen, int64_t q_begin, int64_t q_count, const double *hsum,
+                      double *dlog, void *plane_a, void *plane_b, hipStream_t s);
+size_t vec_plane_bytes(const nqs_ctx *c, int64_t items);
+// Backward: O[B][P] from the saved pre-activations.
+void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zsave,
+                  double *delta_a, double *delta_b, void *O, nqs_dtype odt, hipStream_t s);
+
+// --- MFMA (BF16) network kernels (k_conv_mfma.hip) ---
+bool mfma_supported(const nqs_ctx *c);
+size_t mfma_cache_bytes(const nqs_ctx *c, int64_t B);
+void mfma_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
+                       void *cache, hipStream_t s);
+// mode: NQS_FULL or NQS_INCREMENTAL.  Items [0, qlen[0]) of the queue.
+void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
+                       const uint32_t *queue, const int64_t *qlen, int64_t capacity,
+                       const double *hsum, const void *cache, double *dlog, int *counter,
+                       hipStream_t s);
+int mfma_lds_full_ok(const nqs_ctx *c);
+
+// --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
+void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const uint32_t *queue,
+                          const double *dlog, const double *ediag, double *e_loc, int32_t *err,
+                          hipStream_t s);
+void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
+size_t sr_workspace_bytes(int64_t B, int64_t P);
+void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t B, int64_t P,
+                     double lambda, int n_iter, double *x, double *stats, void *work,
+                     hipStream_t s);
+
+}  // namespace nqs

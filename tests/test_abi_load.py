@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports every entry point include/nqs.h declares,
+and rejects bad arguments on the host (no GPU needed for any of this)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nqs.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nqs_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401 - the binding loads torch's HIP runtime first
+    from paper_2204_07816_amd import nqs
+    if not os.path.exists(nqs.LIB_PATH):
+        pytest.fail("libnqs.so is not built: run __graft_entry__.build()")
+    return nqs.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in nqs.h but not exported"
+
+
+def test_status_strings(lib):
+    for code in range(11):
+        assert lib.nqs_status_str(code)
+    assert b"lattice" in lib.nqs_status_str(2)
+
+
+def _create(lib, L, K, C, n, dtype=0, marshall=1, w=None, spec=True):
+    from paper_2204_07816_amd import nqs
+    sp = nqs.CnnSpec(K, C, marshall, dtype)
+    buf = (ctypes.c_double * max(n, 1))()
+    h = ctypes.c_void_p()
+    return lib.nqs_create(L, 1.0, 0.5, ctypes.byref(sp) if spec else None,
+                          buf if w is None else w, n, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("L", [3, 5, 2, 66, 0, -4])
+def test_create_rejects_bad_lattice(lib, L):
+    assert _create(lib, L, 2, 4, 188) == 2          # NQS_E_LATTICE
+
+
+def test_create_rejects_bad_spec_and_counts(lib):
+    from paper_2204_07816_amd import nqs
+    assert _create(lib, 4, 0, 4, 10) == 3           # K < 1
+    assert _create(lib, 4, 2, 33, 10) == 3          # C > 32
+    assert _create(lib, 4, 2, 4, 188, dtype=7) == 3
+    assert _create(lib, 4, 2, 4, 188, marshall=2) == 3
+    assert _create(lib, 4, 2, 4, 187) == 4          # NQS_E_NPARAMS
+    assert _create(lib, 4, 2, 4, nqs.num_params(2, 4), dtype=2) == 3   # BF16 needs C in {16, 32}
+    assert _create(lib, 4, 2, 4, 188, spec=False) == 1                 # null spec
+
+
+def test_calls_reject_null_context(lib):
+    vp = ctypes.c_void_p
+    assert lib.nqs_local_energy(None, None, 0, None, 0, None) == 1
+    assert lib.nqs_log_psi(None, None, 0, None, None, None) == 1
+    assert lib.nqs_log_deriv(None, None, 0, None, 0, None) == 1
+    assert lib.nqs_sr_solve(None, None, 0, None, 0, 1e-4, 100, None, None, None) == 1
+    assert lib.nqs_destroy(None) == 1
+    assert lib.nqs_local_energy_multi(None, 0, 0, None) == 1
+    p = ctypes.c_int64()
+    assert lib.nqs_num_params(None, ctypes.byref(p)) == 1
+    del vp
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2204_07816_amd import nqs
+    monkeypatch.setattr(nqs, "_lib", None)
+    monkeypatch.setattr(nqs, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        nqs.load()
