@@ -1,0 +1,257 @@
+"""Benchmark of the CNN-VMC hot path on one MI355X.
+
+Workload: 36x36 periodic J1-J2 lattice (J1 = 1, J2 = 0.5), CNN of 8 layers of
+3x3 circular convolutions with 32 channels (P = 65,056), weights N(0, 0.02^2),
+1024 synthetic Sz = 0 configurations.  One step is the whole hot path:
+
+  bond enumeration + Marshall ratios + queue (integer), base pass, exchanged-
+  configuration pass (BF16 MFMA, incremental receptive cone), FP64 ratio sums
+  -> E_loc; energy mean / variance; per-sample log-derivatives O (FP32 out,
+  FP64 backward); SR solve with 100 conjugate-gradient iterations.
+
+value = samples per second of that whole step (inputs resident in HBM).  The
+plain FP64 GPU form (full recompute) is timed on a subset of the same samples
+for comparison, and the BF16 mean energy is checked against it (bar: 1e-5
+relative).  The FP64 CPU oracle is timed on the host cores on a bounded sample.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cone_sites(L: int, k: int, diagonal: bool) -> int:
+    """Sites within Chebyshev distance k of an exchanged pair (exact cone, no
+    clamping needed when 2k + 2 <= L)."""
+    if diagonal:
+        n = 4 * k * k + 8 * k + 2
+        side = 2 * k + 2
+    else:
+        n = (2 * k + 2) * (2 * k + 1)
+        side = 2 * k + 2
+    return min(n, L * L) if side <= L else L * L
+
+
+def item_flops(L: int, K: int, C: int, diagonal: bool) -> float:
+    """Algorithmic FLOPs of one exchanged configuration in incremental mode:
+    every layer recomputed on the cone of sites it can change."""
+    f = 0.0
+    for k in range(1, K + 1):
+        cin = 1 if k == 1 else C
+        f += cone_sites(L, k, diagonal) * C * 9 * cin * 2
+    return f
+
+
+def source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2204_07816_amd", "csrc", "k_conv_mfma.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(launch_items: float):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_net_incremental_36x36_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L, J2, K, C, w, sp, mean_conn, budget_s=12.0):
+    """Oracle (plain FP64 C, OpenMP over configurations) on a bounded sample:
+    the log-amplitude of exchanged configurations of the workload.  The oracle's
+    local energy of one sample is exactly (n_conn + 1) such evaluations plus
+    O(n_conn N) bookkeeping, so samples/s = 1 / ((mean_conn + 1) t_forward)."""
+    import numpy as np
+
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    counts, bonds, _, _ = oracle.connected(L, 1.0, J2, sp[:1])
+    flat = sp[0].reshape(-1)
+    cfgs = []
+    for b in bonds[0]:
+        i, j, _ = oracle.bond_sites(L, int(b))
+        s2 = flat.copy()
+        s2[i], s2[j] = flat[j], flat[i]
+        cfgs.append(s2)
+    cfgs = np.array(cfgs, np.int8).reshape(-1, L, L)
+    m = min(len(cfgs), cores)
+    t0 = time.perf_counter()
+    oracle.log_psi(L, K, C, w, cfgs[:m], nthreads=cores)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / m
+    m2 = int(min(len(cfgs), max(m, budget_s / max(per, 1e-9))))
+    m2 = max(cores, (m2 // cores) * cores)
+    t0 = time.perf_counter()
+    oracle.log_psi(L, K, C, w, cfgs[:m2], nthreads=cores)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / m2
+    sps = 1.0 / ((mean_conn + 1.0) * per)
+    return {
+        "value": sps, "unit": "E_loc samples/s", "cores": cores, "kind": "oracle",
+        "sample": (f"oracle log|psi| of {m2} exchanged configurations of sample 0 "
+                   f"({L}x{L}, K={K}, C={C}), {t1 - t0:.1f} s on {cores} threads; "
+                   f"scaled by (mean connected count {mean_conn:.1f} + 1) forwards per sample"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-samples", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--mode", default="incremental", choices=["incremental", "full"])
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+
+    dev = torch.device("cuda:0")
+    L, J2, K, C, w, sp = inputs.config_inputs("full36")
+    B = sp.shape[0]
+    log(f"workload 36x36 K={K} C={C} B={B}")
+    spd = torch.as_tensor(sp).to(dev)
+    ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16")
+    ctx.reserve(B, args.mode)
+    P = ctx.P
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    st2 = torch.empty(2, dtype=torch.float64, device=dev)
+    O = torch.empty(B, P, dtype=torch.float32, device=dev)
+    x = torch.empty(P, dtype=torch.float64, device=dev)
+    st4 = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.local_energy(spd, mode=args.mode, out=e)
+        ctx.energy_stats(e, out=st2)
+        ctx.log_deriv(spd, dtype="fp32", out=O)
+        ctx.sr_solve(O, e, 1e-4, 100, out=x, stats=st4)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.kernel_time()                      # reset
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.enable_timing(False)
+    k_ms, k_n = ctx.kernel_time()
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
+    assert ctx.get_error() == 0
+
+    # breakdown of one step (events on the current stream)
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_eloc = timed(lambda: ctx.local_energy(spd, mode=args.mode, out=e))
+    t_od = timed(lambda: ctx.log_deriv(spd, dtype="fp32", out=O))
+    t_sr = timed(lambda: ctx.sr_solve(O, e, 1e-4, 100, out=x, stats=st4))
+    e_b = e.cpu().numpy()
+    log(f"breakdown ms: eloc {t_eloc:.2f} log_deriv {t_od:.2f} sr {t_sr:.2f}")
+
+    # algorithmic work of the dominant kernel
+    import oracle
+    counts, bonds, _, _ = oracle.connected(L, 1.0, J2, sp)
+    allb = np.concatenate(bonds)
+    n_diag = int(np.sum(allb % 4 >= 2))
+    n_j1 = int(allb.shape[0] - n_diag)
+    flops_launch = n_j1 * item_flops(L, K, C, False) + n_diag * item_flops(L, K, C, True)
+    if args.mode == "full":
+        per_item = L * L * C * 9 * 2 + (K - 1) * L * L * C * 9 * C * 2
+        flops_launch = float(allb.shape[0]) * per_item
+    avg_ms = k_ms / max(k_n, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile(allb.shape[0])
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
+                "kernel": "k_net<32,4,6> (exchanged configurations, incremental cone)",
+                "avg_launch_ms": avg_ms, "launches": k_n, "flops_per_launch": flops_launch,
+                "items_per_launch": int(allb.shape[0])}
+
+    # plain FP64 GPU form on a subset, and the BF16 parity bar
+    fp64 = None
+    if not args.no_fp64:
+        nsub = args.fp64_samples
+        c64 = nqs.Context(L, 1.0, J2, K, C, w, dtype="fp64")
+        sub = spd[:nsub].contiguous()
+        e64 = torch.empty(nsub, dtype=torch.float64, device=dev)
+        t64 = timed(lambda: c64.local_energy(sub, mode="full", out=e64), reps=1)
+        e64n = e64.cpu().numpy()
+        rel = abs(e_b[:nsub].mean() - e64n.mean()) / abs(e64n.mean())
+        fp64 = {"samples_per_s": nsub / (t64 * 1e-3), "samples": nsub, "ms": t64,
+                "bf16_mean_rel_err": rel, "bf16_max_rel_err": float(
+                    np.max(np.abs(e_b[:nsub] - e64n)) / np.max(np.abs(e64n))),
+                "bar_1e-5_met": bool(rel <= 1e-5)}
+        log(f"fp64 plain: {fp64['samples_per_s']:.2f} samples/s, bf16 mean rel err {rel:.3e}")
+        c64.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
+        log(f"cpu oracle: {cpu['value']:.4f} samples/s on {cpu['cores']} cores")
+
+    value = B / (ms_step * 1e-3)
+    out = {
+        "metric": "E_loc samples/s, 36x36 J1-J2, BF16 vs FP64 GPU at mean-energy rel err <=1e-5",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "36x36 J1-J2 (J2=0.5), CNN 8x3x3x32 (P=65056), 1024 Sz=0 "
+                               "configurations; step = E_loc + stats + O_k + SR(100 CG)",
+                   "L": L, "K": K, "C": C, "B": B, "mode": args.mode,
+                   "mean_connected": float(counts.mean())},
+        "breakdown_ms": {"e_loc": t_eloc, "log_deriv": t_od, "sr_solve": t_sr},
+        "eloc_only_samples_per_s": B / (t_eloc * 1e-3),
+        "fp64_gpu": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

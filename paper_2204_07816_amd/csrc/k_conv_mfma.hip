@@ -33,14 +33,14 @@
 // permutation.
 #include <algorithm>
 
-#include "nqs_internal.h"
+#include "mfma_common.h"
 
 namespace nqs {
 namespace {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+using mf::bf16x8;
+using mf::floatx4;
+using mf::Shape;
 
 enum { kBase = 0, kFull = 1, kIncr = 2 };
 
@@ -78,28 +78,6 @@ __device__ inline bool in_rect(const Rect &R, int gx, int gy, int L)
     return wrapm(gx - R.ox, L) < R.ex && wrapm(gy - R.oy, L) < R.ey;
 }
 
-// ln cosh in FP32: e = expm1|z|, ln cosh z = log1p(e^2 / (2 + 2e)) for
-// |z| <= 1 (no cancellation near 0), |z| - ln 2 + log1p(exp(-2|z|)) above.
-__device__ inline float ln_cosh_f(float z)
-{
-    const float a = fabsf(z);
-    if (a > 1.0f) return a - 0.693147180559945f + log1pf(__expf(-2.0f * a));
-    const float e = expm1f(a);
-    return log1pf(e * e / (2.0f + 2.0f * e));
-}
-
-// Channel permutation: physical slot q of a site holds logical channel
-// chan_of_slot(q).  Slot group g = q / (C/4) is written by MFMA lane group g.
-template <int C>
-__device__ __host__ inline int chan_of_slot(int q)
-{
-    if (C == 32) {
-        const int g = q >> 3, r = q & 7;
-        return r < 4 ? 4 * g + r : 16 + 4 * g + (r - 4);
-    }
-    return q;  // C == 16: lane group g holds channels 4g..4g+3
-}
-
 struct Params {
     const int8_t *spins;
     int L, K, B;
@@ -119,14 +97,6 @@ struct Params {
     const double *hsum_in;
     double *dlog;
     int32_t *err;
-};
-
-template <int C>
-struct Shape {
-    static constexpr int NH = C / 16;          // 16-channel output halves
-    static constexpr int KS = (C == 32) ? 9 : 5;  // K-steps of 32
-    static constexpr int CG = C / 4;            // channels per lane group
-    static constexpr int PSB = C * 2;           // bytes per site
 };
 
 template <int C, int NW, int MAXT>
@@ -182,16 +152,13 @@ k_net(Params prm)
                 float h[S::CG];
 #pragma unroll
                 for (int r = 0; r < S::CG; ++r) {
-                    const int co = chan_of_slot<C>(gg * S::CG + r);
-                    float z = prm.bias[co];
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) z = __builtin_fmaf(prm.w1[t * C + co], sv[t], z);
-                    h[r] = ln_cosh_f(z);
+                    const int co = mf::chan_of_slot<C>(gg * S::CG + r);
+                    h[r] = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C, co, sv));
                 }
                 if (K == 1) continue;  // (single-layer networks are not routed here)
                 uint16_t hb[S::CG];
 #pragma unroll
-                for (int r = 0; r < S::CG; ++r) hb[r] = __builtin_bit_cast(uint16_t, (__bf16)h[r]);
+                for (int r = 0; r < S::CG; ++r) hb[r] = mf::to_bf16(h[r]);
                 const int wi = win_index(W2, gx, gy, L);
                 uint16_t *dst = (uint16_t *)(lds + wi * S::PSB) + gg * S::CG;
 #pragma unroll
@@ -270,17 +237,10 @@ k_net(Params prm)
                 }
 #pragma unroll
                 for (int j = 0; j < S::KS; ++j) {
-                    int tap, slot;
-                    if (C == 32) {
-                        tap = j;
-                        slot = g * 8;
-                    } else {
-                        tap = 2 * j + (g >> 1);
-                        if (tap > 8) tap = 8;     // padding step: weights are zero
-                        slot = (g & 1) * 8;
-                    }
+                    int tap, chunk;
+                    mf::kstep_tap<C>(j, g, &tap, &chunk);
                     const int wi = wr[tap / 3] + wc[tap % 3];
-                    const bf16x8 bv = *(const bf16x8 *)(lds + wi * S::PSB + slot * 2);
+                    const bf16x8 bv = *(const bf16x8 *)(lds + wi * S::PSB + chunk * 16);
 #pragma unroll
                     for (int hh = 0; hh < S::NH; ++hh)
                         acc[ti][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j][hh], bv,
@@ -302,8 +262,7 @@ k_net(Params prm)
                     for (int hh = 0; hh < S::NH; ++hh)
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            hb[hh * 4 + r] =
-                                __builtin_bit_cast(uint16_t, (__bf16)ln_cosh_f(acc[ti][hh][r]));
+                            hb[hh * 4 + r] = mf::to_bf16(mf::ln_cosh(acc[ti][hh][r]));
                     const int wi = win_index(Wn, tgx[ti], tgy[ti], L);
                     uint16_t *dst = (uint16_t *)(lds + wi * S::PSB) + g * S::CG;
 #pragma unroll
@@ -339,7 +298,7 @@ k_net(Params prm)
 #pragma unroll
                     for (int hh = 0; hh < S::NH; ++hh)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) part += (double)ln_cosh_f(acc[ti][hh][r]);
+                        for (int r = 0; r < 4; ++r) part += (double)mf::ln_cosh(acc[ti][hh][r]);
                     part += __shfl_xor(part, 16);
                     part += __shfl_xor(part, 32);
                     if (g == 0 && tgx[ti] >= 0) {
@@ -450,7 +409,12 @@ bool mfma_supported(const nqs_ctx *c)
     if (!(c->C == 16 || c->C == 32) || c->K < 2) return false;
     Variant v;
     size_t lds;
-    return pick_variant(c, true, &v, &lds) && pick_variant(c, false, &v, &lds);
+    return pick_variant(c, true, &v, &lds);
+}
+
+bool mfma_inc_supported(const nqs_ctx *c)
+{
+    return mfma_supported(c) && 2 * mfma_inc_lds_bytes(c) <= 160 * 1024 - 1024;
 }
 
 int mfma_lds_full_ok(const nqs_ctx *c)
@@ -485,6 +449,10 @@ void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
 {
     (void)counter;
     if (capacity <= 0) return;
+    if (mode == NQS_INCREMENTAL) {
+        mfma_inc_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
+        return;
+    }
     const bool full = mode == NQS_FULL;
     Params p = common(c, spins, full ? kFull : kIncr);
     p.queue = queue;

@@ -1,0 +1,433 @@
+// k_net_inc.hip -- the exchanged-configuration pass in incremental mode, the
+// dominant kernel of the local energy [Sec. 5.4.1: forwards of the network
+// over the O(L^2) exchanged configurations are over 95% of the time].
+//
+// An exchange of the antiparallel pair (i, j) changes layer k of the network
+// only on the sites within Chebyshev distance k of i or j.  For every queue
+// item the kernel recomputes layer k on the bounding rectangle R_k of that
+// cone (clamped to the torus) and takes all other inputs from the activations
+// the base pass cached for the sample:
+//
+//   window W_k = R_{k+1} (LDS)   <- h'_{k-1} on R_{k-1} (previous layer, LDS)
+//                                 + h_{k-1} on the ring W_k \ R_{k-1} (cache, HBM/L2)
+//   R_k outputs (MFMA, BF16 x BF16 -> FP32) -> ln cosh -> BF16 -> W_{k+1}
+//   last layer: dlog += sum_{p in R_K} (sum_c h'_K(p, c) - hs(p))  (FP64)
+//
+// Geometry is anchored at the exchanged pair, so every window layout, tap
+// offset and ring list depends only on the bond type and the layer; the ring
+// lists are precomputed per context.  Two LDS windows alternate between
+// layers: each output tile is written to the next window as soon as it is
+// finished, and one barrier per layer separates the layers.  The ring of the
+// next window is fetched into registers before the layer's matrix work and
+// stored after it; the next layer's weights are fetched as soon as the last
+// MFMA of the layer has issued.  Sites inside a window carry their 16-byte
+// chunks XOR-swizzled by site index to spread LDS banks.
+#include <algorithm>
+#include <vector>
+
+#include "mfma_common.h"
+
+namespace nqs {
+namespace {
+
+using mf::bf16x8;
+using mf::floatx4;
+using mf::Shape;
+
+constexpr int kNW = 4;
+constexpr int kThreads = kNW * 64;
+constexpr int kRingRegs = 3;
+
+struct IncParams {
+    const int8_t *spins;
+    int L, K;
+    const uint32_t *queue;
+    const int64_t *qlen;
+    int64_t capacity;
+    const bf16x8 *wa;
+    const float *w1;
+    const float *bias;
+    const uint16_t *cache;
+    const double *hsum;
+    double *dlog;
+    int32_t *err;
+    const int32_t *ring;       // packed (window index | (du+128) << 16 | (dv+128) << 24)
+    const int32_t *ring_off;   // [4][K] entry offsets: ring of W_{k+1} for k = 1..K-1
+    int win_bytes;             // bytes of one window buffer
+};
+
+__device__ __forceinline__ int wrap_l(int a, int L)
+{
+    a %= L;
+    return a < 0 ? a + L : a;
+}
+
+// byte offset of 16-byte chunk c of window site wi
+template <int C>
+__device__ __forceinline__ int chunk_addr(int wi, int c)
+{
+    return wi * Shape<C>::PSB + ((c ^ (wi & (Shape<C>::CHUNKS - 1))) << 4);
+}
+
+// Store the CG channels of lane group g (values already BF16-packed in pairs).
+template <int C>
+__device__ __forceinline__ void store_group(unsigned char *buf, int wi, int g, const uint32_t *pk)
+{
+    if (C == 32) {
+        uint4 v = {pk[0], pk[1], pk[2], pk[3]};
+        *(uint4 *)(buf + chunk_addr<C>(wi, g)) = v;
+    } else {
+        uint2 v = {pk[0], pk[1]};
+        *(uint2 *)(buf + chunk_addr<C>(wi, g >> 1) + ((g & 1) << 3)) = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t pack2(float a, float b)
+{
+    return (uint32_t)mf::to_bf16(a) | ((uint32_t)mf::to_bf16(b) << 16);
+}
+
+template <int C>
+struct Ring {
+    uint4 v[kRingRegs];
+    int wi[kRingRegs];
+};
+
+// Fetch the ring chunks of the next window (first kRingRegs * 256 of them).
+template <int C>
+__device__ __forceinline__ void ring_fetch(Ring<C> &r, const IncParams &p, int e0, int e1,
+                                           int ax, int ay, const uint16_t *layer_cache)
+{
+    const int L = p.L;
+    const int total = (e1 - e0) * Shape<C>::CHUNKS;
+#pragma unroll
+    for (int i = 0; i < kRingRegs; ++i) {
+        const int q = threadIdx.x + i * kThreads;
+        r.wi[i] = -1;
+        if (q < total) {
+            const int ent = p.ring[e0 + q / Shape<C>::CHUNKS];
+            const int c = q % Shape<C>::CHUNKS;
+            const int du = ((ent >> 16) & 255) - 128, dv = ((ent >> 24) & 255) - 128;
+            const int site = wrap_l(ay + dv, L) * L + wrap_l(ax + du, L);
+            r.v[i] = *(const uint4 *)(layer_cache + (int64_t)site * C + c * 8);
+            r.wi[i] = ((ent & 0xffff) << 4) | c;
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void ring_store(const Ring<C> &r, unsigned char *buf, const IncParams &p,
+                                           int e0, int e1, int ax, int ay,
+                                           const uint16_t *layer_cache)
+{
+#pragma unroll
+    for (int i = 0; i < kRingRegs; ++i)
+        if (r.wi[i] >= 0) *(uint4 *)(buf + chunk_addr<C>(r.wi[i] >> 4, r.wi[i] & 15)) = r.v[i];
+    // chunks beyond the prefetched ones (only for large clamped windows)
+    const int L = p.L;
+    const int total = (e1 - e0) * Shape<C>::CHUNKS;
+    for (int q = threadIdx.x + kRingRegs * kThreads; q < total; q += kThreads) {
+        const int ent = p.ring[e0 + q / Shape<C>::CHUNKS];
+        const int c = q % Shape<C>::CHUNKS;
+        const int du = ((ent >> 16) & 255) - 128, dv = ((ent >> 24) & 255) - 128;
+        const int site = wrap_l(ay + dv, L) * L + wrap_l(ax + du, L);
+        *(uint4 *)(buf + chunk_addr<C>(ent & 0xffff, c)) =
+            *(const uint4 *)(layer_cache + (int64_t)site * C + c * 8);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void load_weights(bf16x8 (&wa)[Shape<C>::KS][Shape<C>::NH],
+                                             const bf16x8 *base, int lane)
+{
+#pragma unroll
+    for (int j = 0; j < Shape<C>::KS; ++j)
+#pragma unroll
+        for (int hh = 0; hh < Shape<C>::NH; ++hh)
+            wa[j][hh] = base[(j * Shape<C>::NH + hh) * 64 + lane];
+}
+
+template <int C>
+__global__ void __launch_bounds__(kThreads)
+k_net_inc(IncParams prm)
+{
+    using S = Shape<C>;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    __shared__ double red[kNW];
+    unsigned char *buf0 = lds, *buf1 = lds + prm.win_bytes;
+
+    const int L = prm.L, N = L * L, K = prm.K;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, n16 = lane & 15;
+    const int64_t n_units = min(prm.qlen[0], prm.capacity);
+    const int64_t wl_stride = (int64_t)S::KS * S::NH * 64;
+
+    bf16x8 wa[S::KS][S::NH];
+    load_weights<C>(wa, prm.wa, lane);   // layer 2
+
+    for (int64_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const uint32_t e = prm.queue[unit];
+        const int s = item_sample(e);
+        const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
+        const int xi = i0 % L, yi = i0 / L;
+        const int qi = i0, qj = wrap_l(yi + bond_dy(tau), L) * L + wrap_l(xi + bond_dx(tau), L);
+        const int ax = xi, ay = (tau == 3) ? wrap_l(yi - 1, L) : yi;
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        const int8_t *sp = prm.spins + (int64_t)s * N;
+        const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
+        const int *roff = prm.ring_off + tau * K;
+
+        // ---- layer 1 (vector ALU) into W_2 = R_3 in buf0 ----
+        {
+            Ring<C> ring;
+            ring_fetch<C>(ring, prm, roff[0], roff[1], ax, ay, cache_s);
+            const int ex1 = min(w0 + 2, L), ey1 = min(h0 + 2, L);
+            const int exn = min(w0 + 6, L), eyn = min(h0 + 6, L);
+            const int npos = ex1 * ey1;
+            for (int q = tid; q < npos * 4; q += kThreads) {
+                const int p = q >> 2, gg = q & 3;
+                const int u = p % ex1, v = p / ex1;
+                const int gx = wrap_l(ax + u - 1, L), gy = wrap_l(ay + v - 1, L);
+                float sv[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    int site = wrap_l(gy + t / 3 - 1, L) * L + wrap_l(gx + t % 3 - 1, L);
+                    site = (site == qi) ? qj : ((site == qj) ? qi : site);
+                    sv[t] = (float)sp[site];
+                }
+                uint32_t pk[S::CG / 2];
+#pragma unroll
+                for (int r = 0; r < S::CG; r += 2) {
+                    const float h0v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
+                                                               mf::chan_of_slot<C>(gg * S::CG + r), sv));
+                    const float h1v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
+                                                               mf::chan_of_slot<C>(gg * S::CG + r + 1), sv));
+                    pk[r / 2] = pack2(h0v, h1v);
+                }
+                int wu = u + 2, wv = v + 2;
+                if (wu >= L) wu -= L;
+                if (wv >= L) wv -= L;
+                store_group<C>(buf0, wv * exn + wu, gg, pk);
+            }
+            ring_store<C>(ring, buf0, prm, roff[0], roff[1], ax, ay, cache_s);
+        }
+        __syncthreads();
+
+        double fsum = 0.0;
+        for (int k = 2; k <= K; ++k) {
+            unsigned char *cur = ((k & 1) == 0) ? buf0 : buf1;
+            unsigned char *nxt = ((k & 1) == 0) ? buf1 : buf0;
+            const int ex = min(w0 + 2 * k, L), ey = min(h0 + 2 * k, L);
+            const int wex = min(w0 + 2 * k + 2, L), wey = min(h0 + 2 * k + 2, L);
+            const bool wcx = wex == L, wcy = wey == L;
+            const int nex = min(w0 + 2 * k + 4, L);
+            const int npos = ex * ey;
+            const int ntiles = (npos + 15) >> 4;
+            const uint32_t mul = ((1u << 20) + ex - 1) / ex;
+            const bool last = k == K;
+
+            Ring<C> ring;
+            if (!last) ring_fetch<C>(ring, prm, roff[k - 1], roff[k], ax, ay,
+                                     cache_s + (int64_t)(k - 1) * N * C);
+            float bias[S::NH][4];
+#pragma unroll
+            for (int hh = 0; hh < S::NH; ++hh)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bias[hh][r] = prm.bias[(k - 1) * C + 16 * hh + 4 * g + r];
+
+            for (int t0 = wave; t0 < ntiles; t0 += 2 * kNW) {
+                floatx4 acc[2][S::NH];
+                int pos_u[2], pos_v[2];
+                bool valid[2];
+                int addr[2][3][3];
+                double hs_base[2] = {0.0, 0.0};
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const int tile = t0 + w * kNW;
+                    int p = tile * 16 + n16;
+                    valid[w] = tile < ntiles && p < npos;
+                    if (p >= npos) p = npos - 1;
+                    const int v = (int)(((uint32_t)p * mul) >> 20);
+                    const int u = p - v * ex;
+                    pos_u[w] = u;
+                    pos_v[w] = v;
+                    // window W_k = R_{k+1} coordinates of the tap (dy-1, dx-1)
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) {
+                        int wv = v + dy;
+                        if (wcy && wv >= L) wv -= L;
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) {
+                            int wu = u + dx;
+                            if (wcx && wu >= L) wu -= L;
+                            addr[w][dy][dx] = wv * wex + wu;
+                        }
+                    }
+#pragma unroll
+                    for (int hh = 0; hh < S::NH; ++hh)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[w][hh][r] = bias[hh][r];
+                    if (last && valid[w] && g == 0) {
+                        const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
+                        hs_base[w] = prm.hsum[(int64_t)s * N + site];
+                    }
+                }
+                const bool second = t0 + kNW < ntiles;
+#pragma unroll
+                for (int j = 0; j < S::KS; ++j) {
+                    int tap, chunk;
+                    mf::kstep_tap<C>(j, g, &tap, &chunk);
+                    const int a0 = addr[0][tap / 3][tap % 3];
+                    const bf16x8 b0 = *(const bf16x8 *)(cur + chunk_addr<C>(a0, chunk));
+#pragma unroll
+                    for (int hh = 0; hh < S::NH; ++hh)
+                        acc[0][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j][hh], b0,
+                                                                            acc[0][hh], 0, 0, 0);
+                    if (second) {
+                        const int a1 = addr[1][tap / 3][tap % 3];
+                        const bf16x8 b1 = *(const bf16x8 *)(cur + chunk_addr<C>(a1, chunk));
+#pragma unroll
+                        for (int hh = 0; hh < S::NH; ++hh)
+                            acc[1][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                wa[j][hh], b1, acc[1][hh], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    if (w == 1 && !second) break;
+                    if (!last) {
+                        if (valid[w]) {
+                            uint32_t pk[S::CG / 2];
+#pragma unroll
+                            for (int hh = 0; hh < S::NH; ++hh) {
+                                pk[hh * 2] = pack2(mf::ln_cosh(acc[w][hh][0]), mf::ln_cosh(acc[w][hh][1]));
+                                pk[hh * 2 + 1] = pack2(mf::ln_cosh(acc[w][hh][2]), mf::ln_cosh(acc[w][hh][3]));
+                            }
+                            int wu = pos_u[w] + 2, wv = pos_v[w] + 2;
+                            if (wu >= L) wu -= L;
+                            if (wv >= L) wv -= L;
+                            store_group<C>(nxt, wv * nex + wu, g, pk);
+                        }
+                    } else {
+                        double part = 0.0;
+#pragma unroll
+                        for (int hh = 0; hh < S::NH; ++hh)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) part += (double)mf::ln_cosh(acc[w][hh][r]);
+                        part += __shfl_xor(part, 16);
+                        part += __shfl_xor(part, 32);
+                        if (g == 0 && valid[w]) fsum += part - hs_base[w];
+                    }
+                }
+            }
+            // weights of the next layer (or of layer 2 for the next item)
+            load_weights<C>(wa, prm.wa + (last ? 0 : (int64_t)(k - 1) * wl_stride), lane);
+            if (!last) ring_store<C>(ring, nxt, prm, roff[k - 1], roff[k], ax, ay,
+                                     cache_s + (int64_t)(k - 1) * N * C);
+            __syncthreads();
+        }
+
+        for (int off = 32; off > 0; off >>= 1) fsum += __shfl_xor(fsum, off);
+        if (lane == 0) red[wave] = fsum;
+        __syncthreads();
+        if (tid == 0) {
+            double v = 0.0;
+            for (int w = 0; w < kNW; ++w) v += red[w];
+            if (!isfinite(v)) atomicOr(prm.err, kErrNonFinite);
+            prm.dlog[unit] = v;
+        }
+    }
+}
+
+}  // namespace
+
+// Ring lists: for bond type tau and layer k = 1..K-1, the sites of the next
+// window W_{k+1} = R_{k+2} outside R_k, as (window index, offset from the
+// anchor).  Stored per context; item-independent because the geometry is
+// anchored at the exchanged pair.
+nqs_status mfma_build_ring_tables(nqs_ctx *c)
+{
+    const int L = c->L, K = c->K;
+    std::vector<int32_t> ent, off((size_t)4 * K, 0);
+    for (int tau = 0; tau < 4; ++tau) {
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        for (int k = 1; k < K; ++k) {
+            off[(size_t)tau * K + (k - 1)] = (int32_t)ent.size();
+            const int ex = std::min(w0 + 2 * k, L), ey = std::min(h0 + 2 * k, L);
+            const int nex = std::min(w0 + 2 * k + 4, L), ney = std::min(h0 + 2 * k + 4, L);
+            for (int wv = 0; wv < ney; ++wv)
+                for (int wu = 0; wu < nex; ++wu) {
+                    const int du = wu - (k + 2), dv = wv - (k + 2);   // offsets from the anchor
+                    // inside R_k: anchor offset in [-k, -k + ex) modulo L (a clamped
+                    // window spans one period, which R_k's range may straddle)
+                    const bool in_x = (ex == L) || (((du + k) % L + L) % L < ex);
+                    const bool in_y = (ey == L) || (((dv + k) % L + L) % L < ey);
+                    if (in_x && in_y) continue;
+                    ent.push_back((wv * nex + wu) | ((du + 128) << 16) | ((dv + 128) << 24));
+                }
+        }
+        off[(size_t)tau * K + (K - 1)] = (int32_t)ent.size();
+    }
+    if (ent.empty()) ent.push_back(0);
+    if (c->ring_tab) (void)hipFree(c->ring_tab);
+    if (c->ring_off) (void)hipFree(c->ring_off);
+    c->ring_tab = nullptr;
+    c->ring_off = nullptr;
+    if (hipMalloc((void **)&c->ring_tab, ent.size() * 4) != hipSuccess ||
+        hipMalloc((void **)&c->ring_off, off.size() * 4) != hipSuccess)
+        return NQS_E_NOMEM;
+    if (hipMemcpy(c->ring_tab, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->ring_off, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return NQS_E_HIP;
+    return NQS_OK;
+}
+
+size_t mfma_inc_lds_bytes(const nqs_ctx *c)
+{
+    int wmax = 0;
+    for (int k = 1; k <= c->K; ++k) {
+        const int e = std::min(2 + 2 * k + 2, c->L);   // W_k = R_{k+1}, 2x2 seed
+        wmax = std::max(wmax, e * e);
+    }
+    return (size_t)wmax * c->C * 2;   // one window buffer
+}
+
+void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                      const int64_t *qlen, int64_t capacity, const double *hsum,
+                      const void *cache, double *dlog, hipStream_t s)
+{
+    if (capacity <= 0) return;
+    IncParams p{};
+    p.spins = spins;
+    p.L = c->L;
+    p.K = c->K;
+    p.queue = queue;
+    p.qlen = qlen;
+    p.capacity = capacity;
+    p.wa = (const bf16x8 *)c->w_mfma;
+    p.w1 = c->w_l1;
+    p.bias = c->w_l1 + 9 * c->C;
+    p.cache = (const uint16_t *)cache;
+    p.hsum = hsum;
+    p.dlog = dlog;
+    p.err = c->err;
+    p.ring = c->ring_tab;
+    p.ring_off = c->ring_off;
+    const size_t win = mfma_inc_lds_bytes(c);
+    p.win_bytes = (int)win;
+    const size_t lds = 2 * win;
+    // persistent grid: exactly the workgroups that are resident at once
+    const void *fn = c->C == 32 ? (const void *)k_net_inc<32> : (const void *)k_net_inc<16>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t want = std::min<int64_t>(capacity, (int64_t)c->n_cu * per_cu);
+    if (c->C == 32)
+        NQS_LAUNCH((k_net_inc<32>), dim3((unsigned)want), dim3(kThreads), lds, s, p);
+    else
+        NQS_LAUNCH((k_net_inc<16>), dim3((unsigned)want), dim3(kThreads), lds, s, p);
+}
+
+}  // namespace nqs

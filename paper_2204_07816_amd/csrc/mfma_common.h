@@ -1,0 +1,93 @@
+// mfma_common.h -- pieces shared by the BF16 matrix-core network kernels.
+// The base pass (a sample's own network, whose activations are cached) and
+// the exchanged-configuration passes must run bit-identical arithmetic on
+// identical inputs, so that a site the exchange does not reach contributes
+// exactly zero to f(S') - f(s).  Everything that produces a value — ln cosh,
+// the layer-1 FMA order, the MFMA K-step order, the channel permutation — is
+// defined once, here.
+#pragma once
+
+#include "nqs_internal.h"
+
+namespace nqs {
+namespace mf {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+// ln cosh z in FP32.  |z| < 0.5: ln cosh z = s P(s), s = z^2, with P a
+// degree-4 least-squares fit of ln cosh(sqrt s)/s on [0, 0.25] (fit error
+// 2e-9, below FP32 resolution; no cancellation near 0).  |z| >= 0.5:
+// ln cosh z = |z| - ln 2 + ln 2 * log2(1 + 2^(-2|z| log2 e)) on the hardware
+// exp2 / log2 units (the result is >= 0.12 there, so the absolute error of
+// the logarithm stays ~1e-6 relative).
+__device__ __forceinline__ float ln_cosh(float z)
+{
+    const float a = fabsf(z);
+    const float s = a * a;
+    float p = __builtin_fmaf(0.0017842075321823359f, s, -0.006661977618932724f);
+    p = __builtin_fmaf(p, s, 0.022214891389012337f);
+    p = __builtin_fmaf(p, s, -0.0833331048488617f);
+    p = __builtin_fmaf(p, s, 0.5f);
+    float h = s * p;
+    if (a >= 0.5f) {
+        const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);
+        h = (a - 0.69314718055994531f) + 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + t);
+    }
+    return h;
+}
+
+// Channel permutation: physical slot q of a site holds logical channel
+// chan_of_slot(q).  MFMA lane group g (lanes 16g..16g+15) owns the slots of
+// chunk g, so its outputs are contiguous.
+template <int C>
+__device__ __host__ __forceinline__ int chan_of_slot(int q)
+{
+    if (C == 32) {
+        const int g = q >> 3, r = q & 7;
+        return r < 4 ? 4 * g + r : 16 + 4 * g + (r - 4);
+    }
+    return q;
+}
+
+template <int C>
+struct Shape {
+    static constexpr int NH = C / 16;              // 16-channel output halves
+    static constexpr int KS = (C == 32) ? 9 : 5;   // K-steps of 32 reduction elements
+    static constexpr int CG = C / 4;               // channels per lane group
+    static constexpr int PSB = C * 2;              // bytes per site (BF16)
+    static constexpr int CHUNKS = PSB / 16;        // 16-byte chunks per site
+};
+
+// Tap and 16-byte chunk read by lane group g at K-step j.
+template <int C>
+__device__ __forceinline__ void kstep_tap(int j, int g, int *tap, int *chunk)
+{
+    if (C == 32) {
+        *tap = j;
+        *chunk = g;
+    } else {
+        int t = 2 * j + (g >> 1);
+        *tap = t > 8 ? 8 : t;      // padding step: its weights are zero
+        *chunk = g & 1;
+    }
+}
+
+// Layer-1 pre-activation of logical channel co from the 9 spins of a site's
+// 3x3 neighbourhood, in a fixed FMA order.
+__device__ __forceinline__ float layer1_z(const float *w1, const float *b1, int C, int co,
+                                          const float sv[9])
+{
+    float z = b1[co];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) z = __builtin_fmaf(w1[t * C + co], sv[t], z);
+    return z;
+}
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+
+}  // namespace mf
+}  // namespace nqs

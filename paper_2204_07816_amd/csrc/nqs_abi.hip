@@ -144,6 +144,7 @@ nqs_status pack_weights(nqs_ctx *c)
             for (int co = 0; co < C; ++co) l1.push_back((float)cn.b(l, co));
         if ((st = upload(c->w_mfma, wm)) != NQS_OK) return st;
         if ((st = upload(c->w_l1, l1)) != NQS_OK) return st;
+        if (!c->ring_tab && (st = mfma_build_ring_tables(c)) != NQS_OK) return st;
     }
     return NQS_OK;
 }
@@ -164,7 +165,7 @@ nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
         inc += (double)ex * ex;
         full += (double)c->N;
     }
-    return inc < 0.7 * full ? NQS_INCREMENTAL : NQS_FULL;
+    return (inc < 0.7 * full && mfma_inc_supported(c)) ? NQS_INCREMENTAL : NQS_FULL;
 }
 
 #define NQS_TRY(x)                        \
@@ -402,6 +403,8 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->w_bwd64);
     free_dev(c->w_mfma);
     free_dev(c->w_l1);
+    free_dev(c->ring_tab);
+    free_dev(c->ring_off);
     free_dev(c->err);
     DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
                       &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,
@@ -500,7 +503,8 @@ nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *
     if (B > 0 && !e_loc) return NQS_E_ARG;
     if (mode != NQS_AUTO && mode != NQS_FULL && mode != NQS_INCREMENTAL) return NQS_E_ARG;
     const nqs_mode m = resolve_mode(c, mode);
-    if (m == NQS_INCREMENTAL && c->dtype != NQS_BF16) return NQS_E_UNSUPPORTED;
+    if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+        return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     if (B == 0) return NQS_OK;
@@ -521,7 +525,8 @@ nqs_status nqs_log_ratios(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode m
     const int64_t cap = bonds_per_sample(c) * B;
     if (capacity < cap) return NQS_E_ARG;
     const nqs_mode m = resolve_mode(c, mode);
-    if (m == NQS_INCREMENTAL && c->dtype != NQS_BF16) return NQS_E_UNSUPPORTED;
+    if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+        return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     if (B == 0) return NQS_OK;

@@ -71,6 +71,8 @@ struct nqs_ctx {
     double *w_bwd64 = nullptr;    // transposed packing for the backward data pass
     uint16_t *w_mfma = nullptr;   // BF16 MFMA A-operand packing, layers 2..K
     float *w_l1 = nullptr;        // layer-1 weights + all biases, FP32, MFMA path
+    int32_t *ring_tab = nullptr;  // incremental mode: ring lists per bond type and layer
+    int32_t *ring_off = nullptr;
     // workspace
     nqs::Workspace ws;
     int32_t *err = nullptr;       // device sticky error word
@@ -140,6 +142,13 @@ void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
                        const double *hsum, const void *cache, double *dlog, int *counter,
                        hipStream_t s);
 int mfma_lds_full_ok(const nqs_ctx *c);
+// incremental-mode kernel (k_net_inc.hip)
+nqs_status mfma_build_ring_tables(nqs_ctx *c);
+size_t mfma_inc_lds_bytes(const nqs_ctx *c);
+void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                      const int64_t *qlen, int64_t capacity, const double *hsum,
+                      const void *cache, double *dlog, hipStream_t s);
+bool mfma_inc_supported(const nqs_ctx *c);
 
 // --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
 void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const uint32_t *queue,
