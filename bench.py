@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--mode", default="incremental", choices=["incremental", "full"])
+    ap.add_argument("--only", default=None, choices=["eloc"],
+                    help="profiling aid: run only the local-energy call --steps times, then a "
+                         "1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -155,6 +158,18 @@ def main():
         ctx.energy_stats(e, out=st2)
         ctx.log_deriv(spd, dtype="fp32", out=O)
         ctx.sr_solve(O, e, 1e-4, 100, out=x, stats=st4)
+
+    if args.only == "eloc":
+        for i in range(args.steps):
+            ctx.local_energy(spd, mode=args.mode, out=e)
+            torch.cuda.synchronize()
+            log(f"local energy {i + 1}/{args.steps} done")
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("reference copy of 1 GiB done")
+        return
 
     for i in range(args.warmup):
         step()

@@ -414,7 +414,8 @@ bool mfma_supported(const nqs_ctx *c)
 
 bool mfma_inc_supported(const nqs_ctx *c)
 {
-    return mfma_supported(c) && 2 * mfma_inc_lds_bytes(c) <= 160 * 1024 - 1024;
+    // anchor offsets must stay within one period of the torus
+    return mfma_supported(c) && c->L >= c->K + 2 && 2 * mfma_inc_lds_bytes(c) <= 160 * 1024 - 1024;
 }
 
 int mfma_lds_full_ok(const nqs_ctx *c)

@@ -36,7 +36,7 @@ using mf::Shape;
 
 constexpr int kNW = 4;
 constexpr int kThreads = kNW * 64;
-constexpr int kRingRegs = 3;
+constexpr int kRingRegs = 2;
 
 struct IncParams {
     const int8_t *spins;
@@ -51,22 +51,32 @@ struct IncParams {
     const double *hsum;
     double *dlog;
     int32_t *err;
-    const int32_t *ring;       // packed (window index | (du+128) << 16 | (dv+128) << 24)
+    const int32_t *ring;       // packed (window index | (du mod L) << 16 | (dv mod L) << 24)
     const int32_t *ring_off;   // [4][K] entry offsets: ring of W_{k+1} for k = 1..K-1
     int win_bytes;             // bytes of one window buffer
 };
 
+// a mod L for a in [-L, 2L): every anchor offset of this kernel lies in
+// [-(K+2), L) and the incremental mode requires L >= K + 2.
 __device__ __forceinline__ int wrap_l(int a, int L)
 {
-    a %= L;
-    return a < 0 ? a + L : a;
+    a += (a < 0) ? L : 0;
+    return a - ((a >= L) ? L : 0);
 }
+
+// Window sites are padded to one extra 16-byte chunk (80 B for 32 channels,
+// 48 B for 16): the 16 sites read by a lane group then start on 16 distinct
+// 16-byte bank groups, so the 16-byte LDS loads and stores are conflict-free.
+template <int C>
+struct Win {
+    static constexpr int STRIDE = Shape<C>::PSB + 16;
+};
 
 // byte offset of 16-byte chunk c of window site wi
 template <int C>
 __device__ __forceinline__ int chunk_addr(int wi, int c)
 {
-    return wi * Shape<C>::PSB + ((c ^ (wi & (Shape<C>::CHUNKS - 1))) << 4);
+    return wi * Win<C>::STRIDE + (c << 4);
 }
 
 // Store the CG channels of lane group g (values already BF16-packed in pairs).
@@ -100,18 +110,21 @@ __device__ __forceinline__ void ring_fetch(Ring<C> &r, const IncParams &p, int e
 {
     const int L = p.L;
     const int total = (e1 - e0) * Shape<C>::CHUNKS;
+    // The loads are issued unconditionally (surplus lanes re-read the first
+    // entry) so that the compiler can count outstanding loads exactly and
+    // let the layer's matrix work start before they land.
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i) {
-        const int q = threadIdx.x + i * kThreads;
-        r.wi[i] = -1;
-        if (q < total) {
-            const int ent = p.ring[e0 + q / Shape<C>::CHUNKS];
-            const int c = q % Shape<C>::CHUNKS;
-            const int du = ((ent >> 16) & 255) - 128, dv = ((ent >> 24) & 255) - 128;
-            const int site = wrap_l(ay + dv, L) * L + wrap_l(ax + du, L);
-            r.v[i] = *(const uint4 *)(layer_cache + (int64_t)site * C + c * 8);
-            r.wi[i] = ((ent & 0xffff) << 4) | c;
-        }
+        const int q0 = threadIdx.x + i * kThreads;
+        const bool live = q0 < total;
+        const int q = live ? q0 : 0;
+        const int ent = p.ring[e0 + q / Shape<C>::CHUNKS];
+        const int c = q % Shape<C>::CHUNKS;
+        int x = ax + ((ent >> 16) & 255), y = ay + ((ent >> 24) & 255);
+        x -= (x >= L) ? L : 0;
+        y -= (y >= L) ? L : 0;
+        r.v[i] = *(const uint4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
+        r.wi[i] = live ? (((ent & 0xffff) << 4) | c) : -1;
     }
 }
 
@@ -129,10 +142,11 @@ __device__ __forceinline__ void ring_store(const Ring<C> &r, unsigned char *buf,
     for (int q = threadIdx.x + kRingRegs * kThreads; q < total; q += kThreads) {
         const int ent = p.ring[e0 + q / Shape<C>::CHUNKS];
         const int c = q % Shape<C>::CHUNKS;
-        const int du = ((ent >> 16) & 255) - 128, dv = ((ent >> 24) & 255) - 128;
-        const int site = wrap_l(ay + dv, L) * L + wrap_l(ax + du, L);
+        int x = ax + ((ent >> 16) & 255), y = ay + ((ent >> 24) & 255);
+        x -= (x >= L) ? L : 0;
+        y -= (y >= L) ? L : 0;
         *(uint4 *)(buf + chunk_addr<C>(ent & 0xffff, c)) =
-            *(const uint4 *)(layer_cache + (int64_t)site * C + c * 8);
+            *(const uint4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
     }
 }
 
@@ -147,8 +161,132 @@ __device__ __forceinline__ void load_weights(bf16x8 (&wa)[Shape<C>::KS][Shape<C>
             wa[j][hh] = base[(j * Shape<C>::NH + hh) * 64 + lane];
 }
 
+// Matrix work of NT (1 or 2) tiles of one layer: implicit-GEMM MFMA over
+// window W_k, then ln cosh and either the BF16 store into the next window
+// (inner layers) or the FP64 per-site sums (last layer).  Straight-line code:
+// the tap address of every K-step is one add of a precomputed row byte base
+// and column byte offset.
+template <int C, bool last, int NT>
+__device__ __forceinline__ void tile_group(const bf16x8 (&wa)[Shape<C>::KS][Shape<C>::NH],
+                                           const float (&bias)[Shape<C>::NH][4],
+                                           unsigned char *lds, int cur, int nxt, int t0,
+                                           int ntiles, int npos, uint32_t mul, int ex, int wex,
+                                           int nex, bool wcx, bool wcy, int L, int K, int ax,
+                                           int ay, const double *hsum_s, int g, int n16,
+                                           double &fsum)
+{
+    using S = Shape<C>;
+    constexpr int STRIDE = Win<C>::STRIDE;
+    const int chunk_b = (C == 32 ? g : (g & 1)) << 4;   // 16-byte chunk this lane group reads
+    floatx4 acc[NT][S::NH];
+    int pos_u[NT], pos_v[NT];
+    bool valid[NT];
+    int rowb[NT][3], colb[NT][3];
+    double hs_base[NT];
+#pragma unroll
+    for (int w = 0; w < NT; ++w) {
+        const int tile = t0 + w * kNW;
+        int p = tile * 16 + n16;
+        valid[w] = p < npos;
+        if (p >= npos) p = npos - 1;
+        const int v = (int)(((uint32_t)p * mul) >> 20);
+        const int u = p - __mul24(v, ex);
+        pos_u[w] = u;
+        pos_v[w] = v;
+        // window W_k = R_{k+1} coordinates of the taps (d - 1) around (u, v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int wv = v + d;
+            if (wcy && wv >= L) wv -= L;
+            int wu = u + d;
+            if (wcx && wu >= L) wu -= L;
+            rowb[w][d] = __mul24(wv, wex * STRIDE) + cur + chunk_b;
+            colb[w][d] = __mul24(wu, STRIDE);
+        }
+#pragma unroll
+        for (int hh = 0; hh < S::NH; ++hh)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[w][hh][r] = bias[hh][r];
+        hs_base[w] = 0.0;
+        if (last) {   // unconditional load (clamped position), used by lane group 0
+            const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
+            hs_base[w] = hsum_s[site];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < S::KS; ++j) {
+#pragma unroll
+        for (int w = 0; w < NT; ++w) {
+            int a;
+            if (C == 32) {
+                a = rowb[w][j / 3] + colb[w][j % 3];
+            } else {
+                // lane groups 0-1 read tap 2j, groups 2-3 tap 2j+1 (clamped to 8)
+                const int ta = 2 * j, tb = (2 * j + 1 > 8) ? 8 : 2 * j + 1;
+                const int aa = rowb[w][ta / 3] + colb[w][ta % 3];
+                const int ab = rowb[w][tb / 3] + colb[w][tb % 3];
+                a = (g >> 1) ? ab : aa;
+            }
+            const bf16x8 bv = *(const bf16x8 *)(lds + a);
+#pragma unroll
+            for (int hh = 0; hh < S::NH; ++hh)
+                acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j][hh], bv, acc[w][hh], 0,
+                                                                    0, 0);
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < NT; ++w) {
+        float zv[S::CG], hv[S::CG];
+#pragma unroll
+        for (int hh = 0; hh < S::NH; ++hh)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[w][hh][r];
+        mf::ln_cosh_n<S::CG>(zv, hv);
+        if (!last) {
+            if (valid[w]) {
+                uint32_t pk[S::CG / 2];
+#pragma unroll
+                for (int r = 0; r < S::CG / 2; ++r) pk[r] = pack2(hv[2 * r], hv[2 * r + 1]);
+                int wu = pos_u[w] + 2, wv = pos_v[w] + 2;
+                if (wu >= L) wu -= L;
+                if (wv >= L) wv -= L;
+                store_group<C>(lds + nxt, __mul24(wv, nex) + wu, g, pk);
+            }
+        } else {
+            double part = 0.0;
+#pragma unroll
+            for (int r = 0; r < S::CG; ++r) part += (double)hv[r];
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (g == 0 && valid[w]) fsum += part - hs_base[w];
+        }
+    }
+}
+
+// All tiles of one layer owned by this wave, two in flight where possible.
+// Instantiated separately for the last layer so that inner layers contain no
+// conditional global loads and the compiler's load counting stays exact.
+template <int C, bool last>
+__device__ __forceinline__ void layer_tiles(const bf16x8 (&wa)[Shape<C>::KS][Shape<C>::NH],
+                                            const float (&bias)[Shape<C>::NH][4],
+                                            unsigned char *lds, int cur, int nxt,
+                                            int ntiles, int npos, uint32_t mul, int ex, int wex,
+                                            int nex, bool wcx, bool wcy, int L, int K, int ax,
+                                            int ay, const double *hsum_s, int wave, int g, int n16,
+                                            double &fsum)
+{
+    for (int t0 = wave; t0 < ntiles; t0 += 2 * kNW) {
+        if (t0 + kNW < ntiles)
+            tile_group<C, last, 2>(wa, bias, lds, cur, nxt, t0, ntiles, npos, mul, ex, wex, nex, wcx,
+                                   wcy, L, K, ax, ay, hsum_s, g, n16, fsum);
+        else
+            tile_group<C, last, 1>(wa, bias, lds, cur, nxt, t0, ntiles, npos, mul, ex, wex, nex, wcx,
+                                   wcy, L, K, ax, ay, hsum_s, g, n16, fsum);
+    }
+}
+
 template <int C>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_net_inc(IncParams prm)
 {
     using S = Shape<C>;
@@ -215,8 +353,9 @@ k_net_inc(IncParams prm)
 
         double fsum = 0.0;
         for (int k = 2; k <= K; ++k) {
-            unsigned char *cur = ((k & 1) == 0) ? buf0 : buf1;
-            unsigned char *nxt = ((k & 1) == 0) ? buf1 : buf0;
+            const int cur_off = ((k & 1) == 0) ? 0 : prm.win_bytes;
+            const int nxt_off = ((k & 1) == 0) ? prm.win_bytes : 0;
+            unsigned char *nxt = lds + nxt_off;
             const int ex = min(w0 + 2 * k, L), ey = min(h0 + 2 * k, L);
             const int wex = min(w0 + 2 * k + 2, L), wey = min(h0 + 2 * k + 2, L);
             const bool wcx = wex == L, wcy = wey == L;
@@ -235,91 +374,12 @@ k_net_inc(IncParams prm)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) bias[hh][r] = prm.bias[(k - 1) * C + 16 * hh + 4 * g + r];
 
-            for (int t0 = wave; t0 < ntiles; t0 += 2 * kNW) {
-                floatx4 acc[2][S::NH];
-                int pos_u[2], pos_v[2];
-                bool valid[2];
-                int addr[2][3][3];
-                double hs_base[2] = {0.0, 0.0};
-#pragma unroll
-                for (int w = 0; w < 2; ++w) {
-                    const int tile = t0 + w * kNW;
-                    int p = tile * 16 + n16;
-                    valid[w] = tile < ntiles && p < npos;
-                    if (p >= npos) p = npos - 1;
-                    const int v = (int)(((uint32_t)p * mul) >> 20);
-                    const int u = p - v * ex;
-                    pos_u[w] = u;
-                    pos_v[w] = v;
-                    // window W_k = R_{k+1} coordinates of the tap (dy-1, dx-1)
-#pragma unroll
-                    for (int dy = 0; dy < 3; ++dy) {
-                        int wv = v + dy;
-                        if (wcy && wv >= L) wv -= L;
-#pragma unroll
-                        for (int dx = 0; dx < 3; ++dx) {
-                            int wu = u + dx;
-                            if (wcx && wu >= L) wu -= L;
-                            addr[w][dy][dx] = wv * wex + wu;
-                        }
-                    }
-#pragma unroll
-                    for (int hh = 0; hh < S::NH; ++hh)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[w][hh][r] = bias[hh][r];
-                    if (last && valid[w] && g == 0) {
-                        const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
-                        hs_base[w] = prm.hsum[(int64_t)s * N + site];
-                    }
-                }
-                const bool second = t0 + kNW < ntiles;
-#pragma unroll
-                for (int j = 0; j < S::KS; ++j) {
-                    int tap, chunk;
-                    mf::kstep_tap<C>(j, g, &tap, &chunk);
-                    const int a0 = addr[0][tap / 3][tap % 3];
-                    const bf16x8 b0 = *(const bf16x8 *)(cur + chunk_addr<C>(a0, chunk));
-#pragma unroll
-                    for (int hh = 0; hh < S::NH; ++hh)
-                        acc[0][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j][hh], b0,
-                                                                            acc[0][hh], 0, 0, 0);
-                    if (second) {
-                        const int a1 = addr[1][tap / 3][tap % 3];
-                        const bf16x8 b1 = *(const bf16x8 *)(cur + chunk_addr<C>(a1, chunk));
-#pragma unroll
-                        for (int hh = 0; hh < S::NH; ++hh)
-                            acc[1][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                wa[j][hh], b1, acc[1][hh], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int w = 0; w < 2; ++w) {
-                    if (w == 1 && !second) break;
-                    if (!last) {
-                        if (valid[w]) {
-                            uint32_t pk[S::CG / 2];
-#pragma unroll
-                            for (int hh = 0; hh < S::NH; ++hh) {
-                                pk[hh * 2] = pack2(mf::ln_cosh(acc[w][hh][0]), mf::ln_cosh(acc[w][hh][1]));
-                                pk[hh * 2 + 1] = pack2(mf::ln_cosh(acc[w][hh][2]), mf::ln_cosh(acc[w][hh][3]));
-                            }
-                            int wu = pos_u[w] + 2, wv = pos_v[w] + 2;
-                            if (wu >= L) wu -= L;
-                            if (wv >= L) wv -= L;
-                            store_group<C>(nxt, wv * nex + wu, g, pk);
-                        }
-                    } else {
-                        double part = 0.0;
-#pragma unroll
-                        for (int hh = 0; hh < S::NH; ++hh)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) part += (double)mf::ln_cosh(acc[w][hh][r]);
-                        part += __shfl_xor(part, 16);
-                        part += __shfl_xor(part, 32);
-                        if (g == 0 && valid[w]) fsum += part - hs_base[w];
-                    }
-                }
-            }
+            if (!last)
+                layer_tiles<C, false>(wa, bias, lds, cur_off, nxt_off, ntiles, npos, mul, ex, wex, nex, wcx, wcy,
+                                      L, K, ax, ay, prm.hsum + (int64_t)s * N, wave, g, n16, fsum);
+            else
+                layer_tiles<C, true>(wa, bias, lds, cur_off, nxt_off, ntiles, npos, mul, ex, wex, nex, wcx, wcy,
+                                     L, K, ax, ay, prm.hsum + (int64_t)s * N, wave, g, n16, fsum);
             // weights of the next layer (or of layer 2 for the next item)
             load_weights<C>(wa, prm.wa + (last ? 0 : (int64_t)(k - 1) * wl_stride), lane);
             if (!last) ring_store<C>(ring, nxt, prm, roff[k - 1], roff[k], ax, ay,
@@ -363,7 +423,9 @@ nqs_status mfma_build_ring_tables(nqs_ctx *c)
                     const bool in_x = (ex == L) || (((du + k) % L + L) % L < ex);
                     const bool in_y = (ey == L) || (((dv + k) % L + L) % L < ey);
                     if (in_x && in_y) continue;
-                    ent.push_back((wv * nex + wu) | ((du + 128) << 16) | ((dv + 128) << 24));
+                    // anchor offsets stored reduced modulo L (0 <= offset < L <= 64)
+                    const int dum = ((du % L) + L) % L, dvm = ((dv % L) + L) % L;
+                    ent.push_back((wv * nex + wu) | (dum << 16) | (dvm << 24));
                 }
         }
         off[(size_t)tau * K + (K - 1)] = (int32_t)ent.size();
@@ -389,7 +451,7 @@ size_t mfma_inc_lds_bytes(const nqs_ctx *c)
         const int e = std::min(2 + 2 * k + 2, c->L);   // W_k = R_{k+1}, 2x2 seed
         wmax = std::max(wmax, e * e);
     }
-    return (size_t)wmax * c->C * 2;   // one window buffer
+    return (size_t)wmax * (c->C * 2 + 16);   // one window buffer, padded sites
 }
 
 void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,

@@ -21,20 +21,53 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 // ln cosh z = |z| - ln 2 + ln 2 * log2(1 + 2^(-2|z| log2 e)) on the hardware
 // exp2 / log2 units (the result is >= 0.12 there, so the absolute error of
 // the logarithm stays ~1e-6 relative).
-__device__ __forceinline__ float ln_cosh(float z)
+__device__ __forceinline__ float ln_cosh_small(float a)
 {
-    const float a = fabsf(z);
     const float s = a * a;
     float p = __builtin_fmaf(0.0017842075321823359f, s, -0.006661977618932724f);
     p = __builtin_fmaf(p, s, 0.022214891389012337f);
     p = __builtin_fmaf(p, s, -0.0833331048488617f);
     p = __builtin_fmaf(p, s, 0.5f);
-    float h = s * p;
-    if (a >= 0.5f) {
-        const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);
-        h = (a - 0.69314718055994531f) + 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + t);
-    }
+    return s * p;
+}
+
+__device__ __forceinline__ float ln_cosh_large(float a)
+{
+    const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);
+    return __builtin_fmaf(0.69314718055994531f, __builtin_amdgcn_logf(1.0f + t),
+                          a - 0.69314718055994531f);
+}
+
+__device__ __forceinline__ float ln_cosh(float z)
+{
+    const float a = fabsf(z);
+    float h = ln_cosh_small(a);
+    if (a >= 0.5f) h = ln_cosh_large(a);
     return h;
+}
+
+// ln cosh of n values with a single wave-uniform test for the large branch;
+// every element gets exactly the value ln_cosh() gives it.
+template <int n>
+__device__ __forceinline__ void ln_cosh_n(const float *z, float *h)
+{
+    float amax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        const float a = fabsf(z[i]);
+        h[i] = ln_cosh_small(a);
+        amax = fmaxf(amax, a);
+    }
+    if (__any(amax >= 0.5f)) {
+        // keeps the compiler from if-converting (always executing) this branch
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            const float a = fabsf(z[i]);
+            const float big = ln_cosh_large(a);
+            h[i] = (a >= 0.5f) ? big : h[i];
+        }
+    }
 }
 
 // Channel permutation: physical slot q of a site holds logical channel
