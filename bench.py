@@ -58,8 +58,11 @@ def item_flops(L: int, K: int, C: int, diagonal: bool) -> float:
 
 
 def source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2204_07816_amd", "csrc", "k_conv_mfma.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the dominant kernel's sources (counter summaries are tied to it)."""
+    h = hashlib.sha256()
+    for f in ("k_net_inc.hip", "mfma_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2204_07816_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(launch_items: float):
@@ -223,7 +226,7 @@ def main():
     traffic = traffic_from_profile(allb.shape[0])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                "kernel": "k_net<32,4,6> (exchanged configurations, incremental cone)",
+                "kernel": "k_net_inc<32> (exchanged configurations, incremental cone)",
                 "avg_launch_ms": avg_ms, "launches": k_n, "flops_per_launch": flops_launch,
                 "items_per_launch": int(allb.shape[0])}
 
