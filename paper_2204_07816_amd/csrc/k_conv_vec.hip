@@ -306,6 +306,13 @@ template <typename T>
 void layer_launch(const nqs_ctx *c, const T *in, int64_t M, int Cin, int Cout, const T *wl,
                   const T *bias, T *out, int epi, double *zk, PlaneMap pm, hipStream_t s)
 {
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (f64mma_conv_ok(Cin, Cout)) {
+            f64mma_conv(c, in, M, Cin, Cout, wl, bias, out, epi, zk, pm.queue ? pm.qlen : nullptr,
+                        pm.q_begin, s);
+            return;
+        }
+    }
     const size_t lds = sizeof(T) * 9 * (size_t)Cin * Cout;
     const int N = c->N;
     if (lds > 64 * 1024) {
@@ -424,7 +431,9 @@ void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zs
             NQS_LAUNCH(k_act, dim3(grid_for(layer, c)), dim3(kThreads), 0, s, zprev,
                                layer, nxt);
         const double *hprev = zprev ? nxt : nullptr;
-        if (odt == NQS_FP32)
+        if (hprev && f64mma_wgrad_ok(C))
+            f64mma_wgrad(c, hprev, cur, B, woff[k], O, odt, s);
+        else if (odt == NQS_FP32)
             NQS_LAUNCH((k_wgrad<float>), dim3(B), dim3(kThreads), 0, s, spins, hprev, cur,
                                c->L, C, k, c->P, woff[k], (float *)O);
         else

@@ -131,6 +131,18 @@ size_t vec_plane_bytes(const nqs_ctx *c, int64_t items);
 void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zsave,
                   double *delta_a, double *delta_b, void *O, nqs_dtype odt, hipStream_t s);
 
+// --- FP64 matrix-core layer and weight-gradient kernels (k_conv_f64mma.hip) ---
+bool f64mma_conv_ok(int Cin, int Cout);
+// epi 0: ln cosh; 1: ln cosh + save z to zk; 2: z * tanh(zk).  qlen (may be
+// null) bounds the live planes to qlen[0] - q_begin.
+void f64mma_conv(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cout,
+                 const double *w, const double *bias, double *out, int epi, double *zk,
+                 const int64_t *qlen, int64_t q_begin, hipStream_t s);
+bool f64mma_wgrad_ok(int C);
+// Rows O[s][woff ...] of a C -> C layer: weights [co][ci][t] then bias [co].
+void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
+                  void *O, nqs_dtype odt, hipStream_t s);
+
 // --- MFMA (BF16) network kernels (k_conv_mfma.hip) ---
 bool mfma_supported(const nqs_ctx *c);
 size_t mfma_cache_bytes(const nqs_ctx *c, int64_t B);
