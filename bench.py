@@ -60,7 +60,7 @@ def item_flops(L: int, K: int, C: int, diagonal: bool) -> float:
 def source_hash() -> str:
     """Hash of the dominant kernel's sources (counter summaries are tied to it)."""
     h = hashlib.sha256()
-    for f in ("k_net_inc.hip", "mfma_common.h"):
+    for f in ("k_net_cone.hip", "mfma_common.h"):
         h.update(open(os.path.join(ROOT, "paper_2204_07816_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -68,7 +68,7 @@ def source_hash() -> str:
 def traffic_from_profile(launch_items: float):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "k_net_incremental_36x36_counters.json")
+    p = os.path.join(ROOT, "profiles", "k_net_cone_36x36_counters.json")
     if not os.path.exists(p):
         return None
     try:
@@ -226,7 +226,7 @@ def main():
     traffic = traffic_from_profile(allb.shape[0])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                "kernel": "k_net_inc<32> (exchanged configurations, incremental cone)",
+                "kernel": "k_net_cone (exchanged configurations, incremental cone, unwrapped windows)",
                 "avg_launch_ms": avg_ms, "launches": k_n, "flops_per_launch": flops_launch,
                 "items_per_launch": int(allb.shape[0])}
 

@@ -451,7 +451,10 @@ void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
     (void)counter;
     if (capacity <= 0) return;
     if (mode == NQS_INCREMENTAL) {
-        mfma_inc_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
+        if (cone_supported(c))
+            cone_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
+        else
+            mfma_inc_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
         return;
     }
     const bool full = mode == NQS_FULL;

@@ -1,0 +1,428 @@
+// k_net_cone.hip -- the exchanged-configuration pass in incremental mode for
+// lattices wide enough that no window of the receptive cone wraps around the
+// torus (L >= 2K + 4) and 32 channels: the form taken by the large lattices
+// the local energy is dominated by [Sec. 5.4.1].
+//
+// The method is that of the general incremental kernel: an exchange of the
+// antiparallel pair (i, j) changes layer k only on R_k, the bounding
+// rectangle of the sites within Chebyshev distance k of i or j; layer k is
+// recomputed on R_k from window W_k = R_{k+1} (LDS), which holds layer k-1 of
+// this configuration on R_{k-1} and the cached base-pass activations on the
+// ring W_k \ R_{k-1}; the last layer adds sum_{p in R_K} (hs'(p) - hs(p)).
+// The arithmetic (MFMA K-step order, ln cosh, layer-1 FMA order, BF16
+// rounding, FP64 site sums) is the base pass's, so sites the exchange does
+// not reach cancel exactly.
+//
+// What the unwrapped geometry buys:
+//  * window W_k is a plain rectangle with row pitch P_k = width(R_k) + 8.
+//    Output positions are enumerated row-major over R_k, so the sites read by
+//    the 16 lanes of a tile are consecutive modulo 8 even across a row end;
+//    with 80-byte sites (64 B of channels + 16 B pad) the 16-byte LDS reads of
+//    any 8 lanes then fall in distinct bank groups.
+//  * a tap's LDS address is a per-tile row base plus a compile-time column
+//    offset, so the nine reads of a tile cost two adds.
+//  * the ring W_{k+1} minus R_k is a rectangular annulus two sites wide whose
+//    addresses are computed, not looked up, so its loads issue at once; the
+//    ring of W_{k+2} is fetched at the start of layer k and stored at the
+//    start of layer k + 1, a whole layer ahead of its use.
+//  * layer 1 is spread over all threads (two channels each).
+//  * consecutive queue items (mostly of one sample, sharing its cached
+//    activations) are kept on one XCD so that its L2 serves the ring reads.
+#include <algorithm>
+#include <vector>
+
+#include "mfma_common.h"
+
+namespace nqs {
+namespace {
+
+using mf::bf16x8;
+using mf::floatx4;
+
+constexpr int C = 32;
+constexpr int KS = 9;           // K-steps (one tap of 32 channels each)
+constexpr int NH = 2;           // 16-channel output halves
+constexpr int kNW = 4;
+constexpr int kThreads = kNW * 64;
+constexpr int kRingRegs = 3;
+constexpr int kSite = 80;       // bytes per window site
+constexpr int kPitchPad = 8;    // window pitch = width(R_k) + kPitchPad
+constexpr int kChunks = 4;      // 16-byte chunks of channels per site
+constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte chunk
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+struct ConeParams {
+    const int8_t *spins;
+    int L, K;
+    const uint32_t *queue;
+    const int64_t *qlen;
+    int64_t capacity;
+    const bf16x8 *wa;          // layer k >= 2: [k-2][KS][NH][64 lanes]
+    const float *w1;           // layer 1 [9][C]
+    const float *bias;         // [K][C]
+    const uint16_t *cache;     // base-pass BF16 activations [B][K-1][N][C] (slot order)
+    const double *hsum;        // base-pass per-site channel sums of layer K [B][N]
+    double *dlog;
+    int32_t *err;
+    int buf_b;                 // byte offset of the odd-layer window buffer
+};
+
+__device__ __forceinline__ int wrap_l(int a, int L)
+{
+    a += (a < 0) ? L : 0;
+    return a - ((a >= L) ? L : 0);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    const float2v f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+}
+
+struct Ring {
+    u32x4 v[kRingRegs];
+    int dst[kRingRegs];        // byte address in the window buffer, -1: none
+};
+
+// Ring of W_{k+1} = R_{k+2} minus R_k for an R_k of ex x ey sites: the
+// window's two top rows, two bottom rows, and the two left and two right
+// columns of the ey middle rows; site i of that list as window coordinates.
+__device__ __forceinline__ int2 ring_site(int i, int ex, int ey)
+{
+    const int nex = ex + 4;
+    const int band = (i >= nex) + (i >= 2 * nex) + (i >= 3 * nex);
+    const int j = i - 4 * nex, c = j & 3;
+    const bool bands = i < 4 * nex;
+    // rows 0, 1, ey + 2, ey + 3 in full; columns 0, 1, ex + 2, ex + 3 between
+    const int wu = bands ? i - band * nex : (c < 2 ? c : ex + c);
+    const int wv = bands ? (band < 2 ? band : ey + band) : 2 + (j >> 2);
+    return make_int2(wu, wv);
+}
+
+// Chunk q of the ring of W_{k+1}: source address in the layer-k cache and
+// byte address in the window (pitch P_{k+1} = ex + 2 + kPitchPad sites).
+// (.x: element offset in the layer cache, .y: byte offset in the window)
+__device__ __forceinline__ int2 ring_chunk(int q, int ex, int ey, int k, int ax, int ay, int L)
+{
+    const int2 w = ring_site(q >> 2, ex, ey);
+    const int c = q & 3;
+    const int x = wrap_l(ax + w.x - (k + 2), L), y = wrap_l(ay + w.y - (k + 2), L);
+    return make_int2((y * L + x) * C + c * 8, (w.y * (ex + 2 + kPitchPad) + w.x) * kSite + c * 16);
+}
+
+// Issue the loads of the first kRingRegs * kThreads chunks of the ring of
+// W_{k+1} (R_k of ex x ey).  Loads are unconditional (surplus lanes re-read
+// chunk 0) so that the outstanding-load count stays exact.
+__device__ __forceinline__ void ring_fetch(Ring &r, bool item_live, int lt, int ex, int ey, int k,
+                                           int ax, int ay, int L, const uint16_t *layer_cache)
+{
+    const int total = (4 * (ex + ey) + 16) * kChunks;
+#pragma unroll
+    for (int i = 0; i < kRingRegs; ++i) {
+        const int q0 = lt + i * kThreads;
+        const bool live = item_live && q0 < total;
+        const int2 sd = ring_chunk(live ? q0 : 0, ex, ey, k, ax, ay, L);
+        r.v[i] = *(const u32x4 *)(layer_cache + sd.x);
+        r.dst[i] = live ? sd.y : -1;
+    }
+}
+
+// Store the fetched chunks, then copy any chunks beyond them directly.
+__device__ __forceinline__ void ring_store(const Ring &r, bool item_live, int lt, unsigned char *buf,
+                                           int ex, int ey, int k, int ax, int ay, int L,
+                                           const uint16_t *layer_cache)
+{
+#pragma unroll
+    for (int i = 0; i < kRingRegs; ++i)
+        if (r.dst[i] >= 0) *(u32x4 *)(buf + r.dst[i]) = r.v[i];
+    const int total = item_live ? (4 * (ex + ey) + 16) * kChunks : 0;
+    for (int q = lt + kRingRegs * kThreads; q < total; q += kThreads) {
+        const int2 sd = ring_chunk(q, ex, ey, k, ax, ay, L);
+        *(u32x4 *)(buf + sd.y) = *(const u32x4 *)(layer_cache + sd.x);
+    }
+}
+
+// Weights of one layer (A operands, one 16-byte fragment per lane per
+// K-step and half) and the bias of this lane's output rows 16 hh + 4 g + r.
+__device__ __forceinline__ void load_layer(bf16x8 (&wa)[KS][NH], floatx4 (&bias)[NH],
+                                           const ConeParams &p, int k, int lane, int g)
+{
+    const bf16x8 *base = p.wa + (int64_t)(k - 2) * KS * NH * 64;
+#pragma unroll
+    for (int j = 0; j < KS; ++j)
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh) wa[j][hh] = base[(j * NH + hh) * 64 + lane];
+#pragma unroll
+    for (int hh = 0; hh < NH; ++hh)
+        bias[hh] = *(const floatx4 *)(p.bias + (k - 1) * C + 16 * hh + 4 * g);
+}
+
+// Everything one tile needs (wave-uniform): the tile's first position in R_k
+// and the layer geometry.
+struct TileArgs {
+    int p0, npos, ex;
+    uint32_t mul;              // ceil(2^20 / ex): p / ex = (p * mul) >> 20, exact for ex <= 64, p < 66 ex
+    int p80;                   // row pitch of W_k in bytes
+    int q80;                   // row pitch of W_{k+1} in bytes
+};
+
+// NT tiles of one layer.  Inner layers store the BF16 activations into
+// W_{k+1}; the last layer accumulates the site sums.
+template <bool last, int NT>
+__device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
+                                           const unsigned char *cur, unsigned char *nxt,
+                                           const TileArgs (&ta)[NT], int L, int K, int ax, int ay,
+                                           const double *hsum_s, int g, int n16, double &fsum)
+{
+    floatx4 acc[NT][NH];
+    int ain[NT], aout[NT];
+    bool valid[NT];
+    double hs_base[NT];
+#pragma unroll
+    for (int w = 0; w < NT; ++w) {
+        int p = ta[w].p0 + n16;
+        valid[w] = p < ta[w].npos;
+        p = valid[w] ? p : ta[w].npos - 1;
+        const int v = (int)(((uint32_t)p * ta[w].mul) >> 20);
+        const int u = p - __mul24(v, ta[w].ex);
+        const int u80 = __mul24(u, kSite);
+        // tap (dx, dy) of output (u, v) is window site (u + 1 + dx, v + 1 + dy)
+        ain[w] = __mul24(v, ta[w].p80) + u80 + g * 16;
+        // output goes to W_{k+1} site (u + 2, v + 2)
+        aout[w] = __mul24(v, ta[w].q80) + u80 + 2 * ta[w].q80 + 2 * kSite + g * 16;
+        hs_base[w] = 0.0;
+        if (last) {
+            const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
+            hs_base[w] = hsum_s[site];
+        }
+    }
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int w = 0; w < NT; ++w) {
+            const unsigned char *row = cur + ain[w] + dy * ta[w].p80;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int j = dy * 3 + dx;
+                const bf16x8 bv = *(const bf16x8 *)(row + dx * kSite);
+#pragma unroll
+                for (int hh = 0; hh < NH; ++hh)
+                    acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        wa[j][hh], bv, j == 0 ? bias[hh] : acc[w][hh], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < NT; ++w) {
+        float zv[8], hv[8];
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[w][hh][r];
+        mf::ln_cosh_n<8>(zv, hv);
+        if (!last) {
+            if (valid[w]) {
+                const u32x4 pk = {pack_bf16(hv[0], hv[1]), pack_bf16(hv[2], hv[3]),
+                                  pack_bf16(hv[4], hv[5]), pack_bf16(hv[6], hv[7])};
+                *(u32x4 *)(nxt + aout[w]) = pk;
+            }
+        } else {
+            double part = 0.0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) part += (double)hv[r];
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (g == 0 && valid[w]) fsum += part - hs_base[w];
+        }
+    }
+}
+
+// All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), two at
+// a time, with the layer's weights in `wa`.
+template <bool last>
+__device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
+                                           const unsigned char *cur, unsigned char *nxt, int k,
+                                           int w0, int h0, int L, int K, int ax, int ay,
+                                           const double *hsum_s, int wave, int g, int n16,
+                                           double &fsum)
+{
+    TileArgs a;
+    a.ex = w0 + 2 * k;
+    a.npos = a.ex * (h0 + 2 * k);
+    a.mul = ((1u << 20) + a.ex - 1) / a.ex;
+    a.p80 = (a.ex + kPitchPad) * kSite;        // W_k = R_{k+1}: width ex + 2
+    a.q80 = (a.ex + 2 + kPitchPad) * kSite;    // W_{k+1}: width ex + 4
+    const int ntiles = (a.npos + 15) >> 4;
+    int t = wave;
+    for (; t + kNW < ntiles; t += 2 * kNW) {
+        TileArgs ta[2] = {a, a};
+        ta[0].p0 = t * 16;
+        ta[1].p0 = (t + kNW) * 16;
+        cone_group<last, 2>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
+    }
+    if (t < ntiles) {
+        TileArgs ta[1] = {a};
+        ta[0].p0 = t * 16;
+        cone_group<last, 1>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_net_cone(ConeParams prm)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    __shared__ double red[kNW];
+
+    const int L = prm.L, N = L * L, K = prm.K;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, n16 = lane & 15;
+    const int64_t n_units = min(prm.qlen[0], prm.capacity);
+
+    // XCD-contiguous ranges of the queue
+    const int per_xcd = gridDim.x / kXcd;
+    const int xcd = blockIdx.x % kXcd, slot = blockIdx.x / kXcd;
+    const int64_t seg = (n_units + kXcd - 1) / kXcd;
+    const int64_t u_end = min(n_units, (xcd + 1) * seg);
+
+    bf16x8 wa[KS][NH];
+    floatx4 bias[NH];
+    load_layer(wa, bias, prm, 2, lane, g);
+
+    for (int64_t unit = xcd * seg + slot; unit < u_end; unit += per_xcd) {
+        const uint32_t e = prm.queue[unit];
+        const int s = item_sample(e);
+        const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
+        const int xi = i0 % L, yi = i0 / L;
+        const int qi = i0, qj = wrap_l(yi + bond_dy(tau), L) * L + wrap_l(xi + bond_dx(tau), L);
+        const int ax = xi, ay = (tau == 3) ? wrap_l(yi - 1, L) : yi;
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        const int8_t *sp = prm.spins + (int64_t)s * N;
+        const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
+        const double *hsum_s = prm.hsum + (int64_t)s * N;
+
+        // ---- layer 1 (vector ALU) into W_2 (buffer A), two channels per thread ----
+        {
+            Ring ring;
+            ring_fetch(ring, true, tid, w0 + 2, h0 + 2, 1, ax, ay, L, cache_s);
+            const int ex1 = w0 + 2, ey1 = h0 + 2;
+            const int pos = tid >> 4, m = tid & 15;
+            if (pos < ex1 * ey1) {
+                const int u = pos % ex1, v = pos / ex1;
+                const int gx = wrap_l(ax + u - 1, L), gy = wrap_l(ay + v - 1, L);
+                float sv[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    int site = wrap_l(gy + t / 3 - 1, L) * L + wrap_l(gx + t % 3 - 1, L);
+                    site = (site == qi) ? qj : ((site == qj) ? qi : site);
+                    sv[t] = (float)sp[site];
+                }
+                const float h0v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
+                                                           mf::chan_of_slot<C>(2 * m), sv));
+                const float h1v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
+                                                           mf::chan_of_slot<C>(2 * m + 1), sv));
+                const int p2 = (ex1 + 2) + kPitchPad;    // pitch of W_2
+                *(uint32_t *)(lds + ((v + 2) * p2 + u + 2) * kSite + m * 4) = pack_bf16(h0v, h1v);
+            }
+            ring_store(ring, true, tid, lds, w0 + 2, h0 + 2, 1, ax, ay, L, cache_s);
+        }
+        Ring ring;   // ring of W_{k+1}, fetched one layer ahead
+        ring_fetch(ring, K >= 3, tid, w0 + 4, h0 + 4, 2, ax, ay, L,
+                   cache_s + (int64_t)(K >= 3 ? N * C : 0));
+        __syncthreads();
+
+        double fsum = 0.0;
+        for (int k = 2; k <= K; ++k) {
+            unsigned char *cur = lds + ((k & 1) ? prm.buf_b : 0);
+            unsigned char *nxt = lds + ((k & 1) ? 0 : prm.buf_b);
+            // ring of W_{k+1} into the buffer W_{k-1} occupied, and the ring of
+            // W_{k+2} on its way
+            if (k < K) {
+                ring_store(ring, true, tid, nxt, w0 + 2 * k, h0 + 2 * k, k, ax, ay, L,
+                           cache_s + (int64_t)(k - 1) * N * C);
+                if (k + 1 < K)
+                    ring_fetch(ring, true, tid, w0 + 2 * k + 2, h0 + 2 * k + 2, k + 1, ax, ay, L,
+                               cache_s + (int64_t)k * N * C);
+            }
+            if (k < K)
+                cone_layer<false>(wa, bias, cur, nxt, k, w0, h0, L, K, ax, ay, hsum_s, wave, g,
+                                  n16, fsum);
+            else
+                cone_layer<true>(wa, bias, cur, nxt, k, w0, h0, L, K, ax, ay, hsum_s, wave, g,
+                                 n16, fsum);
+            // weights of the next layer (layer 2 of the next configuration after the last)
+            load_layer(wa, bias, prm, k == K ? 2 : k + 1, lane, g);
+            __syncthreads();
+        }
+
+        for (int off = 32; off > 0; off >>= 1) fsum += __shfl_xor(fsum, off);
+        if (lane == 0) red[wave] = fsum;
+        __syncthreads();
+        if (tid == 0) {
+            double v = 0.0;
+            for (int w = 0; w < kNW; ++w) v += red[w];
+            if (!isfinite(v)) atomicOr(prm.err, kErrNonFinite);
+            prm.dlog[unit] = v;
+        }
+    }
+}
+
+// window pitch (sites) of W_k for a changed box of width w0
+inline int win_pitch(int w0, int k) { return w0 + 2 * k + kPitchPad; }
+
+// bytes of window W_k (rows h0 + 2k + 2, pitch w0 + 2k + 8), largest bond box
+inline size_t win_bytes(int k) { return (size_t)(2 + 2 * k + 2) * win_pitch(2, k) * kSite; }
+
+}  // namespace
+
+bool cone_supported(const nqs_ctx *c)
+{
+    return c->C == 32 && c->K >= 2 && c->L >= 2 * c->K + 4 && mfma_supported(c) &&
+           cone_lds_bytes(c) <= 159 * 1024;
+}
+
+size_t cone_lds_bytes(const nqs_ctx *c)
+{
+    size_t a = 0, b = 0;
+    for (int k = 2; k <= c->K; ++k) ((k & 1) ? b : a) = std::max((k & 1) ? b : a, win_bytes(k));
+    return a + b;
+}
+
+void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
+                  int64_t capacity, const double *hsum, const void *cache, double *dlog,
+                  hipStream_t s)
+{
+    if (capacity <= 0) return;
+    ConeParams p{};
+    p.spins = spins;
+    p.L = c->L;
+    p.K = c->K;
+    p.queue = queue;
+    p.qlen = qlen;
+    p.capacity = capacity;
+    p.wa = (const bf16x8 *)c->w_mfma;
+    p.w1 = c->w_l1;
+    p.bias = c->w_l1 + 9 * C;
+    p.cache = (const uint16_t *)cache;
+    p.hsum = hsum;
+    p.dlog = dlog;
+    p.err = c->err;
+    size_t a = 0;
+    for (int k = 2; k <= c->K; k += 2) a = std::max(a, win_bytes(k));
+    p.buf_b = (int)a;
+    const size_t lds = cone_lds_bytes(c);
+    (void)hipFuncSetAttribute((const void *)k_net_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_net_cone, kThreads,
+                                                     lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    // persistent grid of resident workgroups, a multiple of the XCD count
+    const int64_t want = std::max<int64_t>((int64_t)c->n_cu * per_cu / kXcd * kXcd, kXcd);
+    NQS_LAUNCH(k_net_cone, dim3((unsigned)want), dim3(kThreads), lds, s, p);
+}
+
+}  // namespace nqs

@@ -161,6 +161,12 @@ void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                       const int64_t *qlen, int64_t capacity, const double *hsum,
                       const void *cache, double *dlog, hipStream_t s);
 bool mfma_inc_supported(const nqs_ctx *c);
+// incremental mode, unwrapped windows (k_net_cone.hip): C = 32, L >= 2K + 4
+bool cone_supported(const nqs_ctx *c);
+size_t cone_lds_bytes(const nqs_ctx *c);
+void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
+                  int64_t capacity, const double *hsum, const void *cache, double *dlog,
+                  hipStream_t s);
 
 // --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
 void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const uint32_t *queue,

@@ -24,6 +24,10 @@ CONE_CASES = [
     ("10x10 K4 C16", 10, 0.5, 4, 16, 16, "stress"),
     ("16x16 K6 C32 bj", 16, 0.5, 6, 32, 4, "bj"),
     ("8x8 K2 C16", 8, 0.5, 2, 16, 8, "stress"),
+    # unwrapped-window kernel at its smallest lattice, and with rings larger
+    # than its prefetch registers
+    ("8x8 K2 C32 unwrapped", 8, 0.5, 2, 32, 6, "stress"),
+    ("28x28 K12 C32 ring tail", 28, 0.5, 12, 32, 2, "stress"),
 ]
 
 
