@@ -49,6 +49,7 @@ constexpr int kSite = 80;       // bytes per window site
 constexpr int kPitchPad = 8;    // window pitch = width(R_k) + kPitchPad
 constexpr int kChunks = 4;      // 16-byte chunks of channels per site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
+constexpr int kMaxK = 16;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte chunk
@@ -68,6 +69,8 @@ struct ConeParams {
     double *dlog;
     int32_t *err;
     int buf_b;                 // byte offset of the odd-layer window buffer
+    const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
+    int ring_off[4][kMaxK];    // [tau][k - 1]: first entry of the ring of W_{k+1}; [tau][K-1]: end
 };
 
 __device__ __forceinline__ int wrap_l(int a, int L)
@@ -87,61 +90,64 @@ struct Ring {
     int dst[kRingRegs];        // byte address in the window buffer, -1: none
 };
 
-// Ring of W_{k+1} = R_{k+2} minus R_k for an R_k of ex x ey sites: the
-// window's two top rows, two bottom rows, and the two left and two right
-// columns of the ey middle rows; site i of that list as window coordinates.
-__device__ __forceinline__ int2 ring_site(int i, int ex, int ey)
-{
-    const int nex = ex + 4;
-    const int band = (i >= nex) + (i >= 2 * nex) + (i >= 3 * nex);
-    const int j = i - 4 * nex, c = j & 3;
-    const bool bands = i < 4 * nex;
-    // rows 0, 1, ey + 2, ey + 3 in full; columns 0, 1, ex + 2, ex + 3 between
-    const int wu = bands ? i - band * nex : (c < 2 ? c : ex + c);
-    const int wv = bands ? (band < 2 ? band : ey + band) : 2 + (j >> 2);
-    return make_int2(wu, wv);
-}
+// This thread's ring-table entries (one per prefetched chunk), -1: none.
+struct RingTab {
+    int ent[kRingRegs];
+};
 
-// Chunk q of the ring of W_{k+1}: source address in the layer-k cache and
-// byte address in the window (pitch P_{k+1} = ex + 2 + kPitchPad sites).
-// (.x: element offset in the layer cache, .y: byte offset in the window)
-__device__ __forceinline__ int2 ring_chunk(int q, int ex, int ey, int k, int ax, int ay, int L)
+// Table entries of the ring of W_{k+1} (entries [e0, e1) of the table, one
+// per site): chunk q = lt + i * kThreads reads entry e0 + q / 4.
+__device__ __forceinline__ void ring_tab_load(RingTab &t, const ConeParams &p, bool live, int e0,
+                                              int e1, int lt)
 {
-    const int2 w = ring_site(q >> 2, ex, ey);
-    const int c = q & 3;
-    const int x = wrap_l(ax + w.x - (k + 2), L), y = wrap_l(ay + w.y - (k + 2), L);
-    return make_int2((y * L + x) * C + c * 8, (w.y * (ex + 2 + kPitchPad) + w.x) * kSite + c * 16);
-}
-
-// Issue the loads of the first kRingRegs * kThreads chunks of the ring of
-// W_{k+1} (R_k of ex x ey).  Loads are unconditional (surplus lanes re-read
-// chunk 0) so that the outstanding-load count stays exact.
-__device__ __forceinline__ void ring_fetch(Ring &r, bool item_live, int lt, int ex, int ey, int k,
-                                           int ax, int ay, int L, const uint16_t *layer_cache)
-{
-    const int total = (4 * (ex + ey) + 16) * kChunks;
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i) {
-        const int q0 = lt + i * kThreads;
-        const bool live = item_live && q0 < total;
-        const int2 sd = ring_chunk(live ? q0 : 0, ex, ey, k, ax, ay, L);
-        r.v[i] = *(const u32x4 *)(layer_cache + sd.x);
+        const int q = lt + i * kThreads;
+        const bool ok = live && q < (e1 - e0) * kChunks;
+        const int e = p.ring[ok ? e0 + (q >> 2) : 0];
+        t.ent[i] = ok ? e : -1;
+    }
+}
+
+// Chunk c of ring entry `ent` (window index | (du mod L) << 16 | (dv mod L) << 24,
+// offsets from the anchor): .x element offset in the layer cache, .y byte
+// offset in the window.
+__device__ __forceinline__ int2 ring_chunk(int ent, int c, int ax, int ay, int L)
+{
+    uint32_t x = (uint32_t)(ax + ((ent >> 16) & 255));
+    uint32_t y = (uint32_t)(ay + ((uint32_t)ent >> 24));
+    x = min(x, x - (uint32_t)L);        // x, y < 2L: one conditional period
+    y = min(y, y - (uint32_t)L);
+    return make_int2((int)(__umul24(y, (uint32_t)L) + x) * C + c * 8,
+                     (int)__umul24((uint32_t)(ent & 0xffff), (uint32_t)kSite) + c * 16);
+}
+
+// Issue the loads of the prefetched ring chunks named by `t`.
+__device__ __forceinline__ void ring_fetch(Ring &r, const RingTab &t, int lt, int ax, int ay, int L,
+                                           const uint16_t *layer_cache)
+{
+#pragma unroll
+    for (int i = 0; i < kRingRegs; ++i) {
+        const bool live = t.ent[i] >= 0;
+        const int2 sd = ring_chunk(live ? t.ent[i] : 0, lt & 3, ax, ay, L);
+        r.v[i] = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
         r.dst[i] = live ? sd.y : -1;
     }
 }
 
-// Store the fetched chunks, then copy any chunks beyond them directly.
-__device__ __forceinline__ void ring_store(const Ring &r, bool item_live, int lt, unsigned char *buf,
-                                           int ex, int ey, int k, int ax, int ay, int L,
-                                           const uint16_t *layer_cache)
+// Store the fetched chunks, then copy any chunks of entries [e0, e1) beyond
+// them directly.
+__device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, int lt,
+                                           unsigned char *buf, int e0, int e1, int ax, int ay,
+                                           int L, const uint16_t *layer_cache)
 {
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i)
         if (r.dst[i] >= 0) *(u32x4 *)(buf + r.dst[i]) = r.v[i];
-    const int total = item_live ? (4 * (ex + ey) + 16) * kChunks : 0;
+    const int total = (e1 - e0) * kChunks;
     for (int q = lt + kRingRegs * kThreads; q < total; q += kThreads) {
-        const int2 sd = ring_chunk(q, ex, ey, k, ax, ay, L);
-        *(u32x4 *)(buf + sd.y) = *(const u32x4 *)(layer_cache + sd.x);
+        const int2 sd = ring_chunk(p.ring[e0 + (q >> 2)], q & 3, ax, ay, L);
+        *(u32x4 *)(buf + sd.y) = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
     }
 }
 
@@ -303,10 +309,15 @@ k_net_cone(ConeParams prm)
         const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
         const double *hsum_s = prm.hsum + (int64_t)s * N;
 
+        const int *roff = prm.ring_off[tau];
+
         // ---- layer 1 (vector ALU) into W_2 (buffer A), two channels per thread ----
+        RingTab tab;
         {
+            ring_tab_load(tab, prm, true, roff[0], roff[1], tid);
             Ring ring;
-            ring_fetch(ring, true, tid, w0 + 2, h0 + 2, 1, ax, ay, L, cache_s);
+            ring_fetch(ring, tab, tid, ax, ay, L, cache_s);
+            ring_tab_load(tab, prm, K >= 3, roff[1], roff[K >= 3 ? 2 : 1], tid);
             const int ex1 = w0 + 2, ey1 = h0 + 2;
             const int pos = tid >> 4, m = tid & 15;
             if (pos < ex1 * ey1) {
@@ -326,25 +337,29 @@ k_net_cone(ConeParams prm)
                 const int p2 = (ex1 + 2) + kPitchPad;    // pitch of W_2
                 *(uint32_t *)(lds + ((v + 2) * p2 + u + 2) * kSite + m * 4) = pack_bf16(h0v, h1v);
             }
-            ring_store(ring, true, tid, lds, w0 + 2, h0 + 2, 1, ax, ay, L, cache_s);
+            ring_store(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, cache_s);
         }
-        Ring ring;   // ring of W_{k+1}, fetched one layer ahead
-        ring_fetch(ring, K >= 3, tid, w0 + 4, h0 + 4, 2, ax, ay, L,
-                   cache_s + (int64_t)(K >= 3 ? N * C : 0));
+        // ring of W_{k+1}, fetched one layer ahead; its table entries two ahead
+        Ring ring;
+        ring_fetch(ring, tab, tid, ax, ay, L, cache_s + (int64_t)(K >= 3 ? N * C : 0));
+        ring_tab_load(tab, prm, K >= 4, roff[K >= 4 ? 2 : 0], roff[K >= 4 ? 3 : 0], tid);
         __syncthreads();
 
         double fsum = 0.0;
         for (int k = 2; k <= K; ++k) {
             unsigned char *cur = lds + ((k & 1) ? prm.buf_b : 0);
             unsigned char *nxt = lds + ((k & 1) ? 0 : prm.buf_b);
-            // ring of W_{k+1} into the buffer W_{k-1} occupied, and the ring of
-            // W_{k+2} on its way
+            // ring of W_{k+1} into the buffer W_{k-1} occupied, the ring of
+            // W_{k+2} on its way, and the table entries of the ring of W_{k+3}
             if (k < K) {
-                ring_store(ring, true, tid, nxt, w0 + 2 * k, h0 + 2 * k, k, ax, ay, L,
+                ring_store(ring, prm, tid, nxt, roff[k - 1], roff[k], ax, ay, L,
                            cache_s + (int64_t)(k - 1) * N * C);
-                if (k + 1 < K)
-                    ring_fetch(ring, true, tid, w0 + 2 * k + 2, h0 + 2 * k + 2, k + 1, ax, ay, L,
-                               cache_s + (int64_t)k * N * C);
+                if (k + 1 < K) {
+                    ring_fetch(ring, tab, tid, ax, ay, L, cache_s + (int64_t)k * N * C);
+                    const bool more = k + 2 < K;
+                    ring_tab_load(tab, prm, more, roff[more ? k + 1 : 0], roff[more ? k + 2 : 0],
+                                  tid);
+                }
             }
             if (k < K)
                 cone_layer<false>(wa, bias, cur, nxt, k, w0, h0, L, K, ax, ay, hsum_s, wave, g,
@@ -390,6 +405,40 @@ size_t cone_lds_bytes(const nqs_ctx *c)
     return a + b;
 }
 
+// Ring tables of the unwrapped geometry: for bond type tau and k = 1..K-1 the
+// sites of W_{k+1} = R_{k+2} outside R_k, as (index in W_{k+1}, whose pitch is
+// P_{k+1}) | (offset from the anchor modulo L) << 16 (x) and << 24 (y).
+nqs_status cone_build_ring_tables(nqs_ctx *c)
+{
+    const int L = c->L, K = c->K;
+    std::vector<int32_t> ent;
+    c->cone_off.assign((size_t)4 * kMaxK, 0);
+    for (int tau = 0; tau < 4; ++tau) {
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        for (int k = 1; k < K; ++k) {
+            c->cone_off[(size_t)tau * kMaxK + (k - 1)] = (int)ent.size();
+            const int ex = w0 + 2 * k, ey = h0 + 2 * k;
+            const int pitch = win_pitch(w0, k + 1);
+            for (int wv = 0; wv < ey + 4; ++wv)
+                for (int wu = 0; wu < ex + 4; ++wu) {
+                    if (wu >= 2 && wu < 2 + ex && wv >= 2 && wv < 2 + ey) continue;   // R_k
+                    const int du = wu - (k + 2), dv = wv - (k + 2);
+                    const int dum = ((du % L) + L) % L, dvm = ((dv % L) + L) % L;
+                    ent.push_back((wv * pitch + wu) | (dum << 16) | (dvm << 24));
+                }
+        }
+        c->cone_off[(size_t)tau * kMaxK + (K - 1)] = (int)ent.size();
+    }
+    if (c->cone_tab) (void)hipFree(c->cone_tab);
+    c->cone_tab = nullptr;
+    if (hipMalloc((void **)&c->cone_tab, std::max<size_t>(ent.size(), 1) * 4) != hipSuccess)
+        return NQS_E_NOMEM;
+    if (!ent.empty() &&
+        hipMemcpy(c->cone_tab, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return NQS_E_HIP;
+    return NQS_OK;
+}
+
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,
                   hipStream_t s)
@@ -409,6 +458,9 @@ void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, 
     p.hsum = hsum;
     p.dlog = dlog;
     p.err = c->err;
+    p.ring = c->cone_tab;
+    for (int t = 0; t < 4; ++t)
+        for (int k = 0; k < kMaxK; ++k) p.ring_off[t][k] = c->cone_off[(size_t)t * kMaxK + k];
     size_t a = 0;
     for (int k = 2; k <= c->K; k += 2) a = std::max(a, win_bytes(k));
     p.buf_b = (int)a;

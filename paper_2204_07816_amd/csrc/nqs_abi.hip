@@ -145,6 +145,8 @@ nqs_status pack_weights(nqs_ctx *c)
         if ((st = upload(c->w_mfma, wm)) != NQS_OK) return st;
         if ((st = upload(c->w_l1, l1)) != NQS_OK) return st;
         if (!c->ring_tab && (st = mfma_build_ring_tables(c)) != NQS_OK) return st;
+        if (cone_supported(c) && !c->cone_tab && (st = cone_build_ring_tables(c)) != NQS_OK)
+            return st;
     }
     return NQS_OK;
 }
@@ -405,6 +407,7 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->w_l1);
     free_dev(c->ring_tab);
     free_dev(c->ring_off);
+    free_dev(c->cone_tab);
     free_dev(c->err);
     DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
                       &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,

@@ -73,6 +73,8 @@ struct nqs_ctx {
     float *w_l1 = nullptr;        // layer-1 weights + all biases, FP32, MFMA path
     int32_t *ring_tab = nullptr;  // incremental mode: ring lists per bond type and layer
     int32_t *ring_off = nullptr;
+    int32_t *cone_tab = nullptr;  // same, for the unwrapped-window kernel
+    std::vector<int> cone_off;    // [4][16] entry offsets of cone_tab
     // workspace
     nqs::Workspace ws;
     int32_t *err = nullptr;       // device sticky error word
@@ -164,6 +166,7 @@ bool mfma_inc_supported(const nqs_ctx *c);
 // incremental mode, unwrapped windows (k_net_cone.hip): C = 32, L >= 2K + 4
 bool cone_supported(const nqs_ctx *c);
 size_t cone_lds_bytes(const nqs_ctx *c);
+nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,
                   hipStream_t s);
