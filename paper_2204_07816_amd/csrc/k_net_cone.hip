@@ -14,15 +14,16 @@
 // not reach cancel exactly.
 //
 // What the unwrapped geometry buys:
-//  * window W_k is a plain rectangle with row pitch P_k = width(R_k) + 8.
-//    Output positions are enumerated row-major over R_k, so the sites read by
-//    the 16 lanes of a tile are consecutive modulo 8 even across a row end;
-//    with 80-byte sites (64 B of channels + 16 B pad) the 16-byte LDS reads of
-//    any 8 lanes then fall in distinct bank groups.
+//  * window W_k is a plain rectangle, stored as four channel planes (plane c
+//    holds channels 8c..8c+7 of every site, 16 bytes per site, rows of the
+//    window's width).  The 16 lanes of an MFMA lane group read one plane at 16
+//    consecutive output positions, so within a row they read 256 contiguous
+//    bytes; without padding the two windows of K = 8 take 46 KB, which leaves
+//    room for three workgroups per CU.
 //  * a tap's LDS address is a per-tile row base plus a compile-time column
 //    offset, so the nine reads of a tile cost two adds.
-//  * the ring W_{k+1} minus R_k is a rectangular annulus two sites wide whose
-//    addresses are computed, not looked up, so its loads issue at once; the
+//  * the ring W_{k+1} minus R_k (an annulus two sites wide) is listed per bond
+//    type in a small table whose entries are loaded two layers ahead; the
 //    ring of W_{k+2} is fetched at the start of layer k and stored at the
 //    start of layer k + 1, a whole layer ahead of its use.
 //  * layer 1 is spread over all threads (two channels each).
@@ -44,9 +45,8 @@ constexpr int KS = 9;           // K-steps (one tap of 32 channels each)
 constexpr int NH = 2;           // 16-channel output halves
 constexpr int kNW = 4;
 constexpr int kThreads = kNW * 64;
-constexpr int kRingRegs = 3;
-constexpr int kSite = 80;       // bytes per window site
-constexpr int kPitchPad = 8;    // window pitch = width(R_k) + kPitchPad
+constexpr int kRingRegs = 2;
+constexpr int kChunk = 16;      // bytes of one 8-channel chunk of a site
 constexpr int kChunks = 4;      // 16-byte chunks of channels per site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
 constexpr int kMaxK = 16;
@@ -68,7 +68,8 @@ struct ConeParams {
     const double *hsum;        // base-pass per-site channel sums of layer K [B][N]
     double *dlog;
     int32_t *err;
-    int buf_b;                 // byte offset of the odd-layer window buffer
+    int ps_a, ps_b;            // plane strides (bytes) of the even- and odd-layer buffers
+    int buf_b;                 // byte offset of the odd-layer buffer (4 planes of ps_a)
     const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
     int ring_off[4][kMaxK];    // [tau][k - 1]: first entry of the ring of W_{k+1}; [tau][K-1]: end
 };
@@ -111,25 +112,25 @@ __device__ __forceinline__ void ring_tab_load(RingTab &t, const ConeParams &p, b
 
 // Chunk c of ring entry `ent` (window index | (du mod L) << 16 | (dv mod L) << 24,
 // offsets from the anchor): .x element offset in the layer cache, .y byte
-// offset in the window.
-__device__ __forceinline__ int2 ring_chunk(int ent, int c, int ax, int ay, int L)
+// offset in the window buffer of plane stride ps.
+__device__ __forceinline__ int2 ring_chunk(int ent, int c, int ax, int ay, int L, int ps)
 {
     uint32_t x = (uint32_t)(ax + ((ent >> 16) & 255));
     uint32_t y = (uint32_t)(ay + ((uint32_t)ent >> 24));
     x = min(x, x - (uint32_t)L);        // x, y < 2L: one conditional period
     y = min(y, y - (uint32_t)L);
     return make_int2((int)(__umul24(y, (uint32_t)L) + x) * C + c * 8,
-                     (int)__umul24((uint32_t)(ent & 0xffff), (uint32_t)kSite) + c * 16);
+                     (int)__umul24((uint32_t)c, (uint32_t)ps) + (ent & 0xffff) * kChunk);
 }
 
 // Issue the loads of the prefetched ring chunks named by `t`.
 __device__ __forceinline__ void ring_fetch(Ring &r, const RingTab &t, int lt, int ax, int ay, int L,
-                                           const uint16_t *layer_cache)
+                                           int ps, const uint16_t *layer_cache)
 {
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i) {
         const bool live = t.ent[i] >= 0;
-        const int2 sd = ring_chunk(live ? t.ent[i] : 0, lt & 3, ax, ay, L);
+        const int2 sd = ring_chunk(live ? t.ent[i] : 0, lt & 3, ax, ay, L, ps);
         r.v[i] = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
         r.dst[i] = live ? sd.y : -1;
     }
@@ -139,14 +140,14 @@ __device__ __forceinline__ void ring_fetch(Ring &r, const RingTab &t, int lt, in
 // them directly.
 __device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, int lt,
                                            unsigned char *buf, int e0, int e1, int ax, int ay,
-                                           int L, const uint16_t *layer_cache)
+                                           int L, int ps, const uint16_t *layer_cache)
 {
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i)
         if (r.dst[i] >= 0) *(u32x4 *)(buf + r.dst[i]) = r.v[i];
     const int total = (e1 - e0) * kChunks;
     for (int q = lt + kRingRegs * kThreads; q < total; q += kThreads) {
-        const int2 sd = ring_chunk(p.ring[e0 + (q >> 2)], q & 3, ax, ay, L);
+        const int2 sd = ring_chunk(p.ring[e0 + (q >> 2)], q & 3, ax, ay, L, ps);
         *(u32x4 *)(buf + sd.y) = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
     }
 }
@@ -171,8 +172,9 @@ __device__ __forceinline__ void load_layer(bf16x8 (&wa)[KS][NH], floatx4 (&bias)
 struct TileArgs {
     int p0, npos, ex;
     uint32_t mul;              // ceil(2^20 / ex): p / ex = (p * mul) >> 20, exact for ex <= 64, p < 66 ex
-    int p80;                   // row pitch of W_k in bytes
-    int q80;                   // row pitch of W_{k+1} in bytes
+    int p16;                   // row pitch of W_k in bytes (within a plane)
+    int q16;                   // row pitch of W_{k+1} in bytes
+    int psc, psn;              // plane strides of the buffers of W_k and W_{k+1}
 };
 
 // NT tiles of one layer.  Inner layers store the BF16 activations into
@@ -194,11 +196,12 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
         p = valid[w] ? p : ta[w].npos - 1;
         const int v = (int)(((uint32_t)p * ta[w].mul) >> 20);
         const int u = p - __mul24(v, ta[w].ex);
-        const int u80 = __mul24(u, kSite);
-        // tap (dx, dy) of output (u, v) is window site (u + 1 + dx, v + 1 + dy)
-        ain[w] = __mul24(v, ta[w].p80) + u80 + g * 16;
+        const int u16 = u * kChunk;
+        // tap (dx, dy) of output (u, v) is window site (u + 1 + dx, v + 1 + dy);
+        // lane group g reads plane g
+        ain[w] = __mul24(g, ta[w].psc) + __mul24(v, ta[w].p16) + u16;
         // output goes to W_{k+1} site (u + 2, v + 2)
-        aout[w] = __mul24(v, ta[w].q80) + u80 + 2 * ta[w].q80 + 2 * kSite + g * 16;
+        aout[w] = __mul24(g, ta[w].psn) + __mul24(v + 2, ta[w].q16) + u16 + 2 * kChunk;
         hs_base[w] = 0.0;
         if (last) {
             const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
@@ -209,11 +212,11 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
     for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
         for (int w = 0; w < NT; ++w) {
-            const unsigned char *row = cur + ain[w] + dy * ta[w].p80;
+            const unsigned char *row = cur + ain[w] + dy * ta[w].p16;
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const int j = dy * 3 + dx;
-                const bf16x8 bv = *(const bf16x8 *)(row + dx * kSite);
+                const bf16x8 bv = *(const bf16x8 *)(row + dx * kChunk);
 #pragma unroll
                 for (int hh = 0; hh < NH; ++hh)
                     acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
@@ -246,37 +249,35 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
     }
 }
 
-// All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), two at
-// a time, with the layer's weights in `wa`.
+// All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), one at
+// a time (three workgroups per CU supply the parallelism a second tile in
+// flight would), with the layer's weights in `wa`.
 template <bool last>
 __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
-                                           const unsigned char *cur, unsigned char *nxt, int k,
-                                           int w0, int h0, int L, int K, int ax, int ay,
-                                           const double *hsum_s, int wave, int g, int n16,
+                                           const unsigned char *cur, unsigned char *nxt, int psc,
+                                           int psn, int k, int w0, int h0, int L, int K, int ax,
+                                           int ay, const double *hsum_s, int wave, int g, int n16,
                                            double &fsum)
 {
     TileArgs a;
     a.ex = w0 + 2 * k;
     a.npos = a.ex * (h0 + 2 * k);
     a.mul = ((1u << 20) + a.ex - 1) / a.ex;
-    a.p80 = (a.ex + kPitchPad) * kSite;        // W_k = R_{k+1}: width ex + 2
-    a.q80 = (a.ex + 2 + kPitchPad) * kSite;    // W_{k+1}: width ex + 4
+    a.p16 = (a.ex + 2) * kChunk;               // W_k = R_{k+1}: width ex + 2
+    a.q16 = (a.ex + 4) * kChunk;               // W_{k+1}: width ex + 4
+    a.psc = psc;
+    a.psn = psn;
     const int ntiles = (a.npos + 15) >> 4;
     int t = wave;
-    for (; t + kNW < ntiles; t += 2 * kNW) {
-        TileArgs ta[2] = {a, a};
-        ta[0].p0 = t * 16;
-        ta[1].p0 = (t + kNW) * 16;
-        cone_group<last, 2>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
-    }
-    if (t < ntiles) {
+    for (; t < ntiles; t += kNW) {
         TileArgs ta[1] = {a};
         ta[0].p0 = t * 16;
         cone_group<last, 1>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
     }
 }
 
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// Three workgroups per CU: 166 VGPRs and 46 KB of LDS (K = 8) each.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_net_cone(ConeParams prm)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -316,7 +317,7 @@ k_net_cone(ConeParams prm)
         {
             ring_tab_load(tab, prm, true, roff[0], roff[1], tid);
             Ring ring;
-            ring_fetch(ring, tab, tid, ax, ay, L, cache_s);
+            ring_fetch(ring, tab, tid, ax, ay, L, prm.ps_a, cache_s);
             ring_tab_load(tab, prm, K >= 3, roff[1], roff[K >= 3 ? 2 : 1], tid);
             const int ex1 = w0 + 2, ey1 = h0 + 2;
             const int pos = tid >> 4, m = tid & 15;
@@ -334,14 +335,15 @@ k_net_cone(ConeParams prm)
                                                            mf::chan_of_slot<C>(2 * m), sv));
                 const float h1v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
                                                            mf::chan_of_slot<C>(2 * m + 1), sv));
-                const int p2 = (ex1 + 2) + kPitchPad;    // pitch of W_2
-                *(uint32_t *)(lds + ((v + 2) * p2 + u + 2) * kSite + m * 4) = pack_bf16(h0v, h1v);
+                const int p2 = ex1 + 4;                  // pitch of W_2 (its width)
+                *(uint32_t *)(lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk +
+                              (m & 3) * 4) = pack_bf16(h0v, h1v);
             }
-            ring_store(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, cache_s);
+            ring_store(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, prm.ps_a, cache_s);
         }
         // ring of W_{k+1}, fetched one layer ahead; its table entries two ahead
         Ring ring;
-        ring_fetch(ring, tab, tid, ax, ay, L, cache_s + (int64_t)(K >= 3 ? N * C : 0));
+        ring_fetch(ring, tab, tid, ax, ay, L, prm.ps_b, cache_s + (int64_t)(K >= 3 ? N * C : 0));
         ring_tab_load(tab, prm, K >= 4, roff[K >= 4 ? 2 : 0], roff[K >= 4 ? 3 : 0], tid);
         __syncthreads();
 
@@ -349,24 +351,27 @@ k_net_cone(ConeParams prm)
         for (int k = 2; k <= K; ++k) {
             unsigned char *cur = lds + ((k & 1) ? prm.buf_b : 0);
             unsigned char *nxt = lds + ((k & 1) ? 0 : prm.buf_b);
+            const int psc = (k & 1) ? prm.ps_b : prm.ps_a;
+            const int psn = (k & 1) ? prm.ps_a : prm.ps_b;
             // ring of W_{k+1} into the buffer W_{k-1} occupied, the ring of
             // W_{k+2} on its way, and the table entries of the ring of W_{k+3}
             if (k < K) {
-                ring_store(ring, prm, tid, nxt, roff[k - 1], roff[k], ax, ay, L,
+                ring_store(ring, prm, tid, nxt, roff[k - 1], roff[k], ax, ay, L, psn,
                            cache_s + (int64_t)(k - 1) * N * C);
                 if (k + 1 < K) {
-                    ring_fetch(ring, tab, tid, ax, ay, L, cache_s + (int64_t)k * N * C);
+                    // W_{k+2} lives in the buffer of W_k
+                    ring_fetch(ring, tab, tid, ax, ay, L, psc, cache_s + (int64_t)k * N * C);
                     const bool more = k + 2 < K;
                     ring_tab_load(tab, prm, more, roff[more ? k + 1 : 0], roff[more ? k + 2 : 0],
                                   tid);
                 }
             }
             if (k < K)
-                cone_layer<false>(wa, bias, cur, nxt, k, w0, h0, L, K, ax, ay, hsum_s, wave, g,
-                                  n16, fsum);
+                cone_layer<false>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
+                                  wave, g, n16, fsum);
             else
-                cone_layer<true>(wa, bias, cur, nxt, k, w0, h0, L, K, ax, ay, hsum_s, wave, g,
-                                 n16, fsum);
+                cone_layer<true>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
+                                 wave, g, n16, fsum);
             // weights of the next layer (layer 2 of the next configuration after the last)
             load_layer(wa, bias, prm, k == K ? 2 : k + 1, lane, g);
             __syncthreads();
@@ -384,11 +389,21 @@ k_net_cone(ConeParams prm)
     }
 }
 
-// window pitch (sites) of W_k for a changed box of width w0
-inline int win_pitch(int w0, int k) { return w0 + 2 * k + kPitchPad; }
+// row pitch (sites) of window W_k for a changed box of width w0: its width
+inline int win_pitch(int w0, int k) { return w0 + 2 * k + 2; }
 
-// bytes of window W_k (rows h0 + 2k + 2, pitch w0 + 2k + 8), largest bond box
-inline size_t win_bytes(int k) { return (size_t)(2 + 2 * k + 2) * win_pitch(2, k) * kSite; }
+// bytes of one channel plane of window W_k for the largest bond box (2 x 2)
+inline int plane_bytes(int k) { return (2 * k + 4) * win_pitch(2, k) * kChunk; }
+
+// plane strides of the even- and odd-layer buffers
+inline void plane_strides(int K, int *ps_a, int *ps_b)
+{
+    *ps_a = *ps_b = 0;
+    for (int k = 2; k <= K; ++k) {
+        int &ps = (k & 1) ? *ps_b : *ps_a;
+        ps = std::max(ps, plane_bytes(k));
+    }
+}
 
 }  // namespace
 
@@ -400,9 +415,9 @@ bool cone_supported(const nqs_ctx *c)
 
 size_t cone_lds_bytes(const nqs_ctx *c)
 {
-    size_t a = 0, b = 0;
-    for (int k = 2; k <= c->K; ++k) ((k & 1) ? b : a) = std::max((k & 1) ? b : a, win_bytes(k));
-    return a + b;
+    int a, b;
+    plane_strides(c->K, &a, &b);
+    return (size_t)kChunks * (a + b);
 }
 
 // Ring tables of the unwrapped geometry: for bond type tau and k = 1..K-1 the
@@ -461,9 +476,8 @@ void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, 
     p.ring = c->cone_tab;
     for (int t = 0; t < 4; ++t)
         for (int k = 0; k < kMaxK; ++k) p.ring_off[t][k] = c->cone_off[(size_t)t * kMaxK + k];
-    size_t a = 0;
-    for (int k = 2; k <= c->K; k += 2) a = std::max(a, win_bytes(k));
-    p.buf_b = (int)a;
+    plane_strides(c->K, &p.ps_a, &p.ps_b);
+    p.buf_b = kChunks * p.ps_a;
     const size_t lds = cone_lds_bytes(c);
     (void)hipFuncSetAttribute((const void *)k_net_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
