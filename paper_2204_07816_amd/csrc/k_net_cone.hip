@@ -249,6 +249,10 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
     }
 }
 
+// Waves that work on a layer of ntiles tiles: small layers go to two waves, so
+// that the other two need not fetch that layer's weights.
+__device__ __forceinline__ int active_waves(int ntiles) { return ntiles <= 8 ? 2 : kNW; }
+
 // All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), one at
 // a time (three workgroups per CU supply the parallelism a second tile in
 // flight would), with the layer's weights in `wa`.
@@ -268,8 +272,10 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
     a.psc = psc;
     a.psn = psn;
     const int ntiles = (a.npos + 15) >> 4;
+    const int nw = active_waves(ntiles);
+    if (wave >= nw) return;
     int t = wave;
-    for (; t < ntiles; t += kNW) {
+    for (; t < ntiles; t += nw) {
         TileArgs ta[1] = {a};
         ta[0].p0 = t * 16;
         cone_group<last, 1>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
@@ -284,7 +290,8 @@ k_net_cone(ConeParams prm)
     __shared__ double red[kNW];
 
     const int L = prm.L, N = L * L, K = prm.K;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int g = lane >> 4, n16 = lane & 15;
     const int64_t n_units = min(prm.qlen[0], prm.capacity);
 
@@ -372,8 +379,11 @@ k_net_cone(ConeParams prm)
             else
                 cone_layer<true>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
                                  wave, g, n16, fsum);
-            // weights of the next layer (layer 2 of the next configuration after the last)
-            load_layer(wa, bias, prm, k == K ? 2 : k + 1, lane, g);
+            // weights of the next layer (layer 2 of the next configuration after the
+            // last, whose bond type is not known yet), if this wave works on it
+            const int kn = k == K ? 2 : k + 1;
+            const int nt_next = ((w0 + 2 * kn) * (h0 + 2 * kn) + 15) >> 4;
+            if (k == K || wave < active_waves(nt_next)) load_layer(wa, bias, prm, kn, lane, g);
             __syncthreads();
         }
 
