@@ -99,22 +99,44 @@ struct Params {
     int32_t *err;
 };
 
+// Up to kMaxConnJobs lattices (contexts of one network shape) in one launch of
+// an exchanged-configuration mode: their queue items form one index space, job
+// after job.  The base pass is always a single job.
+struct NetJobs {
+    Params job[kMaxConnJobs];
+    int n;
+};
+
 template <int C, int NW, int MAXT>
 __global__ void __launch_bounds__(NW * 64)
-k_net(Params prm)
+k_net(NetJobs jobs)
 {
     using S = Shape<C>;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ double red[NW];
 
-    const int L = prm.L, N = L * L, K = prm.K;
+    const int K = jobs.job[0].K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, n16 = lane & 15;
-    const bool base = prm.mode == kBase;
-    const bool full = prm.mode != kIncr;
+    const bool base = jobs.job[0].mode == kBase;
+    const bool full = jobs.job[0].mode != kIncr;
 
-    int64_t n_units = base ? prm.B : min(prm.qlen[0], prm.capacity);
-    for (int64_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+    // first item of each job in the common index space
+    int64_t first[kMaxConnJobs + 1];
+    first[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxConnJobs; ++j)
+        first[j + 1] = first[j] + (j >= jobs.n ? 0
+                                               : (base ? jobs.job[j].B
+                                                       : min(jobs.job[j].qlen[0], jobs.job[j].capacity)));
+    const int64_t n_units = first[kMaxConnJobs];
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        int jb = 0;
+#pragma unroll
+        for (int j = 1; j < kMaxConnJobs; ++j) jb = (u >= first[j]) ? j : jb;
+        const Params &prm = jobs.job[jb];
+        const int64_t unit = u - first[jb];
+        const int L = prm.L, N = L * L;
         // ---- geometry of the work item ----
         int s, x0 = 0, y0 = 0, w0 = 1, h0 = 1, qi = -1, qj = -1;
         if (base) {
@@ -360,7 +382,7 @@ bool pick_variant(const nqs_ctx *c, bool full, Variant *v, size_t *lds)
 }
 
 template <int C>
-void launch_variant(const Variant &v, dim3 grid, size_t lds, const Params &p, hipStream_t s)
+void launch_variant(const Variant &v, dim3 grid, size_t lds, const NetJobs &p, hipStream_t s)
 {
 #define NQS_NET(NW, MT)                                                                      \
     if (v.nw == NW && v.maxt == MT) {                                                        \
@@ -377,15 +399,29 @@ void launch_variant(const Variant &v, dim3 grid, size_t lds, const Params &p, hi
 #undef NQS_NET
 }
 
-void launch(const nqs_ctx *c, bool full, dim3 grid, const Params &p, hipStream_t s)
+// One launch over jobs [0, n): the variant (waves, tiles per wave, LDS) is the
+// one of the largest lattice, which covers the smaller ones.
+void launch(const nqs_ctx *const *ctxs, int n, bool full, dim3 grid, const NetJobs &p,
+            hipStream_t s)
 {
+    int big = 0;
+    for (int i = 1; i < n; ++i)
+        if (ctxs[i]->L > ctxs[big]->L) big = i;
     Variant v;
     size_t lds;
-    if (!pick_variant(c, full, &v, &lds)) return;
-    if (c->C == 32)
+    if (!pick_variant(ctxs[big], full, &v, &lds)) return;
+    if (ctxs[big]->C == 32)
         launch_variant<32>(v, grid, lds, p, s);
     else
         launch_variant<16>(v, grid, lds, p, s);
+}
+
+void launch(const nqs_ctx *c, bool full, dim3 grid, const Params &p, hipStream_t s)
+{
+    NetJobs jp{};
+    jp.job[0] = p;
+    jp.n = 1;
+    launch(&c, 1, full, grid, jp, s);
 }
 
 Params common(const nqs_ctx *c, const int8_t *spins, int mode)
@@ -443,6 +479,39 @@ void mfma_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, 
     launch(c, true, dim3(grid), p, s);
 }
 
+void mfma_conn_forward_jobs(nqs_mode mode, const ConnJob *jobs, int n, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (mode == NQS_INCREMENTAL) {
+        bool cone = true;
+        for (int i = 0; i < n; ++i) cone = cone && cone_supported(jobs[i].c);
+        if (cone)
+            cone_forward_jobs(jobs, n, s);
+        else
+            mfma_inc_forward_jobs(jobs, n, s);
+        return;
+    }
+    NetJobs jp{};
+    jp.n = n;
+    const nqs_ctx *ctxs[kMaxConnJobs];
+    int64_t total_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        ctxs[i] = jobs[i].c;
+        Params &p = jp.job[i];
+        p = common(jobs[i].c, jobs[i].spins, kFull);
+        p.queue = jobs[i].queue;
+        p.qlen = jobs[i].qlen;
+        p.capacity = jobs[i].capacity;
+        p.cache_in = (const uint16_t *)jobs[i].cache;
+        p.hsum_in = jobs[i].hsum;
+        p.dlog = jobs[i].dlog;
+        total_cap += jobs[i].capacity;
+    }
+    if (total_cap <= 0) return;
+    const int64_t want = std::min<int64_t>(total_cap, (int64_t)jobs[0].c->n_cu * 2);
+    launch(ctxs, n, true, dim3((unsigned)want), jp, s);
+}
+
 void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
                        const uint32_t *queue, const int64_t *qlen, int64_t capacity,
                        const double *hsum, const void *cache, double *dlog, int *counter,
@@ -450,23 +519,8 @@ void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
 {
     (void)counter;
     if (capacity <= 0) return;
-    if (mode == NQS_INCREMENTAL) {
-        if (cone_supported(c))
-            cone_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
-        else
-            mfma_inc_forward(c, spins, queue, qlen, capacity, hsum, cache, dlog, s);
-        return;
-    }
-    const bool full = mode == NQS_FULL;
-    Params p = common(c, spins, full ? kFull : kIncr);
-    p.queue = queue;
-    p.qlen = qlen;
-    p.capacity = capacity;
-    p.cache_in = (const uint16_t *)cache;
-    p.hsum_in = hsum;
-    p.dlog = dlog;
-    const int64_t want = std::min<int64_t>(capacity, (int64_t)c->n_cu * (full ? 2 : 6));
-    launch(c, full, dim3((unsigned)want), p, s);
+    const ConnJob j{c, spins, queue, qlen, capacity, hsum, cache, dlog};
+    mfma_conn_forward_jobs(mode, &j, 1, s);
 }
 
 }  // namespace nqs

@@ -50,6 +50,7 @@ constexpr int kChunk = 16;      // bytes of one 8-channel chunk of a site
 constexpr int kChunks = 4;      // 16-byte chunks of channels per site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
 constexpr int kMaxK = 16;
+constexpr int kMaxJobs = kMaxConnJobs;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte chunk
@@ -72,6 +73,13 @@ struct ConeParams {
     int buf_b;                 // byte offset of the odd-layer buffer (4 planes of ps_a)
     const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
     int ring_off[4][kMaxK];    // [tau][k - 1]: first entry of the ring of W_{k+1}; [tau][K-1]: end
+};
+
+// Up to kMaxJobs lattices (contexts of one network shape) in one launch: their
+// queue items form one index space, job after job.
+struct ConeJobs {
+    ConeParams job[kMaxJobs];
+    int n;
 };
 
 __device__ __forceinline__ int wrap_l(int a, int L)
@@ -284,16 +292,22 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
 
 // Three workgroups per CU: 166 VGPRs and 46 KB of LDS (K = 8) each.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_net_cone(ConeParams prm)
+k_net_cone(ConeJobs jobs)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ double red[kNW];
 
-    const int L = prm.L, N = L * L, K = prm.K;
+    const int K = jobs.job[0].K;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int g = lane >> 4, n16 = lane & 15;
-    const int64_t n_units = min(prm.qlen[0], prm.capacity);
+    // first item of each job in the common index space
+    int64_t first[kMaxJobs + 1];
+    first[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxJobs; ++j)
+        first[j + 1] = first[j] + (j < jobs.n ? min(jobs.job[j].qlen[0], jobs.job[j].capacity) : 0);
+    const int64_t n_units = first[kMaxJobs];
 
     // XCD-contiguous ranges of the queue
     const int per_xcd = gridDim.x / kXcd;
@@ -303,9 +317,16 @@ k_net_cone(ConeParams prm)
 
     bf16x8 wa[KS][NH];
     floatx4 bias[NH];
-    load_layer(wa, bias, prm, 2, lane, g);
 
-    for (int64_t unit = xcd * seg + slot; unit < u_end; unit += per_xcd) {
+    for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
+        int jb = 0;
+#pragma unroll
+        for (int j = 1; j < kMaxJobs; ++j) jb = (u >= first[j]) ? j : jb;
+        const ConeParams &prm = jobs.job[jb];
+        const int64_t unit = u - first[jb];
+        const int L = prm.L, N = L * L;
+        // layer 2's weights, in flight while layer 1 runs
+        load_layer(wa, bias, prm, 2, lane, g);
         const uint32_t e = prm.queue[unit];
         const int s = item_sample(e);
         const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
@@ -379,11 +400,11 @@ k_net_cone(ConeParams prm)
             else
                 cone_layer<true>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
                                  wave, g, n16, fsum);
-            // weights of the next layer (layer 2 of the next configuration after the
-            // last, whose bond type is not known yet), if this wave works on it
-            const int kn = k == K ? 2 : k + 1;
-            const int nt_next = ((w0 + 2 * kn) * (h0 + 2 * kn) + 15) >> 4;
-            if (k == K || wave < active_waves(nt_next)) load_layer(wa, bias, prm, kn, lane, g);
+            // weights of the next layer, if this wave works on it
+            if (k < K) {
+                const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
+                if (wave < active_waves(nt_next)) load_layer(wa, bias, prm, k + 1, lane, g);
+            }
             __syncthreads();
         }
 
@@ -464,31 +485,37 @@ nqs_status cone_build_ring_tables(nqs_ctx *c)
     return NQS_OK;
 }
 
-void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
-                  int64_t capacity, const double *hsum, const void *cache, double *dlog,
-                  hipStream_t s)
+void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
 {
-    if (capacity <= 0) return;
-    ConeParams p{};
-    p.spins = spins;
-    p.L = c->L;
-    p.K = c->K;
-    p.queue = queue;
-    p.qlen = qlen;
-    p.capacity = capacity;
-    p.wa = (const bf16x8 *)c->w_mfma;
-    p.w1 = c->w_l1;
-    p.bias = c->w_l1 + 9 * C;
-    p.cache = (const uint16_t *)cache;
-    p.hsum = hsum;
-    p.dlog = dlog;
-    p.err = c->err;
-    p.ring = c->cone_tab;
-    for (int t = 0; t < 4; ++t)
-        for (int k = 0; k < kMaxK; ++k) p.ring_off[t][k] = c->cone_off[(size_t)t * kMaxK + k];
-    plane_strides(c->K, &p.ps_a, &p.ps_b);
-    p.buf_b = kChunks * p.ps_a;
-    const size_t lds = cone_lds_bytes(c);
+    if (n <= 0) return;
+    ConeJobs jp{};
+    jp.n = n;
+    int64_t total_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        const nqs_ctx *c = jobs[i].c;
+        ConeParams &p = jp.job[i];
+        p.spins = jobs[i].spins;
+        p.L = c->L;
+        p.K = c->K;
+        p.queue = jobs[i].queue;
+        p.qlen = jobs[i].qlen;
+        p.capacity = jobs[i].capacity;
+        p.wa = (const bf16x8 *)c->w_mfma;
+        p.w1 = c->w_l1;
+        p.bias = c->w_l1 + 9 * C;
+        p.cache = (const uint16_t *)jobs[i].cache;
+        p.hsum = jobs[i].hsum;
+        p.dlog = jobs[i].dlog;
+        p.err = c->err;
+        p.ring = c->cone_tab;
+        for (int t = 0; t < 4; ++t)
+            for (int k = 0; k < kMaxK; ++k) p.ring_off[t][k] = c->cone_off[(size_t)t * kMaxK + k];
+        plane_strides(c->K, &p.ps_a, &p.ps_b);
+        p.buf_b = kChunks * p.ps_a;
+        total_cap += jobs[i].capacity;
+    }
+    if (total_cap <= 0) return;
+    const size_t lds = cone_lds_bytes(jobs[0].c);
     (void)hipFuncSetAttribute((const void *)k_net_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     int per_cu = 0;
@@ -497,8 +524,17 @@ void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, 
         per_cu < 1)
         per_cu = 1;
     // persistent grid of resident workgroups, a multiple of the XCD count
-    const int64_t want = std::max<int64_t>((int64_t)c->n_cu * per_cu / kXcd * kXcd, kXcd);
-    NQS_LAUNCH(k_net_cone, dim3((unsigned)want), dim3(kThreads), lds, s, p);
+    const int64_t want =
+        std::max<int64_t>((int64_t)jobs[0].c->n_cu * per_cu / kXcd * kXcd, kXcd);
+    NQS_LAUNCH(k_net_cone, dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+}
+
+void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
+                  int64_t capacity, const double *hsum, const void *cache, double *dlog,
+                  hipStream_t s)
+{
+    const ConnJob j{c, spins, queue, qlen, capacity, hsum, cache, dlog};
+    cone_forward_jobs(&j, 1, s);
 }
 
 }  // namespace nqs

@@ -38,6 +38,8 @@ constexpr int kNW = 4;
 constexpr int kThreads = kNW * 64;
 constexpr int kRingRegs = 2;
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte chunk
+
 struct IncParams {
     const int8_t *spins;
     int L, K;
@@ -54,6 +56,13 @@ struct IncParams {
     const int32_t *ring;       // packed (window index | (du mod L) << 16 | (dv mod L) << 24)
     const int32_t *ring_off;   // [4][K] entry offsets: ring of W_{k+1} for k = 1..K-1
     int win_bytes;             // bytes of one window buffer
+};
+
+// Up to kMaxConnJobs lattices (contexts of one network shape) in one launch:
+// their queue items form one index space, job after job.
+struct IncJobs {
+    IncParams job[kMaxConnJobs];
+    int n;
 };
 
 // a mod L for a in [-L, 2L): every anchor offset of this kernel lies in
@@ -84,8 +93,8 @@ template <int C>
 __device__ __forceinline__ void store_group(unsigned char *buf, int wi, int g, const uint32_t *pk)
 {
     if (C == 32) {
-        uint4 v = {pk[0], pk[1], pk[2], pk[3]};
-        *(uint4 *)(buf + chunk_addr<C>(wi, g)) = v;
+        const u32x4 v = {pk[0], pk[1], pk[2], pk[3]};
+        *(u32x4 *)(buf + chunk_addr<C>(wi, g)) = v;
     } else {
         uint2 v = {pk[0], pk[1]};
         *(uint2 *)(buf + chunk_addr<C>(wi, g >> 1) + ((g & 1) << 3)) = v;
@@ -99,7 +108,7 @@ __device__ __forceinline__ uint32_t pack2(float a, float b)
 
 template <int C>
 struct Ring {
-    uint4 v[kRingRegs];
+    u32x4 v[kRingRegs];
     int wi[kRingRegs];
 };
 
@@ -123,7 +132,7 @@ __device__ __forceinline__ void ring_fetch(Ring<C> &r, const IncParams &p, int e
         int x = ax + ((ent >> 16) & 255), y = ay + ((ent >> 24) & 255);
         x -= (x >= L) ? L : 0;
         y -= (y >= L) ? L : 0;
-        r.v[i] = *(const uint4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
+        r.v[i] = *(const u32x4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
         r.wi[i] = live ? (((ent & 0xffff) << 4) | c) : -1;
     }
 }
@@ -135,7 +144,7 @@ __device__ __forceinline__ void ring_store(const Ring<C> &r, unsigned char *buf,
 {
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i)
-        if (r.wi[i] >= 0) *(uint4 *)(buf + chunk_addr<C>(r.wi[i] >> 4, r.wi[i] & 15)) = r.v[i];
+        if (r.wi[i] >= 0) *(u32x4 *)(buf + chunk_addr<C>(r.wi[i] >> 4, r.wi[i] & 15)) = r.v[i];
     // chunks beyond the prefetched ones (only for large clamped windows)
     const int L = p.L;
     const int total = (e1 - e0) * Shape<C>::CHUNKS;
@@ -145,8 +154,8 @@ __device__ __forceinline__ void ring_store(const Ring<C> &r, unsigned char *buf,
         int x = ax + ((ent >> 16) & 255), y = ay + ((ent >> 24) & 255);
         x -= (x >= L) ? L : 0;
         y -= (y >= L) ? L : 0;
-        *(uint4 *)(buf + chunk_addr<C>(ent & 0xffff, c)) =
-            *(const uint4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
+        *(u32x4 *)(buf + chunk_addr<C>(ent & 0xffff, c)) =
+            *(const u32x4 *)(layer_cache + (int64_t)(y * L + x) * C + c * 8);
     }
 }
 
@@ -287,23 +296,35 @@ __device__ __forceinline__ void layer_tiles(const bf16x8 (&wa)[Shape<C>::KS][Sha
 
 template <int C>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_net_inc(IncParams prm)
+k_net_inc(IncJobs jobs)
 {
     using S = Shape<C>;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ double red[kNW];
-    unsigned char *buf0 = lds, *buf1 = lds + prm.win_bytes;
+    unsigned char *buf0 = lds, *buf1 = lds + jobs.job[0].win_bytes;
 
-    const int L = prm.L, N = L * L, K = prm.K;
+    const int K = jobs.job[0].K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, n16 = lane & 15;
-    const int64_t n_units = min(prm.qlen[0], prm.capacity);
+    // first item of each job in the common index space
+    int64_t first[kMaxConnJobs + 1];
+    first[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxConnJobs; ++j)
+        first[j + 1] = first[j] + (j < jobs.n ? min(jobs.job[j].qlen[0], jobs.job[j].capacity) : 0);
+    const int64_t n_units = first[kMaxConnJobs];
     const int64_t wl_stride = (int64_t)S::KS * S::NH * 64;
 
     bf16x8 wa[S::KS][S::NH];
-    load_weights<C>(wa, prm.wa, lane);   // layer 2
 
-    for (int64_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        int jb = 0;
+#pragma unroll
+        for (int j = 1; j < kMaxConnJobs; ++j) jb = (u >= first[j]) ? j : jb;
+        const IncParams &prm = jobs.job[jb];
+        const int64_t unit = u - first[jb];
+        const int L = prm.L, N = L * L;
+        load_weights<C>(wa, prm.wa, lane);   // layer 2, in flight while layer 1 runs
         const uint32_t e = prm.queue[unit];
         const int s = item_sample(e);
         const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
@@ -380,8 +401,8 @@ k_net_inc(IncParams prm)
             else
                 layer_tiles<C, true>(wa, bias, lds, cur_off, nxt_off, ntiles, npos, mul, ex, wex, nex, wcx, wcy,
                                      L, K, ax, ay, prm.hsum + (int64_t)s * N, wave, g, n16, fsum);
-            // weights of the next layer (or of layer 2 for the next item)
-            load_weights<C>(wa, prm.wa + (last ? 0 : (int64_t)(k - 1) * wl_stride), lane);
+            // weights of the next layer
+            if (!last) load_weights<C>(wa, prm.wa + (int64_t)(k - 1) * wl_stride, lane);
             if (!last) ring_store<C>(ring, nxt, prm, roff[k - 1], roff[k], ax, ay,
                                      cache_s + (int64_t)(k - 1) * N * C);
             __syncthreads();
@@ -454,42 +475,60 @@ size_t mfma_inc_lds_bytes(const nqs_ctx *c)
     return (size_t)wmax * (c->C * 2 + 16);   // one window buffer, padded sites
 }
 
-void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
-                      const int64_t *qlen, int64_t capacity, const double *hsum,
-                      const void *cache, double *dlog, hipStream_t s)
+void mfma_inc_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
 {
-    if (capacity <= 0) return;
-    IncParams p{};
-    p.spins = spins;
-    p.L = c->L;
-    p.K = c->K;
-    p.queue = queue;
-    p.qlen = qlen;
-    p.capacity = capacity;
-    p.wa = (const bf16x8 *)c->w_mfma;
-    p.w1 = c->w_l1;
-    p.bias = c->w_l1 + 9 * c->C;
-    p.cache = (const uint16_t *)cache;
-    p.hsum = hsum;
-    p.dlog = dlog;
-    p.err = c->err;
-    p.ring = c->ring_tab;
-    p.ring_off = c->ring_off;
-    const size_t win = mfma_inc_lds_bytes(c);
-    p.win_bytes = (int)win;
+    if (n <= 0) return;
+    IncJobs jp{};
+    jp.n = n;
+    size_t win = 0;
+    int64_t total_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        win = std::max(win, mfma_inc_lds_bytes(jobs[i].c));
+        total_cap += jobs[i].capacity;
+    }
+    for (int i = 0; i < n; ++i) {
+        const nqs_ctx *c = jobs[i].c;
+        IncParams &p = jp.job[i];
+        p.spins = jobs[i].spins;
+        p.L = c->L;
+        p.K = c->K;
+        p.queue = jobs[i].queue;
+        p.qlen = jobs[i].qlen;
+        p.capacity = jobs[i].capacity;
+        p.wa = (const bf16x8 *)c->w_mfma;
+        p.w1 = c->w_l1;
+        p.bias = c->w_l1 + 9 * c->C;
+        p.cache = (const uint16_t *)jobs[i].cache;
+        p.hsum = jobs[i].hsum;
+        p.dlog = jobs[i].dlog;
+        p.err = c->err;
+        p.ring = c->ring_tab;
+        p.ring_off = c->ring_off;
+        p.win_bytes = (int)win;   // one buffer size for every job: the largest window
+    }
+    if (total_cap <= 0) return;
+    const int C = jobs[0].c->C;
     const size_t lds = 2 * win;
     // persistent grid: exactly the workgroups that are resident at once
-    const void *fn = c->C == 32 ? (const void *)k_net_inc<32> : (const void *)k_net_inc<16>;
+    const void *fn = C == 32 ? (const void *)k_net_inc<32> : (const void *)k_net_inc<16>;
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int64_t want = std::min<int64_t>(capacity, (int64_t)c->n_cu * per_cu);
-    if (c->C == 32)
-        NQS_LAUNCH((k_net_inc<32>), dim3((unsigned)want), dim3(kThreads), lds, s, p);
+    const int64_t want = std::min<int64_t>(total_cap, (int64_t)jobs[0].c->n_cu * per_cu);
+    if (C == 32)
+        NQS_LAUNCH((k_net_inc<32>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
     else
-        NQS_LAUNCH((k_net_inc<16>), dim3((unsigned)want), dim3(kThreads), lds, s, p);
+        NQS_LAUNCH((k_net_inc<16>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+}
+
+void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                      const int64_t *qlen, int64_t capacity, const double *hsum,
+                      const void *cache, double *dlog, hipStream_t s)
+{
+    const ConnJob j{c, spins, queue, qlen, capacity, hsum, cache, dlog};
+    mfma_inc_forward_jobs(&j, 1, s);
 }
 
 }  // namespace nqs

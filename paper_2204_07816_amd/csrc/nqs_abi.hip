@@ -201,6 +201,18 @@ int64_t vec_chunk(const nqs_ctx *c, int64_t cap)
     return std::min(m, std::max<int64_t>(cap, 1));
 }
 
+// BF16 base pass: log-amplitudes, per-site sums and the activation cache of
+// the samples, in the context's workspace.
+nqs_status bf16_base_stage(nqs_ctx *c, const int8_t *spins, int B, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
+    NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
+    NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+    mfma_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr, s);
+    return NQS_OK;
+}
+
 // Base pass + exchanged-configuration pass: dlog[item].
 nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode, double *dlog,
                            int64_t cap, hipStream_t s)
@@ -209,8 +221,7 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
     if (c->dtype == NQS_BF16) {
-        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
-        mfma_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr, s);
+        NQS_TRY(bf16_base_stage(c, spins, B, s));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
             (void)hipEventCreate(&e0);
@@ -624,15 +635,78 @@ nqs_status nqs_sr_solve(nqs_ctx *c, const void *O, nqs_dtype odt, const double *
 nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode mode, void *stream)
 {
     if (!jobs || n < 0) return NQS_E_ARG;
+    if (mode != NQS_AUTO && mode != NQS_FULL && mode != NQS_INCREMENTAL) return NQS_E_ARG;
     for (int i = 0; i < n; ++i) {
-        if (!jobs[i].ctx) return NQS_E_ARG;
-        if (jobs[i].ctx->K != jobs[0].ctx->K || jobs[i].ctx->C != jobs[0].ctx->C ||
-            jobs[i].ctx->dtype != jobs[0].ctx->dtype)
+        nqs_ctx *c = jobs[i].ctx;
+        if (!c) return NQS_E_ARG;
+        if (c->K != jobs[0].ctx->K || c->C != jobs[0].ctx->C || c->dtype != jobs[0].ctx->dtype)
             return NQS_E_SPEC;
+        for (int j = 0; j < i; ++j)
+            if (jobs[j].ctx == c) return NQS_E_ARG;   // one workspace per job
+        NQS_TRY(check_common(c, jobs[i].spins, jobs[i].B));
+        if (jobs[i].B > 0 && !jobs[i].e_loc) return NQS_E_ARG;
+        const nqs_mode m = resolve_mode(c, mode);
+        if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+            return NQS_E_UNSUPPORTED;
     }
-    for (int i = 0; i < n; ++i)
-        NQS_TRY(nqs_local_energy(jobs[i].ctx, jobs[i].spins, jobs[i].B, jobs[i].e_loc, mode, stream));
-    return NQS_OK;
+    if (n == 0) return NQS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (jobs[0].ctx->dtype != NQS_BF16) {
+        // the vector-ALU (FP64 / FP32) path runs lattice after lattice
+        for (int i = 0; i < n; ++i)
+            NQS_TRY(nqs_local_energy(jobs[i].ctx, jobs[i].spins, jobs[i].B, jobs[i].e_loc, mode,
+                                     stream));
+        return NQS_OK;
+    }
+    // BF16: per lattice the integer stage and the base pass; then the
+    // exchanged configurations of every lattice of one mode in a single
+    // persistent launch (one per mode present, kMaxConnJobs lattices at a
+    // time); then per lattice the FP64 ratio sums.
+    for (int i = 0; i < n; ++i) {
+        nqs_ctx *c = jobs[i].ctx;
+        c->last_stream = s;
+        if (jobs[i].B == 0) continue;
+        const int64_t cap = bonds_per_sample(c) * jobs[i].B;
+        NQS_TRY(integer_stage(c, jobs[i].spins, (int)jobs[i].B, s));
+        NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+        NQS_TRY(bf16_base_stage(c, jobs[i].spins, (int)jobs[i].B, s));
+    }
+    nqs_ctx *c0 = jobs[0].ctx;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c0->timing) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, s);
+    }
+    for (nqs_mode m : {NQS_FULL, NQS_INCREMENTAL}) {
+        ConnJob cj[kMaxConnJobs];
+        int k = 0;
+        for (int i = 0; i <= n; ++i) {
+            if (i < n && jobs[i].B > 0 && resolve_mode(jobs[i].ctx, mode) == m) {
+                nqs_ctx *c = jobs[i].ctx;
+                cj[k++] = ConnJob{c, jobs[i].spins, (const uint32_t *)c->ws.queue.ptr,
+                                  (const int64_t *)c->ws.qlen.ptr, bonds_per_sample(c) * jobs[i].B,
+                                  (const double *)c->ws.hsum.ptr, c->ws.cache.ptr,
+                                  (double *)c->ws.dlog.ptr};
+            }
+            if (k == kMaxConnJobs || (i == n && k > 0)) {
+                mfma_conn_forward_jobs(m, cj, k, s);
+                k = 0;
+            }
+        }
+    }
+    if (c0->timing) {
+        (void)hipEventRecord(e1, s);
+        c0->events.push_back({e0, e1});
+    }
+    for (int i = 0; i < n; ++i) {
+        nqs_ctx *c = jobs[i].ctx;
+        if (jobs[i].B == 0) continue;
+        launch_energy_reduce(c, (int)jobs[i].B, (int64_t *)c->ws.offsets.ptr,
+                             (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
+                             (double *)c->ws.ediag.ptr, jobs[i].e_loc, c->err, s);
+    }
+    return finish_call();
 }
 
 nqs_status nqs_get_error(nqs_ctx *c, nqs_status *sticky)

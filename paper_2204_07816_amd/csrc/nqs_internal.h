@@ -145,6 +145,19 @@ bool f64mma_wgrad_ok(int C);
 void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
                   void *O, nqs_dtype odt, hipStream_t s);
 
+// --- one lattice's share of a multi-lattice exchanged-configuration launch ---
+constexpr int kMaxConnJobs = 8;
+struct ConnJob {
+    const nqs_ctx *c;
+    const int8_t *spins;
+    const uint32_t *queue;
+    const int64_t *qlen;       // device: number of queue items
+    int64_t capacity;
+    const double *hsum;        // base-pass site sums
+    const void *cache;         // base-pass activation cache
+    double *dlog;              // out: f(S') - f(s) per item
+};
+
 // --- MFMA (BF16) network kernels (k_conv_mfma.hip) ---
 bool mfma_supported(const nqs_ctx *c);
 size_t mfma_cache_bytes(const nqs_ctx *c, int64_t B);
@@ -156,6 +169,9 @@ void mfma_conn_forward(const nqs_ctx *c, nqs_mode mode, const int8_t *spins,
                        const double *hsum, const void *cache, double *dlog, int *counter,
                        hipStream_t s);
 int mfma_lds_full_ok(const nqs_ctx *c);
+// One launch over the exchanged configurations of 1..kMaxConnJobs contexts of
+// one network shape (mode NQS_FULL or NQS_INCREMENTAL, supported by all).
+void mfma_conn_forward_jobs(nqs_mode mode, const ConnJob *jobs, int n, hipStream_t s);
 // incremental-mode kernel (k_net_inc.hip)
 nqs_status mfma_build_ring_tables(nqs_ctx *c);
 size_t mfma_inc_lds_bytes(const nqs_ctx *c);
@@ -163,8 +179,12 @@ void mfma_inc_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                       const int64_t *qlen, int64_t capacity, const double *hsum,
                       const void *cache, double *dlog, hipStream_t s);
 bool mfma_inc_supported(const nqs_ctx *c);
+// jobs: 1..kMaxConnJobs contexts of one network shape, all mfma_inc_supported
+void mfma_inc_forward_jobs(const ConnJob *jobs, int n, hipStream_t s);
 // incremental mode, unwrapped windows (k_net_cone.hip): C = 32, L >= 2K + 4
 bool cone_supported(const nqs_ctx *c);
+// jobs: 1..kMaxConnJobs contexts of one network shape, all cone-supported
+void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s);
 size_t cone_lds_bytes(const nqs_ctx *c);
 nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
