@@ -153,9 +153,14 @@ nqs_status nqs_log_ratios(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                           nqs_mode mode, double *dlog, int64_t capacity,
                           void *stream);
 
-/* Several lattices in one launch sequence: every job has its own context
- * (same network shape and conv dtype, any L, J2 and weights).  The
- * exchanged configurations of all jobs share one persistent kernel launch. */
+/* Several lattices at once: every job has its own context (same network
+ * shape and conv dtype, any L, J2 and weights; no context twice).  With BF16
+ * contexts each lattice runs its bond stage and base pass, then the
+ * exchanged configurations of all lattices of one mode (as `mode` resolves
+ * per context) share one persistent kernel launch over their concatenated
+ * queues (up to 8 lattices per launch), then each lattice's FP64 ratio sums
+ * are taken.  FP64 / FP32 contexts run lattice after lattice.  Errors as
+ * nqs_local_energy, checked for every job before any work is queued.      */
 typedef struct {
     nqs_ctx *ctx;
     const int8_t *spins;
@@ -165,8 +170,36 @@ typedef struct {
 nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n_jobs,
                                   nqs_mode mode, void *stream);
 
-/* Which mode AUTO picks for this context (host out).                      */
+/* Which mode AUTO picks for this context (host out): the autotuner's choice
+ * once one exists for the configuration, else a work estimate (incremental
+ * when its cones are below 70% of the full recomputation's positions).     */
 nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
+
+/* Autotuner (serves the batching of [Sec. 5.4.1]: which form of the
+ * exchanged-configuration pass is fastest here).  Runs the bond stage and
+ * base pass of the B samples (device spins), then times the exchanged-
+ * configuration pass in every available form -- full recompute with each
+ * fitting tile variant, and the incremental receptive cone -- and makes AUTO
+ * (and the full pass) use the fastest from then on.  The choice is stored in
+ * the tune cache, a JSON file (NQS_TUNE_CACHE, else
+ * $HOME/.cache/nqs/tune.json), under the key nqs_tune_key gives; contexts of
+ * the same key created later read it.  FP64 / FP32 contexts have only the
+ * full form.  Synchronises the stream; NQS_E_WORKSPACE while the stream is
+ * capturing; NQS_E_ARG for B = 0.  mode_out (host) may be null.  A cache
+ * file that cannot be written is not an error.                             */
+nqs_status nqs_autotune(nqs_ctx *ctx, const int8_t *spins, int64_t B,
+                        nqs_mode *mode_out, void *stream);
+
+/* Tune-cache key of a configuration (host only, writes a NUL-terminated
+ * string of at most len bytes into buf).                                   */
+nqs_status nqs_tune_key(int32_t L, int32_t K, int32_t C, nqs_dtype dtype,
+                        double J2, char *buf, int64_t len);
+
+/* One entry of a tune-cache file (host only): NQS_OK with the entry when the
+ * file parses and holds the key; NQS_E_ARG (outputs untouched) when it is
+ * missing, malformed or lacks the key.                                     */
+nqs_status nqs_tune_lookup(const char *path, const char *key, nqs_mode *mode,
+                           int32_t *full_nw, int32_t *full_maxt);
 
 /* Sticky device error word: synchronises the context's last stream, returns
  * the first device-detected status since the last call (host out), clears. */

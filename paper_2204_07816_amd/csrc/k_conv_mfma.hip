@@ -357,8 +357,12 @@ struct Variant {
     int nw, maxt;
 };
 
-// Smallest (waves, tiles-per-wave) variant that covers the largest layer.
-bool pick_variant(const nqs_ctx *c, bool full, Variant *v, size_t *lds)
+const Variant kVariants[] = {{4, 2}, {4, 4}, {4, 6}, {8, 6}, {8, 11}};
+
+// Smallest (waves, tiles-per-wave) variant that covers the largest layer; for
+// the full-recompute exchanged-configuration pass (tuned = true) the
+// autotuner's choice when it has made one and it fits.
+bool pick_variant(const nqs_ctx *c, bool full, Variant *v, size_t *lds, bool tuned = false)
 {
     const int L = c->L, K = c->K;
     int max_pos = 0, max_win = 0;
@@ -370,8 +374,15 @@ bool pick_variant(const nqs_ctx *c, bool full, Variant *v, size_t *lds)
     }
     if (full) max_win = L * L;
     const int tiles = (max_pos + 15) / 16;
-    static const Variant table[] = {{4, 2}, {4, 4}, {4, 6}, {8, 6}, {8, 11}};
-    for (const Variant &t : table) {
+    if (tuned && c->full_nw > 0) {
+        for (const Variant &t : kVariants)
+            if (t.nw == c->full_nw && t.maxt == c->full_maxt && t.nw * t.maxt >= tiles) {
+                *v = t;
+                *lds = (size_t)max_win * c->C * 2;
+                if (*lds <= 160 * 1024 - 1024) return true;
+            }
+    }
+    for (const Variant &t : kVariants) {
         if (t.nw * t.maxt >= tiles) {
             *v = t;
             *lds = (size_t)max_win * c->C * 2;
@@ -409,7 +420,7 @@ void launch(const nqs_ctx *const *ctxs, int n, bool full, dim3 grid, const NetJo
         if (ctxs[i]->L > ctxs[big]->L) big = i;
     Variant v;
     size_t lds;
-    if (!pick_variant(ctxs[big], full, &v, &lds)) return;
+    if (!pick_variant(ctxs[big], full, &v, &lds, n == 1 && full)) return;
     if (ctxs[big]->C == 32)
         launch_variant<32>(v, grid, lds, p, s);
     else
@@ -439,6 +450,22 @@ Params common(const nqs_ctx *c, const int8_t *spins, int mode)
 }
 
 }  // namespace
+
+int mfma_full_variants(const nqs_ctx *c, int *nw, int *maxt, int cap)
+{
+    // every variant at least as large as the smallest that fits (same LDS)
+    Variant d;
+    size_t lds;
+    if (!pick_variant(c, true, &d, &lds)) return 0;
+    int n = 0;
+    for (const Variant &t : kVariants)
+        if (n < cap && t.nw * t.maxt >= d.nw * d.maxt) {
+            nw[n] = t.nw;
+            maxt[n] = t.maxt;
+            ++n;
+        }
+    return n;
+}
 
 bool mfma_supported(const nqs_ctx *c)
 {

@@ -160,6 +160,8 @@ nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
 {
     if (m != NQS_AUTO) return m;
     if (c->dtype != NQS_BF16) return NQS_FULL;
+    if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !mfma_inc_supported(c)) ? NQS_FULL
+                                                                                      : c->tuned_mode;
     // incremental work: sum_k |R_k| over layers 2..K for a 2x2 seed, clamped
     double inc = 0.0, full = 0.0;
     for (int k = 2; k <= c->K; ++k) {
@@ -401,6 +403,17 @@ nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
     if (st != NQS_OK) {
         nqs_destroy(c);
         return st;
+    }
+    // an earlier autotuner choice for this configuration, if the cache has one
+    {
+        nqs_mode m;
+        int nw = 0, mt = 0;
+        if (tune_lookup(tune_cache_path(), tune_key(c), &m, &nw, &mt)) {
+            c->tuned = 1;
+            c->tuned_mode = m;
+            c->full_nw = nw;
+            c->full_maxt = mt;
+        }
     }
     *out = c;
     return NQS_OK;
@@ -707,6 +720,86 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
                              (double *)c->ws.ediag.ptr, jobs[i].e_loc, c->err, s);
     }
     return finish_call();
+}
+
+nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mode_out,
+                        void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (B == 0) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (stream_capturing(s)) return NQS_E_WORKSPACE;
+    c->last_stream = s;
+    double ms_full = -1.0, ms_inc = -1.0;
+    int best_nw = 0, best_mt = 0;
+    nqs_mode best = NQS_FULL;
+    if (c->dtype == NQS_BF16) {
+        const int64_t cap = bonds_per_sample(c) * B;
+        NQS_TRY(integer_stage(c, spins, (int)B, s));
+        NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+        NQS_TRY(bf16_base_stage(c, spins, (int)B, s));
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        // one exchanged-configuration pass per candidate: a warm run, then two
+        // timed ones (ms per pass)
+        auto time_pass = [&](nqs_mode m, double *ms) -> nqs_status {
+            const ConnJob j{c, spins, (const uint32_t *)c->ws.queue.ptr,
+                            (const int64_t *)c->ws.qlen.ptr, cap, (const double *)c->ws.hsum.ptr,
+                            c->ws.cache.ptr, (double *)c->ws.dlog.ptr};
+            mfma_conn_forward_jobs(m, &j, 1, s);
+            HIP_OK(hipEventRecord(e0, s));
+            mfma_conn_forward_jobs(m, &j, 1, s);
+            mfma_conn_forward_jobs(m, &j, 1, s);
+            HIP_OK(hipEventRecord(e1, s));
+            HIP_OK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIP_OK(hipEventElapsedTime(&t, e0, e1));
+            *ms = t / 2.0;
+            return finish_call();
+        };
+        int nw[8], mt[8];
+        const int nv = mfma_full_variants(c, nw, mt, 8);
+        const int keep_nw = c->full_nw, keep_mt = c->full_maxt;
+        for (int i = 0; i < nv; ++i) {
+            c->full_nw = nw[i];
+            c->full_maxt = mt[i];
+            double ms;
+            const nqs_status st = time_pass(NQS_FULL, &ms);
+            if (st != NQS_OK) {
+                c->full_nw = keep_nw;
+                c->full_maxt = keep_mt;
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            if (ms_full < 0.0 || ms < ms_full) {
+                ms_full = ms;
+                best_nw = nw[i];
+                best_mt = mt[i];
+            }
+        }
+        c->full_nw = best_nw;
+        c->full_maxt = best_mt;
+        best = NQS_FULL;
+        if (mfma_inc_supported(c)) {
+            const nqs_status st = time_pass(NQS_INCREMENTAL, &ms_inc);
+            if (st != NQS_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            if (ms_inc < ms_full) best = NQS_INCREMENTAL;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    c->tuned = 1;
+    c->tuned_mode = best;
+    // a cache that cannot be written leaves the choice with this context only
+    (void)tune_store(tune_cache_path(), tune_key(c), best, best_nw, best_mt, ms_full, ms_inc);
+    if (mode_out) *mode_out = best;
+    return NQS_OK;
 }
 
 nqs_status nqs_get_error(nqs_ctx *c, nqs_status *sticky)

@@ -75,6 +75,10 @@ struct nqs_ctx {
     int32_t *ring_off = nullptr;
     int32_t *cone_tab = nullptr;  // same, for the unwrapped-window kernel
     std::vector<int> cone_off;    // [4][16] entry offsets of cone_tab
+    // autotuner choice (from nqs_autotune or the tune cache)
+    int tuned = 0;
+    nqs_mode tuned_mode = NQS_FULL;
+    int full_nw = 0, full_maxt = 0;   // tile variant of the full-recompute pass (0: default)
     // workspace
     nqs::Workspace ws;
     int32_t *err = nullptr;       // device sticky error word
@@ -190,6 +194,16 @@ nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,
                   hipStream_t s);
+
+// --- autotuner (tune.hip) ---
+std::string tune_cache_path();
+std::string tune_key(const nqs_ctx *c);
+bool tune_lookup(const std::string &path, const std::string &key, nqs_mode *mode, int *nw,
+                 int *maxt);
+bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, int nw, int maxt,
+                double ms_full, double ms_inc);
+// tile variants (waves, tiles per wave) the full-recompute pass can use here
+int mfma_full_variants(const nqs_ctx *c, int *nw, int *maxt, int cap);
 
 // --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
 void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const uint32_t *queue,

@@ -72,6 +72,9 @@ def load():
         "nqs_log_ratios": [vp, vp, i64, i32, vp, i64, vp],
         "nqs_local_energy_multi": [vp, i32, i32, vp],
         "nqs_auto_mode": [vp, P(i32)],
+        "nqs_autotune": [vp, vp, i64, P(i32), vp],
+        "nqs_tune_key": [i32, i32, i32, i32, d, ctypes.c_char_p, i64],
+        "nqs_tune_lookup": [ctypes.c_char_p, ctypes.c_char_p, P(i32), P(i32), P(i32)],
         "nqs_get_error": [vp, P(i32)],
         "nqs_enable_timing": [vp, i32],
         "nqs_kernel_time": [vp, P(d), P(i64)],
@@ -162,6 +165,14 @@ class Context:
     def auto_mode(self) -> str:
         m = ctypes.c_int32()
         _check(load().nqs_auto_mode(self._h, ctypes.byref(m)), "nqs_auto_mode")
+        return {v: k for k, v in _MODES.items()}[m.value]
+
+    def autotune(self, spins) -> str:
+        """Time the exchanged-configuration pass in every available form on these
+        samples; AUTO uses the fastest from then on (and the tune cache keeps it)."""
+        sp, B = self._spins(spins)
+        m = ctypes.c_int32()
+        _check(load().nqs_autotune(self._h, sp, B, ctypes.byref(m), _stream()), "nqs_autotune")
         return {v: k for k, v in _MODES.items()}[m.value]
 
     def _spins(self, spins):
@@ -267,6 +278,25 @@ def local_energy_multi(jobs, mode: str = "auto"):
         arr[i] = ElocJob(ctx.handle.value, sp.value, B, _dev(e, torch.float64, "e_loc").value)
     _check(load().nqs_local_energy_multi(arr, len(jobs), _MODES[mode], _stream()),
            "nqs_local_energy_multi")
+
+
+def tune_key(L: int, K: int, C: int, dtype: str, J2: float) -> str:
+    """Tune-cache key of a configuration (host only)."""
+    buf = ctypes.create_string_buffer(128)
+    _check(load().nqs_tune_key(L, K, C, _DTYPES[dtype], J2, buf, len(buf)), "nqs_tune_key")
+    return buf.value.decode()
+
+
+def tune_lookup(path: str, key: str):
+    """The tune-cache entry of key in the file at path, or None (missing file or
+    key, malformed file).  Host only."""
+    m, nw, mt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    code = load().nqs_tune_lookup(path.encode(), key.encode(), ctypes.byref(m), ctypes.byref(nw),
+                                  ctypes.byref(mt))
+    if code != 0:
+        return None
+    return {"mode": {v: k for k, v in _MODES.items()}[m.value], "full_nw": nw.value,
+            "full_maxt": mt.value}
 
 
 class LogPsiFn(torch.autograd.Function):
