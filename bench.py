@@ -15,7 +15,8 @@ plain FP64 GPU form (full recompute, FP64 convolutions) is timed on the same
 1024 samples for comparison, and the BF16 mean energy is checked against it
 (bar: 1e-5 relative).  A non-gating stress row repeats the BF16-vs-FP64
 comparison at weights whose exchanged configurations differ at O(1) in log
-amplitude.  The FP64 CPU oracle is timed on the host cores on a bounded sample.
+amplitude; another times the mixed-lattice workload (12x12, 16x16, 20x20)
+through one multi-lattice call per step.  The FP64 CPU oracle is timed on the host cores on a bounded sample.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -164,6 +165,41 @@ def stress_row(L, J2, K, C, sp, dev, n_samples=16):
             "gating": False}
 
 
+def mixed_row(dev, reps=3):
+    """Non-gating row: the mixed-lattice workload (12x12 J2=0, 16x16 J2=0.5,
+    20x20 J2=0.55; K=6, C=32, weights N(0, 0.02^2), 4096 configurations each)
+    through one nqs_local_energy_multi call per step, every context autotuned
+    first on 64 of its samples."""
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    jobs, modes, items = [], [], 0
+    for lat in range(3):
+        L, J2, K, C, w, sp = inputs.config_inputs("mixed", lattice=lat)
+        ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16")
+        spd = torch.as_tensor(sp).to(dev)
+        modes.append(ctx.autotune(spd[:64].contiguous()))
+        ctx.reserve(sp.shape[0], modes[-1])
+        e = torch.empty(sp.shape[0], dtype=torch.float64, device=dev)
+        jobs.append((ctx, spd, e))
+        items += int(ctx.connected(spd)[0].sum().item())
+    nqs.local_energy_multi(jobs, mode="auto")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nqs.local_energy_multi(jobs, mode="auto")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    samples = sum(j[1].shape[0] for j in jobs)
+    out = {"samples_per_s": samples / (ms * 1e-3), "ms": ms, "samples": samples,
+           "exchanged_configurations": items,
+           "lattices": {f"{j[0].L}x{j[0].L}": m for j, m in zip(jobs, modes)}}
+    for ctx, _, _ in jobs:
+        assert ctx.get_error() == 0
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +207,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-samples", type=int, default=1024)
     ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -327,6 +364,11 @@ def main():
         log(f"stress row: gain {stress['gain']:.4f}, std log ratio {stress['std_log_ratio']:.3f}, "
             f"bf16 mean rel err {stress['bf16_mean_rel_err']:.3e}")
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_row(dev)
+        log(f"mixed lattices: {mixed['samples_per_s']:.1f} samples/s ({mixed['lattices']})")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -347,6 +389,7 @@ def main():
         "eloc_only_samples_per_s": B / (t_eloc * 1e-3),
         "fp64_gpu": fp64,
         "stress_nongating": stress,
+        "mixed_lattices_nongating": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

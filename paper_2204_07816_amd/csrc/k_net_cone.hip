@@ -72,13 +72,15 @@ struct ConeParams {
     int ps_a, ps_b;            // plane strides (bytes) of the even- and odd-layer buffers
     int buf_b;                 // byte offset of the odd-layer buffer (4 planes of ps_a)
     const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
-    int ring_off[4][kMaxK];    // [tau][k - 1]: first entry of the ring of W_{k+1}; [tau][K-1]: end
 };
 
 // Up to kMaxJobs lattices (contexts of one network shape) in one launch: their
 // queue items form one index space, job after job.
 struct ConeJobs {
     ConeParams job[kMaxJobs];
+    // per job, [tau][k - 1]: first ring-table entry of the ring of W_{k+1};
+    // [tau][K - 1]: end
+    int ring_off[kMaxJobs][4][kMaxK];
     int n;
 };
 
@@ -291,6 +293,8 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
 }
 
 // Three workgroups per CU: 166 VGPRs and 46 KB of LDS (K = 8) each.
+// NJ: the number of jobs the launch can hold.
+template <int NJ>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_net_cone(ConeJobs jobs)
 {
@@ -302,12 +306,12 @@ k_net_cone(ConeJobs jobs)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int g = lane >> 4, n16 = lane & 15;
     // first item of each job in the common index space
-    int64_t first[kMaxJobs + 1];
+    int64_t first[NJ + 1];
     first[0] = 0;
 #pragma unroll
-    for (int j = 0; j < kMaxJobs; ++j)
+    for (int j = 0; j < NJ; ++j)
         first[j + 1] = first[j] + (j < jobs.n ? min(jobs.job[j].qlen[0], jobs.job[j].capacity) : 0);
-    const int64_t n_units = first[kMaxJobs];
+    const int64_t n_units = first[NJ];
 
     // XCD-contiguous ranges of the queue
     const int per_xcd = gridDim.x / kXcd;
@@ -315,18 +319,23 @@ k_net_cone(ConeJobs jobs)
     const int64_t seg = (n_units + kXcd - 1) / kXcd;
     const int64_t u_end = min(n_units, (xcd + 1) * seg);
 
-    bf16x8 wa[KS][NH];
-    floatx4 bias[NH];
-
-    for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
+    auto job_of = [&](int64_t u) {
         int jb = 0;
 #pragma unroll
-        for (int j = 1; j < kMaxJobs; ++j) jb = (u >= first[j]) ? j : jb;
-        const ConeParams &prm = jobs.job[jb];
+        for (int j = 1; j < NJ; ++j) jb = (u >= first[j]) ? j : jb;
+        return jb;
+    };
+    bf16x8 wa[KS][NH];
+    floatx4 bias[NH];
+    if (xcd * seg + slot < u_end) load_layer(wa, bias, jobs.job[job_of(xcd * seg + slot)], 2, lane, g);
+
+    for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
+        const int jb = job_of(u);
+        // this job's parameters, read once per configuration
+        const ConeParams prm = jobs.job[jb];
+        const int *roff_j = jobs.ring_off[jb][0];
         const int64_t unit = u - first[jb];
         const int L = prm.L, N = L * L;
-        // layer 2's weights, in flight while layer 1 runs
-        load_layer(wa, bias, prm, 2, lane, g);
         const uint32_t e = prm.queue[unit];
         const int s = item_sample(e);
         const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
@@ -338,7 +347,7 @@ k_net_cone(ConeJobs jobs)
         const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
         const double *hsum_s = prm.hsum + (int64_t)s * N;
 
-        const int *roff = prm.ring_off[tau];
+        const int *roff = roff_j + tau * kMaxK;
 
         // ---- layer 1 (vector ALU) into W_2 (buffer A), two channels per thread ----
         RingTab tab;
@@ -400,10 +409,13 @@ k_net_cone(ConeJobs jobs)
             else
                 cone_layer<true>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
                                  wave, g, n16, fsum);
-            // weights of the next layer, if this wave works on it
+            // weights of the next layer if this wave works on it; after the last,
+            // layer 2's of the next configuration (whose job may differ)
             if (k < K) {
                 const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
                 if (wave < active_waves(nt_next)) load_layer(wa, bias, prm, k + 1, lane, g);
+            } else if (u + per_xcd < u_end) {
+                load_layer(wa, bias, jobs.job[job_of(u + per_xcd)], 2, lane, g);
             }
             __syncthreads();
         }
@@ -509,24 +521,28 @@ void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
         p.err = c->err;
         p.ring = c->cone_tab;
         for (int t = 0; t < 4; ++t)
-            for (int k = 0; k < kMaxK; ++k) p.ring_off[t][k] = c->cone_off[(size_t)t * kMaxK + k];
+            for (int k = 0; k < kMaxK; ++k) jp.ring_off[i][t][k] = c->cone_off[(size_t)t * kMaxK + k];
         plane_strides(c->K, &p.ps_a, &p.ps_b);
         p.buf_b = kChunks * p.ps_a;
         total_cap += jobs[i].capacity;
     }
     if (total_cap <= 0) return;
     const size_t lds = cone_lds_bytes(jobs[0].c);
-    (void)hipFuncSetAttribute((const void *)k_net_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    // launches of one or two lattices use the two-job instantiation (fewer
+    // scalar registers; a one-job instantiation spills)
+    const void *fn = n > 2 ? (const void *)k_net_cone<kMaxJobs> : (const void *)k_net_cone<2>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_net_cone, kThreads,
-                                                     lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     // persistent grid of resident workgroups, a multiple of the XCD count
     const int64_t want =
         std::max<int64_t>((int64_t)jobs[0].c->n_cu * per_cu / kXcd * kXcd, kXcd);
-    NQS_LAUNCH(k_net_cone, dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+    if (n > 2)
+        NQS_LAUNCH((k_net_cone<kMaxJobs>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+    else
+        NQS_LAUNCH((k_net_cone<2>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
 }
 
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,

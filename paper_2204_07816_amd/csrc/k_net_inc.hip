@@ -315,16 +315,20 @@ k_net_inc(IncJobs jobs)
     const int64_t n_units = first[kMaxConnJobs];
     const int64_t wl_stride = (int64_t)S::KS * S::NH * 64;
 
-    bf16x8 wa[S::KS][S::NH];
-
-    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    auto job_of = [&](int64_t u) {
         int jb = 0;
 #pragma unroll
         for (int j = 1; j < kMaxConnJobs; ++j) jb = (u >= first[j]) ? j : jb;
+        return jb;
+    };
+    bf16x8 wa[S::KS][S::NH];
+    if (blockIdx.x < n_units) load_weights<C>(wa, jobs.job[job_of(blockIdx.x)].wa, lane);   // layer 2
+
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int jb = job_of(u);
         const IncParams &prm = jobs.job[jb];
         const int64_t unit = u - first[jb];
         const int L = prm.L, N = L * L;
-        load_weights<C>(wa, prm.wa, lane);   // layer 2, in flight while layer 1 runs
         const uint32_t e = prm.queue[unit];
         const int s = item_sample(e);
         const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
@@ -401,8 +405,12 @@ k_net_inc(IncJobs jobs)
             else
                 layer_tiles<C, true>(wa, bias, lds, cur_off, nxt_off, ntiles, npos, mul, ex, wex, nex, wcx, wcy,
                                      L, K, ax, ay, prm.hsum + (int64_t)s * N, wave, g, n16, fsum);
-            // weights of the next layer
-            if (!last) load_weights<C>(wa, prm.wa + (int64_t)(k - 1) * wl_stride, lane);
+            // weights of the next layer, or layer 2's of the next item (whose job
+            // may differ)
+            if (!last)
+                load_weights<C>(wa, prm.wa + (int64_t)(k - 1) * wl_stride, lane);
+            else if (u + gridDim.x < n_units)
+                load_weights<C>(wa, jobs.job[job_of(u + gridDim.x)].wa, lane);
             if (!last) ring_store<C>(ring, nxt, prm, roff[k - 1], roff[k], ax, ay,
                                      cache_s + (int64_t)(k - 1) * N * C);
             __syncthreads();
