@@ -208,6 +208,7 @@ def main():
     ap.add_argument("--fp64-samples", type=int, default=1024)
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-recompute", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -309,6 +310,10 @@ def main():
     t_eloc = timed(lambda: ctx.local_energy(spd, mode=args.mode, out=e))
     t_od = timed(lambda: ctx.log_deriv(spd, dtype="fp32", out=O))
     t_sr = timed(lambda: ctx.sr_solve(O, e, 1e-4, 100, out=x, stats=st4))
+    # CG stops early once the residual is below 1e-30 ||F|| (converged beyond
+    # FP64 resolution): report how far it went on this workload
+    sr_info = {"iterations_run": int(st4[3].item()), "rel_residual": float(st4[2].item()),
+               "iteration_cap": 100}
     e_b = e.cpu().numpy()
     log(f"breakdown ms: eloc {t_eloc:.2f} log_deriv {t_od:.2f} sr {t_sr:.2f}")
 
@@ -369,6 +374,30 @@ def main():
         mixed = mixed_row(dev)
         log(f"mixed lattices: {mixed['samples_per_s']:.1f} samples/s ({mixed['lattices']})")
 
+    recompute = None
+    if not args.no_recompute:
+        # SR with O recomputed from the spins in chunks of 256 samples (for
+        # batches whose O does not fit): per-iteration cost, and equality with
+        # the stored-O solve over the same iterations
+        n_it, rows = 5, 256
+        xr = torch.empty_like(x)
+        sr4 = torch.empty_like(st4)
+        ctx.sr_solve_recompute(spd, e, 1e-4, 1, dtype="fp32", chunk_rows=rows, out=xr, stats=sr4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sr_solve_recompute(spd, e, 1e-4, n_it, dtype="fp32", chunk_rows=rows, out=xr,
+                               stats=sr4)
+        torch.cuda.synchronize()
+        t_rc = (time.perf_counter() - t0) * 1000.0
+        t0 = time.perf_counter()
+        ctx.sr_solve(O, e, 1e-4, n_it, out=x, stats=st4)
+        torch.cuda.synchronize()
+        t_st = (time.perf_counter() - t0) * 1000.0
+        recompute = {"chunk_rows": rows, "iterations": n_it, "ms_total": t_rc,
+                     "stored_O_ms_total": t_st,
+                     "equal_to_stored_O": bool(torch.equal(xr, x))}
+        log(f"sr recompute: {t_rc:.1f} ms for {n_it} iterations, equal {recompute['equal_to_stored_O']}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -386,10 +415,12 @@ def main():
                    "hip_graph": not args.no_graph,
                    "mean_connected": float(counts.mean())},
         "breakdown_ms": {"e_loc": t_eloc, "log_deriv": t_od, "sr_solve": t_sr},
+        "sr_cg": sr_info,
         "eloc_only_samples_per_s": B / (t_eloc * 1e-3),
         "fp64_gpu": fp64,
         "stress_nongating": stress,
         "mixed_lattices_nongating": mixed,
+        "sr_recompute_nongating": recompute,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -136,6 +136,22 @@ nqs_status nqs_sr_solve(nqs_ctx *ctx, const void *O, nqs_dtype O_dtype,
                         int32_t n_iter, double *dtheta, double *stats,
                         void *stream);
 
+/* The same SR solve for batches whose O does not fit in device memory
+ * [Sec. 3.2; Sec. 5.4.1]: O is never stored whole.  Its rows are recomputed
+ * from the spins (device int8 [B][L][L], as nqs_log_deriv computes them, in
+ * O_dtype) in chunks of chunk_rows samples (0: as many as fit in 2 GiB),
+ * rounded up to whole reduction blocks of the solve.  Every pass over O
+ * recomputes the chunks it does not hold, 2 (ceil(B / chunk) - 1) chunks per
+ * CG iteration.  dtheta and stats equal nqs_sr_solve's on the stored O of the
+ * same samples bit for bit.  Workspace: one chunk of O plus the backward's
+ * buffers for it, owned by the context.  Errors as nqs_sr_solve, plus
+ * NQS_E_ARG for chunk_rows < 0 and the spin checks of nqs_log_deriv.        */
+nqs_status nqs_sr_solve_recompute(nqs_ctx *ctx, const int8_t *spins,
+                                  nqs_dtype O_dtype, const double *e_loc,
+                                  int64_t B, double diag_shift, int32_t n_iter,
+                                  int64_t chunk_rows, double *dtheta,
+                                  double *stats, void *stream);
+
 /* Inspection of the integer stage [Sec. 5.4.1]: for every sample the count
  * of antiparallel bonds with J != 0 (int32 [B]), exclusive offsets
  * (int64 [B+1]), the bond ids in canonical order and the Marshall ratio

@@ -298,6 +298,86 @@ void sr_solve_t(const OT *O, const double *e, int64_t B, int64_t P, double lam, 
     if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
 }
 
+
+// The same solve with O never held whole: rows [r0, r0 + nb) of O are
+// produced on demand into a buffer of `chunk` rows by `rows` (which recomputes
+// them from the samples).  chunk is a multiple of the reduction row block, so
+// each block's partial column sums see exactly the rows, in exactly the order,
+// of the stored-O solve, and the results are the same bit for bit.  One pass
+// over O needs nc = ceil(B / chunk) chunks; a pass starts with the chunk left
+// in the buffer by the previous one, so an iteration recomputes 2 (nc - 1)
+// chunks.
+template <typename OT>
+void sr_solve_rows_t(const SrRows &rows, OT *obuf, int64_t chunk, const double *e, int64_t B,
+                     int64_t P, double lam, int n_iter, double *x, double *stats,
+                     unsigned char *w, hipStream_t s)
+{
+    const SrLayout l = layout(B, P);
+    double *obar = (double *)(w + l.off_obar), *F = (double *)(w + l.off_F);
+    double *r = (double *)(w + l.off_r), *p = (double *)(w + l.off_p);
+    double *ap = (double *)(w + l.off_ap), *d = (double *)(w + l.off_d);
+    double *u = (double *)(w + l.off_u), *part = (double *)(w + l.off_part);
+    double *dot = (double *)(w + l.off_dot);
+    SrCtl *ctl = (SrCtl *)(w + l.off_ctl);
+    const int64_t rpc = l.rows_per_chunk;
+    const int64_t nc = (B + chunk - 1) / chunk;
+    const unsigned vgrid = (unsigned)std::min<int64_t>(1024, (P + kThreads - 1) / kThreads);
+    const unsigned fgrid = (unsigned)((P + kThreads - 1) / kThreads);
+    const double invB = 1.0 / (double)B;
+    int64_t resident = -1;   // chunk whose rows are in obuf
+
+    // one pass over all chunks: fn(r0, nb) sees rows [r0, r0 + nb) in obuf
+    auto pass = [&](auto &&fn) {
+        int64_t order0 = resident >= 0 ? resident : 0;
+        for (int64_t i = 0; i < nc; ++i) {
+            const int64_t ci = (order0 + i) % nc;
+            const int64_t r0 = ci * chunk;
+            const int nb = (int)std::min<int64_t>(chunk, B - r0);
+            if (ci != resident) {
+                rows(r0, nb, obuf, s);
+                resident = ci;
+            }
+            fn(r0, nb);
+        }
+    };
+    // partial column sums of rows [r0, r0 + nb) into their reduction blocks
+    auto colsum = [&](int64_t r0, int nb, const double *sub, const double *wt, const SrCtl *c) {
+        const dim3 g(fgrid, (unsigned)((nb + rpc - 1) / rpc));
+        NQS_LAUNCH((k_colsum<OT>), g, dim3(kThreads), 0, s, (const OT *)obuf, (int64_t)nb, P, sub,
+                   wt ? wt + r0 : wt, rpc, part + (r0 / rpc) * P, c);
+    };
+
+    NQS_LAUNCH(k_center, dim3(1), dim3(1024), 0, s, e, B, d, ctl);
+    pass([&](int64_t r0, int nb) {
+        colsum(r0, nb, (const double *)nullptr, (const double *)nullptr, (const SrCtl *)nullptr);
+    });
+    NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P, invB,
+               0.0, (const double *)nullptr, obar, (const SrCtl *)nullptr);
+    pass([&](int64_t r0, int nb) { colsum(r0, nb, obar, d, (const SrCtl *)nullptr); });
+    NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P, invB,
+               0.0, (const double *)nullptr, F, (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_init, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, F, P);
+    NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
+               (const SrCtl *)nullptr);
+    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 0, ctl);
+    for (int it = 0; it < n_iter; ++it) {
+        pass([&](int64_t r0, int nb) {
+            NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+                       (const OT *)obuf, P, obar, p, u + r0, ctl);
+        });
+        pass([&](int64_t r0, int nb) { colsum(r0, nb, obar, u, ctl); });
+        NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
+                   invB, lam, p, ap, ctl);
+        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, p, ap, P, dot, ctl);
+        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 1, ctl);
+        NQS_LAUNCH(k_update_xr, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, ap, P, ctl);
+        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot, ctl);
+        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 2, ctl);
+        NQS_LAUNCH(k_update_p, dim3(vgrid), dim3(kThreads), 0, s, p, r, P, ctl, it + 1);
+    }
+    if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
+}
+
 }  // namespace
 
 size_t sr_workspace_bytes(int64_t B, int64_t P) { return layout(B, P).total; }
@@ -312,6 +392,20 @@ void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t 
     else
         sr_solve_t<double>((const double *)O, e_loc, B, P, lambda, n_iter, x, stats,
                            (unsigned char *)work, s);
+}
+
+int64_t sr_row_block(int64_t B) { return layout(B, 1).rows_per_chunk; }
+
+void launch_sr_solve_rows(const SrRows &rows, void *obuf, int64_t chunk, nqs_dtype odt,
+                          const double *e_loc, int64_t B, int64_t P, double lambda, int n_iter,
+                          double *x, double *stats, void *work, hipStream_t s)
+{
+    if (odt == NQS_FP32)
+        sr_solve_rows_t<float>(rows, (float *)obuf, chunk, e_loc, B, P, lambda, n_iter, x, stats,
+                               (unsigned char *)work, s);
+    else
+        sr_solve_rows_t<double>(rows, (double *)obuf, chunk, e_loc, B, P, lambda, n_iter, x,
+                                stats, (unsigned char *)work, s);
 }
 
 }  // namespace nqs

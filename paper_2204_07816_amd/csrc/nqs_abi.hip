@@ -339,6 +339,65 @@ nqs_status ensure(DevBuf &b, size_t bytes, hipStream_t stream)
 
 }  // namespace nqs
 
+namespace {
+
+// samples per pass of the backward: z of every layer + 2 planes + 2 deltas
+// per sample, at most 6 GB
+int64_t deriv_chunk(const nqs_ctx *c, int64_t B)
+{
+    const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
+    const size_t per = plane * (c->K + 4);
+    const int64_t chunk = (int64_t)(((size_t)6 << 30) / per);
+    return std::max<int64_t>(1, std::min<int64_t>(chunk, B));
+}
+
+nqs_status deriv_reserve(nqs_ctx *c, int64_t chunk, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    const size_t plane = sizeof(double) * (size_t)c->N * c->C;
+    NQS_TRY(ensure(w.zsave, plane * c->K * chunk, s));
+    NQS_TRY(ensure(w.delta, plane * 2 * chunk, s));
+    NQS_TRY(ensure(w.plane_a, plane * chunk, s));
+    NQS_TRY(ensure(w.plane_b, plane * chunk, s));
+    NQS_TRY(ensure(w.fbase, sizeof(double) * chunk, s));
+    NQS_TRY(ensure(w.hsum, plane / c->C * chunk, s));
+    return NQS_OK;
+}
+
+// O rows of B samples (workspace reserved for `chunk` samples per pass).  With
+// pre-activations saved, the vector kernels run in FP64 whatever the
+// context's conv dtype.
+void deriv_rows(const nqs_ctx *c, const int8_t *spins, int64_t B, int64_t chunk, void *O,
+                nqs_dtype odt, hipStream_t s)
+{
+    const Workspace &w = c->ws;
+    const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr, (double *)w.hsum.ptr,
+                         w.plane_a.ptr, w.plane_b.ptr, (double *)w.zsave.ptr, s);
+        double *da = (double *)w.delta.ptr;
+        vec_backward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr, da,
+                     da + (size_t)nb * c->N * c->C, (unsigned char *)O + (size_t)b0 * c->P * esz,
+                     odt, s);
+    }
+}
+
+// rows of O held at once by the recompute SR variant: chunk_rows (0: as many
+// as fit in 2 GiB) rounded up to whole reduction blocks, at most the batch
+int64_t recompute_chunk(const nqs_ctx *c, int64_t B, int64_t chunk_rows, nqs_dtype odt)
+{
+    const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
+    const int64_t blk = sr_row_block(B);
+    int64_t want = chunk_rows > 0
+                       ? chunk_rows
+                       : std::max<int64_t>(1, (int64_t)(((size_t)2 << 30) / (esz * (size_t)c->P)));
+    want = (want + blk - 1) / blk * blk;                      // whole reduction blocks
+    return std::min<int64_t>(want, (B + blk - 1) / blk * blk);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *nqs_status_str(nqs_status s)
@@ -604,30 +663,9 @@ nqs_status nqs_log_deriv(nqs_ctx *c, const int8_t *spins, int64_t B, void *O, nq
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     if (B == 0) return NQS_OK;
-    Workspace &w = c->ws;
-    const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
-    // samples per chunk: z of every layer + 2 planes + 2 deltas per sample
-    const size_t per = plane * (c->K + 4);
-    int64_t chunk = (int64_t)(((size_t)6 << 30) / per);
-    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, B));
-    NQS_TRY(ensure(w.zsave, plane * c->K * chunk, s));
-    NQS_TRY(ensure(w.delta, plane * 2 * chunk, s));
-    NQS_TRY(ensure(w.plane_a, plane * chunk, s));
-    NQS_TRY(ensure(w.plane_b, plane * chunk, s));
-    NQS_TRY(ensure(w.fbase, sizeof(double) * chunk, s));
-    NQS_TRY(ensure(w.hsum, plane / c->C * chunk, s));
-    // with pre-activations saved, the vector kernels run in FP64 whatever the
-    // context's conv dtype
-    const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
-    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
-        const int nb = (int)std::min<int64_t>(chunk, B - b0);
-        vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr, (double *)w.hsum.ptr,
-                         w.plane_a.ptr, w.plane_b.ptr, (double *)w.zsave.ptr, s);
-        double *da = (double *)w.delta.ptr;
-        vec_backward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr, da,
-                     da + (size_t)nb * c->N * c->C, (unsigned char *)O + (size_t)b0 * c->P * esz,
-                     odt, s);
-    }
+    const int64_t chunk = deriv_chunk(c, B);
+    NQS_TRY(deriv_reserve(c, chunk, s));
+    deriv_rows(c, spins, B, chunk, O, odt, s);
     return finish_call();
 }
 
@@ -642,6 +680,32 @@ nqs_status nqs_sr_solve(nqs_ctx *c, const void *O, nqs_dtype odt, const double *
     c->last_stream = s;
     NQS_TRY(ensure(c->ws.sr, sr_workspace_bytes(B, c->P), s));
     launch_sr_solve(O, odt, e_loc, B, c->P, diag_shift, n_iter, dtheta, stats, c->ws.sr.ptr, s);
+    return finish_call();
+}
+
+nqs_status nqs_sr_solve_recompute(nqs_ctx *c, const int8_t *spins, nqs_dtype odt,
+                                  const double *e_loc, int64_t B, double diag_shift,
+                                  int32_t n_iter, int64_t chunk_rows, double *dtheta,
+                                  double *stats, void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (!e_loc || !dtheta || B <= 0 || n_iter < 0 || chunk_rows < 0) return NQS_E_ARG;
+    if (odt != NQS_FP32 && odt != NQS_FP64) return NQS_E_ARG;
+    if (!(diag_shift >= 0.0) || !std::isfinite(diag_shift)) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
+    const int64_t chunk = recompute_chunk(c, B, chunk_rows, odt);
+    const int64_t dchunk = deriv_chunk(c, chunk);
+    NQS_TRY(ensure(c->ws.sr, sr_workspace_bytes(B, c->P), s));
+    NQS_TRY(ensure(c->ws.orows, esz * (size_t)chunk * c->P, s));
+    NQS_TRY(deriv_reserve(c, dchunk, s));
+    const nqs_ctx *cc = c;
+    const SrRows rows = [cc, spins, dchunk, odt](int64_t r0, int nb, void *buf, hipStream_t st) {
+        deriv_rows(cc, spins + r0 * cc->N, nb, dchunk, buf, odt, st);
+    };
+    launch_sr_solve_rows(rows, c->ws.orows.ptr, chunk, odt, e_loc, B, c->P, diag_shift, n_iter,
+                         dtheta, stats, c->ws.sr.ptr, s);
     return finish_call();
 }
 

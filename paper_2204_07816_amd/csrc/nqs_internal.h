@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -51,6 +52,7 @@ struct Workspace {
     DevBuf zsave;       // f64 pre-activations for the backward pass
     DevBuf delta;       // f64 backward deltas
     DevBuf sr;          // SR vectors
+    DevBuf orows;       // O rows of the recompute SR variant
     DevBuf counter;     // work counters for persistent kernels
 };
 
@@ -214,5 +216,14 @@ size_t sr_workspace_bytes(int64_t B, int64_t P);
 void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t B, int64_t P,
                      double lambda, int n_iter, double *x, double *stats, void *work,
                      hipStream_t s);
+// rows of O recomputed on demand: fills rows [r0, r0 + nb) of O into buf
+// (row-major, nb rows) on the stream
+using SrRows = std::function<void(int64_t r0, int nb, void *buf, hipStream_t s)>;
+// rows per reduction block of the SR solve for a batch of B (chunks of the
+// recompute variant are multiples of it)
+int64_t sr_row_block(int64_t B);
+void launch_sr_solve_rows(const SrRows &rows, void *obuf, int64_t chunk, nqs_dtype odt,
+                          const double *e_loc, int64_t B, int64_t P, double lambda, int n_iter,
+                          double *x, double *stats, void *work, hipStream_t s);
 
 }  // namespace nqs

@@ -68,6 +68,7 @@ def load():
         "nqs_energy_stats": [vp, vp, i64, vp, vp],
         "nqs_log_deriv": [vp, vp, i64, vp, i32, vp],
         "nqs_sr_solve": [vp, vp, i32, vp, i64, d, i32, vp, vp, vp],
+        "nqs_sr_solve_recompute": [vp, vp, i32, vp, i64, d, i32, i64, vp, vp, vp],
         "nqs_connected": [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp],
         "nqs_log_ratios": [vp, vp, i64, i32, vp, i64, vp],
         "nqs_local_energy_multi": [vp, i32, i32, vp],
@@ -225,6 +226,25 @@ class Context:
                                    _dev(e_loc, torch.float64, "e_loc"), B, diag_shift, n_iter,
                                    _dev(x, torch.float64, "dtheta"),
                                    _dev(st, torch.float64, "stats"), _stream()), "nqs_sr_solve")
+        return x, st
+
+    def sr_solve_recompute(self, spins, e_loc, diag_shift: float = 1e-4, n_iter: int = 100,
+                           dtype: str = "fp32", chunk_rows: int = 0, out=None, stats=None):
+        """SR with O recomputed from the spins in chunks of chunk_rows samples
+        (0: as many as fit in 2 GiB); equals sr_solve on log_deriv's O."""
+        sp, B = self._spins(spins)
+        if e_loc.numel() != B:
+            raise ValueError("e_loc must have one entry per sample")
+        x = out if out is not None else torch.empty(self.P, dtype=torch.float64,
+                                                    device=spins.device)
+        st = stats if stats is not None else torch.empty(4, dtype=torch.float64,
+                                                         device=spins.device)
+        _check(load().nqs_sr_solve_recompute(self._h, sp, _DTYPES[dtype],
+                                             _dev(e_loc, torch.float64, "e_loc"), B,
+                                             diag_shift, n_iter, chunk_rows,
+                                             _dev(x, torch.float64, "dtheta"),
+                                             _dev(st, torch.float64, "stats"), _stream()),
+               "nqs_sr_solve_recompute")
         return x, st
 
     def capacity(self, B: int) -> int:
