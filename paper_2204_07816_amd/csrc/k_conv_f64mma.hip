@@ -51,7 +51,8 @@ struct ConvArgs {
 // for 64 sites x COUT channels per wave.  GEMM: M = sites, N = co, K = (t, ci)
 // in steps of 4; within a 16-channel block, lane group kq at sub-step s takes
 // channel 4 kq + s, so each lane reads 4 consecutive channels of a site.
-// epi 0: ln cosh; 1: ln cosh and save z; 2: z * tanh(zk) (backward data pass).
+// epi 0: ln cosh; 1: ln cosh and save z; 2: z * tanh(zk) (backward data pass);
+// 3: tanh z (the last layer's delta).
 template <int COUT>
 __global__ void __launch_bounds__(kThreads)
 k_conv_mma(ConvArgs a)
@@ -131,8 +132,10 @@ k_conv_mma(ConvArgs a)
             for (int h = 0; h < NH; ++h) {
                 const int64_t o = obase + (int64_t)p * COUT + 16 * h + m16;
                 const double z = acc[mt][h][i];
-                if (a.epi == 2) {
-                    a.out[o] = z * tanh(a.zk[o]);
+                if (a.epi >= 2) {
+                    // one tanh call site: epi 3 writes tanh z, epi 2 z tanh(zk)
+                    const double th = tanh(a.epi == 3 ? z : a.zk[o]);
+                    a.out[o] = a.epi == 3 ? th : z * th;
                 } else {
                     if (a.epi == 1) a.zk[o] = z;
                     a.out[o] = ln_cosh_d(z);

@@ -54,6 +54,13 @@ struct PlaneMap {
     const int64_t *qlen;     // device queue length (items at or past it are skipped)
 };
 
+inline int grid_for(int64_t work, const nqs_ctx *c)
+{
+    int64_t b = (work + kThreads - 1) / kThreads;
+    int64_t cap = (int64_t)c->n_cu * 8;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
 // Number of planes of this launch that hold real work.
 __device__ inline int64_t live_planes(const PlaneMap &pm, int64_t M)
 {
@@ -81,8 +88,10 @@ __device__ inline void plane_origin(const PlaneMap &pm, int64_t m, int L, int *s
 }
 
 // Layer 1 (one input channel): out[m][p][co] = g(b[co] + sum_t W1[t][co] s(p + t)).
-// W1 packed [9][C] then bias [C].
-template <typename T>
+// W1 packed [9][C] then bias [C].  Each thread produces CPT consecutive
+// channels of one site, so a site's spin gathers serve CPT channels and a
+// wave's stores cover contiguous memory.
+template <typename T, int CPT>
 __global__ void __launch_bounds__(kThreads)
 k_layer1(const int8_t *__restrict__ spins, PlaneMap pm, int64_t M, int L, int C,
          const T *__restrict__ w1, T *__restrict__ out, double *__restrict__ zsave)
@@ -92,11 +101,14 @@ k_layer1(const int8_t *__restrict__ spins, PlaneMap pm, int64_t M, int L, int C,
     for (int q = threadIdx.x; q < 10 * C; q += kThreads) w[q] = w1[q];
     __syncthreads();
     const int N = L * L;
-    const int64_t total = live_planes(pm, M) * N;
+    const int groups = C / CPT;
+    const int64_t total = live_planes(pm, M) * N * groups;
     for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * kThreads) {
-        const int64_t m = g / N;
-        const int p = (int)(g - m * N);
+        const int64_t mp = g / groups;
+        const int co0 = (int)(g - mp * groups) * CPT;
+        const int64_t m = mp / N;
+        const int p = (int)(mp - m * N);
         int s, qi, qj;
         plane_origin(pm, m, L, &s, &qi, &qj);
         const int8_t *sp = spins + (int64_t)s * N;
@@ -107,21 +119,40 @@ k_layer1(const int8_t *__restrict__ spins, PlaneMap pm, int64_t M, int L, int C,
             const int yy = wrapi(y + t / 3 - 1, L), xx = wrapi(x + t % 3 - 1, L);
             sv[t] = (T)spin_at(sp, yy * L + xx, qi, qj);
         }
-        T *o = out + g * C;
-        for (int co = 0; co < C; ++co) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int co = co0 + j;
             T z = w[9 * C + co];
 #pragma unroll
             for (int t = 0; t < 9; ++t) z = fma(w[t * C + co], sv[t], z);
-            if (zsave) zsave[g * C + co] = (double)z;
-            o[co] = ln_cosh(z);
+            if (zsave) zsave[mp * C + co] = (double)z;
+            out[mp * C + co] = ln_cosh(z);
         }
     }
+}
+
+template <typename T>
+void layer1_launch(const nqs_ctx *c, const int8_t *spins, PlaneMap pm, int64_t M, const T *w1,
+                   T *out, double *zsave, hipStream_t s)
+{
+    const int C = c->C;
+    const int64_t sites = M * c->N;
+    const size_t lds = sizeof(T) * 10 * C;
+    if (C % 8 == 0)
+        NQS_LAUNCH((k_layer1<T, 8>), dim3(grid_for(sites * (C / 8), c)), dim3(kThreads), lds, s,
+                   spins, pm, M, c->L, C, w1, out, zsave);
+    else if (C % 4 == 0)
+        NQS_LAUNCH((k_layer1<T, 4>), dim3(grid_for(sites * (C / 4), c)), dim3(kThreads), lds, s,
+                   spins, pm, M, c->L, C, w1, out, zsave);
+    else
+        NQS_LAUNCH((k_layer1<T, 1>), dim3(grid_for(sites * C, c)), dim3(kThreads), lds, s,
+                   spins, pm, M, c->L, C, w1, out, zsave);
 }
 
 // Layers 2..K and the backward data pass: out[m][p][co] = epi(bias[co] +
 // sum_{t, ci} W[t][ci][co] in[m][p + off(t)][ci]).  epi: 0 = ln cosh,
 // 1 = ln cosh and save z to zk[m][p][co], 2 = multiply by tanh(zk[m][p][co])
-// (no bias).  Saved pre-activations are laid out [layer][plane][site][channel].
+// (no bias), 3 = tanh z (the last layer's delta, d ln cosh z / dz).  Saved pre-activations are laid out [layer][plane][site][channel].
 template <typename T, int CPT>
 __global__ void __launch_bounds__(kThreads)
 k_layer(const T *__restrict__ in, int64_t M, int L, int Cin, int Cout,
@@ -159,7 +190,10 @@ k_layer(const T *__restrict__ in, int64_t M, int L, int Cin, int Cout,
             }
         }
         T *o = out + mp * Cout + co0;
-        if (epi == 2) {
+        if (epi == 3) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) o[j] = (T)tanh((double)acc[j]);
+        } else if (epi == 2) {
             const double *zp = zk + mp * Cout + co0;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) o[j] = acc[j] * (T)tanh(zp[j]);
@@ -258,6 +292,51 @@ k_wgrad(const int8_t *__restrict__ spins, const double *__restrict__ hprev,
     }
 }
 
+// Layer-1 weight and bias gradients (one input channel), one sample per block:
+//   dW1[co][t] = sum_p delta[p][co] s(p + off(t)),  db1[co] = sum_p delta[p][co].
+// Thread (part, co) sums the sites p = part (mod nparts); the parts are then
+// added in a fixed order, so the result is deterministic.
+template <typename OT>
+__global__ void __launch_bounds__(kThreads)
+k_wgrad1(const int8_t *__restrict__ spins, const double *__restrict__ delta, int L, int C,
+         int64_t P, int64_t woff, OT *__restrict__ O)
+{
+    __shared__ double red[10][kThreads];
+    const int s = blockIdx.x, N = L * L;
+    const int nparts = kThreads / C;
+    const int co = threadIdx.x % C, part = threadIdx.x / C;
+    double g[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) g[j] = 0.0;
+    if (part < nparts) {
+        const double *dl = delta + (int64_t)s * N * C;
+        const int8_t *sp = spins + (int64_t)s * N;
+        for (int p = part; p < N; p += nparts) {
+            const double d = dl[(int64_t)p * C + co];
+            const int x = p % L, y = p / L;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int r = wrapi(y + t / 3 - 1, L) * L + wrapi(x + t % 3 - 1, L);
+                g[t] = fma(d, (double)sp[r], g[t]);
+            }
+            g[9] += d;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) red[j][threadIdx.x] = g[j];
+    __syncthreads();
+    OT *o = O + (int64_t)s * P + woff;
+    for (int q = threadIdx.x; q < 10 * C; q += kThreads) {
+        const int c2 = q / 10, j = q - 10 * (q / 10);
+        double v = 0.0;
+        for (int pt = 0; pt < nparts; ++pt) v += red[j][pt * C + c2];
+        if (j < 9)
+            o[c2 * 9 + j] = (OT)v;
+        else
+            o[9 * C + c2] = (OT)v;
+    }
+}
+
 // delta_K = tanh(z_K)  (d f / d h_K = 1, d ln cosh z / dz = tanh z)
 __global__ void k_delta_last(const double *__restrict__ zK, int64_t total,
                              double *__restrict__ delta)
@@ -265,14 +344,6 @@ __global__ void k_delta_last(const double *__restrict__ zK, int64_t total,
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x)
         delta[g] = tanh(zK[g]);
-}
-
-// h = ln cosh z, elementwise (activations of a layer from its saved z)
-__global__ void k_act(const double *__restrict__ z, int64_t total, double *__restrict__ h)
-{
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x)
-        h[g] = ln_cosh(z[g]);
 }
 
 template <typename T>
@@ -293,13 +364,6 @@ const float *layer_w<float>(const nqs_ctx *c, int k)
     int64_t off = 10 * (int64_t)c->C;
     for (int l = 1; l < k; ++l) off += 9 * (int64_t)c->C * c->C + c->C;
     return c->w_vec32 + off;
-}
-
-inline int grid_for(int64_t work, const nqs_ctx *c)
-{
-    int64_t b = (work + kThreads - 1) / kThreads;
-    int64_t cap = (int64_t)c->n_cu * 8;
-    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 template <typename T>
@@ -338,17 +402,15 @@ void layer_launch(const nqs_ctx *c, const T *in, int64_t M, int Cin, int Cout, c
 // Forward through all layers for M planes; returns the plane holding h_K.
 template <typename T>
 T *forward_planes(const nqs_ctx *c, const int8_t *spins, PlaneMap pm, int64_t M, T *pa, T *pb,
-                  double *zsave, hipStream_t s)
+                  hipStream_t s)
 {
     const int N = c->N, C = c->C;
     const T *w1 = layer_w<T>(c, 0);
-    NQS_LAUNCH((k_layer1<T>), dim3(grid_for(M * N, c)), dim3(kThreads),
-                       sizeof(T) * 10 * C, s, spins, pm, M, c->L, C, w1, pa, zsave);
+    layer1_launch<T>(c, spins, pm, M, w1, pa, nullptr, s);
     T *cur = pa, *nxt = pb;
     for (int k = 1; k < c->K; ++k) {
         const T *wl = layer_w<T>(c, k);
-        layer_launch<T>(c, cur, M, C, C, wl, wl + 9 * C * C, nxt, zsave ? 1 : 0,
-                        zsave ? zsave + (int64_t)k * M * N * C : nullptr, pm, s);
+        layer_launch<T>(c, cur, M, C, C, wl, wl + 9 * C * C, nxt, 0, nullptr, pm, s);
         T *t = cur;
         cur = nxt;
         nxt = t;
@@ -358,10 +420,10 @@ T *forward_planes(const nqs_ctx *c, const int8_t *spins, PlaneMap pm, int64_t M,
 
 template <typename T>
 void base_forward_t(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
-                    void *plane_a, void *plane_b, double *zsave, hipStream_t s)
+                    void *plane_a, void *plane_b, hipStream_t s)
 {
     PlaneMap pm{nullptr, 0, nullptr};
-    T *hK = forward_planes<T>(c, spins, pm, B, (T *)plane_a, (T *)plane_b, zsave, s);
+    T *hK = forward_planes<T>(c, spins, pm, B, (T *)plane_a, (T *)plane_b, s);
     NQS_LAUNCH((k_final<T>), dim3(B), dim3(kThreads), 0, s, hK, (int64_t)B, c->N, c->C,
                        pm, c->L, f, hsum, (const double *)nullptr, (double *)nullptr, c->err);
 }
@@ -372,7 +434,7 @@ void conn_forward_t(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue
                     double *dlog, void *plane_a, void *plane_b, hipStream_t s)
 {
     PlaneMap pm{queue, q_begin, qlen};
-    T *hK = forward_planes<T>(c, spins, pm, q_count, (T *)plane_a, (T *)plane_b, nullptr, s);
+    T *hK = forward_planes<T>(c, spins, pm, q_count, (T *)plane_a, (T *)plane_b, s);
     NQS_LAUNCH((k_final<T>), dim3((unsigned)q_count), dim3(kThreads), 0, s, hK, q_count,
                        c->N, c->C, pm, c->L, (double *)nullptr, (double *)nullptr, hsum, dlog,
                        c->err);
@@ -387,13 +449,13 @@ size_t vec_plane_bytes(const nqs_ctx *c, int64_t items)
 }
 
 void vec_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
-                      void *plane_a, void *plane_b, double *zsave, hipStream_t s)
+                      void *plane_a, void *plane_b, hipStream_t s)
 {
     if (B <= 0) return;
-    if (c->dtype == NQS_FP32 && zsave == nullptr)
-        base_forward_t<float>(c, spins, B, f, hsum, plane_a, plane_b, nullptr, s);
+    if (c->dtype == NQS_FP32)
+        base_forward_t<float>(c, spins, B, f, hsum, plane_a, plane_b, s);
     else
-        base_forward_t<double>(c, spins, B, f, hsum, plane_a, plane_b, zsave, s);
+        base_forward_t<double>(c, spins, B, f, hsum, plane_a, plane_b, s);
 }
 
 void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
@@ -409,14 +471,38 @@ void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                                plane_b, s);
 }
 
-void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zsave,
-                  double *delta_a, double *delta_b, void *O, nqs_dtype odt, hipStream_t s)
+void vec_deriv_forward(const nqs_ctx *c, const int8_t *spins, int B, double *zsave,
+                       double *hsave, double *delta_last, hipStream_t s)
 {
     if (B <= 0) return;
     const int N = c->N, C = c->C, K = c->K;
-    const int64_t layer = (int64_t)B * N * C;   // one layer of saved z: [B][N][C]
-    NQS_LAUNCH(k_delta_last, dim3(grid_for(layer, c)), dim3(kThreads), 0, s,
-                       zsave + (int64_t)(K - 1) * layer, layer, delta_a);
+    const int64_t layer = (int64_t)B * N * C;
+    const PlaneMap pm{nullptr, 0, nullptr};
+    layer1_launch<double>(c, spins, pm, B, layer_w<double>(c, 0), hsave, zsave, s);
+    if (K == 1) {
+        NQS_LAUNCH(k_delta_last, dim3(grid_for(layer, c)), dim3(kThreads), 0, s, zsave, layer,
+                   delta_last);
+        return;
+    }
+    for (int k = 1; k < K; ++k) {
+        const double *wl = layer_w<double>(c, k);
+        const double *in = hsave + (int64_t)(k - 1) * layer;
+        if (k < K - 1)
+            layer_launch<double>(c, in, B, C, C, wl, wl + 9 * C * C, hsave + (int64_t)k * layer,
+                                 1, zsave + (int64_t)k * layer, pm, s);
+        else
+            layer_launch<double>(c, in, B, C, C, wl, wl + 9 * C * C, delta_last, 3, nullptr, pm,
+                                 s);
+    }
+}
+
+void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zsave,
+                  const double *hsave, double *delta_a, double *delta_b, void *O, nqs_dtype odt,
+                  hipStream_t s)
+{
+    if (B <= 0) return;
+    const int N = c->N, C = c->C, K = c->K;
+    const int64_t layer = (int64_t)B * N * C;   // one layer of saved z or h: [B][N][C]
     double *cur = delta_a, *nxt = delta_b;
     std::vector<int64_t> woff(K);   // layer offsets in the canonical parameter vector
     int64_t off = 0;
@@ -425,27 +511,31 @@ void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zs
         off += (int64_t)C * (k == 0 ? 1 : C) * 9 + C;
     }
     for (int k = K - 1; k >= 0; --k) {
-        const double *zprev = (k == 0) ? nullptr : zsave + (int64_t)(k - 1) * layer;
-        // h_{k-1} into the free buffer; it is overwritten by delta_{k-1} below
-        if (zprev)
-            NQS_LAUNCH(k_act, dim3(grid_for(layer, c)), dim3(kThreads), 0, s, zprev,
-                               layer, nxt);
-        const double *hprev = zprev ? nxt : nullptr;
-        if (hprev && f64mma_wgrad_ok(C))
+        if (k == 0) {
+            if (odt == NQS_FP32)
+                NQS_LAUNCH((k_wgrad1<float>), dim3(B), dim3(kThreads), 0, s, spins, cur, c->L, C,
+                           c->P, woff[0], (float *)O);
+            else
+                NQS_LAUNCH((k_wgrad1<double>), dim3(B), dim3(kThreads), 0, s, spins, cur, c->L,
+                           C, c->P, woff[0], (double *)O);
+            break;
+        }
+        const double *hprev = hsave + (int64_t)(k - 1) * layer;
+        if (f64mma_wgrad_ok(C))
             f64mma_wgrad(c, hprev, cur, B, woff[k], O, odt, s);
         else if (odt == NQS_FP32)
             NQS_LAUNCH((k_wgrad<float>), dim3(B), dim3(kThreads), 0, s, spins, hprev, cur,
-                               c->L, C, k, c->P, woff[k], (float *)O);
+                       c->L, C, k, c->P, woff[k], (float *)O);
         else
-            NQS_LAUNCH((k_wgrad<double>), dim3(B), dim3(kThreads), 0, s, spins, hprev,
-                               cur, c->L, C, k, c->P, woff[k], (double *)O);
-        if (k == 0) break;
+            NQS_LAUNCH((k_wgrad<double>), dim3(B), dim3(kThreads), 0, s, spins, hprev, cur,
+                       c->L, C, k, c->P, woff[k], (double *)O);
         // delta_{k-1} = (W_k^T * delta_k) o tanh(z_{k-1}): a forward-shaped
         // convolution with flipped taps and transposed weights, no bias
         int64_t boff = 0;
         for (int l = 1; l < k; ++l) boff += 9 * (int64_t)C * C;
         layer_launch<double>(c, cur, B, C, C, c->w_bwd64 + boff, nullptr, nxt, 2,
-                             const_cast<double *>(zprev), PlaneMap{nullptr, 0, nullptr}, s);
+                             const_cast<double *>(zsave + (int64_t)(k - 1) * layer),
+                             PlaneMap{nullptr, 0, nullptr}, s);
         double *t = cur;
         cur = nxt;
         nxt = t;

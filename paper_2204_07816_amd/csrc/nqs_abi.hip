@@ -244,7 +244,7 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
         vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
-                         (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr, nullptr, s);
+                         (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr, s);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -341,13 +341,13 @@ nqs_status ensure(DevBuf &b, size_t bytes, hipStream_t stream)
 
 namespace {
 
-// samples per pass of the backward: z of every layer + 2 planes + 2 deltas
-// per sample, at most 6 GB
+// samples per pass of the backward: z and h of layers 1..K-1 plus two
+// deltas per sample, at most 8 GB
 int64_t deriv_chunk(const nqs_ctx *c, int64_t B)
 {
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
-    const size_t per = plane * (c->K + 4);
-    const int64_t chunk = (int64_t)(((size_t)6 << 30) / per);
+    const size_t per = plane * (2 * (size_t)std::max(c->K - 1, 1) + 2);
+    const int64_t chunk = (int64_t)(((size_t)8 << 30) / per);
     return std::max<int64_t>(1, std::min<int64_t>(chunk, B));
 }
 
@@ -355,18 +355,15 @@ nqs_status deriv_reserve(nqs_ctx *c, int64_t chunk, hipStream_t s)
 {
     Workspace &w = c->ws;
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;
-    NQS_TRY(ensure(w.zsave, plane * c->K * chunk, s));
+    const size_t saved = plane * std::max(c->K - 1, 1) * chunk;
+    NQS_TRY(ensure(w.zsave, saved, s));
+    NQS_TRY(ensure(w.hsave, saved, s));
     NQS_TRY(ensure(w.delta, plane * 2 * chunk, s));
-    NQS_TRY(ensure(w.plane_a, plane * chunk, s));
-    NQS_TRY(ensure(w.plane_b, plane * chunk, s));
-    NQS_TRY(ensure(w.fbase, sizeof(double) * chunk, s));
-    NQS_TRY(ensure(w.hsum, plane / c->C * chunk, s));
     return NQS_OK;
 }
 
-// O rows of B samples (workspace reserved for `chunk` samples per pass).  With
-// pre-activations saved, the vector kernels run in FP64 whatever the
-// context's conv dtype.
+// O rows of B samples (workspace reserved for `chunk` samples per pass).  The
+// backward runs in FP64 whatever the context's conv dtype.
 void deriv_rows(const nqs_ctx *c, const int8_t *spins, int64_t B, int64_t chunk, void *O,
                 nqs_dtype odt, hipStream_t s)
 {
@@ -374,12 +371,13 @@ void deriv_rows(const nqs_ctx *c, const int8_t *spins, int64_t B, int64_t chunk,
     const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
-        vec_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr, (double *)w.hsum.ptr,
-                         w.plane_a.ptr, w.plane_b.ptr, (double *)w.zsave.ptr, s);
         double *da = (double *)w.delta.ptr;
-        vec_backward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr, da,
-                     da + (size_t)nb * c->N * c->C, (unsigned char *)O + (size_t)b0 * c->P * esz,
-                     odt, s);
+        double *db = da + (size_t)nb * c->N * c->C;
+        vec_deriv_forward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr,
+                          (double *)w.hsave.ptr, da, s);
+        vec_backward(c, spins + b0 * c->N, nb, (const double *)w.zsave.ptr,
+                     (const double *)w.hsave.ptr, da, db,
+                     (unsigned char *)O + (size_t)b0 * c->P * esz, odt, s);
     }
 }
 
@@ -494,7 +492,8 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->err);
     DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
                       &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,
-                      &c->ws.plane_b, &c->ws.zsave, &c->ws.delta,  &c->ws.sr,   &c->ws.counter};
+                      &c->ws.plane_b, &c->ws.zsave, &c->ws.hsave,  &c->ws.delta, &c->ws.sr,
+                      &c->ws.orows,   &c->ws.counter};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &e : c->events) {
@@ -575,8 +574,7 @@ nqs_status nqs_log_psi(nqs_ctx *c, const int8_t *spins, int64_t B, double *log_a
         for (int64_t b0 = 0; b0 < B; b0 += chunk) {
             const int nb = (int)std::min<int64_t>(chunk, B - b0);
             vec_base_forward(c, spins + b0 * c->N, nb, log_abs + b0,
-                             (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr,
-                             nullptr, s);
+                             (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr, w.plane_b.ptr, s);
         }
     }
     return finish_call();

@@ -50,6 +50,7 @@ struct Workspace {
     DevBuf plane_a;     // scratch planes for the vector path
     DevBuf plane_b;
     DevBuf zsave;       // f64 pre-activations for the backward pass
+    DevBuf hsave;       // f64 activations for the backward pass
     DevBuf delta;       // f64 backward deltas
     DevBuf sr;          // SR vectors
     DevBuf orows;       // O rows of the recompute SR variant
@@ -127,7 +128,7 @@ void launch_queue_expand(const nqs_ctx *c, const uint32_t *queue, const int64_t 
 // --- vector (FP64 / FP32) network kernels (k_conv_vec.hip) ---
 // Base pass over B samples: f[B], hsum[B][N]; planes are scratch [B*N*C].
 void vec_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
-                      void *plane_a, void *plane_b, double *zsave, hipStream_t s);
+                      void *plane_a, void *plane_b, hipStream_t s);
 // Full recompute of every queue item in chunks: dlog[item] = f(S') - f(s).
 // Items q_begin + [0, q_count) of the queue; items at or past qlen[0] are skipped
 // on the device, so the host never needs the queue length.
@@ -136,8 +137,15 @@ void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                       double *dlog, void *plane_a, void *plane_b, hipStream_t s);
 size_t vec_plane_bytes(const nqs_ctx *c, int64_t items);
 // Backward: O[B][P] from the saved pre-activations.
+// forward of B samples for the backward: z and h = ln cosh z of layers
+// 1..K-1 into zsave / hsave ([layer][B][N][C] FP64 each), and the last
+// layer's delta tanh z_K into delta_last
+void vec_deriv_forward(const nqs_ctx *c, const int8_t *spins, int B, double *zsave,
+                       double *hsave, double *delta_last, hipStream_t s);
+// backward from delta_a = delta_K (overwritten, with delta_b) to the rows of O
 void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zsave,
-                  double *delta_a, double *delta_b, void *O, nqs_dtype odt, hipStream_t s);
+                  const double *hsave, double *delta_a, double *delta_b, void *O, nqs_dtype odt,
+                  hipStream_t s);
 
 // --- FP64 matrix-core layer and weight-gradient kernels (k_conv_f64mma.hip) ---
 bool f64mma_conv_ok(int Cin, int Cout);
