@@ -51,6 +51,11 @@ constexpr int kChunks = 4;      // 16-byte chunks of channels per site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
 constexpr int kMaxK = 16;
 constexpr int kMaxJobs = kMaxConnJobs;
+// layer-1 weights in LDS: for each of the 16 channel pairs a thread can own,
+// the 9 taps and the bias of both channels (20 floats); then the biases of
+// layers 2..K (C floats each)
+constexpr int kW1Floats = 16 * 20;
+constexpr int kBiasFloats = (kMaxK - 1) * 32;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte chunk
@@ -163,18 +168,15 @@ __device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, i
 }
 
 // Weights of one layer (A operands, one 16-byte fragment per lane per
-// K-step and half) and the bias of this lane's output rows 16 hh + 4 g + r.
-__device__ __forceinline__ void load_layer(bf16x8 (&wa)[KS][NH], floatx4 (&bias)[NH],
-                                           const ConeParams &p, int k, int lane, int g)
+// K-step and half).
+__device__ __forceinline__ void load_layer(bf16x8 (&wa)[KS][NH], const ConeParams &p, int k,
+                                           int lane)
 {
     const bf16x8 *base = p.wa + (int64_t)(k - 2) * KS * NH * 64;
 #pragma unroll
     for (int j = 0; j < KS; ++j)
 #pragma unroll
         for (int hh = 0; hh < NH; ++hh) wa[j][hh] = base[(j * NH + hh) * 64 + lane];
-#pragma unroll
-    for (int hh = 0; hh < NH; ++hh)
-        bias[hh] = *(const floatx4 *)(p.bias + (k - 1) * C + 16 * hh + 4 * g);
 }
 
 // Everything one tile needs (wave-uniform): the tile's first position in R_k
@@ -267,7 +269,7 @@ __device__ __forceinline__ int active_waves(int ntiles) { return ntiles <= 8 ? 2
 // a time (three workgroups per CU supply the parallelism a second tile in
 // flight would), with the layer's weights in `wa`.
 template <bool last>
-__device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
+__device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const float *bs,
                                            const unsigned char *cur, unsigned char *nxt, int psc,
                                            int psn, int k, int w0, int h0, int L, int K, int ax,
                                            int ay, const double *hsum_s, int wave, int g, int n16,
@@ -284,6 +286,11 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
     const int ntiles = (a.npos + 15) >> 4;
     const int nw = active_waves(ntiles);
     if (wave >= nw) return;
+    // bias of this lane's output rows 16 hh + 4 g + r
+    floatx4 bias[NH];
+#pragma unroll
+    for (int hh = 0; hh < NH; ++hh)
+        bias[hh] = *(const floatx4 *)(bs + (k - 2) * C + 16 * hh + 4 * g);
     int t = wave;
     for (; t < ntiles; t += nw) {
         TileArgs ta[1] = {a};
@@ -326,13 +333,28 @@ k_net_cone(ConeJobs jobs)
         return jb;
     };
     bf16x8 wa[KS][NH];
-    floatx4 bias[NH];
-    if (xcd * seg + slot < u_end) load_layer(wa, bias, jobs.job[job_of(xcd * seg + slot)], 2, lane, g);
+    if (xcd * seg + slot < u_end) load_layer(wa, jobs.job[job_of(xcd * seg + slot)], 2, lane);
+    float *w1s = reinterpret_cast<float *>(lds + kChunks * (jobs.job[0].ps_a + jobs.job[0].ps_b));
+    float *bs = w1s + kW1Floats;   // bias of layer k at bs[(k - 2) C]
+    int w1_job = -1;   // job whose layer-1 weights w1s holds
 
     for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
         const int jb = job_of(u);
         // this job's parameters, read once per configuration
         const ConeParams prm = jobs.job[jb];
+        if (jb != w1_job) {
+            // every thread has passed the previous configuration's barriers, so
+            // nobody still reads the old table
+            for (int q = tid; q < kW1Floats; q += kThreads) {
+                const int m = q / 20, r = q - 20 * (q / 20);
+                const int co = mf::chan_of_slot<C>(2 * m + (r >= 10 ? 1 : 0));
+                const int t = r >= 10 ? r - 10 : r;
+                w1s[q] = t < 9 ? prm.w1[t * C + co] : prm.bias[co];
+            }
+            for (int q = tid; q < (K - 1) * C; q += kThreads) bs[q] = prm.bias[C + q];
+            __syncthreads();
+            w1_job = jb;
+        }
         const int *roff_j = jobs.ring_off[jb][0];
         const int64_t unit = u - first[jb];
         const int L = prm.L, N = L * L;
@@ -368,10 +390,16 @@ k_net_cone(ConeJobs jobs)
                     site = (site == qi) ? qj : ((site == qj) ? qi : site);
                     sv[t] = (float)sp[site];
                 }
-                const float h0v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
-                                                           mf::chan_of_slot<C>(2 * m), sv));
-                const float h1v = mf::ln_cosh(mf::layer1_z(prm.w1, prm.bias, C,
-                                                           mf::chan_of_slot<C>(2 * m + 1), sv));
+                // the base pass's FMA order: bias, then taps 0..8
+                const float *wm = w1s + 20 * m;
+                float z0 = wm[9], z1 = wm[19];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    z0 = __builtin_fmaf(wm[t], sv[t], z0);
+                    z1 = __builtin_fmaf(wm[10 + t], sv[t], z1);
+                }
+                const float h0v = mf::ln_cosh(z0);
+                const float h1v = mf::ln_cosh(z1);
                 const int p2 = ex1 + 4;                  // pitch of W_2 (its width)
                 *(uint32_t *)(lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk +
                               (m & 3) * 4) = pack_bf16(h0v, h1v);
@@ -404,18 +432,18 @@ k_net_cone(ConeJobs jobs)
                 }
             }
             if (k < K)
-                cone_layer<false>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
+                cone_layer<false>(wa, bs, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
                                   wave, g, n16, fsum);
             else
-                cone_layer<true>(wa, bias, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
+                cone_layer<true>(wa, bs, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
                                  wave, g, n16, fsum);
             // weights of the next layer if this wave works on it; after the last,
             // layer 2's of the next configuration (whose job may differ)
             if (k < K) {
                 const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
-                if (wave < active_waves(nt_next)) load_layer(wa, bias, prm, k + 1, lane, g);
+                if (wave < active_waves(nt_next)) load_layer(wa, prm, k + 1, lane);
             } else if (u + per_xcd < u_end) {
-                load_layer(wa, bias, jobs.job[job_of(u + per_xcd)], 2, lane, g);
+                load_layer(wa, jobs.job[job_of(u + per_xcd)], 2, lane);
             }
             __syncthreads();
         }
@@ -460,7 +488,7 @@ size_t cone_lds_bytes(const nqs_ctx *c)
 {
     int a, b;
     plane_strides(c->K, &a, &b);
-    return (size_t)kChunks * (a + b);
+    return (size_t)kChunks * (a + b) + sizeof(float) * (kW1Floats + kBiasFloats);
 }
 
 // Ring tables of the unwrapped geometry: for bond type tau and k = 1..K-1 the
