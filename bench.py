@@ -219,9 +219,9 @@ def main():
                          "1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(samples would be split across GPUs, with one all-reduce of P values "
+              "per CG iteration); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

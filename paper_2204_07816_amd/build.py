@@ -2,7 +2,10 @@
 
 Every .hip file under csrc/ is compiled to an object in parallel, then linked
 into one shared library next to this file.  Packed FP32 instructions are
-disabled for the device code (build flags).
+disabled for the device code.  The FP64 matrix-core kernels are built with
+the VGPR form of the MFMA instructions: with accumulators in AGPRs the
+compiler copies them to and from VGPRs on every step of the weight-gradient
+loop.
 """
 from __future__ import annotations
 
@@ -25,9 +28,15 @@ CFLAGS = [
 ]
 
 
+# extra flags per source file
+FILE_FLAGS = {
+    "k_conv_f64mma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

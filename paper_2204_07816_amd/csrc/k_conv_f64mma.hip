@@ -189,30 +189,47 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
 #pragma unroll
     for (int h = 0; h < NH; ++h) dbp[h] = 0.0;
 
-    int y = kq / L, x = kq - (kq / L) * L;     // site of position p = p0 + kq
-    for (int p0 = 0; p0 < N; p0 += 4) {
-        const int p = p0 + kq;
-        double av[NH], bv[kNT];
+    // operands of K-step p0 (sites p0 .. p0 + 3; this lane's site p = p0 + kq
+    // at (y, x)); a column tile past the last one reads tile 0's column and
+    // is never stored
+    auto fetch = [&](int p, int y, int x, double (&av)[NH], double (&bv)[kNT]) {
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            av[h] = dl[(int64_t)p * C + 16 * h + m16];
-            dbp[h] += av[h];
-        }
+        for (int h = 0; h < NH; ++h) av[h] = dl[(int64_t)p * C + 16 * h + m16];
 #pragma unroll
         for (int j = 0; j < kNT; ++j) {
             const int r = wrapi(y + tdy[j], L) * L + wrapi(x + tdx[j], L);
-            bv[j] = tok[j] ? hs[(int64_t)r * C + tci[j]] : 0.0;
+            bv[j] = hs[(int64_t)r * C + tci[j]];
         }
+    };
+    const int y0 = kq / L, x0 = kq - (kq / L) * L;
+    int y = y0, x = x0;                        // site of position p0 + kq
+    double av[NH], bv[kNT];
+    fetch(kq, y, x, av, bv);
+    // the operands of step p0 + 4 are fetched while the matrix cores work on
+    // p0 (the last step fetches step 0's again, unused, so that the loop has
+    // no branch)
+    for (int p0 = 0; p0 < N; p0 += 4) {
+        int xn = x + 4, yn = y;                // L >= 4: at most one row end
+        if (xn >= L) {
+            xn -= L;
+            ++yn;
+        }
+        const bool more = p0 + 4 < N;
+        double an[NH], bn[kNT];
+        fetch(more ? p0 + 4 + kq : kq, more ? yn : y0, more ? xn : x0, an, bn);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) dbp[h] += av[h];
 #pragma unroll
         for (int h = 0; h < NH; ++h)
 #pragma unroll
             for (int j = 0; j < kNT; ++j)
                 acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[j], acc[h][j], 0, 0, 0);
-        x += 4;                       // L >= 4, so x + 4 passes the row end at most once
-        if (x >= L) {
-            x -= L;
-            ++y;
-        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h) av[h] = an[h];
+#pragma unroll
+        for (int j = 0; j < kNT; ++j) bv[j] = bn[j];
+        x = xn;
+        y = yn;
     }
     OT *o = O + s * P + woff;
     // D element i of this lane: co = 16 h + kq + 4 i, column ci = tci[j]
