@@ -8,7 +8,9 @@
 // O is read as FP32 or FP64; every product, sum and dot is FP64.  Scalars
 // (alpha, beta, r.r) stay on the device, so the solve never synchronises
 // with the host and can be captured in a graph.  All reductions are two-stage
-// with a fixed order (deterministic).
+// with a fixed order (deterministic).  One iteration is five launches: Obar p,
+// the partial column sums of Obar^T u, then three kernels that each finish the
+// previous one's reduction themselves (see k_ap_dot).
 #include <algorithm>
 
 #include "nqs_internal.h"
@@ -21,6 +23,7 @@ constexpr int kMaxChunks = 64;
 
 struct SrCtl {
     double rr, ff, alpha, beta, mean, var;
+    double rrv[2];   // r.r at the start of iteration it, in slot it & 1
     int done, it;
 };
 
@@ -102,62 +105,104 @@ k_dot_part(const double *__restrict__ a, const double *__restrict__ b, int64_t n
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// stage 2 of the dot products, plus the scalar recurrences of CG.
-//   what = 0: initial r.r  -> rr = ff = value; done if ff == 0
-//   what = 1: p.Ap         -> alpha = rr / pap, or done if pap <= 0
-//   what = 2: new r.r      -> beta = rr_new / rr, rr = rr_new, it++, done if converged
+// stage 2 of the initial r.r: rr = ff = value; done if ff == 0
 __global__ void __launch_bounds__(kThreads)
-k_dot_final(const double *__restrict__ part, int nparts, int what, SrCtl *ctl)
+k_dot_final(const double *__restrict__ part, int nparts, SrCtl *ctl)
 {
     __shared__ double sh[kThreads];
-    if (ctl->done) return;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nparts; i += kThreads) acc += part[i];
     acc = block_sum(acc, sh);
     if (threadIdx.x != 0) return;
-    if (what == 0) {
-        ctl->rr = acc;
-        ctl->ff = acc;
-        ctl->it = 0;
-        ctl->done = !(acc > 0.0);
-    } else if (what == 1) {
-        if (!(acc > 0.0)) {
-            ctl->done = 1;
-        } else {
-            ctl->alpha = ctl->rr / acc;
-        }
-    } else {
-        ctl->beta = acc / ctl->rr;
-        ctl->rr = acc;
-        ctl->it += 1;
-        // converged far beyond FP64 resolution: ||r|| <= 1e-30 ||F||
-        if (!(acc > ctl->ff * 1e-60)) ctl->done = 1;
-    }
+    ctl->rr = acc;
+    ctl->rrv[0] = acc;
+    ctl->ff = acc;
+    ctl->it = 0;
+    ctl->done = !(acc > 0.0);
 }
 
-// x += alpha p; r -= alpha Ap
-__global__ void k_update_xr(double *__restrict__ x, double *__restrict__ r,
-                            const double *__restrict__ p, const double *__restrict__ ap, int64_t n,
-                            const SrCtl *ctl)
+// One CG iteration after Ap's partial column sums, in three launches whose
+// final reductions are repeated by every block that needs them (the same
+// fixed-order sum in every block, so every block sees the same value):
+//   k_ap_dot:     Ap = scale * sum_c part[c] + lam p, and per block sum p.Ap;
+//   k_update_xr2: alpha = r.r / p.Ap; x += alpha p, r -= alpha Ap, and per
+//                 block sum r.r (p.Ap <= 0: stop without updating);
+//   k_update_p2:  beta = r.r_new / r.r; p = r + beta p; block 0 records r.r,
+//                 counts the iteration and stops once ||r|| <= 1e-30 ||F||.
+// r.r of iteration `it` lives in slot it & 1, so block 0 can write the next
+// one while the other blocks still read the current one.
+__device__ double sum_parts(const double *part, int n, double *sh)
 {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) acc += part[i];
+    return block_sum(acc, sh);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_ap_dot(const double *__restrict__ part, int nchunk, int64_t P, double scale, double lam,
+         const double *__restrict__ p, double *__restrict__ ap, double *__restrict__ pap_part,
+         const SrCtl *ctl)
+{
+    __shared__ double sh[kThreads];
     if (ctl->done) return;
-    const double a = ctl->alpha;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] = fma(a, p[i], x[i]);
-        r[i] = fma(-a, ap[i], r[i]);
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    double d = 0.0;
+    if (i < P) {
+        double acc = 0.0;
+        for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * P + i];
+        const double v = acc * scale + lam * p[i];
+        ap[i] = v;
+        d = p[i] * v;
     }
+    d = block_sum(d, sh);
+    if (threadIdx.x == 0) pap_part[blockIdx.x] = d;
 }
 
-// p = r + beta p   (runs only after a completed iteration)
-__global__ void k_update_p(double *__restrict__ p, const double *__restrict__ r, int64_t n,
-                           const SrCtl *ctl, int it_expected)
+__global__ void __launch_bounds__(kThreads)
+k_update_xr2(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+             const double *__restrict__ ap, int64_t n, const double *__restrict__ pap_part,
+             int nparts, double *__restrict__ rr_part, SrCtl *ctl, int it)
 {
-    if (ctl->it != it_expected) return;
-    const double b = ctl->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+    __shared__ double sh[kThreads];
+    if (ctl->done) return;
+    const double pap = sum_parts(pap_part, nparts, sh);
+    if (!(pap > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
+        return;
+    }
+    const double a = ctl->rrv[it & 1] / pap;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        x[i] = fma(a, p[i], x[i]);
+        const double ri = fma(-a, ap[i], r[i]);
+        r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = acc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->alpha = a;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_update_p2(double *__restrict__ p, const double *__restrict__ r, int64_t n,
+            const double *__restrict__ rr_part, int nparts, SrCtl *ctl, int it)
+{
+    __shared__ double sh[kThreads];
+    if (ctl->done) return;
+    const double rr_new = sum_parts(rr_part, nparts, sh);
+    const double b = rr_new / ctl->rrv[it & 1];
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
         p[i] = fma(b, p[i], r[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->rrv[(it + 1) & 1] = rr_new;
+        ctl->rr = rr_new;
+        ctl->beta = b;
+        ctl->it = it + 1;
+        // converged far beyond FP64 resolution: ||r|| <= 1e-30 ||F||
+        if (!(rr_new > ctl->ff * 1e-60)) ctl->done = 1;
+    }
 }
 
 // x = 0, r = p = F
@@ -217,7 +262,9 @@ __global__ void k_stats_out(const SrCtl *ctl, double *stats)
 
 struct SrLayout {
     int64_t nchunk, rows_per_chunk, ndot;
-    size_t off_obar, off_F, off_r, off_p, off_ap, off_d, off_u, off_part, off_dot, off_ctl, total;
+    int64_t nblk;   // blocks of kThreads covering P (partials of p.Ap and r.r)
+    size_t off_obar, off_F, off_r, off_p, off_ap, off_d, off_u, off_part, off_dot, off_pap,
+        off_rrp, off_ctl, total;
 };
 
 SrLayout layout(int64_t B, int64_t P)
@@ -226,6 +273,7 @@ SrLayout layout(int64_t B, int64_t P)
     l.nchunk = std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (B + 63) / 64));
     l.rows_per_chunk = (B + l.nchunk - 1) / l.nchunk;
     l.ndot = 512;
+    l.nblk = std::max<int64_t>(1, (P + kThreads - 1) / kThreads);
     size_t off = 0;
     auto take = [&](size_t n) {
         size_t o = off;
@@ -241,9 +289,26 @@ SrLayout layout(int64_t B, int64_t P)
     l.off_u = take(B);
     l.off_part = take((size_t)l.nchunk * P);
     l.off_dot = take(l.ndot);
-    l.off_ctl = take(8);
+    l.off_pap = take(l.nblk);
+    l.off_rrp = take(l.nblk);
+    l.off_ctl = take(sizeof(SrCtl) / sizeof(double) + 1);
     l.total = off;
     return l;
+}
+
+// The rest of CG iteration `it` once Ap's partial column sums are in `part`.
+void cg_tail(const SrLayout &l, int64_t P, double invB, double lam, double *x, double *r,
+             double *p, double *ap, const double *part, unsigned char *w, SrCtl *ctl, int it,
+             hipStream_t s)
+{
+    double *pap = (double *)(w + l.off_pap), *rrp = (double *)(w + l.off_rrp);
+    const unsigned nb = (unsigned)l.nblk;
+    NQS_LAUNCH(k_ap_dot, dim3(nb), dim3(kThreads), 0, s, part, (int)l.nchunk, P, invB, lam,
+               (const double *)p, ap, pap, (const SrCtl *)ctl);
+    NQS_LAUNCH(k_update_xr2, dim3(nb), dim3(kThreads), 0, s, x, r, (const double *)p,
+               (const double *)ap, P, (const double *)pap, (int)nb, rrp, ctl, it);
+    NQS_LAUNCH(k_update_p2, dim3(nb), dim3(kThreads), 0, s, p, (const double *)r, P,
+               (const double *)rrp, (int)nb, ctl, it);
 }
 
 template <typename OT>
@@ -277,23 +342,14 @@ void sr_solve_t(const OT *O, const double *e, int64_t B, int64_t P, double lam, 
     NQS_LAUNCH(k_init, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, F, P);
     NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
                        (const SrCtl *)nullptr);
-    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 0, ctl);
+    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, ctl);
     for (int it = 0; it < n_iter; ++it) {
         // Ap = Obar^T (Obar p) / B + lambda p
         NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)B), dim3(kThreads), 0, s, O, P, obar, p,
                            u, ctl);
         NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P, obar, u,
                            l.rows_per_chunk, part, ctl);
-        NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part,
-                           (int)l.nchunk, P, invB, lam, p, ap, ctl);
-        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, p, ap, P,
-                           dot, ctl);
-        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 1, ctl);
-        NQS_LAUNCH(k_update_xr, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, ap, P, ctl);
-        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
-                           ctl);
-        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 2, ctl);
-        NQS_LAUNCH(k_update_p, dim3(vgrid), dim3(kThreads), 0, s, p, r, P, ctl, it + 1);
+        cg_tail(l, P, invB, lam, x, r, p, ap, part, w, ctl, it, s);
     }
     if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
 }
@@ -359,21 +415,14 @@ void sr_solve_rows_t(const SrRows &rows, OT *obuf, int64_t chunk, const double *
     NQS_LAUNCH(k_init, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, F, P);
     NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot,
                (const SrCtl *)nullptr);
-    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 0, ctl);
+    NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, ctl);
     for (int it = 0; it < n_iter; ++it) {
         pass([&](int64_t r0, int nb) {
             NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)nb), dim3(kThreads), 0, s,
                        (const OT *)obuf, P, obar, p, u + r0, ctl);
         });
         pass([&](int64_t r0, int nb) { colsum(r0, nb, obar, u, ctl); });
-        NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
-                   invB, lam, p, ap, ctl);
-        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, p, ap, P, dot, ctl);
-        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 1, ctl);
-        NQS_LAUNCH(k_update_xr, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, ap, P, ctl);
-        NQS_LAUNCH(k_dot_part, dim3((unsigned)l.ndot), dim3(kThreads), 0, s, r, r, P, dot, ctl);
-        NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, 2, ctl);
-        NQS_LAUNCH(k_update_p, dim3(vgrid), dim3(kThreads), 0, s, p, r, P, ctl, it + 1);
+        cg_tail(l, P, invB, lam, x, r, p, ap, part, w, ctl, it, s);
     }
     if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
 }
