@@ -17,7 +17,7 @@ def rownorm_rel(a, b):
                for s in range(b.shape[0]))
 
 
-@pytest.mark.parametrize("L,K,C,B,sigma", [(4, 2, 4, 64, 0.05), (10, 4, 16, 8, 0.3),
+@pytest.mark.parametrize("L,K,C,B,sigma", [(4, 1, 4, 16, 0.4), (4, 2, 4, 64, 0.05), (10, 4, 16, 8, 0.3),
                                            (6, 3, 5, 6, 0.5), (8, 2, 32, 4, 0.2)])
 def test_log_deriv_vs_oracle(L, K, C, B, sigma):
     say("log_deriv", L, K, C, B)
