@@ -120,3 +120,35 @@ def test_energy_stats_gpu():
     st = ctx.energy_stats(e).cpu().numpy()
     m, v = oracle.energy_stats(e.cpu().numpy())
     assert st[0] == pytest.approx(m, rel=1e-13) and st[1] == pytest.approx(v, rel=1e-12)
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-10), ("bf16", 1e-2)])
+def test_exhaustive_all_states_4x4_gpu(dtype, tol):
+    """Every one of the 2^16 configurations of 4x4 (all Sz sectors), J2 = 0.5,
+    K=2, C=16: the GPU's log|psi| and E_loc give sum |psi|^2 E_loc / sum |psi|^2
+    = <psi|H|psi>/<psi|psi>, with H built by exact diagonalisation's own code;
+    FP64 E_loc also matches the oracle on 1024 of the states."""
+    from oracle import ed
+    L, K, C, J2 = 4, 2, 16, 0.5
+    w = inputs.weights(K, C, 0.1, 7)      # log|psi| spans 1.8 over the states
+    ctx = make_ctx(L, J2, K, C, w, dtype=dtype)
+    codes = np.arange(1 << 16, dtype=np.int64)
+    spins = ed.basis_to_spins(codes, L * L).reshape(-1, L, L)
+    la, sg = ctx.log_psi(to_dev(spins))
+    la, sg = la.cpu().numpy(), sg.cpu().numpy()
+    e = ctx.local_energy(to_dev(spins), mode="full").cpu().numpy()
+    assert ctx.get_error() == 0
+    psi = sg * np.exp(la - la.max())
+    lhs = np.sum(psi ** 2 * e) / np.sum(psi ** 2)
+    ph = pp = 0.0
+    for n_up in range(17):
+        H, basis = ed.hamiltonian(L, 1.0, J2, n_up=n_up)
+        v = psi[basis]
+        ph += v @ (H @ v)
+        pp += v @ v
+    say(dtype, "exhaustive <E>", lhs, "vs <H>", ph / pp)
+    assert abs(lhs - ph / pp) <= tol * abs(ph / pp)
+    if dtype == "fp64":
+        pick = np.random.default_rng(3).choice(1 << 16, size=1024, replace=False)
+        ref = oracle.local_energy(L, 1.0, J2, K, C, w, spins[pick])
+        assert rel_inf(e[pick], ref) <= 1e-10

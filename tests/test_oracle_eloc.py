@@ -5,7 +5,8 @@ and of the exact-diagonalisation support code (Sec. 6.1 Hamiltonian).
   (-11.228483, sanity only; not in the paper) and vs ARPACK.
 * Marshall's theorem at J2 = 0: M(s) psi_0(s) has one sign on the whole sector.
 * Exhaustive identity on 4x4: sum_s |psi|^2 E_loc / sum |psi|^2 = <psi|H|psi>/<psi|psi>
-  for the CNN wave function, with H from ED (independent code).
+  for the CNN wave function, with H from ED (independent code), on single Sz
+  sectors and over all 2^16 states.
 * Zero variance: E_loc of the exact eigenvector equals E_0 on every configuration.
 * Variational bound, translation and spin-flip invariance of E_loc.
 """
@@ -137,3 +138,30 @@ def test_energy_stats(orc):
     e = np.array([1.0, 2.0, 4.0, -3.0])
     m, v = orc.energy_stats(e)
     assert m == 1.0 and v == pytest.approx(np.mean((e - 1.0) ** 2))
+
+
+def test_exhaustive_all_2pow16_states(orc):
+    """The identity over the whole 2^16-state space of 4x4 (every Sz sector):
+    H is block diagonal in Sz, so <psi|H|psi> is the sum over sectors of
+    psi_s^T H_s psi_s, with one common normalisation of psi."""
+    L, K, C, J2 = 4, 2, 4, 0.5
+    w = inputs.weights(K, C, 0.4, seed=7)
+    num = den = ph = pp = 0.0
+    parts = []
+    for n_up in range(17):
+        H, basis = ed.hamiltonian(L, 1.0, J2, n_up=n_up)
+        spins = ed.basis_to_spins(basis, L * L).reshape(-1, L, L)
+        la, sg = orc.log_psi(L, K, C, w, spins)
+        parts.append((H, spins, la, sg))
+    lmax = max(p[2].max() for p in parts)
+    n_states = 0
+    for H, spins, la, sg in parts:
+        psi = sg * np.exp(la - lmax)
+        eloc = orc.local_energy(L, 1.0, J2, K, C, w, spins)
+        num += np.sum(psi ** 2 * eloc)
+        den += np.sum(psi ** 2)
+        ph += psi @ (H @ psi)
+        pp += psi @ psi
+        n_states += spins.shape[0]
+    assert n_states == 1 << 16
+    assert num / den == pytest.approx(ph / pp, rel=1e-12)
