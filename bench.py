@@ -209,6 +209,7 @@ def main():
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-recompute", action="store_true")
+    ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -398,6 +399,29 @@ def main():
                      "equal_to_stored_O": bool(torch.equal(xr, x))}
         log(f"sr recompute: {t_rc:.1f} ms for {n_it} iterations, equal {recompute['equal_to_stored_O']}")
 
+    mcmc = None
+    if not args.no_mcmc:
+        # Metropolis steps of the 1024 chains (one pair-exchange proposal per
+        # chain per step), seeded random numbers on the device
+        n_st = 20
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2024)
+        rb = torch.randint(0, 2 ** 31 - 1, (n_st, B), device=dev, dtype=torch.int64,
+                           generator=gen).to(torch.int32)
+        ru = torch.rand(n_st, B, device=dev, dtype=torch.float64, generator=gen)
+        chains = spd.clone()
+        ctx.mcmc(chains, rb[:1], ru[:1], mode=args.mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = ctx.mcmc(chains, rb, ru, mode=args.mode)
+        torch.cuda.synchronize()
+        t_mc = (time.perf_counter() - t0) * 1000.0
+        mcmc = {"chains": B, "steps": n_st, "ms_per_step": t_mc / n_st,
+                "proposals_per_s": B * n_st / (t_mc * 1e-3),
+                "acceptance": float(acc.sum().item()) / (B * n_st)}
+        log(f"mcmc: {mcmc['ms_per_step']:.3f} ms per step of {B} chains, "
+            f"acceptance {mcmc['acceptance']:.3f}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -421,6 +445,7 @@ def main():
         "stress_nongating": stress,
         "mixed_lattices_nongating": mixed,
         "sr_recompute_nongating": recompute,
+        "mcmc_nongating": mcmc,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

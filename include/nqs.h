@@ -169,6 +169,22 @@ nqs_status nqs_log_ratios(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                           nqs_mode mode, double *dlog, int64_t capacity,
                           void *stream);
 
+/* Metropolis sampling of |psi|^2 by pair exchanges [Sec. 3.2; Sec. 5.4.1],
+ * n_steps steps of every chain; chain b is sample b of spins (device int8
+ * [B][L][L], updated in place).  Step t of chain b: the proposal is bond
+ * q = rand_bond[t B + b] mod (N * n), n = 2 (J1 or J2 bonds only) or 4 (both),
+ * site q / n, type the (q mod n)-th of those of the non-zero couplings
+ * (canonical bond id 4 site + type); an antiparallel pair is exchanged when
+ * rand_u[t B + b] < exp(2 (f(S') - f(S))).  The proposal is symmetric, so the
+ * chains sample |psi|^2.  rand_bond: device uint32 [n_steps][B]; rand_u:
+ * device FP64 [n_steps][B] in [0, 1); accepted (device int32 [B], may be
+ * NULL) is increased by each chain's accepted exchanges.  f(S') - f(S) is
+ * computed as nqs_local_energy computes it, in `mode`.  No coupling: no
+ * move.  Errors as nqs_local_energy.                                       */
+nqs_status nqs_mcmc(nqs_ctx *ctx, int8_t *spins, int64_t B, int32_t n_steps,
+                    const uint32_t *rand_bond, const double *rand_u,
+                    int32_t *accepted, nqs_mode mode, void *stream);
+
 /* Several lattices at once: every job has its own context (same network
  * shape and conv dtype, any L, J2 and weights; no context twice).  With BF16
  * contexts each lattice runs its bond stage and base pass, then the

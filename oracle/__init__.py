@@ -195,3 +195,38 @@ def sr_apply(O, v, lam: float = 1e-4):
     _load().oracle_sr_apply(_p(O, ctypes.c_double), B, P, lam, _p(v, ctypes.c_double),
                             _p(y, ctypes.c_double))
     return y
+
+
+def mcmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, rand_bond, rand_u):
+    """Metropolis sampling of |psi|^2 by pair exchanges (Sec. 3.2: walkers
+    sample |psi|^2; Sec. 5.4.1: independent chains whose proposals are the
+    exchanged configurations).  Step t of chain b proposes the bond of
+    q = rand_bond[t, b] mod (N n), n = 2 for one non-zero coupling and 4 for
+    both: site q // n, type the (q mod n)-th of the types of the non-zero
+    couplings (J1: 0, 1; J2: 2, 3).  An antiparallel pair is exchanged when
+    rand_u[t, b] < exp(2 (f(S') - f(S))), f = log|psi| by two full forwards.
+    Returns (spins after the steps, accepted moves per chain)."""
+    s = _spins(spins, L).copy()
+    B, N = s.shape
+    types = ([0, 1] if J1 != 0.0 else []) + ([2, 3] if J2 != 0.0 else [])
+    acc = np.zeros(B, np.int64)
+    if not types:
+        return s.reshape(B, L, L), acc
+    rb = np.asarray(rand_bond, np.int64).astype(np.uint32)
+    ru = np.asarray(rand_u, np.float64)
+    n = len(types)
+    for t in range(rb.shape[0]):
+        prop = s.copy()
+        pairs = []
+        for b in range(B):
+            q = int(rb[t, b]) % (N * n)
+            i, j, _ = bond_sites(L, 4 * (q // n) + types[q % n])
+            pairs.append((i, j))
+            prop[b, i], prop[b, j] = s[b, j], s[b, i]
+        f0, _ = log_psi(L, K, C, w, s)
+        f1, _ = log_psi(L, K, C, w, prop)
+        for b, (i, j) in enumerate(pairs):
+            if s[b, i] != s[b, j] and ru[t, b] < np.exp(2.0 * (f1[b] - f0[b])):
+                s[b] = prop[b]
+                acc[b] += 1
+    return s.reshape(B, L, L), acc

@@ -707,6 +707,32 @@ nqs_status nqs_sr_solve_recompute(nqs_ctx *c, const int8_t *spins, nqs_dtype odt
     return finish_call();
 }
 
+nqs_status nqs_mcmc(nqs_ctx *c, int8_t *spins, int64_t B, int32_t n_steps,
+                    const uint32_t *rand_bond, const double *rand_u, int32_t *accepted,
+                    nqs_mode mode, void *stream)
+{
+    NQS_TRY(check_common(c, spins, B));
+    if (n_steps < 0) return NQS_E_ARG;
+    if (mode != NQS_AUTO && mode != NQS_FULL && mode != NQS_INCREMENTAL) return NQS_E_ARG;
+    if (B > 0 && n_steps > 0 && (!rand_bond || !rand_u)) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (B == 0 || n_steps == 0 || bonds_per_sample(c) == 0) return NQS_OK;
+    const nqs_mode m = resolve_mode(c, mode);
+    Workspace &w = c->ws;
+    NQS_TRY(ensure(w.queue, sizeof(uint32_t) * B, s));
+    NQS_TRY(ensure(w.qlen, sizeof(int64_t) * 4, s));
+    NQS_TRY(ensure(w.dlog, sizeof(double) * B, s));
+    for (int32_t t = 0; t < n_steps; ++t) {
+        launch_mcmc_propose(c, (int)B, rand_bond + (int64_t)t * B, (uint32_t *)w.queue.ptr,
+                            (int64_t *)w.qlen.ptr, s);
+        NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)w.dlog.ptr, B, s));
+        launch_mcmc_accept(c, spins, (int)B, (const uint32_t *)w.queue.ptr,
+                           (const double *)w.dlog.ptr, rand_u + (int64_t)t * B, accepted, s);
+    }
+    return finish_call();
+}
+
 nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode mode, void *stream)
 {
     if (!jobs || n < 0) return NQS_E_ARG;

@@ -220,6 +220,14 @@ void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const
                           const double *dlog, const double *ediag, double *e_loc, int32_t *err,
                           hipStream_t s);
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
+
+// --- Metropolis sampling (k_mcmc.hip) ---
+// queue[s] = (s, bond of proposal rnd[s]), qlen[0] = B
+void launch_mcmc_propose(const nqs_ctx *c, int B, const uint32_t *rnd, uint32_t *queue,
+                         int64_t *qlen, hipStream_t s);
+// exchange the pair of queue[s] in chain s when antiparallel and u[s] < exp(2 dlog[s])
+void launch_mcmc_accept(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
+                        const double *dlog, const double *u, int32_t *accepted, hipStream_t s);
 size_t sr_workspace_bytes(int64_t B, int64_t P);
 void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t B, int64_t P,
                      double lambda, int n_iter, double *x, double *stats, void *work,

@@ -72,6 +72,7 @@ def load():
         "nqs_connected": [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp],
         "nqs_log_ratios": [vp, vp, i64, i32, vp, i64, vp],
         "nqs_local_energy_multi": [vp, i32, i32, vp],
+        "nqs_mcmc": [vp, vp, i64, i32, vp, vp, vp, i32, vp],
         "nqs_auto_mode": [vp, P(i32)],
         "nqs_autotune": [vp, vp, i64, P(i32), vp],
         "nqs_tune_key": [i32, i32, i32, i32, d, ctypes.c_char_p, i64],
@@ -198,6 +199,29 @@ class Context:
         _check(load().nqs_local_energy(self._h, sp, B, _dev(e, torch.float64, "e_loc"),
                                        _MODES[mode], _stream()), "nqs_local_energy")
         return e
+
+    def mcmc(self, spins, rand_bond, rand_u, accepted=None, mode: str = "auto"):
+        """Metropolis steps of every chain (sample) of `spins`, in place:
+        rand_bond [n_steps, B] int32 (its bits read as uint32) or int64 with
+        values in [0, 2^31); rand_u FP64 [n_steps, B] in [0, 1).  Returns the
+        per-chain accepted counts (int32 [B], added to)."""
+        sp, B = self._spins(spins)
+        if rand_bond.dim() != 2 or rand_bond.shape[1] != B or rand_u.shape != rand_bond.shape:
+            raise ValueError("rand_bond and rand_u must both be [n_steps, B]")
+        n_steps = rand_bond.shape[0]
+        rb = rand_bond
+        if rb.dtype != torch.int32:
+            if bool(((rb < 0) | (rb >= 2 ** 31)).any()):
+                raise ValueError("int64 rand_bond values must lie in [0, 2^31)")
+            rb = rb.to(torch.int32)
+        rb = rb.contiguous()
+        ru = rand_u.to(torch.float64).contiguous()
+        acc = accepted if accepted is not None else torch.zeros(B, dtype=torch.int32,
+                                                                device=spins.device)
+        _check(load().nqs_mcmc(self._h, sp, B, n_steps, _dev(rb, torch.int32, "rand_bond"),
+                               _dev(ru, torch.float64, "rand_u"), _dev(acc, torch.int32, "accepted"),
+                               _MODES[mode], _stream()), "nqs_mcmc")
+        return acc
 
     def energy_stats(self, e_loc, out=None):
         st = out if out is not None else torch.empty(2, dtype=torch.float64, device=e_loc.device)
