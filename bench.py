@@ -210,6 +210,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-recompute", action="store_true")
     ap.add_argument("--no-mcmc", action="store_true")
+    ap.add_argument("--no-vmc", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -422,6 +423,25 @@ def main():
         log(f"mcmc: {mcmc['ms_per_step']:.3f} ms per step of {B} chains, "
             f"acceptance {mcmc['acceptance']:.3f}")
 
+    vmc = None
+    if not args.no_vmc:
+        # whole VMC iterations: 10 Metropolis steps of the chains, E_loc,
+        # statistics, O (FP32), SR and the weight update (host repacking)
+        from paper_2204_07816_amd.vmc import VMC
+        cv = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16")
+        run = VMC(cv, w, spd.clone(), steps=10, lr=0.01, diag_shift=1e-3, cg_iters=100,
+                  seed=3, o_dtype="fp32", mode=args.mode)
+        run.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = [run.step() for _ in range(2)]
+        torch.cuda.synchronize()
+        t_v = (time.perf_counter() - t0) * 1000.0 / 2
+        vmc = {"ms_per_iteration": t_v, "chains": B, "mcmc_steps_per_iteration": 10,
+               "samples_per_s": B / (t_v * 1e-3), "energies": [h["energy"] for h in hist]}
+        log(f"vmc: {t_v:.1f} ms per iteration")
+        cv.close()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -446,6 +466,7 @@ def main():
         "mixed_lattices_nongating": mixed,
         "sr_recompute_nongating": recompute,
         "mcmc_nongating": mcmc,
+        "vmc_iteration_nongating": vmc,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -230,3 +230,27 @@ def mcmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, rand_bond, rand
                 s[b] = prop[b]
                 acc[b] += 1
     return s.reshape(B, L, L), acc
+
+
+def vmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, n_iter: int, steps: int,
+        lr: float, lam: float, cg_iters: int, randoms):
+    """The variational Monte Carlo self-learning loop (Sec. 3.2): per
+    iteration, `steps` Metropolis steps of every chain, the local energies and
+    log-derivatives of the resulting samples, the SR direction by CG
+    (sr_cg), and the update theta <- theta - lr * delta.  randoms(it) gives the
+    iteration's (rand_bond, rand_u).  Returns (energy means per iteration,
+    variances per iteration, final weights, final spins)."""
+    w = np.array(w, np.float64)
+    s = _spins(spins, L).reshape(-1, L, L).copy()
+    means, variances = [], []
+    for it in range(n_iter):
+        rb, ru = randoms(it)
+        s, _ = mcmc(L, J1, J2, K, C, w, s, rb, ru)
+        e = local_energy(L, J1, J2, K, C, w, s)
+        m, v = energy_stats(e)
+        means.append(m)
+        variances.append(v)
+        O = log_deriv(L, K, C, w, s)
+        x, _, _ = sr_cg(O, e, lam, cg_iters)
+        w = w - lr * x
+    return np.array(means), np.array(variances), w, s

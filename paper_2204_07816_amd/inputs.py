@@ -99,3 +99,12 @@ def config_inputs(name: str, B: int | None = None, lattice: int = 0):
     w = weights(cfg["K"], cfg["C"], cfg["sigma"], 1000 + idx)
     s = spins_sz0(L, nb, sseed)
     return L, J2, cfg["K"], cfg["C"], w, s
+
+
+def mcmc_randoms(seed: int, iteration: int, steps: int, B: int):
+    """Random numbers of `steps` Metropolis steps of B chains for one
+    iteration of a sampling loop: (proposal integers in [0, 2^31) int64
+    [steps, B], uniforms in [0, 1) FP64 [steps, B]), from the stream seeded by
+    (seed, iteration)."""
+    rng = np.random.Generator(np.random.PCG64([seed, iteration]))
+    return rng.integers(0, 2 ** 31, size=(steps, B)), rng.random((steps, B))
