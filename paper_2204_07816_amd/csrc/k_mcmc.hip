@@ -10,6 +10,10 @@
 //            energy (a parallel pair gives S' = S and exactly 0);
 //   accept:  an antiparallel pair is exchanged when u < exp(2 (f(S') - f(S))),
 //            u the caller's uniform number in [0, 1).
+// Where the incremental cone kernel serves, the base pass is taken once and
+// then kept current: accepted chains run a write-back pass of the cone kernel
+// (their cone's activations and site sums replace the cached ones, which is
+// what a new base pass would give) before their pairs are exchanged.
 // The proposal is symmetric (the reverse move picks the same bond), so the
 // chain satisfies detailed balance for |psi|^2.
 #include <algorithm>
@@ -42,27 +46,56 @@ k_mcmc_propose(const uint32_t *__restrict__ rnd, int B, int N, int j1, int j2,
     queue[s] = pack_item(s, proposal_bond(rnd[s], N, j1, j2));
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_mcmc_accept(int8_t *__restrict__ spins, int B, int L, const uint32_t *__restrict__ queue,
-              const double *__restrict__ dlog, const double *__restrict__ u,
-              int32_t *__restrict__ accepted)
+// Sites of the pair of queue item e in chain s.
+__device__ inline void item_pair(uint32_t e, int L, int *i, int *j)
 {
-    const int s = blockIdx.x * kThreads + threadIdx.x;
-    if (s >= B) return;
-    const int b = item_bond(queue[s]);
-    const int i = b >> 2, t = b & 3;
-    const int x = i % L, y = i / L;
+    const int b = item_bond(e);
+    const int i0 = b >> 2, t = b & 3;
+    const int x = i0 % L, y = i0 / L;
     int xj = x + bond_dx(t), yj = y + bond_dy(t);
     xj = xj < 0 ? xj + L : (xj >= L ? xj - L : xj);
     yj = yj < 0 ? yj + L : (yj >= L ? yj - L : yj);
-    const int j = yj * L + xj;
+    *i = i0;
+    *j = yj * L + xj;
+}
+
+// flag[s] = 1 when chain s accepts its proposal (antiparallel pair and
+// u < exp(2 dlog)); with apply, the pair is exchanged at once.
+__global__ void __launch_bounds__(kThreads)
+k_mcmc_decide(int8_t *__restrict__ spins, int B, int L, const uint32_t *__restrict__ queue,
+              const double *__restrict__ dlog, const double *__restrict__ u,
+              int32_t *__restrict__ flag, int32_t *__restrict__ accepted, int apply)
+{
+    const int s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= B) return;
+    int i, j;
+    item_pair(queue[s], L, &i, &j);
     int8_t *sp = spins + (int64_t)s * L * L;
     const int8_t si = sp[i], sj = sp[j];
-    if (si != sj && u[s] < exp(2.0 * dlog[s])) {
-        sp[i] = sj;
-        sp[j] = si;
+    const int ok = (si != sj && u[s] < exp(2.0 * dlog[s])) ? 1 : 0;
+    if (flag) flag[s] = ok;
+    if (ok) {
+        if (apply) {
+            sp[i] = sj;
+            sp[j] = si;
+        }
         if (accepted) accepted[s] += 1;
     }
+}
+
+// exchange the pairs of the flagged chains
+__global__ void __launch_bounds__(kThreads)
+k_mcmc_apply(int8_t *__restrict__ spins, int B, int L, const uint32_t *__restrict__ queue,
+             const int32_t *__restrict__ flag)
+{
+    const int s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= B || !flag[s]) return;
+    int i, j;
+    item_pair(queue[s], L, &i, &j);
+    int8_t *sp = spins + (int64_t)s * L * L;
+    const int8_t si = sp[i];
+    sp[i] = sp[j];
+    sp[j] = si;
 }
 
 }  // namespace
@@ -75,12 +108,20 @@ void launch_mcmc_propose(const nqs_ctx *c, int B, const uint32_t *rnd, uint32_t 
                c->J1 != 0.0 ? 1 : 0, c->J2 != 0.0 ? 1 : 0, queue, qlen);
 }
 
-void launch_mcmc_accept(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
-                        const double *dlog, const double *u, int32_t *accepted, hipStream_t s)
+void launch_mcmc_decide(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
+                        const double *dlog, const double *u, int32_t *flag, int32_t *accepted,
+                        bool apply, hipStream_t s)
 {
     const int grid = std::max(1, (B + kThreads - 1) / kThreads);
-    NQS_LAUNCH(k_mcmc_accept, dim3(grid), dim3(kThreads), 0, s, spins, B, c->L, queue, dlog, u,
-               accepted);
+    NQS_LAUNCH(k_mcmc_decide, dim3(grid), dim3(kThreads), 0, s, spins, B, c->L, queue, dlog, u,
+               flag, accepted, apply ? 1 : 0);
+}
+
+void launch_mcmc_apply(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
+                       const int32_t *flag, hipStream_t s)
+{
+    const int grid = std::max(1, (B + kThreads - 1) / kThreads);
+    NQS_LAUNCH(k_mcmc_apply, dim3(grid), dim3(kThreads), 0, s, spins, B, c->L, queue, flag);
 }
 
 }  // namespace nqs

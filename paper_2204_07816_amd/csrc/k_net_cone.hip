@@ -77,6 +77,12 @@ struct ConeParams {
     int ps_a, ps_b;            // plane strides (bytes) of the even- and odd-layer buffers
     int buf_b;                 // byte offset of the odd-layer buffer (4 planes of ps_a)
     const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
+    // write-back launches only: the configuration S' of every item whose
+    // chain has commit[chain] != 0 becomes the chain's base pass (the cone's
+    // activations replace the cache and its site sums replace hsum)
+    const int32_t *commit;
+    uint16_t *cache_w;
+    double *hsum_w;
 };
 
 // Up to kMaxJobs lattices (contexts of one network shape) in one launch: their
@@ -191,9 +197,10 @@ struct TileArgs {
 
 // NT tiles of one layer.  Inner layers store the BF16 activations into
 // W_{k+1}; the last layer accumulates the site sums.
-template <bool last, int NT>
+template <bool last, int NT, bool COMMIT>
 __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
                                            const unsigned char *cur, unsigned char *nxt,
+                                           uint16_t *wcache, double *whsum, int k,
                                            const TileArgs (&ta)[NT], int L, int K, int ax, int ay,
                                            const double *hsum_s, int g, int n16, double &fsum)
 {
@@ -201,6 +208,7 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
     int ain[NT], aout[NT];
     bool valid[NT];
     double hs_base[NT];
+    int site_w[NT];            // lattice site of the output (write-back launches)
 #pragma unroll
     for (int w = 0; w < NT; ++w) {
         int p = ta[w].p0 + n16;
@@ -215,10 +223,9 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
         // output goes to W_{k+1} site (u + 2, v + 2)
         aout[w] = __mul24(g, ta[w].psn) + __mul24(v + 2, ta[w].q16) + u16 + 2 * kChunk;
         hs_base[w] = 0.0;
-        if (last) {
-            const int site = wrap_l(ay + v - K, L) * L + wrap_l(ax + u - K, L);
-            hs_base[w] = hsum_s[site];
-        }
+        site_w[w] = 0;
+        if (last || COMMIT) site_w[w] = wrap_l(ay + v - k, L) * L + wrap_l(ax + u - k, L);
+        if (last) hs_base[w] = hsum_s[site_w[w]];
     }
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
@@ -249,6 +256,7 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
                 const u32x4 pk = {pack_bf16(hv[0], hv[1]), pack_bf16(hv[2], hv[3]),
                                   pack_bf16(hv[4], hv[5]), pack_bf16(hv[6], hv[7])};
                 *(u32x4 *)(nxt + aout[w]) = pk;
+                if (COMMIT) *(u32x4 *)(wcache + site_w[w] * C + g * 8) = pk;
             }
         } else {
             double part = 0.0;
@@ -256,7 +264,10 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
             for (int r = 0; r < 8; ++r) part += (double)hv[r];
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
-            if (g == 0 && valid[w]) fsum += part - hs_base[w];
+            if (g == 0 && valid[w]) {
+                fsum += part - hs_base[w];
+                if (COMMIT) whsum[site_w[w]] = part;
+            }
         }
     }
 }
@@ -268,9 +279,10 @@ __device__ __forceinline__ int active_waves(int ntiles) { return ntiles <= 8 ? 2
 // All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), one at
 // a time (three workgroups per CU supply the parallelism a second tile in
 // flight would), with the layer's weights in `wa`.
-template <bool last>
+template <bool last, bool COMMIT>
 __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const float *bs,
-                                           const unsigned char *cur, unsigned char *nxt, int psc,
+                                           const unsigned char *cur, unsigned char *nxt,
+                                           uint16_t *wcache, double *whsum, int psc,
                                            int psn, int k, int w0, int h0, int L, int K, int ax,
                                            int ay, const double *hsum_s, int wave, int g, int n16,
                                            double &fsum)
@@ -295,13 +307,19 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
     for (; t < ntiles; t += nw) {
         TileArgs ta[1] = {a};
         ta[0].p0 = t * 16;
-        cone_group<last, 1>(wa, bias, cur, nxt, ta, L, K, ax, ay, hsum_s, g, n16, fsum);
+        cone_group<last, 1, COMMIT>(wa, bias, cur, nxt, wcache, whsum, k, ta, L, K, ax, ay,
+                                    hsum_s, g, n16, fsum);
     }
 }
 
 // Three workgroups per CU: 166 VGPRs and 46 KB of LDS (K = 8) each.
-// NJ: the number of jobs the launch can hold.
-template <int NJ>
+// NJ: the number of jobs the launch can hold.  COMMIT: write-back launch (one
+// job): items whose chain is flagged in commit[] store the activations of
+// their cone into the cache and their site sums into hsum, so that the cache
+// becomes the base pass of S' (the arithmetic is the base pass's, so the
+// values are those a new base pass would give); other items are skipped.
+// Reads of the cache (ring, layer k) and writes (R_k, layer k) never meet.
+template <int NJ, bool COMMIT>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_net_cone(ConeJobs jobs)
 {
@@ -360,6 +378,7 @@ k_net_cone(ConeJobs jobs)
         const int L = prm.L, N = L * L;
         const uint32_t e = prm.queue[unit];
         const int s = item_sample(e);
+        if (COMMIT && prm.commit[s] == 0) continue;   // uniform over the workgroup
         const int b = item_bond(e), tau = b & 3, i0 = b >> 2;
         const int xi = i0 % L, yi = i0 / L;
         const int qi = i0, qj = wrap_l(yi + bond_dy(tau), L) * L + wrap_l(xi + bond_dx(tau), L);
@@ -368,6 +387,8 @@ k_net_cone(ConeJobs jobs)
         const int8_t *sp = prm.spins + (int64_t)s * N;
         const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
         const double *hsum_s = prm.hsum + (int64_t)s * N;
+        uint16_t *wcache_s = COMMIT ? prm.cache_w + (int64_t)s * (K - 1) * N * C : nullptr;
+        double *whsum_s = COMMIT ? prm.hsum_w + (int64_t)s * N : nullptr;
 
         const int *roff = roff_j + tau * kMaxK;
 
@@ -403,6 +424,9 @@ k_net_cone(ConeJobs jobs)
                 const int p2 = ex1 + 4;                  // pitch of W_2 (its width)
                 *(uint32_t *)(lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk +
                               (m & 3) * 4) = pack_bf16(h0v, h1v);
+                if (COMMIT)
+                    *(uint32_t *)(wcache_s + (gy * L + gx) * C + (m >> 2) * 8 + (m & 3) * 2) =
+                        pack_bf16(h0v, h1v);
             }
             ring_store(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, prm.ps_a, cache_s);
         }
@@ -431,12 +455,13 @@ k_net_cone(ConeJobs jobs)
                                   tid);
                 }
             }
+            uint16_t *wc = COMMIT ? wcache_s + (int64_t)(k - 1) * N * C : nullptr;
             if (k < K)
-                cone_layer<false>(wa, bs, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
-                                  wave, g, n16, fsum);
+                cone_layer<false, COMMIT>(wa, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0, L, K,
+                                          ax, ay, hsum_s, wave, g, n16, fsum);
             else
-                cone_layer<true>(wa, bs, cur, nxt, psc, psn, k, w0, h0, L, K, ax, ay, hsum_s,
-                                 wave, g, n16, fsum);
+                cone_layer<true, COMMIT>(wa, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0, L, K,
+                                         ax, ay, hsum_s, wave, g, n16, fsum);
             // weights of the next layer if this wave works on it; after the last,
             // layer 2's of the next configuration (whose job may differ)
             if (k < K) {
@@ -525,7 +550,9 @@ nqs_status cone_build_ring_tables(nqs_ctx *c)
     return NQS_OK;
 }
 
-void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
+// commit: null for the exchanged-configuration pass; else the write-back
+// launch (one job) for the chains flagged in commit[]
+static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipStream_t s)
 {
     if (n <= 0) return;
     ConeJobs jp{};
@@ -552,13 +579,18 @@ void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
             for (int k = 0; k < kMaxK; ++k) jp.ring_off[i][t][k] = c->cone_off[(size_t)t * kMaxK + k];
         plane_strides(c->K, &p.ps_a, &p.ps_b);
         p.buf_b = kChunks * p.ps_a;
+        p.commit = commit;
+        p.cache_w = (uint16_t *)jobs[i].cache;
+        p.hsum_w = const_cast<double *>(jobs[i].hsum);
         total_cap += jobs[i].capacity;
     }
     if (total_cap <= 0) return;
     const size_t lds = cone_lds_bytes(jobs[0].c);
     // launches of one or two lattices use the two-job instantiation (fewer
     // scalar registers; a one-job instantiation spills)
-    const void *fn = n > 2 ? (const void *)k_net_cone<kMaxJobs> : (const void *)k_net_cone<2>;
+    const void *fn = commit ? (const void *)k_net_cone<2, true>
+                            : (n > 2 ? (const void *)k_net_cone<kMaxJobs, false>
+                                     : (const void *)k_net_cone<2, false>);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
@@ -567,11 +599,25 @@ void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
     // persistent grid of resident workgroups, a multiple of the XCD count
     const int64_t want =
         std::max<int64_t>((int64_t)jobs[0].c->n_cu * per_cu / kXcd * kXcd, kXcd);
-    if (n > 2)
-        NQS_LAUNCH((k_net_cone<kMaxJobs>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+    if (commit)
+        NQS_LAUNCH((k_net_cone<2, true>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+    else if (n > 2)
+        NQS_LAUNCH((k_net_cone<kMaxJobs, false>), dim3((unsigned)want), dim3(kThreads), lds, s,
+                   jp);
     else
-        NQS_LAUNCH((k_net_cone<2>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+        NQS_LAUNCH((k_net_cone<2, false>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
 }
+
+void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s) { cone_launch(jobs, n, nullptr, s); }
+
+void cone_commit(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
+                 int64_t capacity, double *hsum, void *cache, double *dlog, const int32_t *commit,
+                 hipStream_t s)
+{
+    const ConnJob j{c, spins, queue, qlen, capacity, hsum, cache, dlog};
+    cone_launch(&j, 1, commit, s);
+}
+
 
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,

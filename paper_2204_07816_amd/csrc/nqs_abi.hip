@@ -493,7 +493,7 @@ nqs_status nqs_destroy(nqs_ctx *c)
     DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
                       &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,
                       &c->ws.plane_b, &c->ws.zsave, &c->ws.hsave,  &c->ws.delta, &c->ws.sr,
-                      &c->ws.orows,   &c->ws.counter};
+                      &c->ws.orows,   &c->ws.counter, &c->ws.flags};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &e : c->events) {
@@ -723,12 +723,31 @@ nqs_status nqs_mcmc(nqs_ctx *c, int8_t *spins, int64_t B, int32_t n_steps,
     NQS_TRY(ensure(w.queue, sizeof(uint32_t) * B, s));
     NQS_TRY(ensure(w.qlen, sizeof(int64_t) * 4, s));
     NQS_TRY(ensure(w.dlog, sizeof(double) * B, s));
+    uint32_t *queue = (uint32_t *)w.queue.ptr;
+    int64_t *qlen = (int64_t *)w.qlen.ptr;
+    double *dlog = (double *)w.dlog.ptr;
+    if (c->dtype == NQS_BF16 && m == NQS_INCREMENTAL && cone_supported(c)) {
+        // base pass once, kept current by write-back passes of the accepted chains
+        NQS_TRY(ensure(w.flags, sizeof(int32_t) * B, s));
+        int32_t *flag = (int32_t *)w.flags.ptr;
+        NQS_TRY(bf16_base_stage(c, spins, (int)B, s));
+        for (int32_t t = 0; t < n_steps; ++t) {
+            launch_mcmc_propose(c, (int)B, rand_bond + (int64_t)t * B, queue, qlen, s);
+            mfma_conn_forward(c, NQS_INCREMENTAL, spins, queue, qlen, B, (double *)w.hsum.ptr,
+                              w.cache.ptr, dlog, nullptr, s);
+            launch_mcmc_decide(c, spins, (int)B, queue, dlog, rand_u + (int64_t)t * B, flag,
+                               accepted, false, s);
+            cone_commit(c, spins, queue, qlen, B, (double *)w.hsum.ptr, w.cache.ptr, dlog, flag,
+                        s);
+            launch_mcmc_apply(c, spins, (int)B, queue, flag, s);
+        }
+        return finish_call();
+    }
     for (int32_t t = 0; t < n_steps; ++t) {
-        launch_mcmc_propose(c, (int)B, rand_bond + (int64_t)t * B, (uint32_t *)w.queue.ptr,
-                            (int64_t *)w.qlen.ptr, s);
-        NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)w.dlog.ptr, B, s));
-        launch_mcmc_accept(c, spins, (int)B, (const uint32_t *)w.queue.ptr,
-                           (const double *)w.dlog.ptr, rand_u + (int64_t)t * B, accepted, s);
+        launch_mcmc_propose(c, (int)B, rand_bond + (int64_t)t * B, queue, qlen, s);
+        NQS_TRY(log_ratio_stage(c, spins, (int)B, m, dlog, B, s));
+        launch_mcmc_decide(c, spins, (int)B, queue, dlog, rand_u + (int64_t)t * B, nullptr,
+                           accepted, true, s);
     }
     return finish_call();
 }

@@ -55,6 +55,7 @@ struct Workspace {
     DevBuf sr;          // SR vectors
     DevBuf orows;       // O rows of the recompute SR variant
     DevBuf counter;     // work counters for persistent kernels
+    DevBuf flags;       // int32 per chain: accepted proposals of a Metropolis step
 };
 
 }  // namespace nqs
@@ -199,6 +200,11 @@ void mfma_inc_forward_jobs(const ConnJob *jobs, int n, hipStream_t s);
 bool cone_supported(const nqs_ctx *c);
 // jobs: 1..kMaxConnJobs contexts of one network shape, all cone-supported
 void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s);
+// write-back pass of the cone kernel: for every queue item whose chain has
+// commit[chain] != 0, the cache and hsum of the chain become those of S'
+void cone_commit(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
+                 int64_t capacity, double *hsum, void *cache, double *dlog, const int32_t *commit,
+                 hipStream_t s);
 size_t cone_lds_bytes(const nqs_ctx *c);
 nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
@@ -225,9 +231,14 @@ void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t 
 // queue[s] = (s, bond of proposal rnd[s]), qlen[0] = B
 void launch_mcmc_propose(const nqs_ctx *c, int B, const uint32_t *rnd, uint32_t *queue,
                          int64_t *qlen, hipStream_t s);
-// exchange the pair of queue[s] in chain s when antiparallel and u[s] < exp(2 dlog[s])
-void launch_mcmc_accept(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
-                        const double *dlog, const double *u, int32_t *accepted, hipStream_t s);
+// flag[s] (may be null) = chain s accepts (antiparallel pair, u[s] < exp(2 dlog[s]));
+// accepted[s] (may be null) counts them; apply: exchange the pair at once
+void launch_mcmc_decide(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
+                        const double *dlog, const double *u, int32_t *flag, int32_t *accepted,
+                        bool apply, hipStream_t s);
+// exchange the pairs of the chains with flag[s] != 0
+void launch_mcmc_apply(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,
+                       const int32_t *flag, hipStream_t s);
 size_t sr_workspace_bytes(int64_t B, int64_t P);
 void launch_sr_solve(const void *O, nqs_dtype odt, const double *e_loc, int64_t B, int64_t P,
                      double lambda, int n_iter, double *x, double *stats, void *work,

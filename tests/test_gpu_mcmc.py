@@ -6,7 +6,11 @@ probability min(1, |psi(S')/psi(S)|^2).
   sampler fed the same random numbers, exactly (the accept decisions agree
   unless a uniform lands within ~1e-13 of exp(2 dlog)).
 * BF16 path: the incremental cone and the full recompute give the same
-  configurations (their log-ratios agree to 1e-12).
+  configurations (their log-ratios agree to 1e-12).  Where the cone kernel
+  serves, the incremental sampler takes the base pass once and keeps it
+  current by write-back passes of the accepted chains, so this also checks
+  that the written-back activations equal a new base pass: any difference
+  would change later log-ratios and decisions.
 * Stationarity on 4x4: the mean local energy of the chains after mixing
   equals the exact |psi|^2-weighted mean over all 12,870 Sz = 0 states within
   5 standard errors, for FP64 and BF16 amplitudes.
@@ -45,7 +49,8 @@ def test_mcmc_fp64_equals_oracle(J2):
     assert ctx.get_error() == 0
 
 
-@pytest.mark.parametrize("name,L,K,C", [("16x16 K6 C32 cone", 16, 6, 32),
+@pytest.mark.parametrize("name,L,K,C", [("16x16 K6 C32 cone with write-back", 16, 6, 32),
+                                        ("36x36 K8 C32 cone with write-back", 36, 8, 32),
                                         ("10x10 K4 C16 wrapped windows", 10, 4, 16)])
 def test_mcmc_bf16_incremental_equals_full(name, L, K, C):
     say("case", name)
