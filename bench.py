@@ -425,21 +425,38 @@ def main():
 
     vmc = None
     if not args.no_vmc:
-        # whole VMC iterations: 10 Metropolis steps of the chains, E_loc,
-        # statistics, O (FP32), SR and the weight update (host repacking)
+        # whole VMC iterations captured in one HIP graph: 10 Metropolis steps
+        # of the chains, E_loc, statistics, O (FP32), SR and the weight update
+        # on the device; each iteration's random numbers are staged first
         from paper_2204_07816_amd.vmc import VMC
         cv = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16")
-        run = VMC(cv, w, spd.clone(), steps=10, lr=0.01, diag_shift=1e-3, cg_iters=100,
+        run = VMC(cv, spd.clone(), steps=10, lr=0.01, diag_shift=1e-3, cg_iters=100,
                   seed=3, o_dtype="fp32", mode=args.mode)
-        run.step()
+        run.step()                                  # sizes every workspace
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run.stage()
+            run.enqueue()
+        torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hist = [run.step() for _ in range(2)]
-        torch.cuda.synchronize()
-        t_v = (time.perf_counter() - t0) * 1000.0 / 2
+        gv = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gv):
+            run.enqueue()
+        n_v, t_v, energies = 3, 0.0, []
+        for i in range(n_v):
+            run.stage(10 + i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gv.replay()
+            torch.cuda.synchronize()
+            t_v += (time.perf_counter() - t0) * 1000.0
+            energies.append(run.stats()["energy"])
+        t_v /= n_v
         vmc = {"ms_per_iteration": t_v, "chains": B, "mcmc_steps_per_iteration": 10,
-               "samples_per_s": B / (t_v * 1e-3), "energies": [h["energy"] for h in hist]}
-        log(f"vmc: {t_v:.1f} ms per iteration")
+               "samples_per_s": B / (t_v * 1e-3), "hip_graph": True, "energies": energies}
+        log(f"vmc: {t_v:.1f} ms per graph-replayed iteration")
+        del gv
         cv.close()
 
     cpu = None

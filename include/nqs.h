@@ -100,6 +100,19 @@ nqs_status nqs_num_params(const nqs_ctx *ctx, int64_t *P);
 /* Replace the weights (host, canonical order, n == P); synchronous.       */
 nqs_status nqs_set_weights(nqs_ctx *ctx, const double *weights, int64_t n);
 
+/* The VMC parameter update on the device [Sec. 3.2]: theta <- theta + scale
+ * * dtheta (dtheta device FP64 [P], canonical order; product rounded, then
+ * the sum), and every kernel family's packing rebuilt from the result on the
+ * stream.  Allocates nothing and never synchronises, so it can be captured
+ * with the rest of a VMC iteration.  The kernels then see exactly what
+ * nqs_set_weights of the updated vector would give them.                  */
+nqs_status nqs_update_weights(nqs_ctx *ctx, const double *dtheta, double scale,
+                              void *stream);
+
+/* The current weights (host FP64 [n], canonical order, n == P); waits for
+ * the device.                                                               */
+nqs_status nqs_get_weights(nqs_ctx *ctx, double *weights, int64_t n);
+
 /* Pre-allocate workspace for batches up to B_max in the given mode, so that
  * later calls allocate nothing (and may be captured into a hipGraph).    */
 nqs_status nqs_reserve(nqs_ctx *ctx, int64_t B_max, nqs_mode mode);

@@ -80,12 +80,17 @@ void free_dev(T *&p)
     p = nullptr;
 }
 
+// A packing's size depends only on the network shape, which a context never
+// changes, so a buffer that exists is refilled in place: its address stays
+// valid for kernels captured in a graph before the weights were set again.
 template <typename T>
 nqs_status upload(T *&dst, const std::vector<T> &src)
 {
-    free_dev(dst);
     if (src.empty()) return NQS_OK;
-    if (hipMalloc((void **)&dst, src.size() * sizeof(T)) != hipSuccess) return NQS_E_NOMEM;
+    if (!dst && hipMalloc((void **)&dst, src.size() * sizeof(T)) != hipSuccess) {
+        dst = nullptr;
+        return NQS_E_NOMEM;
+    }
     HIP_OK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
     return NQS_OK;
 }
@@ -518,6 +523,25 @@ nqs_status nqs_set_weights(nqs_ctx *c, const double *weights, int64_t n)
     HIP_OK(hipDeviceSynchronize());
     c->w_host.assign(weights, weights + n);
     return pack_weights(c);
+}
+
+nqs_status nqs_update_weights(nqs_ctx *c, const double *dtheta, double scale, void *stream)
+{
+    if (!c || !dtheta || !std::isfinite(scale)) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    device_update_weights(c, dtheta, scale, s);
+    return finish_call();
+}
+
+nqs_status nqs_get_weights(nqs_ctx *c, double *weights, int64_t n)
+{
+    if (!c || !weights) return NQS_E_ARG;
+    if (n != c->P) return NQS_E_NPARAMS;
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(weights, c->w_canon, sizeof(double) * n, hipMemcpyDeviceToHost));
+    c->w_host.assign(weights, weights + n);
+    return NQS_OK;
 }
 
 nqs_status nqs_auto_mode(const nqs_ctx *c, nqs_mode *mode)

@@ -227,6 +227,10 @@ void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const
                           hipStream_t s);
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
 
+// --- device-side parameter update (k_pack.hip) ---
+// theta += scale * dtheta (device FP64 [P]) and every packing rebuilt on the device
+void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipStream_t s);
+
 // --- Metropolis sampling (k_mcmc.hip) ---
 // queue[s] = (s, bond of proposal rnd[s]), qlen[0] = B
 void launch_mcmc_propose(const nqs_ctx *c, int B, const uint32_t *rnd, uint32_t *queue,

@@ -73,6 +73,8 @@ def load():
         "nqs_log_ratios": [vp, vp, i64, i32, vp, i64, vp],
         "nqs_local_energy_multi": [vp, i32, i32, vp],
         "nqs_mcmc": [vp, vp, i64, i32, vp, vp, vp, i32, vp],
+        "nqs_update_weights": [vp, vp, d, vp],
+        "nqs_get_weights": [vp, vp, i64],
         "nqs_auto_mode": [vp, P(i32)],
         "nqs_autotune": [vp, vp, i64, P(i32), vp],
         "nqs_tune_key": [i32, i32, i32, i32, d, ctypes.c_char_p, i64],
@@ -160,6 +162,21 @@ class Context:
         w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
         _check(load().nqs_set_weights(self._h, ctypes.c_void_p(w.data_ptr()), w.numel()),
                "nqs_set_weights")
+
+    def update_weights(self, dtheta, scale: float):
+        """theta <- theta + scale * dtheta on the device (dtheta FP64 [P] tensor)."""
+        if dtheta.numel() != self.P:
+            raise ValueError("dtheta must hold P values")
+        _check(load().nqs_update_weights(self._h, _dev(dtheta, torch.float64, "dtheta"),
+                                         float(scale), _stream()), "nqs_update_weights")
+
+    def get_weights(self):
+        """The current canonical weights (numpy FP64 [P])."""
+        import numpy as np
+        out = np.empty(self.P, np.float64)
+        _check(load().nqs_get_weights(self._h, out.ctypes.data_as(ctypes.c_void_p), self.P),
+               "nqs_get_weights")
+        return out
 
     def reserve(self, B_max: int, mode: str = "auto"):
         _check(load().nqs_reserve(self._h, B_max, _MODES[mode]), "nqs_reserve")
