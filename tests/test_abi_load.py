@@ -71,6 +71,11 @@ def test_calls_reject_null_context(lib):
     assert lib.nqs_sr_solve(None, None, 0, None, 0, 1e-4, 100, None, None, None) == 1
     assert lib.nqs_destroy(None) == 1
     assert lib.nqs_local_energy_multi(None, 0, 0, None) == 1
+    assert lib.nqs_sr_solve_recompute(None, None, 0, None, 0, 1e-4, 100, 0, None, None,
+                                      None) == 1
+    assert lib.nqs_mcmc(None, None, 0, 0, None, None, None, 0, None) == 1
+    assert lib.nqs_update_weights(None, None, 1.0, None) == 1
+    assert lib.nqs_get_weights(None, None, 0) == 1
     p = ctypes.c_int64()
     assert lib.nqs_num_params(None, ctypes.byref(p)) == 1
     del vp
