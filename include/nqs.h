@@ -30,8 +30,9 @@
  *   - stream: a hipStream_t (NULL = default stream).  All work is enqueued
  *     asynchronously on it; no call synchronises unless documented.
  *   - Limits: even L with 4 <= L <= 64; 1 <= K <= 16; 1 <= C <= 32 for the
- *     FP64/FP32 paths, C in {16, 32} and K >= 2 for BF16; B <= 131072 per
- *     call.
+ *     FP64/FP32 paths; C in {16, 32}, K >= 2 and L <= 36 for BF16 (its base
+ *     pass keeps a whole layer of a configuration in one workgroup's
+ *     accumulators, at most 1408 sites); B <= 131072 per call.
  *
  * Errors
  *   - Argument problems found on the host are returned at once and nothing

@@ -60,6 +60,7 @@ def test_create_rejects_bad_spec_and_counts(lib):
     assert _create(lib, 4, 2, 4, 188, marshall=2) == 3
     assert _create(lib, 4, 2, 4, 187) == 4          # NQS_E_NPARAMS
     assert _create(lib, 4, 2, 4, nqs.num_params(2, 4), dtype=2) == 3   # BF16 needs C in {16, 32}
+    assert _create(lib, 38, 2, 32, nqs.num_params(2, 32), dtype=2) == 3  # BF16 needs L <= 36
     assert _create(lib, 4, 2, 4, 188, spec=False) == 1                 # null spec
 
 

@@ -113,6 +113,20 @@ def test_batch_edges_fp64():
     assert one[0] == pytest.approx(ref[1], rel=1e-12)
 
 
+def test_largest_lattice_fp64():
+    """64x64 (the largest lattice; bond ids up to 2^14 - 1), K=2, C=4, stress
+    weights: every E_loc of two configurations against the oracle."""
+    L, K, C = 64, 2, 4
+    w = inputs.stress_weights(K, C, 1.0, seed=8)
+    sp = inputs.spins_any(64, 2, 9)
+    ctx = make_ctx(L, 0.5, K, C, w)
+    e = ctx.local_energy(to_dev(sp), mode="full").cpu().numpy()
+    ref = oracle.local_energy(L, 1.0, 0.5, K, C, w, sp)
+    say("64x64 fp64 max rel", rel_inf(e, ref))
+    assert rel_inf(e, ref) <= 1e-10
+    assert ctx.get_error() == 0
+
+
 def test_energy_stats_gpu():
     L, K, C = 4, 2, 4
     ctx = make_ctx(L, 0.5, K, C, inputs.weights(K, C, 0.05, 1))
