@@ -1,6 +1,9 @@
-// k_net_inc.hip -- the exchanged-configuration pass in incremental mode, the
-// dominant kernel of the local energy [Sec. 5.4.1: forwards of the network
-// over the O(L^2) exchanged configurations are over 95% of the time].
+// k_net_inc.hip -- the exchanged-configuration pass in incremental mode for
+// any lattice the incremental method applies to (windows may wrap around the
+// torus, 16 or 32 channels) [Sec. 5.4.1: forwards of the network over the
+// O(L^2) exchanged configurations are over 95% of the time].  Lattices wide
+// enough that no window wraps, with 32 channels, take the faster unwrapped
+// form in k_net_cone.hip.
 //
 // An exchange of the antiparallel pair (i, j) changes layer k of the network
 // only on the sites within Chebyshev distance k of i or j.  For every queue
