@@ -50,6 +50,11 @@ def _load():
         "oracle_log_psi": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), P(i8), ci]),
         "oracle_local_energy": (None, [ci, d, d, ci, ci, P(d), P(i8), i64, P(d), ci]),
         "oracle_local_energy_table": (None, [ci, d, d, P(d), P(i8), P(i8), i64, P(d), ci]),
+        "oracle_tj_check": (ci, [ci, P(i8), i64]),
+        "oracle_tj_connected": (None, [ci, d, d, P(i8), P(i32), P(i32), P(i8), P(d), P(d)]),
+        "oracle_tj_local_energy": (None, [ci, d, d, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_tj_local_energy_table": (None, [ci, d, d, i64, P(i64), P(d), P(i8), P(i8), i64,
+                                                P(d), ci]),
         "oracle_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
         "oracle_energy_stats": (None, [P(d), i64, P(d)]),
         "oracle_sr_cg": (None, [P(d), P(d), i64, i64, d, ci, P(d), P(d)]),
@@ -145,6 +150,71 @@ def local_energy_table(L: int, J1: float, J2: float, log_abs_tab, sign_tab, spin
     return e
 
 
+def tj_connected(L: int, t: float, J: float, spins):
+    """t-J connected lists (Sec. 6.1, Eq. tJ): (counts[B], bond-id arrays,
+    Marshall-ratio arrays, matrix-element arrays, e_diag[B])."""
+    s = _spins(spins, L)
+    B, N = s.shape
+    lib = _load()
+    counts = np.zeros(B, np.int32)
+    ediag = np.zeros(B, np.float64)
+    bonds, mus, hs = [], [], []
+    bid = np.zeros(4 * N, np.int32)
+    mu = np.zeros(4 * N, np.int8)
+    hv = np.zeros(4 * N, np.float64)
+    for b in range(B):
+        c = ctypes.c_int32()
+        e = ctypes.c_double()
+        row = np.ascontiguousarray(s[b])
+        lib.oracle_tj_connected(L, t, J, _p(row, ctypes.c_int8), ctypes.byref(c),
+                                _p(bid, ctypes.c_int32), _p(mu, ctypes.c_int8),
+                                _p(hv, ctypes.c_double), ctypes.byref(e))
+        counts[b] = c.value
+        ediag[b] = e.value
+        bonds.append(bid[:c.value].copy())
+        mus.append(mu[:c.value].copy())
+        hs.append(hv[:c.value].copy())
+    return counts, bonds, mus, hs, ediag
+
+
+def tj_check(L: int, spins) -> bool:
+    s = _spins(spins, L)
+    return bool(_load().oracle_tj_check(L, _p(s, ctypes.c_int8), s.shape[0]))
+
+
+def tj_local_energy(L: int, t: float, J: float, K: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_tj_local_energy(L, t, J, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8),
+                                   B, _p(e, ctypes.c_double), nthreads)
+    return e
+
+
+def tj_key(spins, L: int):
+    """Table keys sum_i c_i 4^i (c = 0 hole, 1 up, 2 down) of [B][N] configurations."""
+    s = _spins(spins, L).astype(np.int64)
+    code = np.where(s > 0, 1, np.where(s < 0, 2, 0)).astype(np.int64)
+    return (code << (2 * np.arange(L * L, dtype=np.int64))).sum(axis=1)
+
+
+def tj_local_energy_table(L: int, t: float, J: float, keys, log_abs_tab, sign_tab, spins,
+                          nthreads: int = 0):
+    s = _spins(spins, L)
+    k = np.ascontiguousarray(keys, np.int64)
+    assert L * L <= 31 and np.all(np.diff(k) > 0)
+    la = np.ascontiguousarray(log_abs_tab, np.float64)
+    sg = np.ascontiguousarray(sign_tab, np.int8)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_tj_local_energy_table(L, t, J, k.shape[0], _p(k, ctypes.c_int64),
+                                         _p(la, ctypes.c_double), _p(sg, ctypes.c_int8),
+                                         _p(s, ctypes.c_int8), B, _p(e, ctypes.c_double),
+                                         nthreads)
+    return e
+
+
 def log_deriv(L: int, K: int, C: int, w, spins, nthreads: int = 0):
     s = _spins(spins, L)
     w = np.ascontiguousarray(w, np.float64)
@@ -197,18 +267,11 @@ def sr_apply(O, v, lam: float = 1e-4):
     return y
 
 
-def mcmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, rand_bond, rand_u):
-    """Metropolis sampling of |psi|^2 by pair exchanges (Sec. 3.2: walkers
-    sample |psi|^2; Sec. 5.4.1: independent chains whose proposals are the
-    exchanged configurations).  Step t of chain b proposes the bond of
-    q = rand_bond[t, b] mod (N n), n = 2 for one non-zero coupling and 4 for
-    both: site q // n, type the (q mod n)-th of the types of the non-zero
-    couplings (J1: 0, 1; J2: 2, 3).  An antiparallel pair is exchanged when
-    rand_u[t, b] < exp(2 (f(S') - f(S))), f = log|psi| by two full forwards.
-    Returns (spins after the steps, accepted moves per chain)."""
+def _metropolis(L, types, K, C, w, spins, rand_bond, rand_u):
+    """Metropolis steps of every chain with proposals over the bond types
+    `types` (see mcmc); the pair's site values are exchanged on acceptance."""
     s = _spins(spins, L).copy()
     B, N = s.shape
-    types = ([0, 1] if J1 != 0.0 else []) + ([2, 3] if J2 != 0.0 else [])
     acc = np.zeros(B, np.int64)
     if not types:
         return s.reshape(B, L, L), acc
@@ -232,6 +295,45 @@ def mcmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, rand_bond, rand
     return s.reshape(B, L, L), acc
 
 
+def mcmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, rand_bond, rand_u):
+    """Metropolis sampling of |psi|^2 by pair exchanges (Sec. 3.2: walkers
+    sample |psi|^2; Sec. 5.4.1: independent chains whose proposals are the
+    exchanged configurations).  Step t of chain b proposes the bond of
+    q = rand_bond[t, b] mod (N n), n = 2 for one non-zero coupling and 4 for
+    both: site q // n, type the (q mod n)-th of the types of the non-zero
+    couplings (J1: 0, 1; J2: 2, 3).  A pair of different values is exchanged
+    when rand_u[t, b] < exp(2 (f(S') - f(S))), f = log|psi| by two full
+    forwards.  Returns (spins after the steps, accepted moves per chain)."""
+    types = ([0, 1] if J1 != 0.0 else []) + ([2, 3] if J2 != 0.0 else [])
+    return _metropolis(L, types, K, C, w, spins, rand_bond, rand_u)
+
+
+def tj_mcmc(L: int, t: float, J: float, K: int, C: int, w, spins, rand_bond, rand_u):
+    """The same sampler for the t-J model (Sec. 6.1): proposals over the
+    nearest-neighbour bonds (n = 2) when t or J is non-zero; a move exchanges
+    two antiparallel electrons or an electron and a hole, so the numbers of up
+    electrons, down electrons and holes are conserved."""
+    types = [0, 1] if (t != 0.0 or J != 0.0) else []
+    return _metropolis(L, types, K, C, w, spins, rand_bond, rand_u)
+
+
+def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms):
+    w = np.array(w, np.float64)
+    s = _spins(spins, L).reshape(-1, L, L).copy()
+    means, variances = [], []
+    for it in range(n_iter):
+        rb, ru = randoms(it)
+        s, _ = sampler(w, s, rb, ru)
+        e = eloc(w, s)
+        m, v = energy_stats(e)
+        means.append(m)
+        variances.append(v)
+        O = log_deriv(L, K, C, w, s)
+        x, _, _ = sr_cg(O, e, lam, cg_iters)
+        w = w - lr * x
+    return np.array(means), np.array(variances), w, s
+
+
 def vmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, n_iter: int, steps: int,
         lr: float, lam: float, cg_iters: int, randoms):
     """The variational Monte Carlo self-learning loop (Sec. 3.2): per
@@ -240,17 +342,15 @@ def vmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, n_iter: int, ste
     (sr_cg), and the update theta <- theta - lr * delta.  randoms(it) gives the
     iteration's (rand_bond, rand_u).  Returns (energy means per iteration,
     variances per iteration, final weights, final spins)."""
-    w = np.array(w, np.float64)
-    s = _spins(spins, L).reshape(-1, L, L).copy()
-    means, variances = [], []
-    for it in range(n_iter):
-        rb, ru = randoms(it)
-        s, _ = mcmc(L, J1, J2, K, C, w, s, rb, ru)
-        e = local_energy(L, J1, J2, K, C, w, s)
-        m, v = energy_stats(e)
-        means.append(m)
-        variances.append(v)
-        O = log_deriv(L, K, C, w, s)
-        x, _, _ = sr_cg(O, e, lam, cg_iters)
-        w = w - lr * x
-    return np.array(means), np.array(variances), w, s
+    del steps   # the step count is the leading dimension of the randoms
+    return _vmc(L, lambda w, s, rb, ru: mcmc(L, J1, J2, K, C, w, s, rb, ru),
+                lambda w, s: local_energy(L, J1, J2, K, C, w, s),
+                K, C, w, spins, n_iter, lr, lam, cg_iters, randoms)
+
+
+def tj_vmc(L: int, t: float, J: float, K: int, C: int, w, spins, n_iter: int, lr: float,
+           lam: float, cg_iters: int, randoms):
+    """The same loop for the t-J model (tj_mcmc, tj_local_energy)."""
+    return _vmc(L, lambda w, s, rb, ru: tj_mcmc(L, t, J, K, C, w, s, rb, ru),
+                lambda w, s: tj_local_energy(L, t, J, K, C, w, s),
+                K, C, w, spins, n_iter, lr, lam, cg_iters, randoms)

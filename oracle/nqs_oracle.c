@@ -15,6 +15,8 @@
  *   - CNN with periodic (PBC) padding and a product of neurons as output:
  *     Sec. 5.2; the layer shape (3x3 conv, ln cosh, sum pool) is the
  *     configuration this library is checked on.
+ *   - t-J model: Sec. 6.1, Eq. (tJ), with the fermions encoded by the
+ *     Jordan-Wigner transformation along the site order i = y*L + x.
  *   - O_loc = per-sample log-derivative and the SR update: Sec. 3.2 and
  *     Sec. 5.4.1 ("Distributed SR computation"), solved here by CG with an
  *     absolute diagonal shift, 1/Ns normalisation, x0 = 0.
@@ -24,7 +26,11 @@
  * exact 4x4 J2 = 0 ground state; exhaustive <psi|H|psi>/<psi|psi> on 4x4;
  * zero variance of E_loc for the exact eigenvector; translation and spin-flip
  * invariance; torch-CPU circular conv2d for the forward; central finite
- * differences and torch autograd for O; numpy dense solve for SR.
+ * differences and torch autograd for O; numpy dense solve for SR.  t-J:
+ * an exact diagonalisation built from fermion creation / annihilation
+ * operators (itself pinned by free-fermion spectra and by the no-hole
+ * reduction to the Heisenberg model) gives E_loc = E0 on every configuration
+ * of its ground state and <psi|H|psi> for a CNN amplitude.
  */
 #include "nqs_oracle.h"
 
@@ -300,6 +306,191 @@ void oracle_local_energy_table(int L, double J1, double J2,
 {
     amp_src a = {L, 0, 0, NULL, log_abs_tab, sign_tab};
     local_energy_batch(&a, J1, J2, spins, B, e_loc, nthreads);
+}
+
+/* ------------------------------------------------------------------ */
+/* t-J model (Sec. 6.1, Eq. tJ)                                         */
+/* ------------------------------------------------------------------ */
+/* A site holds an up electron (+1), a down electron (-1) or a hole (0); no
+ * site is doubly occupied.  The fermion modes are ordered site by site along
+ * i = y*L + x (the one-dimensional order of the Jordan-Wigner encoding, Sec.
+ * 6.1), and a basis state is the product of its creation operators in that
+ * order.  Only nearest-neighbour bonds (t = 0, 1) carry terms:
+ *   - J (S_i.S_j - n_i n_j / 4): diagonal J (s_i s_j - |s_i| |s_j|) / 4, and
+ *     for an antiparallel pair the spin exchange with <S'|H|S> = +J/2 (the
+ *     two Jordan-Wigner strings of the exchange cancel);
+ *   - -t sum_sigma (c+_{i sigma} c_{j sigma} + h.c.): an electron next to a
+ *     hole moves onto it, <S'|H|S> = -t (-1)^{n}, n the number of electrons
+ *     on the sites strictly between i and j in the site order (the
+ *     Jordan-Wigner string of the hop).                                   */
+
+static int jw_string_sign(const int8_t *spins, int i, int j)
+{
+    int lo = i < j ? i : j, hi = i < j ? j : i, n = 0;
+    for (int k = lo + 1; k < hi; ++k) n += (spins[k] != 0);
+    return (n % 2 == 0) ? 1 : -1;
+}
+
+static int valid_tj_spin(int v) { return v == 1 || v == -1 || v == 0; }
+
+/* <S'|H|S> of the nearest-neighbour pair (si, sj) of S, or 0 when the pair
+ * has no off-diagonal term (equal values, or a zero coupling).             */
+static double tj_offdiag(double t, double J, const int8_t *spins, int si, int sj)
+{
+    int a = spins[si], b = spins[sj];
+    if (a == b) return 0.0;
+    if (a != 0 && b != 0) return J / 2.0;                     /* exchange */
+    return -t * (double)jw_string_sign(spins, si, sj);        /* hop      */
+}
+
+static double tj_diag_bond(double J, int a, int b)
+{
+    return J * ((double)a * (double)b / 4.0 - (double)(a != 0) * (double)(b != 0) / 4.0);
+}
+
+void oracle_tj_connected(int L, double t, double J, const int8_t *spins,
+                         int32_t *count, int32_t *bond_ids, int8_t *mu,
+                         double *hval, double *e_diag)
+{
+    const int N = L * L;
+    int8_t *moved = (int8_t *)malloc((size_t)N);
+    int n = 0;
+    double diag = 0.0;
+    int m0 = oracle_marshall_sign(L, spins);
+    for (int b = 0; b < 4 * N; ++b) {
+        int si, sj;
+        if (oracle_bond_sites(L, b, &si, &sj) != 1) continue;
+        diag += tj_diag_bond(J, spins[si], spins[sj]);
+        double h = tj_offdiag(t, J, spins, si, sj);
+        if (h == 0.0) continue;
+        memcpy(moved, spins, (size_t)N);
+        moved[si] = spins[sj];
+        moved[sj] = spins[si];
+        bond_ids[n] = b;
+        mu[n] = (int8_t)(oracle_marshall_sign(L, moved) * m0);
+        hval[n] = h;
+        ++n;
+    }
+    *count = n;
+    *e_diag = diag;
+    free(moved);
+}
+
+/* tabulated amplitudes of the t-J configurations: key = sum_i c_i 4^i with
+ * c = 0 hole, 1 up, 2 down (N <= 31); keys sorted ascending.              */
+typedef struct {
+    int64_t n;
+    const int64_t *keys;
+    const double *log_abs;
+    const int8_t *sign;
+} tj_table;
+
+static int64_t tj_key(int N, const int8_t *spins)
+{
+    int64_t k = 0;
+    for (int i = N - 1; i >= 0; --i) {
+        int c = spins[i] > 0 ? 1 : (spins[i] < 0 ? 2 : 0);
+        k = 4 * k + c;
+    }
+    return k;
+}
+
+/* 1 and the amplitude when the configuration is in the table, else 0 */
+static int tj_lookup(const tj_table *tab, int N, const int8_t *spins, double *log_abs, int *sign)
+{
+    int64_t key = tj_key(N, spins), lo = 0, hi = tab->n - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (tab->keys[mid] == key) {
+            *log_abs = tab->log_abs[mid];
+            *sign = tab->sign[mid];
+            return 1;
+        }
+        if (tab->keys[mid] < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0;
+}
+
+/* E_loc(S) = sum_<ij> J (s_i s_j - |s_i||s_j|)/4 + sum_S' <S'|H|S> W(S')/W(S)
+ * over the nearest-neighbour pairs with an off-diagonal term.  W from the
+ * CNN (w != NULL, Marshall sign) or from the table.                       */
+static double tj_local_energy_one(int L, int K, int C, const double *w, const tj_table *tab,
+                                  double t, double J, const int8_t *spins, int8_t *work,
+                                  double *h_a, double *h_b)
+{
+    const int N = L * L;
+    double f0 = 0.0;
+    int m0 = 1;
+    if (w) {
+        f0 = cnn_forward(L, K, C, w, spins, h_a, h_b, NULL);
+        m0 = oracle_marshall_sign(L, spins);
+    } else if (!tj_lookup(tab, N, spins, &f0, &m0) || m0 == 0) {
+        return NAN;                                  /* W(S) = 0: undefined */
+    }
+    double e = 0.0;
+    for (int b = 0; b < 4 * N; ++b) {
+        int si, sj;
+        if (oracle_bond_sites(L, b, &si, &sj) != 1) continue;
+        e += tj_diag_bond(J, spins[si], spins[sj]);
+        double h = tj_offdiag(t, J, spins, si, sj);
+        if (h == 0.0) continue;
+        memcpy(work, spins, (size_t)N);
+        work[si] = spins[sj];
+        work[sj] = spins[si];
+        double f1;
+        int m1;
+        if (w) {
+            f1 = cnn_forward(L, K, C, w, work, h_a, h_b, NULL);
+            m1 = oracle_marshall_sign(L, work);
+        } else if (!tj_lookup(tab, N, work, &f1, &m1)) {
+            continue;                                /* W(S') = 0 */
+        }
+        e += h * (double)(m1 * m0) * exp(f1 - f0);
+    }
+    return e;
+}
+
+static void tj_local_energy_batch(int L, int K, int C, const double *w, const tj_table *tab,
+                                  double t, double J, const int8_t *spins, int64_t B,
+                                  double *e_loc, int nthreads)
+{
+    const int N = L * L;
+    const int Cb = C > 0 ? C : 1;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        int8_t *work = (int8_t *)malloc((size_t)N);
+        double *ha = (double *)malloc(sizeof(double) * (size_t)Cb * N);
+        double *hb = (double *)malloc(sizeof(double) * (size_t)Cb * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s)
+            e_loc[s] = tj_local_energy_one(L, K, C, w, tab, t, J, spins + s * N, work, ha, hb);
+        free(work);
+        free(ha);
+        free(hb);
+    }
+}
+
+int oracle_tj_check(int L, const int8_t *spins, int64_t B)
+{
+    for (int64_t q = 0; q < B * (int64_t)L * L; ++q)
+        if (!valid_tj_spin(spins[q])) return 0;
+    return 1;
+}
+
+void oracle_tj_local_energy(int L, double t, double J, int K, int C, const double *w,
+                            const int8_t *spins, int64_t B, double *e_loc, int nthreads)
+{
+    tj_local_energy_batch(L, K, C, w, NULL, t, J, spins, B, e_loc, nthreads);
+}
+
+void oracle_tj_local_energy_table(int L, double t, double J, int64_t n_tab, const int64_t *keys,
+                                  const double *log_abs_tab, const int8_t *sign_tab,
+                                  const int8_t *spins, int64_t B, double *e_loc, int nthreads)
+{
+    tj_table tab = {n_tab, keys, log_abs_tab, sign_tab};
+    tj_local_energy_batch(L, 0, 0, NULL, &tab, t, J, spins, B, e_loc, nthreads);
 }
 
 /* ------------------------------------------------------------------ */

@@ -13,7 +13,8 @@
  * connected configuration, channel-major [C][L][L] activations, FP64 only.
  *
  * Conventions (shared *interface* with the GPU library, independent code):
- *   - spins: int8, +1/-1, layout [y][x], site i = y*L + x            (Sec. 5.4.1, spin image)
+ *   - spins: int8, +1/-1 (t-J: also 0 for a hole), layout [y][x],
+ *     site i = y*L + x                                                (Sec. 5.4.1, spin image)
  *   - H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j,  S = sigma/2   (Sec. 6.1, Eq. J1J2)
  *   - psi(s) = M(s) * exp(f(s)),  M = Marshall sign (-1)^{#up spins on sublattice A},
  *     A = {(x+y) even}; f = CNN log-amplitude                         (Sec. 3.2 Eq. psi, Table 1 "sign rule")
@@ -72,6 +73,37 @@ void oracle_local_energy_table(int L, double J1, double J2,
                                const double *log_abs_tab, const int8_t *sign_tab,
                                const int8_t *spins, int64_t B, double *e_loc,
                                int nthreads);
+
+/* t-J model [Sec. 6.1, Eq. tJ]: site values +1 (up electron), -1 (down
+ * electron), 0 (hole); nearest-neighbour bonds only; fermion modes ordered
+ * site by site along i = y*L + x (Jordan-Wigner order).
+ *   H = -t sum_<ij>,sigma (c+_i c_j + h.c.) + J sum_<ij> (S_i.S_j - n_i n_j / 4)
+ * psi(s) = M(s) exp(f(s)) as for the spin model (M counts up electrons on
+ * sublattice A).  oracle_tj_check: 1 when every value is -1, 0 or +1.     */
+int oracle_tj_check(int L, const int8_t *spins, int64_t B);
+
+/* Connected configurations of one t-J sample in increasing bond id: every
+ * nearest-neighbour pair with an off-diagonal term (antiparallel electrons
+ * and J != 0: exchange, <S'|H|S> = J/2; an electron next to a hole and
+ * t != 0: hop, <S'|H|S> = -t (-1)^{electrons strictly between the two sites
+ * in the site order}).  Writes count, bond ids, the Marshall ratio
+ * M(S')/M(s), the matrix element hval and the diagonal energy
+ * sum_<ij> J (s_i s_j - |s_i||s_j|) / 4.  Arrays hold 4*L*L entries.     */
+void oracle_tj_connected(int L, double t, double J, const int8_t *spins,
+                         int32_t *count, int32_t *bond_ids, int8_t *mu,
+                         double *hval, double *e_diag);
+
+/* t-J local energy with the CNN amplitude (full recomputation of every S'). */
+void oracle_tj_local_energy(int L, double t, double J, int K, int C, const double *w,
+                            const int8_t *spins, int64_t B, double *e_loc, int nthreads);
+
+/* Same with a tabulated wave function: configuration s has amplitude
+ * sign_tab[k] exp(log_abs_tab[k]) when keys[k] = sum_i c_i 4^i (c = 0 hole,
+ * 1 up, 2 down), keys sorted ascending, N <= 31; a configuration missing
+ * from the table has amplitude 0 (E_loc of such an s is NaN).            */
+void oracle_tj_local_energy_table(int L, double t, double J, int64_t n_tab, const int64_t *keys,
+                                  const double *log_abs_tab, const int8_t *sign_tab,
+                                  const int8_t *spins, int64_t B, double *e_loc, int nthreads);
 
 /* Per-sample log-derivatives O[s][p] = d f(s) / d theta_p, FP64, by the
  * reverse-mode chain rule through the network.                          */

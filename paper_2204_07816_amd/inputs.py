@@ -5,7 +5,10 @@ The paper's inputs are MCMC samples of trained networks, which do not exist
 here; they are replaced by
 
 * spin configurations drawn uniformly from the Sz = 0 sector (each sample is a
-  random permutation of N/2 up and N/2 down spins), and
+  random permutation of N/2 up and N/2 down spins); for the t-J model,
+  uniform over the configurations with the given number of holes and equally
+  many up and down electrons (hole doping 1/8 in the named t-J workloads),
+  and
 * CNN weights and biases drawn i.i.d. from N(0, sigma^2) in canonical
   parameter order (layer by layer: W_k[co][ci][ky][kx], then b_k[co]).
 
@@ -58,6 +61,22 @@ def spins_any(L: int, B: int, seed: int) -> np.ndarray:
     return np.where(rng.random((B, L, L)) < 0.5, 1, -1).astype(np.int8)
 
 
+def spins_tj(L: int, B: int, n_holes: int, seed: int) -> np.ndarray:
+    """int8 [B, L, L] t-J configurations (+1 up electron, -1 down, 0 hole),
+    uniform over those with n_holes holes and equally many up and down
+    electrons."""
+    N = L * L
+    assert 0 <= n_holes <= N and (N - n_holes) % 2 == 0
+    ne = (N - n_holes) // 2
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = np.concatenate([np.ones(ne, np.int8), -np.ones(ne, np.int8),
+                           np.zeros(n_holes, np.int8)])
+    out = np.empty((B, N), np.int8)
+    for b in range(B):
+        out[b] = rng.permutation(base)
+    return out.reshape(B, L, L)
+
+
 def neel(L: int) -> np.ndarray:
     y, x = np.mgrid[0:L, 0:L]
     return np.where((x + y) % 2 == 0, 1, -1).astype(np.int8)
@@ -83,6 +102,24 @@ CONFIGS = {
     "sr24": dict(index=3, L=24, J2=0.5, K=6, C=32, sigma=0.02, B=4096),
     "full36": dict(index=4, L=36, J2=0.5, K=8, C=32, sigma=0.02, B=1024),
 }
+
+
+# t-J workloads (t = 1, J = 0.4, hole doping 1/8, the parameters of the
+# paper's t-J runs): seeds weights 1100 + index, spins 2100 + index.
+TJ_CONFIGS = {
+    "tj8": dict(index=0, L=8, t=1.0, J=0.4, n_holes=8, K=4, C=16, sigma=0.02, B=2048),
+    "tj12": dict(index=1, L=12, t=1.0, J=0.4, n_holes=18, K=6, C=32, sigma=0.02, B=4096),
+}
+
+
+def tj_config_inputs(name: str, B: int | None = None):
+    """(L, t, J, K, C, weights, configurations) of a named t-J workload."""
+    cfg = TJ_CONFIGS[name]
+    idx = cfg["index"]
+    nb = cfg["B"] if B is None else B
+    w = weights(cfg["K"], cfg["C"], cfg["sigma"], 1100 + idx)
+    s = spins_tj(cfg["L"], nb, cfg["n_holes"], 2100 + idx)
+    return cfg["L"], cfg["t"], cfg["J"], cfg["K"], cfg["C"], w, s
 
 
 def config_inputs(name: str, B: int | None = None, lattice: int = 0):
