@@ -15,12 +15,16 @@
  *   O_k(s) = d log|psi(s)| / d theta_k per sample                          [Sec. 3.2, O_loc by backward]
  *   SR: (S + lambda I) dtheta = F, S = Obar^T Obar / Ns,
  *       F = Obar^T (E - Ebar) / Ns                                        [Sec. 3.2; Sec. 5.4.1 distributed SR]
+ *   t-J contexts (nqs_create_tj): H = -t sum_<ij>,sigma (c+_i c_j + h.c.)
+ *     + J sum_<ij> (S_i.S_j - n_i n_j / 4), fermions encoded by the
+ *     Jordan-Wigner transformation along the site order                   [Sec. 6.1, Eq. tJ]
  *
  * Conventions
  *   - Every array argument is a DEVICE pointer unless marked "host".  The
  *     caller owns every buffer it passes; the context owns its weights and
  *     its workspace.
  *   - spins: int8 +1/-1, layout [B][L][L] (row y, column x), site i = y*L+x.
+ *     t-J contexts: +1 up electron, -1 down electron, 0 hole.
  *   - weights: FP64, canonical order, layer by layer: W_k[co][ci][ky][kx]
  *     then b_k[co]; layer 1 has one input channel, layers 2..K have C.
  *     The convolution is a cross-correlation:
@@ -37,7 +41,8 @@
  * Errors
  *   - Argument problems found on the host are returned at once and nothing
  *     is enqueued.
- *   - Problems found on the device (a spin that is not +1/-1, a non-finite
+ *   - Problems found on the device (a spin that is not +1/-1, or not
+ *     -1/0/+1 in a t-J context, a non-finite
  *     log-amplitude difference or local energy) set a sticky error word in
  *     the context; nqs_get_error() reads (and clears) it.
  *   - A call that needs more workspace than nqs_reserve() provided allocates
@@ -91,6 +96,28 @@ typedef struct {
  * weights: host, n_weights FP64 values in canonical order (copied).       */
 nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
                       const double *weights, int64_t n_weights, nqs_ctx **out);
+
+/* A context for the t-J model [Sec. 6.1, Eq. tJ] on an L x L torus, with the
+ * same network, limits and entry points as nqs_create.  Site values: +1 up
+ * electron, -1 down electron, 0 hole (no double occupancy).  Only nearest-
+ * neighbour bonds (t = 0, 1) carry terms:
+ *   - diagonal: J (s_i s_j - |s_i||s_j|) / 4 per bond (-J/2 per
+ *     antiparallel pair);
+ *   - spin exchange of an antiparallel pair (J != 0): <S'|H|S> = +J/2;
+ *   - hop of an electron onto a neighbouring hole (t != 0): <S'|H|S> =
+ *     -t (-1)^n, n = electrons on the sites strictly between the two in the
+ *     order i = y*L + x (the Jordan-Wigner string; the fermion modes are
+ *     ordered site by site).
+ * Every S' is the pair's values exchanged, so nqs_connected lists them as
+ * bond ids like the spin model (mu = M(S')/M(s): -1 when an up spin or
+ * electron changes sublattice), nqs_log_ratios gives their f(S') - f(s),
+ * and nqs_mcmc proposes nearest-neighbour pairs (n = 2) and exchanges pairs
+ * of different values, conserving the numbers of up and down electrons.
+ * The Marshall sign counts up electrons on sublattice A.  t-J contexts
+ * share the autotuner key of a J2 = 0 spin context of the same shape.
+ * Errors as nqs_create (t, J must be finite).                             */
+nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
+                         const double *weights, int64_t n_weights, nqs_ctx **out);
 
 /* Release the context and its device memory (synchronises the device).  */
 nqs_status nqs_destroy(nqs_ctx *ctx);
@@ -167,7 +194,8 @@ nqs_status nqs_sr_solve_recompute(nqs_ctx *ctx, const int8_t *spins,
                                   double *stats, void *stream);
 
 /* Inspection of the integer stage [Sec. 5.4.1]: for every sample the count
- * of antiparallel bonds with J != 0 (int32 [B]), exclusive offsets
+ * of antiparallel bonds with J != 0 (t-J: of the pairs with an off-diagonal
+ * term, see nqs_create_tj) (int32 [B]), exclusive offsets
  * (int64 [B+1]), the bond ids in canonical order and the Marshall ratio
  * mu = M(S')/M(s) of each (int32 / int8 [capacity]), and the diagonal energy
  * (FP64 [B]).  capacity must be >= the number of bonds with J != 0 times B

@@ -7,8 +7,9 @@
 //   propose: bond id from the caller's random integer (uniform over the bonds
 //            of the Hamiltonian, canonical order), queue item (chain, bond);
 //   ratio:   f(S') - f(S) by the exchanged-configuration pass of the local
-//            energy (a parallel pair gives S' = S and exactly 0);
-//   accept:  an antiparallel pair is exchanged when u < exp(2 (f(S') - f(S))),
+//            energy (a pair of equal values gives S' = S and exactly 0);
+//   accept:  a pair of different values (antiparallel spins; t-J also an
+//            electron and a hole) is exchanged when u < exp(2 (f(S') - f(S))),
 //            u the caller's uniform number in [0, 1).
 // Where the incremental cone kernel serves, the base pass is taken once and
 // then kept current: accepted chains run a write-back pass of the cone kernel
@@ -26,7 +27,8 @@ namespace {
 constexpr int kThreads = 256;
 
 // Bond id of proposal r: r mod (N * ntypes) = site * ntypes + type index,
-// types {0, 1} (J1) and/or {2, 3} (J2) as the couplings are non-zero.
+// types {0, 1} (nearest neighbours) and/or {2, 3} (next-nearest) as the
+// bonds of each class carry terms (t-J: nearest neighbours only).
 __device__ __host__ inline int proposal_bond(uint32_t r, int N, int j1, int j2)
 {
     const int ntypes = 2 * (j1 + j2);
@@ -59,8 +61,8 @@ __device__ inline void item_pair(uint32_t e, int L, int *i, int *j)
     *j = yj * L + xj;
 }
 
-// flag[s] = 1 when chain s accepts its proposal (antiparallel pair and
-// u < exp(2 dlog)); with apply, the pair is exchanged at once.
+// flag[s] = 1 when chain s accepts its proposal (the pair's values differ
+// and u < exp(2 dlog)); with apply, the pair is exchanged at once.
 __global__ void __launch_bounds__(kThreads)
 k_mcmc_decide(int8_t *__restrict__ spins, int B, int L, const uint32_t *__restrict__ queue,
               const double *__restrict__ dlog, const double *__restrict__ u,
@@ -105,7 +107,7 @@ void launch_mcmc_propose(const nqs_ctx *c, int B, const uint32_t *rnd, uint32_t 
 {
     const int grid = std::max(1, (B + kThreads - 1) / kThreads);
     NQS_LAUNCH(k_mcmc_propose, dim3(grid), dim3(kThreads), 0, s, rnd, B, c->N,
-               c->J1 != 0.0 ? 1 : 0, c->J2 != 0.0 ? 1 : 0, queue, qlen);
+               nn_moves(c) ? 1 : 0, nnn_moves(c) ? 1 : 0, queue, qlen);
 }
 
 void launch_mcmc_decide(const nqs_ctx *c, int8_t *spins, int B, const uint32_t *queue,

@@ -158,7 +158,7 @@ nqs_status pack_weights(nqs_ctx *c)
 
 int64_t bonds_per_sample(const nqs_ctx *c)
 {
-    return (int64_t)2 * c->N * ((c->J1 != 0.0 ? 1 : 0) + (c->J2 != 0.0 ? 1 : 0));
+    return (int64_t)2 * c->N * ((nn_moves(c) ? 1 : 0) + (nnn_moves(c) ? 1 : 0));
 }
 
 nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
@@ -401,33 +401,16 @@ int64_t recompute_chunk(const nqs_ctx *c, int64_t B, int64_t chunk_rows, nqs_dty
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-const char *nqs_status_str(nqs_status s)
-{
-    switch (s) {
-    case NQS_OK: return "ok";
-    case NQS_E_ARG: return "invalid argument";
-    case NQS_E_LATTICE: return "unsupported lattice (L must be even, 4 <= L <= 64)";
-    case NQS_E_SPEC: return "unsupported network specification";
-    case NQS_E_NPARAMS: return "weight count does not match the network";
-    case NQS_E_SPIN: return "spin value other than +1/-1";
-    case NQS_E_NONFINITE: return "non-finite log-amplitude ratio or local energy";
-    case NQS_E_NOMEM: return "device allocation failed";
-    case NQS_E_WORKSPACE: return "workspace too small during stream capture";
-    case NQS_E_HIP: return "HIP runtime error";
-    case NQS_E_UNSUPPORTED: return "not supported by this build";
-    }
-    return "unknown status";
-}
-
-nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
-                      const double *weights, int64_t n_weights, nqs_ctx **out)
+nqs_status create_ctx(int32_t L, int model, double J1, double J2, double t_hop,
+                      const nqs_cnn_spec *spec, const double *weights, int64_t n_weights,
+                      nqs_ctx **out)
 {
     if (!spec || !weights || !out) return NQS_E_ARG;
     *out = nullptr;
     if (L < 4 || L > 64 || (L % 2) != 0) return NQS_E_LATTICE;
-    if (!std::isfinite(J1) || !std::isfinite(J2)) return NQS_E_ARG;
+    if (!std::isfinite(J1) || !std::isfinite(J2) || !std::isfinite(t_hop)) return NQS_E_ARG;
     const int K = spec->n_layers, C = spec->channels;
     if (K < 1 || K > 16 || C < 1 || C > 32) return NQS_E_SPEC;
     if (spec->conv_dtype != NQS_FP64 && spec->conv_dtype != NQS_FP32 &&
@@ -442,6 +425,8 @@ nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
     c->C = C;
     c->J1 = J1;
     c->J2 = J2;
+    c->model = model;
+    c->t_hop = t_hop;
     c->marshall = spec->marshall_sign;
     c->dtype = spec->conv_dtype;
     c->P = n_weights;
@@ -479,6 +464,40 @@ nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
     }
     *out = c;
     return NQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nqs_status_str(nqs_status s)
+{
+    switch (s) {
+    case NQS_OK: return "ok";
+    case NQS_E_ARG: return "invalid argument";
+    case NQS_E_LATTICE: return "unsupported lattice (L must be even, 4 <= L <= 64)";
+    case NQS_E_SPEC: return "unsupported network specification";
+    case NQS_E_NPARAMS: return "weight count does not match the network";
+    case NQS_E_SPIN: return "spin value other than +1/-1";
+    case NQS_E_NONFINITE: return "non-finite log-amplitude ratio or local energy";
+    case NQS_E_NOMEM: return "device allocation failed";
+    case NQS_E_WORKSPACE: return "workspace too small during stream capture";
+    case NQS_E_HIP: return "HIP runtime error";
+    case NQS_E_UNSUPPORTED: return "not supported by this build";
+    }
+    return "unknown status";
+}
+
+nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
+                      const double *weights, int64_t n_weights, nqs_ctx **out)
+{
+    return create_ctx(L, kModelSpin, J1, J2, 0.0, spec, weights, n_weights, out);
+}
+
+nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
+                         const double *weights, int64_t n_weights, nqs_ctx **out)
+{
+    return create_ctx(L, kModelTJ, J, 0.0, t, spec, weights, n_weights, out);
 }
 
 nqs_status nqs_destroy(nqs_ctx *c)
@@ -620,8 +639,9 @@ nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *
     NQS_TRY(integer_stage(c, spins, (int)B, s));
     NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
     NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)c->ws.dlog.ptr, cap, s));
-    launch_energy_reduce(c, (int)B, (int64_t *)c->ws.offsets.ptr, (uint32_t *)c->ws.queue.ptr,
-                         (double *)c->ws.dlog.ptr, (double *)c->ws.ediag.ptr, e_loc, c->err, s);
+    launch_energy_reduce(c, spins, (int)B, (int64_t *)c->ws.offsets.ptr,
+                         (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
+                         (double *)c->ws.ediag.ptr, e_loc, c->err, s);
     return finish_call();
 }
 
@@ -662,8 +682,8 @@ nqs_status nqs_connected(nqs_ctx *c, const int8_t *spins, int64_t B, int32_t *co
     HIP_OK(hipMemcpyAsync(offsets, c->ws.offsets.ptr, sizeof(int64_t) * (B + 1),
                           hipMemcpyDeviceToDevice, s));
     HIP_OK(hipMemcpyAsync(e_diag, c->ws.ediag.ptr, sizeof(double) * B, hipMemcpyDeviceToDevice, s));
-    launch_queue_expand(c, (uint32_t *)c->ws.queue.ptr, (int64_t *)c->ws.qlen.ptr, capacity,
-                        bond_ids, mu, s);
+    launch_queue_expand(c, spins, (uint32_t *)c->ws.queue.ptr, (int64_t *)c->ws.qlen.ptr,
+                        capacity, bond_ids, mu, s);
     return finish_call();
 }
 
@@ -846,7 +866,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     for (int i = 0; i < n; ++i) {
         nqs_ctx *c = jobs[i].ctx;
         if (jobs[i].B == 0) continue;
-        launch_energy_reduce(c, (int)jobs[i].B, (int64_t *)c->ws.offsets.ptr,
+        launch_energy_reduce(c, jobs[i].spins, (int)jobs[i].B, (int64_t *)c->ws.offsets.ptr,
                              (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
                              (double *)c->ws.ediag.ptr, jobs[i].e_loc, c->err, s);
     }

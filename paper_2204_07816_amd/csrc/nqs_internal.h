@@ -27,6 +27,12 @@ __host__ __device__ inline uint32_t pack_item(int sample, int bond) {
 __host__ __device__ inline int item_sample(uint32_t e) { return (int)(e >> kBondBits); }
 __host__ __device__ inline int item_bond(uint32_t e) { return (int)(e & ((1u << kBondBits) - 1)); }
 
+// Hamiltonian of a context: the J1-J2 spin model [Sec. 6.1, Eq. J1J2] or
+// the t-J model [Sec. 6.1, Eq. tJ] (site values +1 / -1 / 0, nearest-
+// neighbour bonds only, J held in J1).
+constexpr int kModelSpin = 0;
+constexpr int kModelTJ = 1;
+
 // Device-side sticky error codes (ORed bits, mapped to nqs_status on read).
 constexpr int kErrSpin = 1;
 constexpr int kErrNonFinite = 2;
@@ -63,6 +69,8 @@ struct Workspace {
 struct nqs_ctx {
     int L = 0, N = 0, K = 0, C = 0;
     double J1 = 1.0, J2 = 0.0;
+    int model = nqs::kModelSpin;
+    double t_hop = 0.0;           // t-J hopping amplitude t
     int marshall = 1;
     nqs_dtype dtype = NQS_FP64;
     int64_t P = 0;
@@ -123,8 +131,13 @@ void launch_queue_fill(const nqs_ctx *c, const int8_t *spins, int B, const int64
 // Marshall sign per sample (+ spin validation); sign may be null.
 void launch_marshall(const nqs_ctx *c, const int8_t *spins, int B, int8_t *sign, hipStream_t s);
 // inspection: bond ids + Marshall ratios from the queue.
-void launch_queue_expand(const nqs_ctx *c, const uint32_t *queue, const int64_t *qlen,
-                         int64_t capacity, int32_t *bond_ids, int8_t *mu, hipStream_t s);
+void launch_queue_expand(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                         const int64_t *qlen, int64_t capacity, int32_t *bond_ids, int8_t *mu,
+                         hipStream_t s);
+// whether nearest-neighbour (t = 0, 1) and next-nearest (t = 2, 3) bonds
+// carry off-diagonal terms in this context
+inline bool nn_moves(const nqs_ctx *c);
+inline bool nnn_moves(const nqs_ctx *c);
 
 // --- vector (FP64 / FP32) network kernels (k_conv_vec.hip) ---
 // Base pass over B samples: f[B], hsum[B][N]; planes are scratch [B*N*C].
@@ -222,9 +235,9 @@ bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, 
 int mfma_full_variants(const nqs_ctx *c, int *nw, int *maxt, int cap);
 
 // --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
-void launch_energy_reduce(const nqs_ctx *c, int B, const int64_t *offsets, const uint32_t *queue,
-                          const double *dlog, const double *ediag, double *e_loc, int32_t *err,
-                          hipStream_t s);
+void launch_energy_reduce(const nqs_ctx *c, const int8_t *spins, int B, const int64_t *offsets,
+                          const uint32_t *queue, const double *dlog, const double *ediag,
+                          double *e_loc, int32_t *err, hipStream_t s);
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
 
 // --- device-side parameter update (k_pack.hip) ---
@@ -256,5 +269,11 @@ int64_t sr_row_block(int64_t B);
 void launch_sr_solve_rows(const SrRows &rows, void *obuf, int64_t chunk, nqs_dtype odt,
                           const double *e_loc, int64_t B, int64_t P, double lambda, int n_iter,
                           double *x, double *stats, void *work, hipStream_t s);
+
+inline bool nn_moves(const nqs_ctx *c)
+{
+    return c->J1 != 0.0 || (c->model == kModelTJ && c->t_hop != 0.0);
+}
+inline bool nnn_moves(const nqs_ctx *c) { return c->J2 != 0.0; }
 
 }  // namespace nqs

@@ -59,6 +59,7 @@ def load():
     P = ctypes.POINTER
     sig = {
         "nqs_create": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
+        "nqs_create_tj": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
         "nqs_destroy": [vp],
         "nqs_num_params": [vp, P(i64)],
         "nqs_set_weights": [vp, vp, i64],
@@ -124,19 +125,33 @@ def num_params(K: int, C: int) -> int:
 
 
 class Context:
-    """One lattice + network (nqs_create / nqs_destroy)."""
+    """One lattice + network (nqs_create / nqs_create_tj / nqs_destroy)."""
 
     def __init__(self, L: int, J1: float, J2: float, K: int, C: int, weights,
-                 dtype: str = "fp64", marshall_sign: bool = True):
+                 dtype: str = "fp64", marshall_sign: bool = True, *,
+                 tj_hop: float | None = None):
         lib = load()
         w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
         spec = CnnSpec(K, C, 1 if marshall_sign else 0, _DTYPES[dtype])
         h = ctypes.c_void_p()
-        _check(lib.nqs_create(L, J1, J2, ctypes.byref(spec), ctypes.c_void_p(w.data_ptr()),
-                              w.numel(), ctypes.byref(h)), "nqs_create")
+        if tj_hop is None:
+            _check(lib.nqs_create(L, J1, J2, ctypes.byref(spec), ctypes.c_void_p(w.data_ptr()),
+                                  w.numel(), ctypes.byref(h)), "nqs_create")
+        else:
+            _check(lib.nqs_create_tj(L, tj_hop, J1, ctypes.byref(spec),
+                                     ctypes.c_void_p(w.data_ptr()), w.numel(), ctypes.byref(h)),
+                   "nqs_create_tj")
         self._h = h
         self.L, self.J1, self.J2, self.K, self.C, self.dtype = L, J1, J2, K, C, dtype
+        self.model = "spin" if tj_hop is None else "tj"
+        self.t = tj_hop
         self.P = self.num_params()
+
+    @classmethod
+    def tj(cls, L: int, t: float, J: float, K: int, C: int, weights, dtype: str = "fp64",
+           marshall_sign: bool = True) -> "Context":
+        """A t-J context (nqs_create_tj): site values +1 up, -1 down, 0 hole."""
+        return cls(L, J, 0.0, K, C, weights, dtype, marshall_sign, tj_hop=t)
 
     @property
     def handle(self):
@@ -289,7 +304,8 @@ class Context:
         return x, st
 
     def capacity(self, B: int) -> int:
-        per = 2 * self.L * self.L * ((1 if self.J1 != 0 else 0) + (1 if self.J2 != 0 else 0))
+        nn = self.J1 != 0 or (self.model == "tj" and self.t != 0)
+        per = 2 * self.L * self.L * ((1 if nn else 0) + (1 if self.J2 != 0 else 0))
         return per * B
 
     def connected(self, spins):

@@ -88,3 +88,18 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(nqs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         nqs.load()
+
+
+def test_create_tj_rejects_bad_arguments(lib):
+    from paper_2204_07816_amd import nqs
+    sp = nqs.CnnSpec(2, 4, 1, 0)
+    buf = (ctypes.c_double * 188)()
+    h = ctypes.c_void_p()
+    assert lib.nqs_create_tj(5, 1.0, 0.4, ctypes.byref(sp), buf, 188, ctypes.byref(h)) == 2
+    assert lib.nqs_create_tj(4, float("nan"), 0.4, ctypes.byref(sp), buf, 188,
+                             ctypes.byref(h)) == 1
+    assert lib.nqs_create_tj(4, 1.0, float("inf"), ctypes.byref(sp), buf, 188,
+                             ctypes.byref(h)) == 1
+    assert lib.nqs_create_tj(4, 1.0, 0.4, None, buf, 188, ctypes.byref(h)) == 1
+    assert lib.nqs_create_tj(4, 1.0, 0.4, ctypes.byref(sp), buf, 187, ctypes.byref(h)) == 4
+    assert not h.value
