@@ -200,6 +200,58 @@ def mixed_row(dev, reps=3):
     return out
 
 
+def tj_row(dev, reps=3, fp64_samples=256):
+    """Non-gating row: the t-J workload (12x12, t = 1, J = 0.4, hole doping
+    1/8, K=6, C=32, weights N(0, 0.02^2), 4096 configurations): E_loc per
+    pass in BF16 (autotuned on 64 samples), the exchanged-configuration
+    kernel's average launch and algorithmic rate, and the BF16 mean against
+    the FP64 GPU form on a subset."""
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    L, t, J, K, C, w, sp = inputs.tj_config_inputs("tj12")
+    B = sp.shape[0]
+    ctx = nqs.Context.tj(L, t, J, K, C, w, dtype="bf16")
+    spd = torch.as_tensor(sp).to(dev)
+    mode = ctx.autotune(spd[:64].contiguous())
+    ctx.reserve(B, mode)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    ctx.local_energy(spd, mode=mode, out=e)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.local_energy(spd, mode=mode, out=e)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    k_ms, k_n = ctx.kernel_time()
+    ctx.enable_timing(False)
+    items = int(ctx.connected(spd)[0].sum().item())
+    if mode == "incremental":
+        per_item = item_flops(L, K, C, False)
+    else:
+        per_item = L * L * C * 9 * 2 + (K - 1) * L * L * C * 9 * C * 2
+    avg = k_ms / max(k_n, 1)
+    achieved = items * per_item / (avg * 1e-3) / 1e12
+    c64 = nqs.Context.tj(L, t, J, K, C, w, dtype="fp64")
+    e64 = c64.local_energy(spd[:fp64_samples].contiguous(), mode="full").cpu().numpy()
+    eb = e.cpu().numpy()[:fp64_samples]
+    rel = abs(eb.mean() - e64.mean()) / abs(e64.mean())
+    assert ctx.get_error() == 0 and c64.get_error() == 0
+    out = {"workload": f"{L}x{L} t-J (t={t}, J={J}, {inputs.TJ_CONFIGS['tj12']['n_holes']} "
+                       f"holes), CNN {K}x3x3x{C}, {B} configurations",
+           "samples_per_s": B / (ms * 1e-3), "ms": ms, "mode": mode,
+           "exchanged_configurations": items, "mean_energy": float(e.mean().item()),
+           "kernel_avg_launch_ms": avg, "kernel_tflops": achieved,
+           "kernel_frac_bf16_peak": achieved / PEAK_BF16_TFLOPS,
+           "bf16_mean_rel_err_vs_fp64": float(rel), "fp64_samples": fp64_samples,
+           "bar_1e-5_met": bool(rel <= 1e-5)}
+    ctx.close()
+    c64.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,14 +263,16 @@ def main():
     ap.add_argument("--no-recompute", action="store_true")
     ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--no-vmc", action="store_true")
+    ap.add_argument("--no-tj", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--mode", default="incremental", choices=["incremental", "full"])
-    ap.add_argument("--only", default=None, choices=["eloc"],
-                    help="profiling aid: run only the local-energy call --steps times, then a "
-                         "1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--only", default=None, choices=["eloc", "tj"],
+                    help="profiling aid: eloc runs only the local-energy call --steps times, "
+                         "then a 1 GiB device copy (reference for the HBM byte counters); tj "
+                         "runs only the t-J row and prints it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -232,6 +286,9 @@ def main():
     from paper_2204_07816_amd import inputs, nqs
 
     dev = torch.device("cuda:0")
+    if args.only == "tj":
+        print(json.dumps(tj_row(dev)), flush=True)
+        return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
     log(f"workload 36x36 K={K} C={C} B={B}")
@@ -459,6 +516,12 @@ def main():
         del gv
         cv.close()
 
+    tj = None
+    if not args.no_tj:
+        tj = tj_row(dev)
+        log(f"t-J 12x12: {tj['samples_per_s']:.1f} samples/s ({tj['mode']}), kernel "
+            f"{tj['kernel_tflops']:.0f} TFLOP/s, bf16 mean rel err {tj['bf16_mean_rel_err_vs_fp64']:.2e}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -484,6 +547,7 @@ def main():
         "sr_recompute_nongating": recompute,
         "mcmc_nongating": mcmc,
         "vmc_iteration_nongating": vmc,
+        "tj_nongating": tj,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
