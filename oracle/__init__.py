@@ -56,6 +56,10 @@ def _load():
         "oracle_tj_local_energy_table": (None, [ci, d, d, i64, P(i64), P(d), P(i8), P(i8), i64,
                                                 P(d), ci]),
         "oracle_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_cnn1_num_params": (i64, [ci, ci]),
+        "oracle_cnn1_log_psi": (None, [ci, ci, ci, P(d), ci, P(i8), i64, P(d), P(i8), ci]),
+        "oracle_cnn1_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d), ci]),
+        "oracle_cnn1_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
         "oracle_energy_stats": (None, [P(d), i64, P(d)]),
         "oracle_sr_cg": (None, [P(d), P(d), i64, i64, d, ci, P(d), P(d)]),
         "oracle_sr_dense": (ci, [P(d), P(d), i64, i64, d, P(d)]),
@@ -224,6 +228,46 @@ def log_deriv(L: int, K: int, C: int, w, spins, nthreads: int = 0):
     O = np.zeros((B, P), np.float64)
     _load().oracle_log_deriv(L, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
                              _p(O, ctypes.c_double), nthreads)
+    return O
+
+
+def cnn1_num_params(Kb: int, C: int) -> int:
+    return int(_load().oracle_cnn1_num_params(Kb, C))
+
+
+def cnn1_log_psi(L: int, Kb: int, C: int, w, spins, marshall: bool = True, nthreads: int = 0):
+    """CNN1 (Sec. 5.2, reading in nqs_oracle.h): (log|psi| [B], sign [B])."""
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    assert w.shape[0] == cnn1_num_params(Kb, C)
+    B = s.shape[0]
+    la = np.zeros(B, np.float64)
+    sg = np.zeros(B, np.int8)
+    _load().oracle_cnn1_log_psi(L, Kb, C, _p(w, ctypes.c_double), int(marshall),
+                                _p(s, ctypes.c_int8), B, _p(la, ctypes.c_double),
+                                _p(sg, ctypes.c_int8), nthreads)
+    return la, sg
+
+
+def cnn1_local_energy(L: int, J1: float, J2: float, Kb: int, C: int, w, spins,
+                      marshall: bool = True, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_cnn1_local_energy(L, J1, J2, Kb, C, _p(w, ctypes.c_double), int(marshall),
+                                     _p(s, ctypes.c_int8), B, _p(e, ctypes.c_double), nthreads)
+    return e
+
+
+def cnn1_log_deriv(L: int, Kb: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    P = cnn1_num_params(Kb, C)
+    O = np.zeros((B, P), np.float64)
+    _load().oracle_cnn1_log_deriv(L, Kb, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
+                                  _p(O, ctypes.c_double), nthreads)
     return O
 
 

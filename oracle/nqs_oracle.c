@@ -15,6 +15,12 @@
  *   - CNN with periodic (PBC) padding and a product of neurons as output:
  *     Sec. 5.2; the layer shape (3x3 conv, ln cosh, sum pool) is the
  *     configuration this library is checked on.
+ *   - CNN1 (Sec. 5.2: convolution, 1D max-pooling, transposed convolution,
+ *     product of neurons) in the reading stated in nqs_oracle.h; its
+ *     hyper-parameters are in a missing figure, so the architecture itself
+ *     is parity unpinned against the paper (the functions are pinned
+ *     against torch's conv2d / conv_transpose2d / autograd and the exact
+ *     diagonalisation).
  *   - t-J model: Sec. 6.1, Eq. (tJ), with the fermions encoded by the
  *     Jordan-Wigner transformation along the site order i = y*L + x.
  *   - O_loc = per-sample log-derivative and the SR update: Sec. 3.2 and
@@ -491,6 +497,338 @@ void oracle_tj_local_energy_table(int L, double t, double J, int64_t n_tab, cons
 {
     tj_table tab = {n_tab, keys, log_abs_tab, sign_tab};
     tj_local_energy_batch(L, 0, 0, NULL, &tab, t, J, spins, B, e_loc, nthreads);
+}
+
+/* ------------------------------------------------------------------ */
+/* CNN1 (Sec. 5.2): blocks of convolution, 1D max-pooling, transposed    */
+/* convolution; output the product of the neurons                        */
+/* ------------------------------------------------------------------ */
+/* Reading (the block figure is missing): block k maps c_in channels
+ * (1 for the spins, else C) to C channels by
+ *   z[co][p]  = a[co] + sum_{ci,ky,kx} W[co][ci][ky][kx] h[ci][p + (ky-1, kx-1)]   (co < 2C)
+ *   m[c][p]   = max(z[2c][p], z[2c+1][p])          (1D max-pool over channel pairs)
+ *   u[co][p]  = v[co] + sum_{ci,ky,kx} V[ci][co][ky][kx] m[ci][p - (ky-1, kx-1)]
+ *               (transposed convolution, stride 1)
+ * with every lattice index taken mod L (padding by the periodic boundary).
+ * psi_net = prod_{c,p} u_K[c][p]: log|psi| = sum log|u_K|, sign = prod sign(u_K).
+ * Canonical order per block: W, a, V, v.                                 */
+
+int64_t oracle_cnn1_num_params(int Kb, int C)
+{
+    if (Kb < 1 || C < 1) return 0;
+    int64_t p = 0;
+    for (int k = 0; k < Kb; ++k) {
+        int cin = (k == 0) ? 1 : C;
+        p += (int64_t)2 * C * cin * 9 + 2 * C + (int64_t)C * C * 9 + C;
+    }
+    return p;
+}
+
+typedef struct {
+    int64_t W, a, V, v;   /* offsets of one block's parameters */
+    int cin;
+} cnn1_block;
+
+static cnn1_block cnn1_offsets(int C, int k)
+{
+    cnn1_block o;
+    int64_t off = 0;
+    for (int l = 0; l < k; ++l) {
+        int ci = (l == 0) ? 1 : C;
+        off += (int64_t)2 * C * ci * 9 + 2 * C + (int64_t)C * C * 9 + C;
+    }
+    o.cin = (k == 0) ? 1 : C;
+    o.W = off;
+    o.a = o.W + (int64_t)2 * C * o.cin * 9;
+    o.V = o.a + 2 * C;
+    o.v = o.V + (int64_t)C * C * 9;
+    return o;
+}
+
+/* one block: h [cin][N] -> z [2C][N], m [C][N], u [C][N] */
+static void cnn1_block_forward(int L, int C, const double *w, cnn1_block o, const double *h,
+                               double *z, double *m, double *u)
+{
+    const int N = L * L;
+    for (int co = 0; co < 2 * C; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = w[o.a + co];
+                for (int ci = 0; ci < o.cin; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx)
+                            acc += w[o.W + ((co * o.cin + ci) * 3 + ky) * 3 + kx] *
+                                   h[ci * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                z[co * N + y * L + x] = acc;
+            }
+    for (int c = 0; c < C; ++c)
+        for (int p = 0; p < N; ++p) {
+            double z0 = z[(2 * c) * N + p], z1 = z[(2 * c + 1) * N + p];
+            m[c * N + p] = (z1 > z0) ? z1 : z0;
+        }
+    for (int co = 0; co < C; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = w[o.v + co];
+                for (int ci = 0; ci < C; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx)
+                            acc += w[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] *
+                                   m[ci * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                u[co * N + y * L + x] = acc;
+            }
+}
+
+/* forward of all blocks; zs / us (may be NULL) keep every block's z and u.
+ * Returns log|psi_net|; *neg = number of negative output neurons.       */
+static double cnn1_forward(int L, int Kb, int C, const double *w, const int8_t *spins,
+                           double *hin, double *z, double *m, double *u, double *zs, double *us,
+                           int *neg)
+{
+    const int N = L * L;
+    for (int i = 0; i < N; ++i) hin[i] = (double)spins[i];
+    const double *h = hin;
+    for (int k = 0; k < Kb; ++k) {
+        cnn1_block o = cnn1_offsets(C, k);
+        double *zk = zs ? zs + (size_t)k * 2 * C * N : z;
+        double *uk = us ? us + (size_t)k * C * N : u;
+        cnn1_block_forward(L, C, w, o, h, zk, m, uk);
+        if (!us) {                       /* the next block reads u from hin */
+            memcpy(hin, uk, sizeof(double) * (size_t)C * N);
+            h = hin;
+        } else {
+            h = uk;
+        }
+    }
+    const double *uK = us ? us + (size_t)(Kb - 1) * C * N : hin;
+    double f = 0.0;
+    int n = 0;
+    for (int q = 0; q < C * N; ++q) {
+        f += log(fabs(uK[q]));
+        n += (uK[q] < 0.0);
+    }
+    *neg = n;
+    return f;
+}
+
+typedef struct {
+    double *hin, *z, *m, *u;
+} cnn1_bufs;
+
+static void cnn1_bufs_alloc(cnn1_bufs *b, int L, int C)
+{
+    size_t n = (size_t)L * L * (size_t)C;
+    b->hin = (double *)malloc(sizeof(double) * n);
+    b->z = (double *)malloc(sizeof(double) * 2 * n);
+    b->m = (double *)malloc(sizeof(double) * n);
+    b->u = (double *)malloc(sizeof(double) * n);
+}
+
+static void cnn1_bufs_free(cnn1_bufs *b)
+{
+    free(b->hin);
+    free(b->z);
+    free(b->m);
+    free(b->u);
+}
+
+/* psi = M(s)^marshall * prod u_K: log|psi| and sign */
+static double cnn1_amplitude(int L, int Kb, int C, const double *w, int marshall,
+                             const int8_t *spins, cnn1_bufs *b, int *sign)
+{
+    int neg;
+    double f = cnn1_forward(L, Kb, C, w, spins, b->hin, b->z, b->m, b->u, NULL, NULL, &neg);
+    int sg = (neg % 2 == 0) ? 1 : -1;
+    if (marshall) sg *= oracle_marshall_sign(L, spins);
+    *sign = sg;
+    return f;
+}
+
+void oracle_cnn1_log_psi(int L, int Kb, int C, const double *w, int marshall,
+                         const int8_t *spins, int64_t B, double *log_abs, int8_t *sign,
+                         int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn1_bufs b;
+        cnn1_bufs_alloc(&b, L, C);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            int sg;
+            log_abs[s] = cnn1_amplitude(L, Kb, C, w, marshall, spins + s * N, &b, &sg);
+            if (sign) sign[s] = (int8_t)sg;
+        }
+        cnn1_bufs_free(&b);
+    }
+}
+
+void oracle_cnn1_local_energy(int L, double J1, double J2, int Kb, int C, const double *w,
+                              int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                              int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn1_bufs b;
+        cnn1_bufs_alloc(&b, L, C);
+        int8_t *work = (int8_t *)malloc((size_t)N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            const int8_t *sp = spins + s * N;
+            int m0;
+            double f0 = cnn1_amplitude(L, Kb, C, w, marshall, sp, &b, &m0);
+            double e = 0.0;
+            for (int bd = 0; bd < 4 * N; ++bd) {
+                int si, sj;
+                int cls = oracle_bond_sites(L, bd, &si, &sj);
+                double J = (cls == 1) ? J1 : J2;
+                e += J * (double)sp[si] * (double)sp[sj] / 4.0;
+                if (J == 0.0 || sp[si] == sp[sj]) continue;
+                memcpy(work, sp, (size_t)N);
+                work[si] = sp[sj];
+                work[sj] = sp[si];
+                int m1;
+                double f1 = cnn1_amplitude(L, Kb, C, w, marshall, work, &b, &m1);
+                e += (J / 2.0) * (double)(m1 * m0) * exp(f1 - f0);
+            }
+            e_loc[s] = e;
+        }
+        free(work);
+        cnn1_bufs_free(&b);
+    }
+}
+
+/* O[p] = d log|psi| / d theta_p by reverse mode through the blocks; the
+ * max routes its gradient to the larger input (the first on a tie).      */
+static void cnn1_log_deriv_one(int L, int Kb, int C, const double *w, const int8_t *spins,
+                               double *O, double *zs, double *us, cnn1_bufs *b,
+                               double *gu, double *gm, double *gz, double *gh)
+{
+    const int N = L * L;
+    int neg;
+    cnn1_forward(L, Kb, C, w, spins, b->hin, b->z, b->m, b->u, zs, us, &neg);
+    const double *uK = us + (size_t)(Kb - 1) * C * N;
+    for (int q = 0; q < C * N; ++q) gu[q] = 1.0 / uK[q];
+    for (int k = Kb - 1; k >= 0; --k) {
+        cnn1_block o = cnn1_offsets(C, k);
+        const double *zk = zs + (size_t)k * 2 * C * N;
+        /* block input h and the pooled m */
+        double *h = b->hin;
+        if (k == 0) {
+            for (int i = 0; i < N; ++i) h[i] = (double)spins[i];
+        } else {
+            memcpy(h, us + (size_t)(k - 1) * C * N, sizeof(double) * (size_t)C * N);
+        }
+        double *m = b->m;
+        for (int c = 0; c < C; ++c)
+            for (int p = 0; p < N; ++p) {
+                double z0 = zk[(2 * c) * N + p], z1 = zk[(2 * c + 1) * N + p];
+                m[c * N + p] = (z1 > z0) ? z1 : z0;
+            }
+        /* transposed convolution: dV, dv, and dL/dm */
+        for (int ci = 0; ci < C; ++ci)
+            for (int co = 0; co < C; ++co)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double acc = 0.0;
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x)
+                                acc += gu[co * N + y * L + x] *
+                                       m[ci * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                        O[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] = acc;
+                    }
+        for (int co = 0; co < C; ++co) {
+            double acc = 0.0;
+            for (int p = 0; p < N; ++p) acc += gu[co * N + p];
+            O[o.v + co] = acc;
+        }
+        for (int ci = 0; ci < C; ++ci)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    double acc = 0.0;
+                    for (int co = 0; co < C; ++co)
+                        for (int ky = 0; ky < 3; ++ky)
+                            for (int kx = 0; kx < 3; ++kx)
+                                acc += w[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] *
+                                       gu[co * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                    gm[ci * N + y * L + x] = acc;
+                }
+        /* max over channel pairs */
+        for (int c = 0; c < C; ++c)
+            for (int p = 0; p < N; ++p) {
+                double z0 = zk[(2 * c) * N + p], z1 = zk[(2 * c + 1) * N + p];
+                int second = (z1 > z0);
+                gz[(2 * c) * N + p] = second ? 0.0 : gm[c * N + p];
+                gz[(2 * c + 1) * N + p] = second ? gm[c * N + p] : 0.0;
+            }
+        /* convolution: dW, da, and dL/dh for the block below */
+        for (int co = 0; co < 2 * C; ++co)
+            for (int ci = 0; ci < o.cin; ++ci)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double acc = 0.0;
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x)
+                                acc += gz[co * N + y * L + x] *
+                                       h[ci * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                        O[o.W + ((co * o.cin + ci) * 3 + ky) * 3 + kx] = acc;
+                    }
+        for (int co = 0; co < 2 * C; ++co) {
+            double acc = 0.0;
+            for (int p = 0; p < N; ++p) acc += gz[co * N + p];
+            O[o.a + co] = acc;
+        }
+        if (k > 0) {
+            for (int ci = 0; ci < C; ++ci)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        double acc = 0.0;
+                        for (int co = 0; co < 2 * C; ++co)
+                            for (int ky = 0; ky < 3; ++ky)
+                                for (int kx = 0; kx < 3; ++kx)
+                                    acc += w[o.W + ((co * C + ci) * 3 + ky) * 3 + kx] *
+                                           gz[co * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                        gh[ci * N + y * L + x] = acc;
+                    }
+            memcpy(gu, gh, sizeof(double) * (size_t)C * N);
+        }
+    }
+}
+
+void oracle_cnn1_log_deriv(int L, int Kb, int C, const double *w, const int8_t *spins,
+                           int64_t B, double *O, int nthreads)
+{
+    const int N = L * L;
+    const int64_t P = oracle_cnn1_num_params(Kb, C);
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn1_bufs b;
+        cnn1_bufs_alloc(&b, L, C);
+        size_t cn = (size_t)C * N;
+        double *zs = (double *)malloc(sizeof(double) * 2 * cn * Kb);
+        double *us = (double *)malloc(sizeof(double) * cn * Kb);
+        double *gu = (double *)malloc(sizeof(double) * cn);
+        double *gm = (double *)malloc(sizeof(double) * cn);
+        double *gz = (double *)malloc(sizeof(double) * 2 * cn);
+        double *gh = (double *)malloc(sizeof(double) * cn);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s)
+            cnn1_log_deriv_one(L, Kb, C, w, spins + s * N, O + s * P, zs, us, &b, gu, gm, gz, gh);
+        free(zs);
+        free(us);
+        free(gu);
+        free(gm);
+        free(gz);
+        free(gh);
+        cnn1_bufs_free(&b);
+    }
 }
 
 /* ------------------------------------------------------------------ */

@@ -105,6 +105,31 @@ void oracle_tj_local_energy_table(int L, double t, double J, int64_t n_tab, cons
                                   const double *log_abs_tab, const int8_t *sign_tab,
                                   const int8_t *spins, int64_t B, double *e_loc, int nthreads);
 
+/* CNN1 [Sec. 5.2: blocks of a 2D convolution, a 1D max-pooling and a
+ * transposed convolution, periodic padding, output the product of the
+ * neurons].  The block figure is missing; the reading implemented here:
+ * block k maps c_in (1, then C) channels to C by
+ *   z = a + W (*) h        3x3 circular convolution, c_in -> 2C, W[2C][c_in][3][3]
+ *   m[c] = max(z[2c], z[2c+1])             max-pool of window 2 over channels
+ *   u = v + V (*)^T m      3x3 circular transposed convolution, stride 1,
+ *                          C -> C, V[C_in][C_out][3][3]:
+ *                          u[co][p] = v[co] + sum V[ci][co][ky][kx] m[ci][p - (ky-1, kx-1)]
+ * and psi = M(s)^marshall prod_{c,p} u_K[c][p] (so log|psi| = sum log|u_K|
+ * and the network carries a sign).  Canonical order per block: W, a, V, v. */
+int64_t oracle_cnn1_num_params(int Kb, int C);
+void oracle_cnn1_log_psi(int L, int Kb, int C, const double *w, int marshall,
+                         const int8_t *spins, int64_t B, double *log_abs, int8_t *sign,
+                         int nthreads);
+/* J1-J2 local energy with the CNN1 amplitude (sign ratio of the network
+ * and, if marshall, of the Marshall sign), full recomputation.          */
+void oracle_cnn1_local_energy(int L, double J1, double J2, int Kb, int C, const double *w,
+                              int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                              int nthreads);
+/* O[s][p] = d log|psi(s)| / d theta_p by reverse mode; a max passes its
+ * gradient to the larger input, the first one on a tie.                 */
+void oracle_cnn1_log_deriv(int L, int Kb, int C, const double *w, const int8_t *spins,
+                           int64_t B, double *O, int nthreads);
+
 /* Per-sample log-derivatives O[s][p] = d f(s) / d theta_p, FP64, by the
  * reverse-mode chain rule through the network.                          */
 void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,

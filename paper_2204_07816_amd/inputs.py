@@ -43,6 +43,18 @@ def stress_weights(K: int, C: int, gain: float, seed: int, sigma1: float = 0.5) 
     return np.concatenate(out).astype(np.float64)
 
 
+def cnn1_num_params(Kb: int, C: int) -> int:
+    """Parameters of the CNN1 blocks: per block a 3x3 convolution c_in -> 2C
+    with bias and a 3x3 transposed convolution C -> C with bias."""
+    return sum(2 * C * (1 if k == 0 else C) * 9 + 2 * C + C * C * 9 + C for k in range(Kb))
+
+
+def cnn1_weights(Kb: int, C: int, sigma: float, seed: int) -> np.ndarray:
+    """CNN1 parameters, i.i.d. N(0, sigma^2) in canonical order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(0.0, sigma, cnn1_num_params(Kb, C)).astype(np.float64)
+
+
 def spins_sz0(L: int, B: int, seed: int) -> np.ndarray:
     """int8 [B, L, L] configurations, uniform over the Sz = 0 sector."""
     N = L * L
