@@ -15,6 +15,8 @@
  *   O_k(s) = d log|psi(s)| / d theta_k per sample                          [Sec. 3.2, O_loc by backward]
  *   SR: (S + lambda I) dtheta = F, S = Obar^T Obar / Ns,
  *       F = Obar^T (E - Ebar) / Ns                                        [Sec. 3.2; Sec. 5.4.1 distributed SR]
+ *   CNN1 contexts (nqs_create_cnn1): blocks of convolution, max-pooling and
+ *     transposed convolution, psi the product of the output neurons       [Sec. 5.2]
  *   t-J contexts (nqs_create_tj): H = -t sum_<ij>,sigma (c+_i c_j + h.c.)
  *     + J sum_<ij> (S_i.S_j - n_i n_j / 4), fermions encoded by the
  *     Jordan-Wigner transformation along the site order                   [Sec. 6.1, Eq. tJ]
@@ -118,6 +120,34 @@ nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
  * Errors as nqs_create (t, J must be finite).                             */
 nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
                          const double *weights, int64_t n_weights, nqs_ctx **out);
+
+/* A context whose network is CNN1 [Sec. 5.2: blocks of a 2D convolution, a
+ * 1D max-pooling and a transposed convolution, padded by the periodic
+ * boundary; the coefficient is the product of the output neurons], for the
+ * J1-J2 model, in FP64.  The block figure is missing; the block read here,
+ * for k = 1..blocks, c_in = 1 (spins) then channels = C:
+ *   z = a + W (*) h       3x3 circular convolution c_in -> 2C, W[2C][c_in][3][3]
+ *   m[c] = max(z[2c], z[2c+1])            max-pool of window 2 over channels
+ *   u[co][p] = v[co] + sum V[ci][co][ky][kx] m[ci][p - (ky-1, kx-1)]
+ *                         3x3 circular transposed convolution C -> C, stride 1
+ *   psi = M(s)^marshall_sign * prod_{c,p} u_blocks[c][p]
+ * Weights (host FP64, copied), canonical order per block: W, a, V, v;
+ * n_weights = sum_k (2C c_in 9 + 2C + 9 C^2 + C).
+ * Entry points serving CNN1 contexts: nqs_log_psi (sign = M^marshall times
+ * the sign of the neuron product), nqs_local_energy, nqs_log_ratios and
+ * nqs_mcmc (FULL or AUTO mode; the per-item sign ratio of the network enters
+ * E_loc), nqs_log_deriv (d log|psi| / d theta by a backward pass: 1/u at the
+ * output, a max passes its gradient to the larger input, the first on a
+ * tie), nqs_sr_solve, nqs_sr_solve_recompute, nqs_energy_stats,
+ * nqs_connected, nqs_set_weights, nqs_update_weights, nqs_get_weights,
+ * nqs_reserve.  nqs_local_energy_multi and nqs_autotune return
+ * NQS_E_UNSUPPORTED, and INCREMENTAL mode does too.  An output neuron of
+ * exactly 0 makes log|psi| infinite: NQS_E_NONFINITE.
+ * Errors: NQS_E_LATTICE, NQS_E_SPEC (blocks or channels outside 1..16 /
+ * 1..32, marshall_sign not 0/1), NQS_E_NPARAMS, NQS_E_ARG as nqs_create.  */
+nqs_status nqs_create_cnn1(int32_t L, double J1, double J2, int32_t blocks, int32_t channels,
+                           int32_t marshall_sign, const double *weights, int64_t n_weights,
+                           nqs_ctx **out);
 
 /* Release the context and its device memory (synchronises the device).  */
 nqs_status nqs_destroy(nqs_ctx *ctx);

@@ -311,9 +311,13 @@ def sr_apply(O, v, lam: float = 1e-4):
     return y
 
 
-def _metropolis(L, types, K, C, w, spins, rand_bond, rand_u):
+def _metropolis(L, types, K, C, w, spins, rand_bond, rand_u, logpsi=None):
     """Metropolis steps of every chain with proposals over the bond types
-    `types` (see mcmc); the pair's site values are exchanged on acceptance."""
+    `types` (see mcmc); the pair's site values are exchanged on acceptance.
+    logpsi(w, spins) -> log|psi| (default: the ln cosh CNN)."""
+    if logpsi is None:
+        def logpsi(w_, s_):
+            return log_psi(L, K, C, w_, s_)[0]
     s = _spins(spins, L).copy()
     B, N = s.shape
     acc = np.zeros(B, np.int64)
@@ -330,8 +334,8 @@ def _metropolis(L, types, K, C, w, spins, rand_bond, rand_u):
             i, j, _ = bond_sites(L, 4 * (q // n) + types[q % n])
             pairs.append((i, j))
             prop[b, i], prop[b, j] = s[b, j], s[b, i]
-        f0, _ = log_psi(L, K, C, w, s)
-        f1, _ = log_psi(L, K, C, w, prop)
+        f0 = logpsi(w, s)
+        f1 = logpsi(w, prop)
         for b, (i, j) in enumerate(pairs):
             if s[b, i] != s[b, j] and ru[t, b] < np.exp(2.0 * (f1[b] - f0[b])):
                 s[b] = prop[b]
@@ -361,7 +365,14 @@ def tj_mcmc(L: int, t: float, J: float, K: int, C: int, w, spins, rand_bond, ran
     return _metropolis(L, types, K, C, w, spins, rand_bond, rand_u)
 
 
-def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms):
+def cnn1_mcmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, rand_bond, rand_u):
+    """The sampler of mcmc with the CNN1 amplitude."""
+    types = ([0, 1] if J1 != 0.0 else []) + ([2, 3] if J2 != 0.0 else [])
+    return _metropolis(L, types, Kb, C, w, spins, rand_bond, rand_u,
+                       lambda w_, s_: cnn1_log_psi(L, Kb, C, w_, s_)[0])
+
+
+def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms, oderiv=None):
     w = np.array(w, np.float64)
     s = _spins(spins, L).reshape(-1, L, L).copy()
     means, variances = [], []
@@ -372,7 +383,7 @@ def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms):
         m, v = energy_stats(e)
         means.append(m)
         variances.append(v)
-        O = log_deriv(L, K, C, w, s)
+        O = oderiv(w, s) if oderiv else log_deriv(L, K, C, w, s)
         x, _, _ = sr_cg(O, e, lam, cg_iters)
         w = w - lr * x
     return np.array(means), np.array(variances), w, s
@@ -398,3 +409,13 @@ def tj_vmc(L: int, t: float, J: float, K: int, C: int, w, spins, n_iter: int, lr
     return _vmc(L, lambda w, s, rb, ru: tj_mcmc(L, t, J, K, C, w, s, rb, ru),
                 lambda w, s: tj_local_energy(L, t, J, K, C, w, s),
                 K, C, w, spins, n_iter, lr, lam, cg_iters, randoms)
+
+
+def cnn1_vmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, n_iter: int, lr: float,
+             lam: float, cg_iters: int, randoms, marshall: bool = True):
+    """The loop of vmc with the CNN1 amplitude (cnn1_mcmc, cnn1_local_energy,
+    cnn1_log_deriv)."""
+    return _vmc(L, lambda w, s, rb, ru: cnn1_mcmc(L, J1, J2, Kb, C, w, s, rb, ru),
+                lambda w, s: cnn1_local_energy(L, J1, J2, Kb, C, w, s, marshall=marshall),
+                Kb, C, w, spins, n_iter, lr, lam, cg_iters, randoms,
+                oderiv=lambda w, s: cnn1_log_deriv(L, Kb, C, w, s))

@@ -1,0 +1,457 @@
+// k_cnn1.hip -- the CNN1 network family [Sec. 5.2: blocks of a 2D
+// convolution, a 1D max-pooling and a transposed convolution, padded by the
+// periodic boundary; the wave-function coefficient is the product of the
+// output neurons], in FP64 on the vector ALU.
+//
+// The block figure is not available, so the block is read as
+//   z = a + W (*) h          3x3 circular convolution, c_in -> 2C channels
+//   m[c] = max(z[2c], z[2c+1])             max-pool of window 2 over channels
+//   u = v + V (*)^T m        3x3 circular transposed convolution, stride 1,
+//                            u[co][p] = v[co] + sum V[ci][co][ky][kx] m[ci][p - (ky-1, kx-1)]
+// with h = spins for the first block and u of the block below otherwise;
+// log|psi_net| = sum log|u_K| and sign(psi_net) = prod sign(u_K).
+// Canonical parameter order per block: W[2C][c_in][3][3], a[2C],
+// V[C][C][3][3] (input channel first), v[C].
+//
+// Planes are NHWC ([plane][site][channel]) in HBM.  The forward serves the
+// samples (base planes) and the exchanged configurations of the local
+// energy (one plane per queue item, the pair exchanged as the spins are
+// read), recomputed in full.  The backward gives O = d log|psi| / d theta per
+// sample: 1/u at the output, then per block the transposed convolution's
+// weight gradients, its data gradient routed through the max to the larger
+// input (the first on a tie), the convolution's weight gradients and its
+// data gradient.  Every weight gradient is a fixed-order sum over the sites
+// of one sample, so rows are deterministic.
+#include <algorithm>
+
+#include "nqs_internal.h"
+
+namespace nqs {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline int wrapc(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
+
+// offsets of block k's parameters in the canonical vector
+struct Cnn1Block {
+    int64_t W, a, V, v;
+    int cin;
+};
+
+Cnn1Block block_of(int C, int k)
+{
+    int64_t off = 0;
+    for (int l = 0; l < k; ++l) {
+        const int ci = (l == 0) ? 1 : C;
+        off += (int64_t)2 * C * ci * 9 + 2 * C + (int64_t)C * C * 9 + C;
+    }
+    Cnn1Block b;
+    b.cin = (k == 0) ? 1 : C;
+    b.W = off;
+    b.a = b.W + (int64_t)2 * C * b.cin * 9;
+    b.V = b.a + 2 * C;
+    b.v = b.V + (int64_t)C * C * 9;
+    return b;
+}
+
+// planes of a launch: samples (queue null) or queue items q_begin + m
+struct C1Planes {
+    const uint32_t *queue;
+    int64_t q_begin;
+    const int64_t *qlen;
+};
+
+__device__ inline int64_t c1_live(const C1Planes &pm, int64_t M)
+{
+    if (!pm.queue) return M;
+    const int64_t left = pm.qlen[0] - pm.q_begin;
+    return left < 0 ? 0 : (left < M ? left : M);
+}
+
+// sample of plane m and the exchanged pair (-1, -1 for a sample plane)
+__device__ inline void c1_origin(const C1Planes &pm, int64_t m, int L, int *s, int *qi, int *qj)
+{
+    if (!pm.queue) {
+        *s = (int)m;
+        *qi = -1;
+        *qj = -1;
+        return;
+    }
+    const uint32_t e = pm.queue[pm.q_begin + m];
+    const int b = item_bond(e), i = b >> 2, t = b & 3;
+    const int x = i % L, y = i / L;
+    *s = item_sample(e);
+    *qi = i;
+    *qj = wrapc(y + bond_dy(t), L) * L + wrapc(x + bond_dx(t), L);
+}
+
+// Convolution and max-pool of one block: thread (plane, site, c) forms
+// z[2c], z[2c+1] and m[c].  in: [M][N][cin] (null: the spins of the plane).
+__global__ void __launch_bounds__(kThreads)
+k_c1_conv(const int8_t *__restrict__ spins, C1Planes pm, int64_t M, int L, int C, int cin,
+          const double *__restrict__ in, const double *__restrict__ W,
+          const double *__restrict__ a, double *__restrict__ mout, double *__restrict__ zsave)
+{
+    const int N = L * L;
+    const int64_t total = c1_live(pm, M) * N * C;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * kThreads) {
+        const int c = (int)(g % C);
+        const int64_t mp = g / C;
+        const int64_t m = mp / N;
+        const int p = (int)(mp - m * N);
+        const int x = p % L, y = p / L;
+        double z0 = a[2 * c], z1 = a[2 * c + 1];
+        const double *w0 = W + (int64_t)(2 * c) * cin * 9;
+        const double *w1 = w0 + (int64_t)cin * 9;
+        if (!in) {
+            int s, qi, qj;
+            c1_origin(pm, m, L, &s, &qi, &qj);
+            const int8_t *sp = spins + (int64_t)s * N;
+            for (int t = 0; t < 9; ++t) {
+                int q = wrapc(y + t / 3 - 1, L) * L + wrapc(x + t % 3 - 1, L);
+                q = (q == qi) ? qj : ((q == qj) ? qi : q);
+                const double h = (double)sp[q];
+                z0 = fma(w0[t], h, z0);
+                z1 = fma(w1[t], h, z1);
+            }
+        } else {
+            for (int t = 0; t < 9; ++t) {
+                const int q = wrapc(y + t / 3 - 1, L) * L + wrapc(x + t % 3 - 1, L);
+                const double *hq = in + (m * N + q) * cin;
+                for (int ci = 0; ci < cin; ++ci) {
+                    z0 = fma(w0[ci * 9 + t], hq[ci], z0);
+                    z1 = fma(w1[ci * 9 + t], hq[ci], z1);
+                }
+            }
+        }
+        mout[mp * C + c] = (z1 > z0) ? z1 : z0;
+        if (zsave) {
+            zsave[mp * 2 * C + 2 * c] = z0;
+            zsave[mp * 2 * C + 2 * c + 1] = z1;
+        }
+    }
+}
+
+// Transposed convolution of one block: thread (plane, site, co).
+__global__ void __launch_bounds__(kThreads)
+k_c1_convt(C1Planes pm, int64_t M, int L, int C, const double *__restrict__ min_,
+           const double *__restrict__ V, const double *__restrict__ v, double *__restrict__ uout)
+{
+    const int N = L * L;
+    const int64_t total = c1_live(pm, M) * N * C;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * kThreads) {
+        const int co = (int)(g % C);
+        const int64_t mp = g / C;
+        const int64_t m = mp / N;
+        const int p = (int)(mp - m * N);
+        const int x = p % L, y = p / L;
+        double u = v[co];
+        for (int t = 0; t < 9; ++t) {
+            const int q = wrapc(y - t / 3 + 1, L) * L + wrapc(x - t % 3 + 1, L);
+            const double *mq = min_ + (m * N + q) * C;
+            for (int ci = 0; ci < C; ++ci) u = fma(V[((int64_t)ci * C + co) * 9 + t], mq[ci], u);
+        }
+        uout[mp * C + co] = u;
+    }
+}
+
+// Per plane: f = sum log|u| (fixed reduction tree) and the parity of the
+// negative neurons.  Sample planes write f and the network sign (and
+// multiply it into sign_pub when given); item planes write
+// dlog = f' - f(sample) and the sign ratio.
+__global__ void __launch_bounds__(kThreads)
+k_c1_final(C1Planes pm, int64_t M, int NC, const double *__restrict__ u, double *__restrict__ f,
+           int8_t *__restrict__ sgn, int8_t *__restrict__ sign_pub,
+           const double *__restrict__ fbase, const int8_t *__restrict__ sbase, int32_t *err)
+{
+    __shared__ double red[kThreads];
+    __shared__ int neg[kThreads];
+    const int64_t m = blockIdx.x;
+    if (m >= c1_live(pm, M)) return;
+    const double *um = u + m * NC;
+    double acc = 0.0;
+    int n = 0;
+    for (int q = threadIdx.x; q < NC; q += kThreads) {
+        acc += log(fabs(um[q]));
+        n += (um[q] < 0.0);
+    }
+    red[threadIdx.x] = acc;
+    neg[threadIdx.x] = n;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            red[threadIdx.x] += red[threadIdx.x + off];
+            neg[threadIdx.x] += neg[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double fm = red[0];
+        const int8_t sm = (neg[0] & 1) ? -1 : 1;
+        if (!isfinite(fm)) atomicOr(err, kErrNonFinite);
+        if (!pm.queue) {
+            f[m] = fm;
+            sgn[m] = sm;
+            if (sign_pub) sign_pub[m] = (int8_t)(sign_pub[m] * sm);
+        } else {
+            const int s = item_sample(pm.queue[pm.q_begin + m]);
+            f[m] = fm - fbase[s];
+            sgn[m] = (int8_t)(sm * sbase[s]);
+        }
+    }
+}
+
+// ---- backward ----
+
+__global__ void k_c1_ginit(const double *__restrict__ u, int64_t n, double *__restrict__ g)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        g[i] = 1.0 / u[i];
+}
+
+// Weight and bias gradients of one block into the O rows.
+//   transposed (T = 1): O[V + (ci C + co) 9 + t] = sum_p g[p][co] m[p - off t][ci],
+//                       m from the saved z of the block; O[v + co] = sum_p g[p][co]
+//   convolution (T = 0): O[W + (co cin + ci) 9 + t] = sum_p gz[p][co] h[p + off t][ci],
+//                       h = spins (first block) or u of the block below;
+//                       O[a + co] = sum_p gz[p][co]
+template <typename OT>
+__global__ void __launch_bounds__(kThreads)
+k_c1_wgrad(int nb, int L, int C, int T, int nco, int cin, const double *__restrict__ g,
+           const double *__restrict__ z, const double *__restrict__ h,
+           const int8_t *__restrict__ spins, int64_t offw, int64_t offb, int64_t P,
+           OT *__restrict__ O)
+{
+    const int N = L * L;
+    const int nw = nco * cin * 9;         // weights, then nco biases
+    const int per = nw + nco;
+    const int64_t total = (int64_t)nb * per;
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int b = (int)(id / per);
+        const int r = (int)(id - (int64_t)b * per);
+        const double *gb = g + (int64_t)b * N * nco;
+        double acc = 0.0;
+        int64_t dst;
+        if (r >= nw) {
+            const int co = r - nw;
+            for (int p = 0; p < N; ++p) acc += gb[(int64_t)p * nco + co];
+            dst = offb + co;
+        } else if (T) {
+            // r = (ci C + co) 9 + t
+            const int t = r % 9, cc = r / 9, co = cc % C, ci = cc / C;
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const double *zb = z + (int64_t)b * N * 2 * C;
+            for (int p = 0; p < N; ++p) {
+                const int q = wrapc(p / L - dy, L) * L + wrapc(p % L - dx, L);
+                const double z0 = zb[(int64_t)q * 2 * C + 2 * ci];
+                const double z1 = zb[(int64_t)q * 2 * C + 2 * ci + 1];
+                acc = fma(gb[(int64_t)p * nco + co], (z1 > z0) ? z1 : z0, acc);
+            }
+            dst = offw + r;
+        } else {
+            // r = (co cin + ci) 9 + t
+            const int t = r % 9, cc = r / 9, ci = cc % cin, co = cc / cin;
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            for (int p = 0; p < N; ++p) {
+                const int q = wrapc(p / L + dy, L) * L + wrapc(p % L + dx, L);
+                const double hv = h ? h[((int64_t)b * N + q) * cin + ci]
+                                    : (double)spins[(int64_t)b * N + q];
+                acc = fma(gb[(int64_t)p * nco + co], hv, acc);
+            }
+            dst = offw + r;
+        }
+        O[(int64_t)b * P + dst] = (OT)acc;
+    }
+}
+
+// dL/dm of the transposed convolution, routed through the max:
+// gm[q][ci] = sum_{co,t} V[ci][co][t] g[q + off t][co]; gz[q][2ci + a] = gm
+// for the larger input a (first on a tie), 0 for the other.
+__global__ void __launch_bounds__(kThreads)
+k_c1_gmax(int nb, int L, int C, const double *__restrict__ g, const double *__restrict__ V,
+          const double *__restrict__ z, double *__restrict__ gz)
+{
+    const int N = L * L;
+    const int64_t total = (int64_t)nb * N * C;
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int ci = (int)(id % C);
+        const int64_t bq = id / C;
+        const int64_t b = bq / N;
+        const int q = (int)(bq - b * N);
+        const int x = q % L, y = q / L;
+        double gm = 0.0;
+        for (int t = 0; t < 9; ++t) {
+            const int p = wrapc(y + t / 3 - 1, L) * L + wrapc(x + t % 3 - 1, L);
+            const double *gp = g + (b * N + p) * C;
+            for (int co = 0; co < C; ++co) gm = fma(V[((int64_t)ci * C + co) * 9 + t], gp[co], gm);
+        }
+        const double z0 = z[bq * 2 * C + 2 * ci], z1 = z[bq * 2 * C + 2 * ci + 1];
+        const bool second = z1 > z0;
+        gz[bq * 2 * C + 2 * ci] = second ? 0.0 : gm;
+        gz[bq * 2 * C + 2 * ci + 1] = second ? gm : 0.0;
+    }
+}
+
+// dL/dh of the convolution: gh[q][ci] = sum_{co,t} W[co][ci][t] gz[q - off t][co]
+__global__ void __launch_bounds__(kThreads)
+k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__restrict__ W,
+           double *__restrict__ gh)
+{
+    const int N = L * L;
+    const int64_t total = (int64_t)nb * N * C;
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int ci = (int)(id % C);
+        const int64_t bq = id / C;
+        const int64_t b = bq / N;
+        const int q = (int)(bq - b * N);
+        const int x = q % L, y = q / L;
+        double acc = 0.0;
+        for (int t = 0; t < 9; ++t) {
+            const int p = wrapc(y - t / 3 + 1, L) * L + wrapc(x - t % 3 + 1, L);
+            const double *gp = gz + (b * N + p) * 2 * C;
+            for (int co = 0; co < 2 * C; ++co)
+                acc = fma(W[((int64_t)co * C + ci) * 9 + t], gp[co], acc);
+        }
+        gh[bq * C + ci] = acc;
+    }
+}
+
+int grid_of(const nqs_ctx *c, int64_t work)
+{
+    const int64_t b = (work + kThreads - 1) / kThreads;
+    const int64_t cap = (int64_t)std::max(c->n_cu, 1) * 16;
+    return (int)std::max<int64_t>(1, std::min(b, cap));
+}
+
+// the blocks over M planes: the result u of the last block ends in pa
+void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t M, double *pa,
+                    double *pb, hipStream_t s)
+{
+    const int L = c->L, C = c->C;
+    const int64_t work = M * c->N * C;
+    for (int k = 0; k < c->K; ++k) {
+        const Cnn1Block o = block_of(C, k);
+        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
+                   o.cin, k == 0 ? (const double *)nullptr : (const double *)pa,
+                   (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a, pb,
+                   (double *)nullptr);
+        NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
+                   (const double *)pb, (const double *)c->w_canon + o.V,
+                   (const double *)c->w_canon + o.v, pa);
+    }
+}
+
+}  // namespace
+
+int64_t cnn1_params(int Kb, int C)
+{
+    int64_t p = 0;
+    for (int k = 0; k < Kb; ++k)
+        p += (int64_t)2 * C * (k == 0 ? 1 : C) * 9 + 2 * C + (int64_t)C * C * 9 + C;
+    return p;
+}
+
+size_t cnn1_plane_bytes(const nqs_ctx *c, int64_t planes)
+{
+    return sizeof(double) * (size_t)planes * c->N * c->C;
+}
+
+int64_t cnn1_chunk(const nqs_ctx *c, int64_t work)
+{
+    int64_t m = (int64_t)(((size_t)1 << 30) / cnn1_plane_bytes(c, 1));
+    m = std::max<int64_t>(1, std::min<int64_t>(m, 65535));
+    return std::min(m, std::max<int64_t>(work, 1));
+}
+
+void cnn1_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, int8_t *sgn,
+                       int8_t *sign_pub, void *pa, void *pb, hipStream_t s)
+{
+    if (B <= 0) return;
+    const C1Planes pm{nullptr, 0, nullptr};
+    blocks_forward(c, spins, pm, B, (double *)pa, (double *)pb, s);
+    NQS_LAUNCH(k_c1_final, dim3(B), dim3(kThreads), 0, s, pm, (int64_t)B, c->N * c->C,
+               (const double *)pa, f, sgn, sign_pub, (const double *)nullptr,
+               (const int8_t *)nullptr, c->err);
+}
+
+void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                       const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
+                       const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
+                       hipStream_t s)
+{
+    if (M <= 0) return;
+    const C1Planes pm{queue, q0, qlen};
+    blocks_forward(c, spins, pm, M, (double *)pa, (double *)pb, s);
+    NQS_LAUNCH(k_c1_final, dim3((unsigned)M), dim3(kThreads), 0, s, pm, M, c->N * c->C,
+               (const double *)pa, dlog + q0, isign + q0, (int8_t *)nullptr, fbase, sbase,
+               c->err);
+}
+
+size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c)
+{
+    // saved z (K * 2C), saved u (K * C), pooled m, g, gh (C each), gz (2C)
+    return sizeof(double) * (size_t)c->N * c->C * (3 * (size_t)c->K + 5);
+}
+
+void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
+                     double *usave, double *work, void *O, nqs_dtype odt, hipStream_t s)
+{
+    const int L = c->L, C = c->C, N = c->N, K = c->K;
+    const int64_t plane = (int64_t)nb * N * C;
+    double *mbuf = work, *g = work + plane, *gh = work + 2 * plane, *gz = work + 3 * plane;
+    const C1Planes pm{nullptr, 0, nullptr};
+    const double *w = c->w_canon;
+    // forward with every block's z and u kept
+    for (int k = 0; k < K; ++k) {
+        const Cnn1Block o = block_of(C, k);
+        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, spins, pm,
+                   (int64_t)nb, L, C, o.cin,
+                   k == 0 ? (const double *)nullptr : (const double *)(usave + (k - 1) * plane),
+                   w + o.W, w + o.a, mbuf, zsave + (int64_t)k * 2 * plane);
+        NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, pm, (int64_t)nb, L,
+                   C, (const double *)mbuf, w + o.V, w + o.v, usave + (int64_t)k * plane);
+    }
+    NQS_LAUNCH(k_c1_ginit, dim3(grid_of(c, plane)), dim3(kThreads), 0, s,
+               (const double *)(usave + (int64_t)(K - 1) * plane), plane, g);
+    for (int k = K - 1; k >= 0; --k) {
+        const Cnn1Block o = block_of(C, k);
+        const double *zk = zsave + (int64_t)k * 2 * plane;
+        const double *hk = k == 0 ? nullptr : usave + (int64_t)(k - 1) * plane;
+        const int64_t wt = (int64_t)nb * (C * C * 9 + C);
+        const int64_t wc = (int64_t)nb * (2 * C * o.cin * 9 + 2 * C);
+        if (odt == NQS_FP32) {
+            NQS_LAUNCH(k_c1_wgrad<float>, dim3(grid_of(c, wt)), dim3(kThreads), 0, s, nb, L, C,
+                       1, C, C, (const double *)g, zk, (const double *)nullptr, spins, o.V, o.v,
+                       c->P, (float *)O);
+        } else {
+            NQS_LAUNCH(k_c1_wgrad<double>, dim3(grid_of(c, wt)), dim3(kThreads), 0, s, nb, L, C,
+                       1, C, C, (const double *)g, zk, (const double *)nullptr, spins, o.V, o.v,
+                       c->P, (double *)O);
+        }
+        NQS_LAUNCH(k_c1_gmax, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
+                   (const double *)g, w + o.V, zk, gz);
+        if (odt == NQS_FP32) {
+            NQS_LAUNCH(k_c1_wgrad<float>, dim3(grid_of(c, wc)), dim3(kThreads), 0, s, nb, L, C,
+                       0, 2 * C, o.cin, (const double *)gz, (const double *)nullptr, hk, spins,
+                       o.W, o.a, c->P, (float *)O);
+        } else {
+            NQS_LAUNCH(k_c1_wgrad<double>, dim3(grid_of(c, wc)), dim3(kThreads), 0, s, nb, L, C,
+                       0, 2 * C, o.cin, (const double *)gz, (const double *)nullptr, hk, spins,
+                       o.W, o.a, c->P, (double *)O);
+        }
+        if (k > 0) {
+            NQS_LAUNCH(k_c1_gdata, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
+                       (const double *)gz, w + o.W, gh);
+            std::swap(g, gh);
+        }
+    }
+}
+
+}  // namespace nqs

@@ -18,8 +18,9 @@ constexpr int kThreads = 256;
 
 __global__ void __launch_bounds__(kThreads)
 k_energy_reduce(const int64_t *__restrict__ offsets, const uint32_t *__restrict__ queue,
-                const double *__restrict__ dlog, const double *__restrict__ ediag, double J1,
-                double J2, int marshall, double *__restrict__ e_loc, int32_t *err)
+                const double *__restrict__ dlog, const int8_t *__restrict__ isign,
+                const double *__restrict__ ediag, double J1, double J2, int marshall,
+                double *__restrict__ e_loc, int32_t *err)
 {
     __shared__ double red[kThreads];
     const int s = blockIdx.x;
@@ -29,7 +30,8 @@ k_energy_reduce(const int64_t *__restrict__ offsets, const uint32_t *__restrict_
         const int t = item_bond(queue[q]) & 3;
         const double half_j = 0.5 * (t < 2 ? J1 : J2);
         // J1 pairs join the two sublattices: the Marshall ratio is -1
-        const double mu = (marshall && t < 2) ? -1.0 : 1.0;
+        double mu = (marshall && t < 2) ? -1.0 : 1.0;
+        if (isign) mu *= (double)isign[q];      // the network's own sign ratio
         acc += half_j * mu * exp(dlog[q]);
     }
     red[threadIdx.x] = acc;
@@ -148,8 +150,8 @@ k_energy_stats(const double *__restrict__ e, int B, double *__restrict__ stats)
 }  // namespace
 
 void launch_energy_reduce(const nqs_ctx *c, const int8_t *spins, int B, const int64_t *offsets,
-                          const uint32_t *queue, const double *dlog, const double *ediag,
-                          double *e_loc, int32_t *err, hipStream_t s)
+                          const uint32_t *queue, const double *dlog, const int8_t *isign,
+                          const double *ediag, double *e_loc, int32_t *err, hipStream_t s)
 {
     if (B <= 0) return;
     if (c->model == kModelTJ)
@@ -157,7 +159,7 @@ void launch_energy_reduce(const nqs_ctx *c, const int8_t *spins, int B, const in
                    queue, dlog, ediag, c->t_hop, c->J1, c->marshall, e_loc, err);
     else
         NQS_LAUNCH(k_energy_reduce, dim3(B), dim3(kThreads), 0, s, offsets, queue, dlog,
-                   ediag, c->J1, c->J2, c->marshall, e_loc, err);
+                   isign, ediag, c->J1, c->J2, c->marshall, e_loc, err);
 }
 
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s)

@@ -97,6 +97,7 @@ nqs_status upload(T *&dst, const std::vector<T> &src)
 
 nqs_status pack_weights(nqs_ctx *c)
 {
+    if (c->net == kNetCnn1) return upload(c->w_canon, c->w_host);   // read as it is
     const int K = c->K, C = c->C;
     Canon cn{c->w_host.data(), K, C};
     // vector path: layer 1 [9][C] + b; layer k [9][Cin][C] + b
@@ -220,12 +221,47 @@ nqs_status bf16_base_stage(nqs_ctx *c, const int8_t *spins, int B, hipStream_t s
     return NQS_OK;
 }
 
+// CNN1: base pass (log|psi_net| and sign of the samples), then every queue
+// item recomputed in full: dlog[item] and the sign ratio in ws.isign.
+nqs_status cnn1_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, double *dlog, int64_t cap,
+                            hipStream_t s)
+{
+    Workspace &w = c->ws;
+    const int64_t chunk = cnn1_chunk(c, std::max<int64_t>(cap, B));
+    NQS_TRY(ensure(w.sgn, std::max(B, 1), s));
+    NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
+    NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        cnn1_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+                          (int8_t *)w.sgn.ptr + b0, nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, s);
+    }
+    for (int64_t q0 = 0; q0 < cap; q0 += chunk)
+        cnn1_conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
+                          std::min(chunk, cap - q0), (const double *)w.fbase.ptr,
+                          (const int8_t *)w.sgn.ptr, dlog, (int8_t *)w.isign.ptr, w.plane_a.ptr,
+                          w.plane_b.ptr, s);
+    if (c->timing) {
+        (void)hipEventRecord(e1, s);
+        c->events.push_back({e0, e1});
+    }
+    return NQS_OK;
+}
+
 // Base pass + exchanged-configuration pass: dlog[item].
 nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode, double *dlog,
                            int64_t cap, hipStream_t s)
 {
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
+    if (c->net == kNetCnn1) return cnn1_ratio_stage(c, spins, B, dlog, cap, s);
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
     if (c->dtype == NQS_BF16) {
         NQS_TRY(bf16_base_stage(c, spins, B, s));
@@ -350,6 +386,10 @@ namespace {
 // deltas per sample, at most 8 GB
 int64_t deriv_chunk(const nqs_ctx *c, int64_t B)
 {
+    if (c->net == kNetCnn1) {
+        const int64_t n = (int64_t)(((size_t)8 << 30) / cnn1_deriv_bytes_per_sample(c));
+        return std::max<int64_t>(1, std::min<int64_t>(n, B));
+    }
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
     const size_t per = plane * (2 * (size_t)std::max(c->K - 1, 1) + 2);
     const int64_t chunk = (int64_t)(((size_t)8 << 30) / per);
@@ -360,6 +400,12 @@ nqs_status deriv_reserve(nqs_ctx *c, int64_t chunk, hipStream_t s)
 {
     Workspace &w = c->ws;
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;
+    if (c->net == kNetCnn1) {
+        NQS_TRY(ensure(w.zsave, plane * 2 * c->K * chunk, s));
+        NQS_TRY(ensure(w.hsave, plane * c->K * chunk, s));
+        NQS_TRY(ensure(w.delta, plane * 5 * chunk, s));
+        return NQS_OK;
+    }
     const size_t saved = plane * std::max(c->K - 1, 1) * chunk;
     NQS_TRY(ensure(w.zsave, saved, s));
     NQS_TRY(ensure(w.hsave, saved, s));
@@ -376,6 +422,12 @@ void deriv_rows(const nqs_ctx *c, const int8_t *spins, int64_t B, int64_t chunk,
     const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        if (c->net == kNetCnn1) {
+            cnn1_deriv_rows(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr,
+                            (double *)w.hsave.ptr, (double *)w.delta.ptr,
+                            (unsigned char *)O + (size_t)b0 * c->P * esz, odt, s);
+            continue;
+        }
         double *da = (double *)w.delta.ptr;
         double *db = da + (size_t)nb * c->N * c->C;
         vec_deriv_forward(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr,
@@ -403,7 +455,7 @@ int64_t recompute_chunk(const nqs_ctx *c, int64_t B, int64_t chunk_rows, nqs_dty
 
 namespace {
 
-nqs_status create_ctx(int32_t L, int model, double J1, double J2, double t_hop,
+nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, double t_hop,
                       const nqs_cnn_spec *spec, const double *weights, int64_t n_weights,
                       nqs_ctx **out)
 {
@@ -417,7 +469,9 @@ nqs_status create_ctx(int32_t L, int model, double J1, double J2, double t_hop,
         spec->conv_dtype != NQS_BF16)
         return NQS_E_SPEC;
     if (spec->marshall_sign != 0 && spec->marshall_sign != 1) return NQS_E_SPEC;
-    if (n_weights != params_of(K, C)) return NQS_E_NPARAMS;
+    if (net == kNetCnn1 && spec->conv_dtype != NQS_FP64) return NQS_E_SPEC;
+    if (n_weights != (net == kNetCnn1 ? cnn1_params(K, C) : params_of(K, C)))
+        return NQS_E_NPARAMS;
     nqs_ctx *c = new nqs_ctx();
     c->L = L;
     c->N = L * L;
@@ -426,6 +480,7 @@ nqs_status create_ctx(int32_t L, int model, double J1, double J2, double t_hop,
     c->J1 = J1;
     c->J2 = J2;
     c->model = model;
+    c->net = net;
     c->t_hop = t_hop;
     c->marshall = spec->marshall_sign;
     c->dtype = spec->conv_dtype;
@@ -491,13 +546,21 @@ const char *nqs_status_str(nqs_status s)
 nqs_status nqs_create(int32_t L, double J1, double J2, const nqs_cnn_spec *spec,
                       const double *weights, int64_t n_weights, nqs_ctx **out)
 {
-    return create_ctx(L, kModelSpin, J1, J2, 0.0, spec, weights, n_weights, out);
+    return create_ctx(L, kModelSpin, kNetLnCosh, J1, J2, 0.0, spec, weights, n_weights, out);
+}
+
+nqs_status nqs_create_cnn1(int32_t L, double J1, double J2, int32_t blocks, int32_t channels,
+                           int32_t marshall_sign, const double *weights, int64_t n_weights,
+                           nqs_ctx **out)
+{
+    const nqs_cnn_spec spec{blocks, channels, marshall_sign, NQS_FP64};
+    return create_ctx(L, kModelSpin, kNetCnn1, J1, J2, 0.0, &spec, weights, n_weights, out);
 }
 
 nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
                          const double *weights, int64_t n_weights, nqs_ctx **out)
 {
-    return create_ctx(L, kModelTJ, J, 0.0, t, spec, weights, n_weights, out);
+    return create_ctx(L, kModelTJ, kNetLnCosh, J, 0.0, t, spec, weights, n_weights, out);
 }
 
 nqs_status nqs_destroy(nqs_ctx *c)
@@ -586,7 +649,13 @@ nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
     NQS_TRY(ensure(w.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
-    if (c->dtype == NQS_BF16) {
+    if (c->net == kNetCnn1) {
+        const int64_t chunk = cnn1_chunk(c, std::max<int64_t>(cap, B));
+        NQS_TRY(ensure(w.sgn, std::max(B, 1), s));
+        NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
+        NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+    } else if (c->dtype == NQS_BF16) {
         NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
     } else {
         const int64_t chunk = vec_chunk(c, std::max<int64_t>(cap, B));
@@ -607,7 +676,17 @@ nqs_status nqs_log_psi(nqs_ctx *c, const int8_t *spins, int64_t B, double *log_a
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)B * c->N, s));
     launch_marshall(c, spins, (int)B, sign, s);
-    if (c->dtype == NQS_BF16) {
+    if (c->net == kNetCnn1) {
+        const int64_t chunk = cnn1_chunk(c, B);
+        NQS_TRY(ensure(w.sgn, (size_t)B, s));
+        NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+        for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+            const int nb = (int)std::min<int64_t>(chunk, B - b0);
+            cnn1_base_forward(c, spins + b0 * c->N, nb, log_abs + b0, (int8_t *)w.sgn.ptr + b0,
+                              sign ? sign + b0 : nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
+        }
+    } else if (c->dtype == NQS_BF16) {
         NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
         mfma_base_forward(c, spins, (int)B, log_abs, (double *)w.hsum.ptr, w.cache.ptr, s);
     } else {
@@ -641,6 +720,7 @@ nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *
     NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)c->ws.dlog.ptr, cap, s));
     launch_energy_reduce(c, spins, (int)B, (int64_t *)c->ws.offsets.ptr,
                          (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
+                         c->net == kNetCnn1 ? (const int8_t *)c->ws.isign.ptr : nullptr,
                          (double *)c->ws.ediag.ptr, e_loc, c->err, s);
     return finish_call();
 }
@@ -803,6 +883,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     for (int i = 0; i < n; ++i) {
         nqs_ctx *c = jobs[i].ctx;
         if (!c) return NQS_E_ARG;
+        if (c->net == kNetCnn1) return NQS_E_UNSUPPORTED;
         if (c->K != jobs[0].ctx->K || c->C != jobs[0].ctx->C || c->dtype != jobs[0].ctx->dtype)
             return NQS_E_SPEC;
         for (int j = 0; j < i; ++j)
@@ -867,7 +948,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
         nqs_ctx *c = jobs[i].ctx;
         if (jobs[i].B == 0) continue;
         launch_energy_reduce(c, jobs[i].spins, (int)jobs[i].B, (int64_t *)c->ws.offsets.ptr,
-                             (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
+                             (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr, nullptr,
                              (double *)c->ws.ediag.ptr, jobs[i].e_loc, c->err, s);
     }
     return finish_call();
@@ -878,6 +959,7 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
 {
     NQS_TRY(check_common(c, spins, B));
     if (B == 0) return NQS_E_ARG;
+    if (c->net == kNetCnn1) return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stream_capturing(s)) return NQS_E_WORKSPACE;
     c->last_stream = s;

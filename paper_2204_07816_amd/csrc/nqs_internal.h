@@ -33,6 +33,13 @@ __host__ __device__ inline int item_bond(uint32_t e) { return (int)(e & ((1u << 
 constexpr int kModelSpin = 0;
 constexpr int kModelTJ = 1;
 
+// Network family of a context: the ln cosh CNN (K layers of 3x3 circular
+// convolutions with ln cosh, summed) or CNN1 (K blocks of convolution,
+// max-pool over channel pairs and transposed convolution; product of the
+// output neurons) [Sec. 5.2].
+constexpr int kNetLnCosh = 0;
+constexpr int kNetCnn1 = 1;
+
 // Device-side sticky error codes (ORed bits, mapped to nqs_status on read).
 constexpr int kErrSpin = 1;
 constexpr int kErrNonFinite = 2;
@@ -62,6 +69,8 @@ struct Workspace {
     DevBuf orows;       // O rows of the recompute SR variant
     DevBuf counter;     // work counters for persistent kernels
     DevBuf flags;       // int32 per chain: accepted proposals of a Metropolis step
+    DevBuf sgn;         // int8 [B] network sign of the samples (CNN1)
+    DevBuf isign;       // int8 [capacity] network sign ratio per queue item (CNN1)
 };
 
 }  // namespace nqs
@@ -70,6 +79,7 @@ struct nqs_ctx {
     int L = 0, N = 0, K = 0, C = 0;
     double J1 = 1.0, J2 = 0.0;
     int model = nqs::kModelSpin;
+    int net = nqs::kNetLnCosh;
     double t_hop = 0.0;           // t-J hopping amplitude t
     int marshall = 1;
     nqs_dtype dtype = NQS_FP64;
@@ -235,9 +245,28 @@ bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, 
 int mfma_full_variants(const nqs_ctx *c, int *nw, int *maxt, int cap);
 
 // --- energy / SR kernels (k_energy.hip, k_sr.hip) ---
+// isign (may be null): per-item sign ratio of the network (CNN1)
 void launch_energy_reduce(const nqs_ctx *c, const int8_t *spins, int B, const int64_t *offsets,
-                          const uint32_t *queue, const double *dlog, const double *ediag,
-                          double *e_loc, int32_t *err, hipStream_t s);
+                          const uint32_t *queue, const double *dlog, const int8_t *isign,
+                          const double *ediag, double *e_loc, int32_t *err, hipStream_t s);
+
+// --- CNN1 network family (k_cnn1.hip), FP64 ---
+int64_t cnn1_params(int Kb, int C);
+size_t cnn1_plane_bytes(const nqs_ctx *c, int64_t planes);
+int64_t cnn1_chunk(const nqs_ctx *c, int64_t work);
+// samples: f[B] = log|psi_net|, sgn[B] = its sign; sign_pub (may be null)
+// is multiplied by the network sign.  pa, pb: cnn1_plane_bytes(c, B) each.
+void cnn1_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, int8_t *sgn,
+                       int8_t *sign_pub, void *pa, void *pb, hipStream_t s);
+// queue items q0 .. q0+M-1: dlog[q] = f(S') - f(s), isign[q] = sign ratio
+void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                       const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
+                       const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
+                       hipStream_t s);
+size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c);
+// O rows of nb samples; zsave: K*2*nb*N*C, usave: K*nb*N*C, work: 5*nb*N*C doubles
+void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
+                     double *usave, double *work, void *O, nqs_dtype odt, hipStream_t s);
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
 
 // --- device-side parameter update (k_pack.hip) ---

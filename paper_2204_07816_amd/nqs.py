@@ -60,6 +60,7 @@ def load():
     sig = {
         "nqs_create": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
         "nqs_create_tj": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
+        "nqs_create_cnn1": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_destroy": [vp],
         "nqs_num_params": [vp, P(i64)],
         "nqs_set_weights": [vp, vp, i64],
@@ -125,16 +126,23 @@ def num_params(K: int, C: int) -> int:
 
 
 class Context:
-    """One lattice + network (nqs_create / nqs_create_tj / nqs_destroy)."""
+    """One lattice + network (nqs_create / nqs_create_tj / nqs_create_cnn1 /
+    nqs_destroy)."""
 
     def __init__(self, L: int, J1: float, J2: float, K: int, C: int, weights,
                  dtype: str = "fp64", marshall_sign: bool = True, *,
-                 tj_hop: float | None = None):
+                 tj_hop: float | None = None, net: str = "lncosh"):
         lib = load()
         w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
         spec = CnnSpec(K, C, 1 if marshall_sign else 0, _DTYPES[dtype])
         h = ctypes.c_void_p()
-        if tj_hop is None:
+        if net == "cnn1":
+            if dtype != "fp64" or tj_hop is not None:
+                raise ValueError("CNN1 contexts are FP64 spin-model contexts")
+            _check(lib.nqs_create_cnn1(L, J1, J2, K, C, 1 if marshall_sign else 0,
+                                       ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                       ctypes.byref(h)), "nqs_create_cnn1")
+        elif tj_hop is None:
             _check(lib.nqs_create(L, J1, J2, ctypes.byref(spec), ctypes.c_void_p(w.data_ptr()),
                                   w.numel(), ctypes.byref(h)), "nqs_create")
         else:
@@ -144,8 +152,15 @@ class Context:
         self._h = h
         self.L, self.J1, self.J2, self.K, self.C, self.dtype = L, J1, J2, K, C, dtype
         self.model = "spin" if tj_hop is None else "tj"
+        self.net = net
         self.t = tj_hop
         self.P = self.num_params()
+
+    @classmethod
+    def cnn1(cls, L: int, J1: float, J2: float, blocks: int, C: int, weights,
+             marshall_sign: bool = True) -> "Context":
+        """A CNN1 context (nqs_create_cnn1), FP64: `blocks` blocks of C channels."""
+        return cls(L, J1, J2, blocks, C, weights, "fp64", marshall_sign, net="cnn1")
 
     @classmethod
     def tj(cls, L: int, t: float, J: float, K: int, C: int, weights, dtype: str = "fp64",

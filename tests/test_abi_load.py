@@ -103,3 +103,17 @@ def test_create_tj_rejects_bad_arguments(lib):
     assert lib.nqs_create_tj(4, 1.0, 0.4, None, buf, 188, ctypes.byref(h)) == 1
     assert lib.nqs_create_tj(4, 1.0, 0.4, ctypes.byref(sp), buf, 187, ctypes.byref(h)) == 4
     assert not h.value
+
+
+def test_create_cnn1_rejects_bad_arguments(lib):
+    buf = (ctypes.c_double * 2000)()
+    h = ctypes.c_void_p()
+    # CNN1 with 2 blocks of 4 channels: 2*4*1*9 + 8 + 144 + 4 + 2*4*4*9 + 8 + 144 + 4 = 672
+    assert lib.nqs_create_cnn1(5, 1.0, 0.5, 2, 4, 1, buf, 672, ctypes.byref(h)) == 2
+    assert lib.nqs_create_cnn1(4, 1.0, 0.5, 0, 4, 1, buf, 672, ctypes.byref(h)) == 3
+    assert lib.nqs_create_cnn1(4, 1.0, 0.5, 2, 33, 1, buf, 672, ctypes.byref(h)) == 3
+    assert lib.nqs_create_cnn1(4, 1.0, 0.5, 2, 4, 2, buf, 672, ctypes.byref(h)) == 3
+    assert lib.nqs_create_cnn1(4, 1.0, 0.5, 2, 4, 1, buf, 671, ctypes.byref(h)) == 4
+    assert lib.nqs_create_cnn1(4, float("nan"), 0.5, 2, 4, 1, buf, 672, ctypes.byref(h)) == 1
+    assert lib.nqs_create_cnn1(4, 1.0, 0.5, 2, 4, 1, None, 672, ctypes.byref(h)) == 1
+    assert not h.value

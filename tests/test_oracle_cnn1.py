@@ -118,3 +118,15 @@ def test_rayleigh_quotient_over_sector(orc, J2, marshall):
     lhs = np.sum(psi ** 2 * e) / np.sum(psi ** 2)
     rhs = psi @ (H @ psi) / (psi @ psi)
     assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+def test_cnn1_mcmc_conserves_sz_and_is_reproducible(orc):
+    L, Kb, C, B, T = 4, 2, 3, 16, 20
+    w = inputs.cnn1_weights(Kb, C, 0.3, 51)
+    sp = inputs.spins_sz0(L, B, 52)
+    rb, ru = inputs.mcmc_randoms(53, 0, T, B)
+    out, acc = orc.cnn1_mcmc(L, 1.0, 0.5, Kb, C, w, sp, rb, ru)
+    assert np.array_equal(out.sum(axis=(1, 2)), sp.sum(axis=(1, 2)))
+    assert 0 < acc.sum() < B * T
+    out2, acc2 = orc.cnn1_mcmc(L, 1.0, 0.5, Kb, C, w, sp, rb, ru)
+    assert np.array_equal(out, out2) and np.array_equal(acc, acc2)
