@@ -16,7 +16,10 @@ plain FP64 GPU form (full recompute, FP64 convolutions) is timed on the same
 (bar: 1e-5 relative).  A non-gating stress row repeats the BF16-vs-FP64
 comparison at weights whose exchanged configurations differ at O(1) in log
 amplitude; another times the mixed-lattice workload (12x12, 16x16, 20x20)
-through one multi-lattice call per step.  The FP64 CPU oracle is timed on the host cores on a bounded sample.
+through one multi-lattice call per step.  Further non-gating rows: SR with O
+recomputed, Metropolis steps, a graph-replayed VMC iteration, the t-J local
+energy (12x12, hole doping 1/8) and the CNN1 network (10x10, FP64).  The FP64
+CPU oracle is timed on the host cores on a bounded sample.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -252,6 +255,64 @@ def tj_row(dev, reps=3, fp64_samples=256):
     return out
 
 
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 (vector and dense matrix cores alike)
+
+
+def cnn1_row(dev, reps=2, oracle_samples=4):
+    """Non-gating row: the CNN1 network (6 blocks of convolution, channel-pair
+    max-pool and transposed convolution, 16 channels, P = 37,440; product of
+    the output neurons) on 10x10 J1-J2 (J2 = 0.5), 1024 configurations, FP64:
+    E_loc by full recomputation (blocks 2.. on the FP64 matrix cores), the
+    exchanged-configuration pass's rate against the FP64 peak, O_k, and E_loc
+    against the oracle on a few samples."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2204_07816_amd import inputs, nqs
+    L, J2, Kb, C, w, sp = inputs.cnn1_config_inputs()
+    B = sp.shape[0]
+    ctx = nqs.Context.cnn1(L, 1.0, J2, Kb, C, w)
+    ctx.reserve(B, "full")
+    spd = torch.as_tensor(sp).to(dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    ctx.local_energy(spd[:8].contiguous(), mode="full")
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.local_energy(spd, mode="full", out=e)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    k_ms, k_n = ctx.kernel_time()
+    ctx.enable_timing(False)
+    O = torch.empty(B, ctx.P, dtype=torch.float32, device=dev)
+    ctx.log_deriv(spd, dtype="fp32", out=O)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.log_deriv(spd, dtype="fp32", out=O)
+    torch.cuda.synchronize()
+    ms_o = (time.perf_counter() - t0) * 1000.0
+    items = int(ctx.connected(spd)[0].sum().item())
+    N = L * L
+    per_item = sum(2 * N * (2 * C * (1 if k == 0 else C) * 9 + C * C * 9) for k in range(Kb))
+    avg = k_ms / max(k_n, 1)
+    achieved = items * per_item / (avg * 1e-3) / 1e12
+    ref = oracle.cnn1_local_energy(L, 1.0, J2, Kb, C, w, sp[:oracle_samples])
+    eb = e.cpu().numpy()[:oracle_samples]
+    rel = float(np.max(np.abs(eb - ref)) / np.max(np.abs(ref)))
+    assert ctx.get_error() == 0
+    ctx.close()
+    return {"workload": f"{L}x{L} J1-J2 (J2={J2}), CNN1 {Kb} blocks x {C} channels "
+                        f"(P={inputs.cnn1_num_params(Kb, C)}), {B} configurations, FP64",
+            "samples_per_s": B / (ms * 1e-3), "ms": ms, "exchanged_configurations": items,
+            "conn_pass_ms": avg, "conn_pass_tflops": achieved,
+            "bound": "mfma" if C == 16 else "alu",
+            "frac_fp64_peak": achieved / PEAK_FP64_TFLOPS,
+            "log_deriv_ms": ms_o, "oracle_max_rel_err": rel, "oracle_samples": oracle_samples}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,15 +325,16 @@ def main():
     ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--no-vmc", action="store_true")
     ap.add_argument("--no-tj", action="store_true")
+    ap.add_argument("--no-cnn1", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--mode", default="incremental", choices=["incremental", "full"])
-    ap.add_argument("--only", default=None, choices=["eloc", "tj"],
+    ap.add_argument("--only", default=None, choices=["eloc", "tj", "cnn1"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); tj "
-                         "runs only the t-J row and prints it")
+                         "runs only the t-J row and prints it; cnn1 likewise the CNN1 row")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -288,6 +350,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only == "tj":
         print(json.dumps(tj_row(dev)), flush=True)
+        return
+    if args.only == "cnn1":
+        print(json.dumps(cnn1_row(dev)), flush=True)
         return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
@@ -522,6 +587,12 @@ def main():
         log(f"t-J 12x12: {tj['samples_per_s']:.1f} samples/s ({tj['mode']}), kernel "
             f"{tj['kernel_tflops']:.0f} TFLOP/s, bf16 mean rel err {tj['bf16_mean_rel_err_vs_fp64']:.2e}")
 
+    cnn1 = None
+    if not args.no_cnn1:
+        cnn1 = cnn1_row(dev)
+        log(f"CNN1 10x10: {cnn1['samples_per_s']:.1f} samples/s, exchanged-configuration pass "
+            f"{cnn1['conn_pass_tflops']:.2f} TFLOP/s FP64, oracle rel err {cnn1['oracle_max_rel_err']:.1e}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -548,6 +619,7 @@ def main():
         "mcmc_nongating": mcmc,
         "vmc_iteration_nongating": vmc,
         "tj_nongating": tj,
+        "cnn1_nongating": cnn1,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,7 +1,7 @@
 // k_cnn1.hip -- the CNN1 network family [Sec. 5.2: blocks of a 2D
 // convolution, a 1D max-pooling and a transposed convolution, padded by the
 // periodic boundary; the wave-function coefficient is the product of the
-// output neurons], in FP64 on the vector ALU.
+// output neurons], in FP64.
 //
 // The block figure is not available, so the block is read as
 //   z = a + W (*) h          3x3 circular convolution, c_in -> 2C channels
@@ -12,6 +12,16 @@
 // log|psi_net| = sum log|u_K| and sign(psi_net) = prod sign(u_K).
 // Canonical parameter order per block: W[2C][c_in][3][3], a[2C],
 // V[C][C][3][3] (input channel first), v[C].
+//
+// With 16 channels, blocks 2.. run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64, k_conv_f64mma.hip): the convolution 16 -> 32 with
+// the channel-pair max in its epilogue, and the transposed convolution as a
+// convolution with flipped, transposed taps (V[ci][co][8 - t]).  Their
+// packing (built on the device from the canonical vector): per block k >= 2,
+//   [9][16][32] convolution taps, column 16 h + j holding channel 2 j + h,
+//   [32] its bias in the same column order, [9][16][16] transposed taps,
+//   [16] bias (6960 doubles, the block's parameter count).
+// The first block (one input channel) stays on the vector ALU.
 //
 // Planes are NHWC ([plane][site][channel]) in HBM.  The forward serves the
 // samples (base planes) and the exchanged configurations of the local
@@ -323,6 +333,35 @@ k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__
     }
 }
 
+constexpr int kPackBlock = 6960;     // packed doubles per MFMA block (C = 16)
+
+__global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restrict__ out)
+{
+    const int64_t n = (int64_t)(Kb - 1) * kPackBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kThreads) {
+        const int k = 1 + (int)(q / kPackBlock);
+        int r = (int)(q - (int64_t)(k - 1) * kPackBlock);
+        // canonical offsets of block k (c_in = 16): W, a, V, v
+        const int64_t W = 2640 + (int64_t)(k - 1) * kPackBlock;
+        const int64_t a = W + 32 * 16 * 9, V = a + 32, v = V + 16 * 16 * 9;
+        double val;
+        if (r < 4608) {
+            const int n = r % 32, ci = (r / 32) % 16, t = r / 512;
+            const int co = 2 * (n % 16) + n / 16;
+            val = w[W + ((int64_t)co * 16 + ci) * 9 + t];
+        } else if ((r -= 4608) < 32) {
+            val = w[a + 2 * (r % 16) + r / 16];
+        } else if ((r -= 32) < 2304) {
+            const int co = r % 16, ci = (r / 16) % 16, t = r / 256;
+            val = w[V + ((int64_t)ci * 16 + co) * 9 + (8 - t)];
+        } else {
+            val = w[v + (r - 2304)];
+        }
+        out[q] = val;
+    }
+}
+
 int grid_of(const nqs_ctx *c, int64_t work)
 {
     const int64_t b = (work + kThreads - 1) / kThreads;
@@ -330,22 +369,36 @@ int grid_of(const nqs_ctx *c, int64_t work)
     return (int)std::max<int64_t>(1, std::min(b, cap));
 }
 
+bool mfma_blocks(const nqs_ctx *c) { return c->C == 16 && c->K >= 2; }
+
+// one block over M planes: h (null for the first block: the spins) -> m
+// (pooled, into mbuf) -> u; zsave (may be null) keeps z
+void block_forward(const nqs_ctx *c, int k, const int8_t *spins, C1Planes pm, int64_t M,
+                   const double *h, double *mbuf, double *u, double *zsave, hipStream_t s)
+{
+    const int L = c->L, C = c->C;
+    const int64_t work = M * c->N * C;
+    const Cnn1Block o = block_of(C, k);
+    if (k > 0 && mfma_blocks(c)) {
+        const double *pk = c->w_vec64 + (int64_t)(k - 1) * kPackBlock;
+        f64mma_cnn1_conv(c, h, M, pk, pk + 4608, mbuf, zsave, pm.qlen, pm.q_begin, s);
+        f64mma_cnn1_convt(c, mbuf, M, pk + 4640, pk + 4640 + 2304, u, pm.qlen, pm.q_begin, s);
+        return;
+    }
+    NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
+               o.cin, h, (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a,
+               mbuf, zsave);
+    NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
+               (const double *)mbuf, (const double *)c->w_canon + o.V,
+               (const double *)c->w_canon + o.v, u);
+}
+
 // the blocks over M planes: the result u of the last block ends in pa
 void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t M, double *pa,
                     double *pb, hipStream_t s)
 {
-    const int L = c->L, C = c->C;
-    const int64_t work = M * c->N * C;
-    for (int k = 0; k < c->K; ++k) {
-        const Cnn1Block o = block_of(C, k);
-        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
-                   o.cin, k == 0 ? (const double *)nullptr : (const double *)pa,
-                   (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a, pb,
-                   (double *)nullptr);
-        NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
-                   (const double *)pb, (const double *)c->w_canon + o.V,
-                   (const double *)c->w_canon + o.v, pa);
-    }
+    for (int k = 0; k < c->K; ++k)
+        block_forward(c, k, spins, pm, M, k == 0 ? nullptr : pa, pb, pa, nullptr, s);
 }
 
 }  // namespace
@@ -394,6 +447,19 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
                c->err);
 }
 
+size_t cnn1_packed_doubles(const nqs_ctx *c)
+{
+    return mfma_blocks(c) ? (size_t)(c->K - 1) * kPackBlock : 0;
+}
+
+void cnn1_pack_device(const nqs_ctx *c, hipStream_t s)
+{
+    if (!mfma_blocks(c)) return;
+    const int64_t n = (int64_t)(c->K - 1) * kPackBlock;
+    NQS_LAUNCH(k_c1_pack, dim3(grid_of(c, n)), dim3(kThreads), 0, s,
+               (const double *)c->w_canon, c->K, c->w_vec64);
+}
+
 size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c)
 {
     // saved z (K * 2C), saved u (K * C), pooled m, g, gh (C each), gz (2C)
@@ -409,15 +475,9 @@ void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsav
     const C1Planes pm{nullptr, 0, nullptr};
     const double *w = c->w_canon;
     // forward with every block's z and u kept
-    for (int k = 0; k < K; ++k) {
-        const Cnn1Block o = block_of(C, k);
-        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, spins, pm,
-                   (int64_t)nb, L, C, o.cin,
-                   k == 0 ? (const double *)nullptr : (const double *)(usave + (k - 1) * plane),
-                   w + o.W, w + o.a, mbuf, zsave + (int64_t)k * 2 * plane);
-        NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, pm, (int64_t)nb, L,
-                   C, (const double *)mbuf, w + o.V, w + o.v, usave + (int64_t)k * plane);
-    }
+    for (int k = 0; k < K; ++k)
+        block_forward(c, k, spins, pm, nb, k == 0 ? nullptr : usave + (int64_t)(k - 1) * plane,
+                      mbuf, usave + (int64_t)k * plane, zsave + (int64_t)k * 2 * plane, s);
     NQS_LAUNCH(k_c1_ginit, dim3(grid_of(c, plane)), dim3(kThreads), 0, s,
                (const double *)(usave + (int64_t)(K - 1) * plane), plane, g);
     for (int k = K - 1; k >= 0; --k) {

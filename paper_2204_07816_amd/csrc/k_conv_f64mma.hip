@@ -53,7 +53,12 @@ struct ConvArgs {
 // channel 4 kq + s, so each lane reads 4 consecutive channels of a site.
 // epi 0: ln cosh; 1: ln cosh and save z; 2: z * tanh(zk) (backward data pass);
 // 3: tanh z (the last layer's delta).
-template <int COUT>
+// MODE 1 (CNN1 convolution, COUT = 32): column 16 h + j holds z[2 j + h], so
+// one lane holds both inputs of a channel-pair max: out [M][N][16] gets
+// max(z[2j], z[2j+1]) (the second only when larger), zk (may be null) the z
+// in natural channel order [M][N][32].  MODE 2 (CNN1 transposed
+// convolution): out = z, no activation.
+template <int COUT, int MODE = 0>
 __global__ void __launch_bounds__(kThreads)
 k_conv_mma(ConvArgs a)
 {
@@ -122,6 +127,36 @@ k_conv_mma(ConvArgs a)
         }
     }
     const int64_t obase = plane * (int64_t)N * COUT;
+    if constexpr (MODE == 1) {
+        static_assert(COUT == 32, "channel pairs span the two 16-column tiles");
+#pragma unroll
+        for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = p0 + mt * 16 + kq + 4 * i;
+                if (p >= N) continue;
+                const double z0 = acc[mt][0][i], z1 = acc[mt][1][i];
+                a.out[plane * (int64_t)N * 16 + (int64_t)p * 16 + m16] = (z1 > z0) ? z1 : z0;
+                if (a.zk) {
+                    a.zk[obase + (int64_t)p * 32 + 2 * m16] = z0;
+                    a.zk[obase + (int64_t)p * 32 + 2 * m16 + 1] = z1;
+                }
+            }
+        return;
+    }
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = p0 + mt * 16 + kq + 4 * i;
+                if (p >= N) continue;
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+                    a.out[obase + (int64_t)p * COUT + 16 * h + m16] = acc[mt][h][i];
+            }
+        return;
+    }
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
@@ -272,6 +307,31 @@ void f64mma_conv(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cou
         NQS_LAUNCH((k_conv_mma<32>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
     else
         NQS_LAUNCH((k_conv_mma<16>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
+// CNN1 with 16 channels: the convolution 16 -> 32 with the channel-pair max
+// in the epilogue (packed columns, see MODE 1), and the transposed
+// convolution 16 -> 16 as a convolution with flipped, transposed taps.
+void f64mma_cnn1_conv(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                      const double *bias, double *out, double *zsave, const int64_t *qlen,
+                      int64_t q_begin, hipStream_t s)
+{
+    if (M <= 0) return;
+    ConvArgs a{in, w, bias, out, zsave, qlen, q_begin, M, c->L, 16, 0};
+    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
+    NQS_LAUNCH((k_conv_mma<32, 1>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
+void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                       const double *bias, double *out, const int64_t *qlen, int64_t q_begin,
+                       hipStream_t s)
+{
+    if (M <= 0) return;
+    ConvArgs a{in, w, bias, out, nullptr, qlen, q_begin, M, c->L, 16, 0};
+    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
+    NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
 }
 
 bool f64mma_wgrad_ok(int C) { return C == 16 || C == 32; }

@@ -162,7 +162,10 @@ void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipSt
     const int K = c->K, C = c->C;
     NQS_LAUNCH(k_axpy, dim3(grid_of(c->P)), dim3(kThreads), 0, s, c->w_canon, dtheta, scale,
                c->P);
-    if (c->net == kNetCnn1) return;     // CNN1 kernels read the canonical vector
+    if (c->net == kNetCnn1) {           // only the matrix-core packing of CNN1
+        cnn1_pack_device(c, s);
+        return;
+    }
     NQS_LAUNCH(k_pack_vec, dim3(grid_of(c->P)), dim3(kThreads), 0, s, (const double *)c->w_canon,
                K, C, c->P, c->w_vec64, c->w_vec32);
     if (K > 1)

@@ -97,7 +97,19 @@ nqs_status upload(T *&dst, const std::vector<T> &src)
 
 nqs_status pack_weights(nqs_ctx *c)
 {
-    if (c->net == kNetCnn1) return upload(c->w_canon, c->w_host);   // read as it is
+    if (c->net == kNetCnn1) {
+        // canonical vector, plus the matrix-core packing built from it on the device
+        nqs_status st = upload(c->w_canon, c->w_host);
+        const size_t np = cnn1_packed_doubles(c);
+        if (st != NQS_OK || np == 0) return st;
+        if (!c->w_vec64 && hipMalloc((void **)&c->w_vec64, np * sizeof(double)) != hipSuccess) {
+            c->w_vec64 = nullptr;
+            return NQS_E_NOMEM;
+        }
+        cnn1_pack_device(c, nullptr);
+        HIP_OK(hipDeviceSynchronize());
+        return NQS_OK;
+    }
     const int K = c->K, C = c->C;
     Canon cn{c->w_host.data(), K, C};
     // vector path: layer 1 [9][C] + b; layer k [9][Cin][C] + b

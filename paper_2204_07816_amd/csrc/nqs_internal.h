@@ -263,6 +263,16 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
                        const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
                        const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
                        hipStream_t s);
+// matrix-core packing of blocks 2.. (16 channels): its size in doubles (0
+// when the vector kernels serve) and its rebuild from w_canon into w_vec64
+size_t cnn1_packed_doubles(const nqs_ctx *c);
+void cnn1_pack_device(const nqs_ctx *c, hipStream_t s);
+void f64mma_cnn1_conv(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                      const double *bias, double *out, double *zsave, const int64_t *qlen,
+                      int64_t q_begin, hipStream_t s);
+void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                       const double *bias, double *out, const int64_t *qlen, int64_t q_begin,
+                       hipStream_t s);
 size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c);
 // O rows of nb samples; zsave: K*2*nb*N*C, usave: K*nb*N*C, work: 5*nb*N*C doubles
 void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,

@@ -49,10 +49,19 @@ def cnn1_num_params(Kb: int, C: int) -> int:
     return sum(2 * C * (1 if k == 0 else C) * 9 + 2 * C + C * C * 9 + C for k in range(Kb))
 
 
-def cnn1_weights(Kb: int, C: int, sigma: float, seed: int) -> np.ndarray:
-    """CNN1 parameters, i.i.d. N(0, sigma^2) in canonical order."""
+def cnn1_weights(Kb: int, C: int, sigma: float, seed: int, out_bias: float = 0.0) -> np.ndarray:
+    """CNN1 parameters, i.i.d. N(0, sigma^2) in canonical order (per block
+    W, a, V, v), with out_bias added to every transposed-convolution bias v
+    (out_bias = 1 keeps the output neurons near 1, away from the zeros of
+    their product)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return rng.normal(0.0, sigma, cnn1_num_params(Kb, C)).astype(np.float64)
+    w = rng.normal(0.0, sigma, cnn1_num_params(Kb, C)).astype(np.float64)
+    off = 0
+    for k in range(Kb):
+        off += 2 * C * (1 if k == 0 else C) * 9 + 2 * C + C * C * 9
+        w[off:off + C] += out_bias
+        off += C
+    return w
 
 
 def spins_sz0(L: int, B: int, seed: int) -> np.ndarray:
@@ -114,6 +123,20 @@ CONFIGS = {
     "sr24": dict(index=3, L=24, J2=0.5, K=6, C=32, sigma=0.02, B=4096),
     "full36": dict(index=4, L=36, J2=0.5, K=8, C=32, sigma=0.02, B=1024),
 }
+
+
+# CNN1 workload: the 10x10 J1-J2 point (J2 = 0.5) of the paper's strong
+# scaling runs, 6 blocks (the paper's block count) of 16 channels; weights
+# seed 1200, spins seed 2200.
+CNN1_CONFIG = dict(L=10, J2=0.5, blocks=6, C=16, sigma=0.05, out_bias=1.0, B=1024)
+
+
+def cnn1_config_inputs(B: int | None = None):
+    """(L, J2, blocks, C, weights, spins) of the CNN1 workload."""
+    cfg = CNN1_CONFIG
+    nb = cfg["B"] if B is None else B
+    w = cnn1_weights(cfg["blocks"], cfg["C"], cfg["sigma"], 1200, cfg["out_bias"])
+    return cfg["L"], cfg["J2"], cfg["blocks"], cfg["C"], w, spins_sz0(cfg["L"], nb, 2200)
 
 
 # t-J workloads (t = 1, J = 0.4, hole doping 1/8, the parameters of the

@@ -32,7 +32,7 @@ def c1_ctx(L, Kb, C, w, J2=0.5, marshall=True):
 
 
 PSI_CASES = [(4, 2, 4, 0.3, 64), (6, 3, 3, 0.5, 40), (10, 6, 8, 0.2, 16), (16, 4, 16, 0.15, 6),
-             (8, 1, 2, 0.7, 33)]
+             (8, 1, 2, 0.7, 33), (6, 2, 16, 0.3, 20)]
 
 
 @pytest.mark.parametrize("L,Kb,C,sigma,B", PSI_CASES)
@@ -49,14 +49,17 @@ def test_cnn1_log_psi(L, Kb, C, sigma, B):
         assert ctx.get_error() == 0
 
 
-ELOC_CASES = [(4, 0.5, 2, 4, 0.3, 128), (6, 0.0, 3, 3, 0.5, 24), (10, 0.5, 6, 8, 0.2, 6),
-              (8, 0.55, 2, 5, 0.4, 12)]
+# 16 channels: blocks 2.. on the FP64 matrix cores; other widths: vector ALU
+ELOC_CASES = [(4, 0.5, 2, 4, 0.3, 0.0, 128), (6, 0.0, 3, 3, 0.5, 0.0, 24),
+              (10, 0.5, 6, 8, 0.2, 0.0, 6), (8, 0.55, 2, 5, 0.4, 0.0, 12),
+              (10, 0.5, 6, 16, 0.1, 1.0, 6), (12, 0.0, 3, 16, 0.2, 0.0, 4),
+              (6, 0.5, 2, 16, 0.3, 1.0, 16)]
 
 
-@pytest.mark.parametrize("L,J2,Kb,C,sigma,B", ELOC_CASES)
-def test_cnn1_local_energy(L, J2, Kb, C, sigma, B):
+@pytest.mark.parametrize("L,J2,Kb,C,sigma,ob,B", ELOC_CASES)
+def test_cnn1_local_energy(L, J2, Kb, C, sigma, ob, B):
     say("eloc cnn1", L, J2, Kb, C, B)
-    w = inputs.cnn1_weights(Kb, C, sigma, 71)
+    w = inputs.cnn1_weights(Kb, C, sigma, 71, out_bias=ob)
     sp = inputs.spins_sz0(L, B, 72)
     ctx = c1_ctx(L, Kb, C, w, J2=J2)
     e = ctx.local_energy(to_dev(sp), mode="full").cpu().numpy()
@@ -82,11 +85,12 @@ def test_cnn1_rayleigh_quotient_against_ed():
     assert lhs == pytest.approx(rhs, rel=1e-10)
 
 
-@pytest.mark.parametrize("L,Kb,C,sigma,B", [(4, 2, 4, 0.3, 16), (6, 3, 3, 0.5, 8),
-                                            (10, 6, 8, 0.2, 4)])
-def test_cnn1_log_deriv(L, Kb, C, sigma, B):
+@pytest.mark.parametrize("L,Kb,C,sigma,ob,B", [(4, 2, 4, 0.3, 0.0, 16), (6, 3, 3, 0.5, 0.0, 8),
+                                               (10, 6, 8, 0.2, 0.0, 4), (8, 3, 16, 0.2, 0.0, 4),
+                                               (10, 6, 16, 0.1, 1.0, 3)])
+def test_cnn1_log_deriv(L, Kb, C, sigma, ob, B):
     say("log_deriv cnn1", L, Kb, C, B)
-    w = inputs.cnn1_weights(Kb, C, sigma, 81)
+    w = inputs.cnn1_weights(Kb, C, sigma, 81, out_bias=ob)
     sp = inputs.spins_sz0(L, B, 82)
     ctx = c1_ctx(L, Kb, C, w)
     O = ctx.log_deriv(to_dev(sp), dtype="fp64").cpu().numpy()
@@ -115,17 +119,8 @@ def test_cnn1_mcmc_equals_oracle():
 
 
 def smooth_weights(Kb, C, sigma, seed):
-    """N(0, sigma^2) weights with 1 added to every transposed-convolution bias,
-    so the output neurons stay near 1, away from the zeros of the product."""
-    w = inputs.cnn1_weights(Kb, C, sigma, seed)
-    off = 0
-    for k in range(Kb):
-        cin = 1 if k == 0 else C
-        off += 2 * C * cin * 9 + 2 * C + C * C * 9
-        w[off:off + C] += 1.0
-        off += C
-    assert off == w.shape[0]
-    return w
+    """Output neurons near 1, away from the zeros of their product."""
+    return inputs.cnn1_weights(Kb, C, sigma, seed, out_bias=1.0)
 
 
 def test_cnn1_vmc_matches_oracle():
@@ -147,8 +142,9 @@ def test_cnn1_vmc_matches_oracle():
     assert ctx.get_error() == 0
 
 
-def test_cnn1_sr_recompute_and_device_update():
-    L, Kb, C, B = 6, 3, 4, 96
+@pytest.mark.parametrize("C", [4, 16])
+def test_cnn1_sr_recompute_and_device_update(C):
+    L, Kb, B = 6, 3, 96
     w = smooth_weights(Kb, C, 0.1, 111)
     sp = to_dev(inputs.spins_sz0(L, B, 112))
     ctx = c1_ctx(L, Kb, C, w)
