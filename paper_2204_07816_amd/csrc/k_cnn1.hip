@@ -13,15 +13,16 @@
 // Canonical parameter order per block: W[2C][c_in][3][3], a[2C],
 // V[C][C][3][3] (input channel first), v[C].
 //
-// With 16 channels, blocks 2.. run on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64, k_conv_f64mma.hip): the convolution 16 -> 32 with
-// the channel-pair max in its epilogue, and the transposed convolution as a
-// convolution with flipped, transposed taps (V[ci][co][8 - t]).  Their
-// packing (built on the device from the canonical vector): per block k >= 2,
-//   [9][16][32] convolution taps, column 16 h + j holding channel 2 j + h,
-//   [32] its bias in the same column order, [9][16][16] transposed taps,
-//   [16] bias (6960 doubles, the block's parameter count).
-// The first block (one input channel) stays on the vector ALU.
+// With 16 channels the FP64 matrix cores (v_mfma_f64_16x16x4f64,
+// k_conv_f64mma.hip) run every transposed convolution, as a convolution with
+// flipped, transposed taps (V[ci][co][8 - t]), and the convolutions 16 -> 32
+// of blocks 2.., with the channel-pair max in their epilogue.  The first
+// convolution (one input channel) stays on the vector ALU.  The packing,
+// built on the device from the canonical vector:
+//   block 1: [9][16][16] transposed taps, [16] bias (2320 doubles);
+//   block k >= 2: [9][16][32] convolution taps, column 16 h + j holding
+//   channel 2 j + h, [32] its bias in the same column order, then the
+//   transposed part as for block 1 (6960 doubles).
 //
 // Planes are NHWC ([plane][site][channel]) in HBM.  The forward serves the
 // samples (base planes) and the exchanged configurations of the local
@@ -333,19 +334,32 @@ k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__
     }
 }
 
-constexpr int kPackBlock = 6960;     // packed doubles per MFMA block (C = 16)
+constexpr int kPackFirst = 2320;     // packed doubles of block 1 (C = 16)
+constexpr int kPackBlock = 6960;     // packed doubles of blocks 2.. (C = 16)
 
 __global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restrict__ out)
 {
-    const int64_t n = (int64_t)(Kb - 1) * kPackBlock;
+    const int64_t n = kPackFirst + (int64_t)(Kb - 1) * kPackBlock;
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * kThreads) {
-        const int k = 1 + (int)(q / kPackBlock);
-        int r = (int)(q - (int64_t)(k - 1) * kPackBlock);
+        double val;
+        if (q < kPackFirst) {
+            // block 1: canonical W[32][1][9] at 0, a at 288, V at 320, v at 2624
+            const int r = (int)q;
+            if (r < 2304) {
+                const int co = r % 16, ci = (r / 16) % 16, t = r / 256;
+                val = w[320 + ((int64_t)ci * 16 + co) * 9 + (8 - t)];
+            } else {
+                val = w[2624 + (r - 2304)];
+            }
+            out[q] = val;
+            continue;
+        }
+        const int k = 1 + (int)((q - kPackFirst) / kPackBlock);
+        int r = (int)(q - kPackFirst - (int64_t)(k - 1) * kPackBlock);
         // canonical offsets of block k (c_in = 16): W, a, V, v
         const int64_t W = 2640 + (int64_t)(k - 1) * kPackBlock;
         const int64_t a = W + 32 * 16 * 9, V = a + 32, v = V + 16 * 16 * 9;
-        double val;
         if (r < 4608) {
             const int n = r % 32, ci = (r / 32) % 16, t = r / 512;
             const int co = 2 * (n % 16) + n / 16;
@@ -369,7 +383,7 @@ int grid_of(const nqs_ctx *c, int64_t work)
     return (int)std::max<int64_t>(1, std::min(b, cap));
 }
 
-bool mfma_blocks(const nqs_ctx *c) { return c->C == 16 && c->K >= 2; }
+bool mfma_blocks(const nqs_ctx *c) { return c->C == 16; }
 
 // one block over M planes: h (null for the first block: the spins) -> m
 // (pooled, into mbuf) -> u; zsave (may be null) keeps z
@@ -379,18 +393,25 @@ void block_forward(const nqs_ctx *c, int k, const int8_t *spins, C1Planes pm, in
     const int L = c->L, C = c->C;
     const int64_t work = M * c->N * C;
     const Cnn1Block o = block_of(C, k);
-    if (k > 0 && mfma_blocks(c)) {
-        const double *pk = c->w_vec64 + (int64_t)(k - 1) * kPackBlock;
+    const bool mm = mfma_blocks(c);
+    // packed transposed taps and bias of this block (matrix-core path)
+    const double *pt = nullptr;
+    if (mm) pt = k == 0 ? c->w_vec64 : c->w_vec64 + kPackFirst + (int64_t)(k - 1) * kPackBlock + 4640;
+    if (k > 0 && mm) {
+        const double *pk = pt - 4640;
         f64mma_cnn1_conv(c, h, M, pk, pk + 4608, mbuf, zsave, pm.qlen, pm.q_begin, s);
-        f64mma_cnn1_convt(c, mbuf, M, pk + 4640, pk + 4640 + 2304, u, pm.qlen, pm.q_begin, s);
-        return;
+    } else {
+        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
+                   o.cin, h, (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a,
+                   mbuf, zsave);
     }
-    NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
-               o.cin, h, (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a,
-               mbuf, zsave);
-    NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
-               (const double *)mbuf, (const double *)c->w_canon + o.V,
-               (const double *)c->w_canon + o.v, u);
+    if (mm) {
+        f64mma_cnn1_convt(c, mbuf, M, pt, pt + 2304, u, pm.qlen, pm.q_begin, s);
+    } else {
+        NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
+                   (const double *)mbuf, (const double *)c->w_canon + o.V,
+                   (const double *)c->w_canon + o.v, u);
+    }
 }
 
 // the blocks over M planes: the result u of the last block ends in pa
@@ -449,13 +470,13 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
 
 size_t cnn1_packed_doubles(const nqs_ctx *c)
 {
-    return mfma_blocks(c) ? (size_t)(c->K - 1) * kPackBlock : 0;
+    return mfma_blocks(c) ? (size_t)kPackFirst + (size_t)(c->K - 1) * kPackBlock : 0;
 }
 
 void cnn1_pack_device(const nqs_ctx *c, hipStream_t s)
 {
     if (!mfma_blocks(c)) return;
-    const int64_t n = (int64_t)(c->K - 1) * kPackBlock;
+    const int64_t n = kPackFirst + (int64_t)(c->K - 1) * kPackBlock;
     NQS_LAUNCH(k_c1_pack, dim3(grid_of(c, n)), dim3(kThreads), 0, s,
                (const double *)c->w_canon, c->K, c->w_vec64);
 }

@@ -32,7 +32,7 @@ def c1_ctx(L, Kb, C, w, J2=0.5, marshall=True):
 
 
 PSI_CASES = [(4, 2, 4, 0.3, 64), (6, 3, 3, 0.5, 40), (10, 6, 8, 0.2, 16), (16, 4, 16, 0.15, 6),
-             (8, 1, 2, 0.7, 33), (6, 2, 16, 0.3, 20)]
+             (8, 1, 2, 0.7, 33), (6, 2, 16, 0.3, 20), (6, 1, 16, 0.3, 12)]
 
 
 @pytest.mark.parametrize("L,Kb,C,sigma,B", PSI_CASES)
