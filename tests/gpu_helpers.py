@@ -37,3 +37,42 @@ def rel_inf(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def graph_replays_equal_eager(ctx, w, start, n=3, **kw):
+    """n eager VMC iterations from (w, start), then one iteration captured in a
+    HIP graph and replayed n times from the same start with each iteration's
+    random numbers staged: every replay must equal its eager iteration."""
+    from paper_2204_07816_amd.vmc import VMC
+    run = VMC(ctx, start.clone(), **kw)
+    eager = [run.step() for _ in range(n)]
+    w_eager, s_eager = run.weights, run.spins.clone()
+    ctx.set_weights(w)
+    run.spins.copy_(start)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run.stage(0)
+        run.enqueue()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ctx.set_weights(w)
+    run.spins.copy_(start)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run.enqueue()
+    torch.cuda.synchronize()
+    ctx.set_weights(w)
+    run.spins.copy_(start)
+    torch.cuda.synchronize()
+    for it in range(n):
+        run.stage(it)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        st = run.stats()
+        say("iteration", it, "graph", st["energy"], "eager", eager[it]["energy"])
+        assert st["energy"] == eager[it]["energy"] and st["variance"] == eager[it]["variance"]
+    assert np.array_equal(run.weights, w_eager)
+    assert torch.equal(run.spins, s_eager)
+    del g

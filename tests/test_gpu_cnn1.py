@@ -12,6 +12,7 @@ against the oracle.  The block architecture is a reading of a missing figure
 * Metropolis chains equal the oracle's; the FP64 VMC loop reproduces the
   oracle's; SR with O recomputed equals SR on the stored O bit for bit; the
   device weight update equals setting the weights from the host;
+* a CNN1 VMC iteration captured in a HIP graph equals the eager iterations;
 * incremental mode, the multi-lattice call and the autotuner are refused.
 """
 import numpy as np
@@ -22,7 +23,7 @@ import oracle
 from oracle import ed
 from paper_2204_07816_amd import inputs, nqs
 from paper_2204_07816_amd.vmc import VMC
-from gpu_helpers import DEV, rel_inf, say, to_dev
+from gpu_helpers import DEV, graph_replays_equal_eager, rel_inf, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -173,4 +174,13 @@ def test_cnn1_refusals():
             call()
         assert info.value.code == 10            # NQS_E_UNSUPPORTED
     assert ctx.auto_mode() == "full"
+    assert ctx.get_error() == 0
+
+
+def test_cnn1_vmc_iteration_captured_in_graph():
+    L, Kb, C, B = 8, 3, 16, 32
+    w = smooth_weights(Kb, C, 0.05, 131)
+    ctx = c1_ctx(L, Kb, C, w)
+    graph_replays_equal_eager(ctx, w, to_dev(inputs.spins_sz0(L, B, 132)), steps=4, lr=0.01,
+                              diag_shift=1e-2, cg_iters=20, seed=133)
     assert ctx.get_error() == 0

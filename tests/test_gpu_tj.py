@@ -16,6 +16,8 @@ oracle and the fermion-operator exact diagonalisation.
   identical samples, weights to 1e-6 of their scale).
 * A multi-lattice launch mixing t-J and spin lattices equals the single
   calls bit for bit; a site value outside {-1, 0, 1} sets NQS_E_SPIN.
+* A BF16 t-J VMC iteration captured in a HIP graph and replayed equals the
+  eager iterations bit for bit.
 """
 import numpy as np
 import pytest
@@ -25,7 +27,8 @@ import oracle
 from oracle import ed
 from paper_2204_07816_amd import inputs, nqs
 from paper_2204_07816_amd.vmc import VMC
-from gpu_helpers import DEV, make_ctx, oracle_item_dlog, rel_inf, say, to_dev
+from gpu_helpers import (DEV, graph_replays_equal_eager, make_ctx, oracle_item_dlog, rel_inf,
+                         say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -244,4 +247,14 @@ def test_tj_bad_value_sets_sticky_error():
     assert ctx.get_error() == 5          # NQS_E_SPIN
     ok = inputs.spins_tj(L, 4, 4, 3)
     ctx.local_energy(to_dev(ok), mode="full")
+    assert ctx.get_error() == 0
+
+
+def test_tj_vmc_iteration_captured_in_graph():
+    L, K, C, B = 16, 6, 32, 32
+    w = inputs.weights(K, C, 0.05, 141)
+    ctx = tj_ctx(L, K, C, w, dtype="bf16")
+    graph_replays_equal_eager(ctx, w, to_dev(inputs.spins_tj(L, B, 32, 142)), steps=4, lr=0.02,
+                              diag_shift=1e-2, cg_iters=20, seed=143, o_dtype="fp32",
+                               mode="incremental")
     assert ctx.get_error() == 0
