@@ -261,10 +261,14 @@ nqs_status nqs_mcmc(nqs_ctx *ctx, int8_t *spins, int64_t B, int32_t n_steps,
  * shape and conv dtype, any L, J2 and weights; no context twice).  With BF16
  * contexts each lattice runs its bond stage and base pass, then the
  * exchanged configurations of all lattices of one mode (as `mode` resolves
- * per context) share one persistent kernel launch over their concatenated
- * queues (up to 8 lattices per launch), then each lattice's FP64 ratio sums
- * are taken.  FP64 / FP32 contexts run lattice after lattice.  Errors as
- * nqs_local_energy, checked for every job before any work is queued.      */
+ * per context) and one kernel family share one persistent launch over their
+ * concatenated queues (up to 8 lattices per launch; in incremental mode the
+ * lattices with unwrapped cones share the cone kernel and the others the
+ * general incremental kernel), then each lattice's FP64 ratio sums are
+ * taken, so every lattice's energies equal its single-lattice call's.
+ * FP64 / FP32 contexts run lattice after lattice; CNN1 contexts are
+ * refused (NQS_E_UNSUPPORTED).  Errors as nqs_local_energy, checked for
+ * every job before any work is queued.                                    */
 typedef struct {
     nqs_ctx *ctx;
     const int8_t *spins;

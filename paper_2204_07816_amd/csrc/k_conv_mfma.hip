@@ -510,12 +510,19 @@ void mfma_conn_forward_jobs(nqs_mode mode, const ConnJob *jobs, int n, hipStream
 {
     if (n <= 0) return;
     if (mode == NQS_INCREMENTAL) {
-        bool cone = true;
-        for (int i = 0; i < n; ++i) cone = cone && cone_supported(jobs[i].c);
-        if (cone)
-            cone_forward_jobs(jobs, n, s);
-        else
-            mfma_inc_forward_jobs(jobs, n, s);
+        // lattices the unwrapped-window kernel serves share one launch of it;
+        // the others (wrapped windows, 16 channels) one launch of the general
+        // kernel: each lattice runs exactly as in its single-lattice call
+        ConnJob cone[kMaxConnJobs], rest[kMaxConnJobs];
+        int nc = 0, nr = 0;
+        for (int i = 0; i < n; ++i) {
+            if (cone_supported(jobs[i].c))
+                cone[nc++] = jobs[i];
+            else
+                rest[nr++] = jobs[i];
+        }
+        if (nc > 0) cone_forward_jobs(cone, nc, s);
+        if (nr > 0) mfma_inc_forward_jobs(rest, nr, s);
         return;
     }
     NetJobs jp{};

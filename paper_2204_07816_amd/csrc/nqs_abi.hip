@@ -916,9 +916,9 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
         return NQS_OK;
     }
     // BF16: per lattice the integer stage and the base pass; then the
-    // exchanged configurations of every lattice of one mode in a single
-    // persistent launch (one per mode present, kMaxConnJobs lattices at a
-    // time); then per lattice the FP64 ratio sums.
+    // exchanged configurations of every lattice of one mode and kernel
+    // family in one persistent launch (kMaxConnJobs lattices at a time);
+    // then per lattice the FP64 ratio sums.
     for (int i = 0; i < n; ++i) {
         nqs_ctx *c = jobs[i].ctx;
         c->last_stream = s;
