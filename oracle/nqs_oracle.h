@@ -107,7 +107,8 @@ void oracle_tj_local_energy_table(int L, double t, double J, int64_t n_tab, cons
 
 /* CNN1 [Sec. 5.2: blocks of a 2D convolution, a 1D max-pooling and a
  * transposed convolution, periodic padding, output the product of the
- * neurons].  The block figure is missing; the reading implemented here:
+ * neurons].  The block figure is missing, so the architecture is parity
+ * unpinned against the paper; the reading implemented here:
  * block k maps c_in (1, then C) channels to C by
  *   z = a + W (*) h        3x3 circular convolution, c_in -> 2C, W[2C][c_in][3][3]
  *   m[c] = max(z[2c], z[2c+1])             max-pool of window 2 over channels

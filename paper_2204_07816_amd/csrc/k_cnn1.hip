@@ -334,8 +334,16 @@ k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__
     }
 }
 
-constexpr int kPackFirst = 2320;     // packed doubles of block 1 (C = 16)
-constexpr int kPackBlock = 6960;     // packed doubles of blocks 2.. (C = 16)
+// canonical sizes with 16 channels
+constexpr int kMC = 16;
+constexpr int kConvT = kMC * kMC * 9;                  // V: 2304
+constexpr int kConv1 = 2 * kMC * 9;                    // W of block 1 (c_in = 1): 288
+constexpr int kConvK = 2 * kMC * kMC * 9;              // W of blocks 2..: 4608
+constexpr int kBlock1 = kConv1 + 2 * kMC + kConvT + kMC;          // 2640
+constexpr int kBlockK = kConvK + 2 * kMC + kConvT + kMC;          // blocks 2..: 6960
+constexpr int kPackFirst = kConvT + kMC;                          // packed block 1: 2320
+constexpr int kPackBlock = kBlockK;         // packed block k >= 2: same count, reordered
+static_assert(kBlock1 == 2640 && kPackFirst == 2320 && kPackBlock == 6960, "packing sizes");
 
 __global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restrict__ out)
 {
@@ -344,13 +352,14 @@ __global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restri
          q += (int64_t)gridDim.x * kThreads) {
         double val;
         if (q < kPackFirst) {
-            // block 1: canonical W[32][1][9] at 0, a at 288, V at 320, v at 2624
+            // block 1: canonical W at 0, a at kConv1, V, then v
+            const int64_t V = kConv1 + 2 * kMC, v = V + kConvT;
             const int r = (int)q;
-            if (r < 2304) {
-                const int co = r % 16, ci = (r / 16) % 16, t = r / 256;
-                val = w[320 + ((int64_t)ci * 16 + co) * 9 + (8 - t)];
+            if (r < kConvT) {
+                const int co = r % kMC, ci = (r / kMC) % kMC, t = r / (kMC * kMC);
+                val = w[V + ((int64_t)ci * kMC + co) * 9 + (8 - t)];
             } else {
-                val = w[2624 + (r - 2304)];
+                val = w[v + (r - kConvT)];
             }
             out[q] = val;
             continue;
@@ -358,19 +367,20 @@ __global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restri
         const int k = 1 + (int)((q - kPackFirst) / kPackBlock);
         int r = (int)(q - kPackFirst - (int64_t)(k - 1) * kPackBlock);
         // canonical offsets of block k (c_in = 16): W, a, V, v
-        const int64_t W = 2640 + (int64_t)(k - 1) * kPackBlock;
-        const int64_t a = W + 32 * 16 * 9, V = a + 32, v = V + 16 * 16 * 9;
-        if (r < 4608) {
-            const int n = r % 32, ci = (r / 32) % 16, t = r / 512;
-            const int co = 2 * (n % 16) + n / 16;
-            val = w[W + ((int64_t)co * 16 + ci) * 9 + t];
-        } else if ((r -= 4608) < 32) {
-            val = w[a + 2 * (r % 16) + r / 16];
-        } else if ((r -= 32) < 2304) {
-            const int co = r % 16, ci = (r / 16) % 16, t = r / 256;
-            val = w[V + ((int64_t)ci * 16 + co) * 9 + (8 - t)];
+        const int64_t W = kBlock1 + (int64_t)(k - 1) * kBlockK;
+        const int64_t a = W + kConvK, V = a + 2 * kMC, v = V + kConvT;
+        if (r < kConvK) {
+            // [t][ci][n], column n = 16 h + j holds output channel 2 j + h
+            const int n = r % (2 * kMC), ci = (r / (2 * kMC)) % kMC, t = r / (2 * kMC * kMC);
+            const int co = 2 * (n % kMC) + n / kMC;
+            val = w[W + ((int64_t)co * kMC + ci) * 9 + t];
+        } else if ((r -= kConvK) < 2 * kMC) {
+            val = w[a + 2 * (r % kMC) + r / kMC];
+        } else if ((r -= 2 * kMC) < kConvT) {
+            const int co = r % kMC, ci = (r / kMC) % kMC, t = r / (kMC * kMC);
+            val = w[V + ((int64_t)ci * kMC + co) * 9 + (8 - t)];
         } else {
-            val = w[v + (r - 2304)];
+            val = w[v + (r - kConvT)];
         }
         out[q] = val;
     }
@@ -383,7 +393,7 @@ int grid_of(const nqs_ctx *c, int64_t work)
     return (int)std::max<int64_t>(1, std::min(b, cap));
 }
 
-bool mfma_blocks(const nqs_ctx *c) { return c->C == 16; }
+bool mfma_blocks(const nqs_ctx *c) { return c->C == kMC; }
 
 // one block over M planes: h (null for the first block: the spins) -> m
 // (pooled, into mbuf) -> u; zsave (may be null) keeps z
@@ -396,17 +406,19 @@ void block_forward(const nqs_ctx *c, int k, const int8_t *spins, C1Planes pm, in
     const bool mm = mfma_blocks(c);
     // packed transposed taps and bias of this block (matrix-core path)
     const double *pt = nullptr;
-    if (mm) pt = k == 0 ? c->w_vec64 : c->w_vec64 + kPackFirst + (int64_t)(k - 1) * kPackBlock + 4640;
+    if (mm)
+        pt = k == 0 ? c->w_vec64
+                    : c->w_vec64 + kPackFirst + (int64_t)(k - 1) * kPackBlock + kConvK + 2 * kMC;
     if (k > 0 && mm) {
-        const double *pk = pt - 4640;
-        f64mma_cnn1_conv(c, h, M, pk, pk + 4608, mbuf, zsave, pm.qlen, pm.q_begin, s);
+        const double *pk = pt - (kConvK + 2 * kMC);
+        f64mma_cnn1_conv(c, h, M, pk, pk + kConvK, mbuf, zsave, pm.qlen, pm.q_begin, s);
     } else {
         NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
                    o.cin, h, (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a,
                    mbuf, zsave);
     }
     if (mm) {
-        f64mma_cnn1_convt(c, mbuf, M, pt, pt + 2304, u, pm.qlen, pm.q_begin, s);
+        f64mma_cnn1_convt(c, mbuf, M, pt, pt + kConvT, u, pm.qlen, pm.q_begin, s);
     } else {
         NQS_LAUNCH(k_c1_convt, dim3(grid_of(c, work)), dim3(kThreads), 0, s, pm, M, L, C,
                    (const double *)mbuf, (const double *)c->w_canon + o.V,
