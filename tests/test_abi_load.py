@@ -117,3 +117,12 @@ def test_create_cnn1_rejects_bad_arguments(lib):
     assert lib.nqs_create_cnn1(4, float("nan"), 0.5, 2, 4, 1, buf, 672, ctypes.byref(h)) == 1
     assert lib.nqs_create_cnn1(4, 1.0, 0.5, 2, 4, 1, None, 672, ctypes.byref(h)) == 1
     assert not h.value
+
+
+def test_binding_rejects_cnn1_outside_fp64(lib):
+    from paper_2204_07816_amd import inputs, nqs
+    w = inputs.cnn1_weights(2, 4, 0.1, 1)
+    with pytest.raises(ValueError):
+        nqs.Context(4, 1.0, 0.5, 2, 4, w, dtype="bf16", net="cnn1")
+    with pytest.raises(ValueError):
+        nqs.Context(4, 1.0, 0.5, 2, 4, w, net="cnn1", tj_hop=1.0)
