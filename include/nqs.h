@@ -149,6 +149,15 @@ nqs_status nqs_create_cnn1(int32_t L, double J1, double J2, int32_t blocks, int3
                            int32_t marshall_sign, const double *weights, int64_t n_weights,
                            nqs_ctx **out);
 
+/* The t-J model [Sec. 6.1, Eq. tJ; the terms and site values of
+ * nqs_create_tj] with the CNN1 amplitude of nqs_create_cnn1, whose own sign
+ * (the sign of the neuron product) multiplies every term of E_loc with the
+ * Jordan-Wigner and Marshall signs.  Same entry points and errors as
+ * nqs_create_cnn1.                                                          */
+nqs_status nqs_create_cnn1_tj(int32_t L, double t, double J, int32_t blocks, int32_t channels,
+                              int32_t marshall_sign, const double *weights, int64_t n_weights,
+                              nqs_ctx **out);
+
 /* Release the context and its device memory (synchronises the device).  */
 nqs_status nqs_destroy(nqs_ctx *ctx);
 

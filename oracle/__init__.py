@@ -60,6 +60,8 @@ def _load():
         "oracle_cnn1_log_psi": (None, [ci, ci, ci, P(d), ci, P(i8), i64, P(d), P(i8), ci]),
         "oracle_cnn1_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d), ci]),
         "oracle_cnn1_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_tj_cnn1_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d),
+                                               ci]),
         "oracle_energy_stats": (None, [P(d), i64, P(d)]),
         "oracle_sr_cg": (None, [P(d), P(d), i64, i64, d, ci, P(d), P(d)]),
         "oracle_sr_dense": (ci, [P(d), P(d), i64, i64, d, P(d)]),
@@ -260,6 +262,19 @@ def cnn1_local_energy(L: int, J1: float, J2: float, Kb: int, C: int, w, spins,
     return e
 
 
+def tj_cnn1_local_energy(L: int, t: float, J: float, Kb: int, C: int, w, spins,
+                         marshall: bool = True, nthreads: int = 0):
+    """t-J local energy (Sec. 6.1) with the CNN1 amplitude, sign included."""
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_tj_cnn1_local_energy(L, t, J, Kb, C, _p(w, ctypes.c_double), int(marshall),
+                                        _p(s, ctypes.c_int8), B, _p(e, ctypes.c_double),
+                                        nthreads)
+    return e
+
+
 def cnn1_log_deriv(L: int, Kb: int, C: int, w, spins, nthreads: int = 0):
     s = _spins(spins, L)
     w = np.ascontiguousarray(w, np.float64)
@@ -419,3 +434,10 @@ def cnn1_vmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, n_iter: in
                 lambda w, s: cnn1_local_energy(L, J1, J2, Kb, C, w, s, marshall=marshall),
                 Kb, C, w, spins, n_iter, lr, lam, cg_iters, randoms,
                 oderiv=lambda w, s: cnn1_log_deriv(L, Kb, C, w, s))
+
+
+def tj_cnn1_mcmc(L: int, t: float, J: float, Kb: int, C: int, w, spins, rand_bond, rand_u):
+    """The t-J sampler (tj_mcmc) with the CNN1 amplitude."""
+    types = [0, 1] if (t != 0.0 or J != 0.0) else []
+    return _metropolis(L, types, Kb, C, w, spins, rand_bond, rand_u,
+                       lambda w_, s_: cnn1_log_psi(L, Kb, C, w_, s_)[0])

@@ -831,6 +831,46 @@ void oracle_cnn1_log_deriv(int L, int Kb, int C, const double *w, const int8_t *
     }
 }
 
+/* t-J local energy (Sec. 6.1, Eq. tJ) with the CNN1 amplitude: the terms of
+ * tj_connected, each weighted by psi(S')/psi(s) including the network's sign. */
+void oracle_tj_cnn1_local_energy(int L, double t, double J, int Kb, int C, const double *w,
+                                 int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                                 int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn1_bufs b;
+        cnn1_bufs_alloc(&b, L, C);
+        int8_t *work = (int8_t *)malloc((size_t)N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            const int8_t *sp = spins + s * N;
+            int m0;
+            double f0 = cnn1_amplitude(L, Kb, C, w, marshall, sp, &b, &m0);
+            double e = 0.0;
+            for (int bd = 0; bd < 4 * N; ++bd) {
+                int si, sj;
+                if (oracle_bond_sites(L, bd, &si, &sj) != 1) continue;
+                e += tj_diag_bond(J, sp[si], sp[sj]);
+                double h = tj_offdiag(t, J, sp, si, sj);
+                if (h == 0.0) continue;
+                memcpy(work, sp, (size_t)N);
+                work[si] = sp[sj];
+                work[sj] = sp[si];
+                int m1;
+                double f1 = cnn1_amplitude(L, Kb, C, w, marshall, work, &b, &m1);
+                e += h * (double)(m1 * m0) * exp(f1 - f0);
+            }
+            e_loc[s] = e;
+        }
+        free(work);
+        cnn1_bufs_free(&b);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Log-derivatives by reverse-mode chain rule                           */
 /* ------------------------------------------------------------------ */

@@ -131,6 +131,11 @@ void oracle_cnn1_local_energy(int L, double J1, double J2, int Kb, int C, const 
 void oracle_cnn1_log_deriv(int L, int Kb, int C, const double *w, const int8_t *spins,
                            int64_t B, double *O, int nthreads);
 
+/* t-J local energy [Sec. 6.1] with the CNN1 amplitude (its sign included). */
+void oracle_tj_cnn1_local_energy(int L, double t, double J, int Kb, int C, const double *w,
+                                 int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                                 int nthreads);
+
 /* Per-sample log-derivatives O[s][p] = d f(s) / d theta_p, FP64, by the
  * reverse-mode chain rule through the network.                          */
 void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,

@@ -52,8 +52,8 @@ constexpr int kMaxSites = 64 * 64;
 __global__ void __launch_bounds__(kThreads)
 k_energy_reduce_tj(const int8_t *__restrict__ spins, int L, const int64_t *__restrict__ offsets,
                    const uint32_t *__restrict__ queue, const double *__restrict__ dlog,
-                   const double *__restrict__ ediag, double t_hop, double J, int marshall,
-                   double *__restrict__ e_loc, int32_t *err)
+                   const int8_t *__restrict__ isign, const double *__restrict__ ediag,
+                   double t_hop, double J, int marshall, double *__restrict__ e_loc, int32_t *err)
 {
     __shared__ uint16_t pre[kMaxSites + 1];   // pre[k] = electrons on sites 0 .. k-1
     __shared__ int scan[kThreads];
@@ -99,6 +99,7 @@ k_energy_reduce_tj(const int8_t *__restrict__ spins, int L, const int64_t *__res
             // an up electron changes sublattice: Marshall ratio -1
             coef = (marshall && a + c > 0) ? -h : h;
         }
+        if (isign) coef *= (double)isign[q];      // the network's own sign ratio
         acc += coef * exp(dlog[q]);
     }
     red[threadIdx.x] = acc;
@@ -156,7 +157,7 @@ void launch_energy_reduce(const nqs_ctx *c, const int8_t *spins, int B, const in
     if (B <= 0) return;
     if (c->model == kModelTJ)
         NQS_LAUNCH(k_energy_reduce_tj, dim3(B), dim3(kThreads), 0, s, spins, c->L, offsets,
-                   queue, dlog, ediag, c->t_hop, c->J1, c->marshall, e_loc, err);
+                   queue, dlog, isign, ediag, c->t_hop, c->J1, c->marshall, e_loc, err);
     else
         NQS_LAUNCH(k_energy_reduce, dim3(B), dim3(kThreads), 0, s, offsets, queue, dlog,
                    isign, ediag, c->J1, c->J2, c->marshall, e_loc, err);

@@ -569,6 +569,14 @@ nqs_status nqs_create_cnn1(int32_t L, double J1, double J2, int32_t blocks, int3
     return create_ctx(L, kModelSpin, kNetCnn1, J1, J2, 0.0, &spec, weights, n_weights, out);
 }
 
+nqs_status nqs_create_cnn1_tj(int32_t L, double t, double J, int32_t blocks, int32_t channels,
+                              int32_t marshall_sign, const double *weights, int64_t n_weights,
+                              nqs_ctx **out)
+{
+    const nqs_cnn_spec spec{blocks, channels, marshall_sign, NQS_FP64};
+    return create_ctx(L, kModelTJ, kNetCnn1, J, 0.0, t, &spec, weights, n_weights, out);
+}
+
 nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
                          const double *weights, int64_t n_weights, nqs_ctx **out)
 {

@@ -61,6 +61,7 @@ def load():
         "nqs_create": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
         "nqs_create_tj": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
         "nqs_create_cnn1": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
+        "nqs_create_cnn1_tj": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_destroy": [vp],
         "nqs_num_params": [vp, P(i64)],
         "nqs_set_weights": [vp, vp, i64],
@@ -137,11 +138,18 @@ class Context:
         spec = CnnSpec(K, C, 1 if marshall_sign else 0, _DTYPES[dtype])
         h = ctypes.c_void_p()
         if net == "cnn1":
-            if dtype != "fp64" or tj_hop is not None:
-                raise ValueError("CNN1 contexts are FP64 spin-model contexts")
-            _check(lib.nqs_create_cnn1(L, J1, J2, K, C, 1 if marshall_sign else 0,
-                                       ctypes.c_void_p(w.data_ptr()), w.numel(),
-                                       ctypes.byref(h)), "nqs_create_cnn1")
+            if dtype != "fp64":
+                raise ValueError("CNN1 contexts are FP64")
+            if tj_hop is None:
+                _check(lib.nqs_create_cnn1(L, J1, J2, K, C, 1 if marshall_sign else 0,
+                                           ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                           ctypes.byref(h)), "nqs_create_cnn1")
+            else:
+                if J2 != 0.0:
+                    raise ValueError("t-J contexts have no next-nearest coupling")
+                _check(lib.nqs_create_cnn1_tj(L, tj_hop, J1, K, C, 1 if marshall_sign else 0,
+                                              ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                              ctypes.byref(h)), "nqs_create_cnn1_tj")
         elif tj_hop is None:
             _check(lib.nqs_create(L, J1, J2, ctypes.byref(spec), ctypes.c_void_p(w.data_ptr()),
                                   w.numel(), ctypes.byref(h)), "nqs_create")
@@ -161,6 +169,12 @@ class Context:
              marshall_sign: bool = True) -> "Context":
         """A CNN1 context (nqs_create_cnn1), FP64: `blocks` blocks of C channels."""
         return cls(L, J1, J2, blocks, C, weights, "fp64", marshall_sign, net="cnn1")
+
+    @classmethod
+    def cnn1_tj(cls, L: int, t: float, J: float, blocks: int, C: int, weights,
+                marshall_sign: bool = True) -> "Context":
+        """A t-J context with the CNN1 amplitude (nqs_create_cnn1_tj), FP64."""
+        return cls(L, J, 0.0, blocks, C, weights, "fp64", marshall_sign, tj_hop=t, net="cnn1")
 
     @classmethod
     def tj(cls, L: int, t: float, J: float, K: int, C: int, weights, dtype: str = "fp64",

@@ -125,4 +125,13 @@ def test_binding_rejects_cnn1_outside_fp64(lib):
     with pytest.raises(ValueError):
         nqs.Context(4, 1.0, 0.5, 2, 4, w, dtype="bf16", net="cnn1")
     with pytest.raises(ValueError):
-        nqs.Context(4, 1.0, 0.5, 2, 4, w, net="cnn1", tj_hop=1.0)
+        nqs.Context(4, 0.4, 0.5, 2, 4, w, net="cnn1", tj_hop=1.0)     # t-J has no J2
+
+
+def test_create_cnn1_tj_rejects_bad_arguments(lib):
+    buf = (ctypes.c_double * 2000)()
+    h = ctypes.c_void_p()
+    assert lib.nqs_create_cnn1_tj(5, 1.0, 0.4, 2, 4, 1, buf, 672, ctypes.byref(h)) == 2
+    assert lib.nqs_create_cnn1_tj(4, 1.0, 0.4, 2, 4, 1, buf, 671, ctypes.byref(h)) == 4
+    assert lib.nqs_create_cnn1_tj(4, float("inf"), 0.4, 2, 4, 1, buf, 672, ctypes.byref(h)) == 1
+    assert not h.value

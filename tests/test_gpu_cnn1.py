@@ -184,3 +184,65 @@ def test_cnn1_vmc_iteration_captured_in_graph():
     graph_replays_equal_eager(ctx, w, to_dev(inputs.spins_sz0(L, B, 132)), steps=4, lr=0.01,
                               diag_shift=1e-2, cg_iters=20, seed=133)
     assert ctx.get_error() == 0
+
+
+def test_cnn1_empty_batch():
+    L, Kb, C = 6, 2, 16
+    ctx = c1_ctx(L, Kb, C, smooth_weights(Kb, C, 0.1, 141))
+    empty = to_dev(np.zeros((0, L, L), np.int8))
+    assert ctx.local_energy(empty).numel() == 0
+    la, sg = ctx.log_psi(empty)
+    assert la.numel() == 0 and sg.numel() == 0
+    assert ctx.log_deriv(empty, dtype="fp64").shape == (0, ctx.P)
+    assert ctx.get_error() == 0
+
+
+# ---- t-J with the CNN1 amplitude (nqs_create_cnn1_tj): the network's sign
+# ---- enters every term with the Jordan-Wigner and Marshall signs
+
+@pytest.mark.parametrize("L,nh,Kb,C,sigma,ob,B", [(8, 8, 3, 16, 0.1, 1.0, 12),
+                                                  (6, 10, 2, 4, 0.3, 0.0, 24),
+                                                  (12, 18, 2, 16, 0.05, 1.0, 4)])
+def test_cnn1_tj_local_energy(L, nh, Kb, C, sigma, ob, B):
+    say("t-J cnn1 eloc", L, nh, Kb, C, B)
+    t, J = 1.0, 0.4
+    w = inputs.cnn1_weights(Kb, C, sigma, 151, out_bias=ob)
+    sp = inputs.spins_tj(L, B, nh, 152)
+    ctx = nqs.Context.cnn1_tj(L, t, J, Kb, C, w)
+    e = ctx.local_energy(to_dev(sp)).cpu().numpy()
+    ref = oracle.tj_cnn1_local_energy(L, t, J, Kb, C, w, sp)
+    say("  max rel", rel_inf(e, ref))
+    assert rel_inf(e, ref) <= 1e-10
+    assert ctx.get_error() == 0
+
+
+def test_cnn1_tj_rayleigh_quotient_against_ed():
+    L, Kb, C, t, J = 4, 2, 3, 1.0, 0.4
+    H, basis = ed.tj_hamiltonian(L, t, J, 2, 2)
+    w = inputs.cnn1_weights(Kb, C, 0.3, 61)
+    spins = ed.tj_modes_to_spins(basis, 16).reshape(-1, 4, 4)
+    ctx = nqs.Context.cnn1_tj(L, t, J, Kb, C, w)
+    la, sg = ctx.log_psi(to_dev(spins))
+    la, sg = la.cpu().numpy(), sg.cpu().numpy()
+    e = ctx.local_energy(to_dev(spins)).cpu().numpy()
+    psi = sg * np.exp(la - la.max())
+    lhs = np.sum(psi ** 2 * e) / np.sum(psi ** 2)
+    rhs = psi @ (H @ psi) / (psi @ psi)
+    say("t-J sector (2,2) with CNN1: <H> gpu", lhs, "ed", rhs)
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+    assert ctx.get_error() == 0
+
+
+def test_cnn1_tj_mcmc_equals_oracle():
+    L, Kb, C, B, T = 6, 2, 3, 32, 20
+    w = inputs.cnn1_weights(Kb, C, 0.3, 161)
+    sp = inputs.spins_tj(L, B, 4, 162)
+    rb, ru = inputs.mcmc_randoms(163, 0, T, B)
+    ctx = nqs.Context.cnn1_tj(L, 1.0, 0.4, Kb, C, w)
+    d = to_dev(sp)
+    acc = ctx.mcmc(d, torch.tensor(rb, device=DEV), torch.tensor(ru, device=DEV))
+    ref, racc = oracle.tj_cnn1_mcmc(L, 1.0, 0.4, Kb, C, w, sp, rb, ru)
+    say("accepted", int(acc.sum()), "of", B * T)
+    assert np.array_equal(d.cpu().numpy(), ref)
+    assert np.array_equal(acc.cpu().numpy(), racc)
+    assert ctx.get_error() == 0

@@ -258,3 +258,23 @@ def test_tj_vmc_iteration_captured_in_graph():
                               diag_shift=1e-2, cg_iters=20, seed=143, o_dtype="fp32",
                                mode="incremental")
     assert ctx.get_error() == 0
+
+
+def test_tj_empty_batch_and_extremes():
+    L, K, C = 8, 2, 4
+    w = inputs.weights(K, C, 0.1, 151)
+    ctx = tj_ctx(L, K, C, w)
+    empty = to_dev(np.zeros((0, L, L), np.int8))
+    counts, offs, bonds, mu, e_diag = ctx.connected(empty)
+    assert offs.cpu().tolist() == [0]
+    assert ctx.local_energy(empty).numel() == 0
+    # all holes: no term at all; a single electron: only hops, no diagonal part
+    sp = np.zeros((2, L, L), np.int8)
+    sp[1, 3, 4] = 1
+    counts, offs, bonds, mu, e_diag = ctx.connected(to_dev(sp))
+    assert counts.cpu().tolist() == [0, 4]
+    assert e_diag.cpu().tolist() == [0.0, 0.0]
+    e = ctx.local_energy(to_dev(sp), mode="full").cpu().numpy()
+    ref = oracle.tj_local_energy(L, T_HOP, J_EX, K, C, w, sp)
+    assert e[0] == 0.0 and e[1] == pytest.approx(ref[1], rel=1e-12)
+    assert ctx.get_error() == 0

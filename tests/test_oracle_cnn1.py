@@ -130,3 +130,20 @@ def test_cnn1_mcmc_conserves_sz_and_is_reproducible(orc):
     assert 0 < acc.sum() < B * T
     out2, acc2 = orc.cnn1_mcmc(L, 1.0, 0.5, Kb, C, w, sp, rb, ru)
     assert np.array_equal(out, out2) and np.array_equal(acc, acc2)
+
+
+@pytest.mark.parametrize("marshall", [True, False])
+def test_tj_rayleigh_quotient_with_cnn1_sign(orc, marshall):
+    """The t-J local energy with the signed CNN1 amplitude, summed over the
+    whole 4x4 sector of two up and two down electrons, equals <psi|H|psi> /
+    <psi|psi> with H from the fermion-operator exact diagonalisation."""
+    L, Kb, C, t, J = 4, 2, 3, 1.0, 0.4
+    H, basis = ed.tj_hamiltonian(L, t, J, 2, 2)
+    w = inputs.cnn1_weights(Kb, C, 0.3, 61)
+    spins = ed.tj_modes_to_spins(basis, 16).reshape(-1, 4, 4)
+    la, sg = orc.cnn1_log_psi(L, Kb, C, w, spins, marshall=marshall)
+    psi = sg * np.exp(la - la.max())
+    e = orc.tj_cnn1_local_energy(L, t, J, Kb, C, w, spins, marshall=marshall)
+    lhs = np.sum(psi ** 2 * e) / np.sum(psi ** 2)
+    rhs = psi @ (H @ psi) / (psi @ psi)
+    assert lhs == pytest.approx(rhs, rel=1e-10)
