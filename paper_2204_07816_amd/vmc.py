@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import inputs
-from .nqs import Context
+from .nqs import Context, NqsError
 
 
 class VMC:
@@ -63,6 +63,11 @@ class VMC:
         ctx.update_weights(self.x, -self.lr)
 
     def stats(self) -> dict:
+        """The iteration's energy statistics; raises NqsError when the device
+        flagged an error (a non-finite local energy, say a diverged update)."""
+        code = self.ctx.get_error()
+        if code:
+            raise NqsError(code, "VMC iteration")
         st2, st4 = self.st2.cpu().numpy(), self.st4.cpu().numpy()
         return {"energy": float(st2[0]), "variance": float(st2[1]),
                 "acceptance": float(self.acc.sum().item()) / (self.B * max(self.steps, 1)),

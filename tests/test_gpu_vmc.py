@@ -129,3 +129,18 @@ def test_vmc_iteration_captured_in_graph():
     assert np.array_equal(run.weights, w_eager)
     assert torch.equal(run.spins, s_eager)
     del g
+
+
+def test_vmc_raises_on_non_finite_energy():
+    """Weights large enough that psi(S')/psi(S) overflows: the device flags a
+    non-finite local energy and the loop reports it instead of going on."""
+    L, J2, K, C, B = 4, 0.0, 2, 4, 64
+    w = inputs.stress_weights(K, C, 1.0, 81) * 400.0
+    ctx = make_ctx(L, J2, K, C, w)
+    run = VMC(ctx, to_dev(inputs.spins_sz0(L, B, 82)), steps=2, lr=0.01, diag_shift=1e-2,
+              cg_iters=10, seed=83)
+    from paper_2204_07816_amd.nqs import NqsError
+    with pytest.raises(NqsError) as info:
+        run.step()
+    assert info.value.code == 6          # NQS_E_NONFINITE
+    assert ctx.get_error() == 0          # read and cleared by the loop
