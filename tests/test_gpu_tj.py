@@ -278,3 +278,39 @@ def test_tj_empty_batch_and_extremes():
     ref = oracle.tj_local_energy(L, T_HOP, J_EX, K, C, w, sp)
     assert e[0] == 0.0 and e[1] == pytest.approx(ref[1], rel=1e-12)
     assert ctx.get_error() == 0
+
+
+def test_tj_mcmc_stationary_mean_energy_4x4():
+    """Chains of hops and exchanges sample |psi|^2: on the 4x4 sector of two up
+    and two down electrons (10,920 configurations) chains started together in
+    the least probable configuration reach a mean local energy within 5
+    standard errors of the exact |psi|^2-weighted mean.  (Weights with
+    log|psi| spanning 5.8; at a span of 15 the mass sits on ~20 states and
+    1600 steps at 2% acceptance do not mix, for the oracle's sampler too.)"""
+    L, K, C = 4, 2, 4
+    w = inputs.weights(K, C, 0.4, 11)
+    ctx = tj_ctx(L, K, C, w)
+    H, basis = ed.tj_hamiltonian(L, T_HOP, J_EX, 2, 2)
+    sector = ed.tj_modes_to_spins(basis, L * L).reshape(-1, L, L)
+    allsp = to_dev(sector)
+    la = ctx.log_psi(allsp)[0].cpu().numpy()
+    e_all = ctx.local_energy(allsp, mode="full").cpu().numpy()
+    p = np.exp(2 * (la - la.max()))
+    p /= p.sum()
+    exact = float(p @ e_all)
+    B, T = 2048, 1600
+    sp = np.repeat(sector[np.argmin(la)][None], B, axis=0)
+    rb, ru = _rand(T, B, 172)
+    d = to_dev(sp)
+    acc = ctx.mcmc(d, torch.tensor(rb, device=DEV), torch.tensor(ru, device=DEV))
+    e = ctx.local_energy(d, mode="full").cpu().numpy()
+    se = e.std(ddof=1) / np.sqrt(B)
+    e0 = float(e_all[np.argmin(la)])
+    say("ptp log psi", np.ptp(la), "exact", exact, "mcmc", e.mean(), "+-", se, "start", e0,
+        "acceptance", float(acc.float().mean()) / T)
+    assert abs(e.mean() - exact) < 5 * se
+    assert abs(e0 - exact) > 10 * se
+    out = d.cpu().numpy()
+    for v in (1, -1, 0):
+        assert np.array_equal((out == v).sum(axis=(1, 2)), (sp == v).sum(axis=(1, 2)))
+    assert ctx.get_error() == 0
