@@ -238,7 +238,8 @@ nqs_status nqs_sr_solve_recompute(nqs_ctx *ctx, const int8_t *spins,
  * (int64 [B+1]), the bond ids in canonical order and the Marshall ratio
  * mu = M(S')/M(s) of each (int32 / int8 [capacity]), and the diagonal energy
  * (FP64 [B]).  capacity must be >= the number of bonds with J != 0 times B
- * (4*L*L*B when J2 != 0).  Lists are bit-exact and deterministic.         */
+ * (4*L*L*B when J2 != 0; t-J contexts: 2*L*L*B when t or J != 0).  Lists
+ * are bit-exact and deterministic.                                          */
 nqs_status nqs_connected(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                          int32_t *counts, int64_t *offsets, int32_t *bond_ids,
                          int8_t *mu, int64_t capacity, double *e_diag,
