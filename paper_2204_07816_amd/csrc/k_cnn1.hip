@@ -22,7 +22,12 @@
 //   block 1: [9][16][16] transposed taps, [16] bias (2320 doubles);
 //   block k >= 2: [9][16][32] convolution taps, column 16 h + j holding
 //   channel 2 j + h, [32] its bias in the same column order, then the
-//   transposed part as for block 1 (6960 doubles).
+//   transposed part as for block 1 (6960 doubles);
+// then for the backward's data gradients, also convolutions on the matrix
+// cores: per block [9][16][16] taps V[ci][co][t] read as [t][co][ci] (the
+// gradient through the transposed convolution), then per block k >= 2
+// [9][32][16] taps W[co][ci][8 - t] read as [t][co][ci] (the gradient
+// through the convolution).
 //
 // Planes are NHWC ([plane][site][channel]) in HBM.  The forward serves the
 // samples (base planes) and the exchanged configurations of the local
@@ -309,6 +314,23 @@ k_c1_gmax(int nb, int L, int C, const double *__restrict__ g, const double *__re
     }
 }
 
+// the max's routing of dL/dm (gm [nb][N][C], computed on the matrix cores)
+// into dL/dz: gz[q][2ci + a] = gm for the larger input a (first on a tie)
+__global__ void __launch_bounds__(kThreads)
+k_c1_route(int64_t n, int C, const double *__restrict__ gm, const double *__restrict__ z,
+           double *__restrict__ gz)
+{
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < n;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int ci = (int)(id % C);
+        const int64_t bq = id / C;
+        const double z0 = z[bq * 2 * C + 2 * ci], z1 = z[bq * 2 * C + 2 * ci + 1];
+        const bool second = z1 > z0;
+        gz[bq * 2 * C + 2 * ci] = second ? 0.0 : gm[id];
+        gz[bq * 2 * C + 2 * ci + 1] = second ? gm[id] : 0.0;
+    }
+}
+
 // dL/dh of the convolution: gh[q][ci] = sum_{co,t} W[co][ci][t] gz[q - off t][co]
 __global__ void __launch_bounds__(kThreads)
 k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__restrict__ W,
@@ -345,12 +367,48 @@ constexpr int kPackFirst = kConvT + kMC;                          // packed bloc
 constexpr int kPackBlock = kBlockK;         // packed block k >= 2: same count, reordered
 static_assert(kBlock1 == 2640 && kPackFirst == 2320 && kPackBlock == 6960, "packing sizes");
 
+// offsets of block k's canonical V and W (c_in = 1 for k = 0, else 16)
+__host__ __device__ inline int64_t canon_V(int k)
+{
+    return k == 0 ? kConv1 + 2 * kMC : kBlock1 + (int64_t)(k - 1) * kBlockK + kConvK + 2 * kMC;
+}
+__host__ __device__ inline int64_t canon_W(int k) { return kBlock1 + (int64_t)(k - 1) * kBlockK; }
+__host__ __device__ inline int64_t fwd_pack_size(int Kb)
+{
+    return kPackFirst + (int64_t)(Kb - 1) * kPackBlock;
+}
+// backward packing: gradient through V of block k, and through W of block k >= 1
+__host__ __device__ inline int64_t bwd_gm_off(int Kb, int k) { return fwd_pack_size(Kb) + (int64_t)k * kConvT; }
+__host__ __device__ inline int64_t bwd_gd_off(int Kb, int k)
+{
+    return fwd_pack_size(Kb) + (int64_t)Kb * kConvT + (int64_t)(k - 1) * kConvK;
+}
+
+// backward packing entry q (0 <= q < Kb kConvT + (Kb - 1) kConvK)
+__device__ inline double bwd_pack_value(const double *w, int Kb, int64_t q)
+{
+    if (q < (int64_t)Kb * kConvT) {
+        const int k = (int)(q / kConvT), r = (int)(q - (int64_t)k * kConvT);
+        const int ci = r % kMC, co = (r / kMC) % kMC, t = r / (kMC * kMC);
+        return w[canon_V(k) + ((int64_t)ci * kMC + co) * 9 + t];
+    }
+    q -= (int64_t)Kb * kConvT;
+    const int k = 1 + (int)(q / kConvK), r = (int)(q - (int64_t)(k - 1) * kConvK);
+    const int ci = r % kMC, co = (r / kMC) % (2 * kMC), t = r / (2 * kMC * kMC);
+    return w[canon_W(k) + ((int64_t)co * kMC + ci) * 9 + (8 - t)];
+}
+
 __global__ void k_c1_pack(const double *__restrict__ w, int Kb, double *__restrict__ out)
 {
-    const int64_t n = kPackFirst + (int64_t)(Kb - 1) * kPackBlock;
+    const int64_t nf = fwd_pack_size(Kb);
+    const int64_t n = nf + (int64_t)Kb * kConvT + (int64_t)(Kb - 1) * kConvK;
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * kThreads) {
         double val;
+        if (q >= nf) {
+            out[q] = bwd_pack_value(w, Kb, q - nf);
+            continue;
+        }
         if (q < kPackFirst) {
             // block 1: canonical W at 0, a at kConv1, V, then v
             const int64_t V = kConv1 + 2 * kMC, v = V + kConvT;
@@ -482,13 +540,15 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
 
 size_t cnn1_packed_doubles(const nqs_ctx *c)
 {
-    return mfma_blocks(c) ? (size_t)kPackFirst + (size_t)(c->K - 1) * kPackBlock : 0;
+    return mfma_blocks(c) ? (size_t)(fwd_pack_size(c->K) + (int64_t)c->K * kConvT +
+                                     (int64_t)(c->K - 1) * kConvK)
+                          : 0;
 }
 
 void cnn1_pack_device(const nqs_ctx *c, hipStream_t s)
 {
     if (!mfma_blocks(c)) return;
-    const int64_t n = kPackFirst + (int64_t)(c->K - 1) * kPackBlock;
+    const int64_t n = (int64_t)cnn1_packed_doubles(c);
     NQS_LAUNCH(k_c1_pack, dim3(grid_of(c, n)), dim3(kThreads), 0, s,
                (const double *)c->w_canon, c->K, c->w_vec64);
 }
@@ -528,8 +588,15 @@ void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsav
                        1, C, C, (const double *)g, zk, (const double *)nullptr, spins, o.V, o.v,
                        c->P, (double *)O);
         }
-        NQS_LAUNCH(k_c1_gmax, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
-                   (const double *)g, w + o.V, zk, gz);
+        if (mfma_blocks(c)) {
+            // dL/dm = V-convolution of g on the matrix cores (into mbuf), then the max
+            f64mma_cnn1_plain(c, g, nb, kMC, c->w_vec64 + bwd_gm_off(K, k), mbuf, s);
+            NQS_LAUNCH(k_c1_route, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, plane, C,
+                       (const double *)mbuf, zk, gz);
+        } else {
+            NQS_LAUNCH(k_c1_gmax, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
+                       (const double *)g, w + o.V, zk, gz);
+        }
         if (odt == NQS_FP32) {
             NQS_LAUNCH(k_c1_wgrad<float>, dim3(grid_of(c, wc)), dim3(kThreads), 0, s, nb, L, C,
                        0, 2 * C, o.cin, (const double *)gz, (const double *)nullptr, hk, spins,
@@ -540,8 +607,11 @@ void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsav
                        o.W, o.a, c->P, (double *)O);
         }
         if (k > 0) {
-            NQS_LAUNCH(k_c1_gdata, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
-                       (const double *)gz, w + o.W, gh);
+            if (mfma_blocks(c))
+                f64mma_cnn1_plain(c, gz, nb, 2 * kMC, c->w_vec64 + bwd_gd_off(K, k), gh, s);
+            else
+                NQS_LAUNCH(k_c1_gdata, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
+                           (const double *)gz, w + o.W, gh);
             std::swap(g, gh);
         }
     }

@@ -334,6 +334,18 @@ void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const doub
     NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
 }
 
+// plain convolution Cin (16 or 32) -> 16 with no bias and no activation
+// (the data gradients of the CNN1 backward)
+void f64mma_cnn1_plain(const nqs_ctx *c, const double *in, int64_t M, int Cin, const double *w,
+                       double *out, hipStream_t s)
+{
+    if (M <= 0) return;
+    ConvArgs a{in, w, nullptr, out, nullptr, nullptr, 0, M, c->L, Cin, 0};
+    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
+    NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
 bool f64mma_wgrad_ok(int C) { return C == 16 || C == 32; }
 
 void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,

@@ -273,6 +273,8 @@ void f64mma_cnn1_conv(const nqs_ctx *c, const double *in, int64_t M, const doubl
 void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const double *w,
                        const double *bias, double *out, const int64_t *qlen, int64_t q_begin,
                        hipStream_t s);
+void f64mma_cnn1_plain(const nqs_ctx *c, const double *in, int64_t M, int Cin, const double *w,
+                       double *out, hipStream_t s);
 size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c);
 // O rows of nb samples; zsave: K*2*nb*N*C, usave: K*nb*N*C, work: 5*nb*N*C doubles
 void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
