@@ -31,6 +31,7 @@ CFLAGS = [
 # extra flags per source file
 FILE_FLAGS = {
     "k_conv_f64mma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "k_cnn1.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

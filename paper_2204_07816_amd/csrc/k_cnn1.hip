@@ -47,7 +47,20 @@ namespace {
 
 constexpr int kThreads = 256;
 
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
 __device__ inline int wrapc(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
+
+// canonical sizes with 16 channels
+constexpr int kMC = 16;
+constexpr int kConvT = kMC * kMC * 9;                  // V: 2304
+constexpr int kConv1 = 2 * kMC * 9;                    // W of block 1 (c_in = 1): 288
+constexpr int kConvK = 2 * kMC * kMC * 9;              // W of blocks 2..: 4608
+constexpr int kBlock1 = kConv1 + 2 * kMC + kConvT + kMC;          // 2640
+constexpr int kBlockK = kConvK + 2 * kMC + kConvT + kMC;          // blocks 2..: 6960
+constexpr int kPackFirst = kConvT + kMC;                          // packed block 1: 2320
+constexpr int kPackBlock = kBlockK;         // packed block k >= 2: same count, reordered
+static_assert(kBlock1 == 2640 && kPackFirst == 2320 && kPackBlock == 6960, "packing sizes");
 
 // offsets of block k's parameters in the canonical vector
 struct Cnn1Block {
@@ -314,6 +327,92 @@ k_c1_gmax(int nb, int L, int C, const double *__restrict__ g, const double *__re
     }
 }
 
+// Weight and bias gradients of blocks 2.. with 16 channels on the FP64 matrix
+// cores, per sample: a GEMM over the sites (K, steps of 4) with rows = output
+// channels co (A = the gradient at the block's output, 16 per tile) and
+// columns = (tap t, input channel ci), one 16-column tile per tap.
+//   TRANS = false (convolution 16 -> 32): rows gz[p][co] (2 tiles),
+//     columns h[p + off t][ci]; dW[co][ci][t] at offw, da[co] at offb;
+//   TRANS = true (transposed convolution): rows g[p][co] (1 tile), columns
+//     m[p - off t][ci] with m = max(z[2ci], z[2ci+1]) re-formed from the
+//     saved z; dV[ci][co][t] at offw, dv[co] at offb.
+// One wave per (sample, 3 taps); three waves per sample.  Fixed summation
+// order, so rows are deterministic.
+template <typename OT, bool TRANS>
+__global__ void __launch_bounds__(kThreads)
+k_c1_wgrad_mma(int nb, int L, const double *__restrict__ grad, const double *__restrict__ src,
+               int64_t offw, int64_t offb, int64_t P, OT *__restrict__ O)
+{
+    constexpr int NH = TRANS ? 1 : 2;           // 16-row tiles of output channels
+    constexpr int NCO = 16 * NH;
+    constexpr int NT = 3;                       // taps per wave
+    const int N = L * L;
+    const int lane = threadIdx.x & 63;
+    const int m16 = lane & 15, kq = lane >> 4;
+    const int64_t wave_id = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t b = wave_id / 3;
+    if (b >= nb) return;
+    const int t0 = (int)(wave_id - b * 3) * NT;
+    const double *gb = grad + b * (int64_t)N * NCO;
+    const double *sb = src + b * (int64_t)N * (TRANS ? 2 * kMC : kMC);
+    const int sg = TRANS ? -1 : 1;
+    double4_t acc[NH][NT];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[h][j] = (double4_t){0, 0, 0, 0};
+    double dbp[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) dbp[h] = 0.0;
+    for (int p0 = 0; p0 < N; p0 += 4) {
+        const int p = p0 + kq, y = p / L, x = p - (p / L) * L;
+        double av[NH], bv[NT];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) av[h] = gb[(int64_t)p * NCO + 16 * h + m16];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int t = t0 + j;
+            const int r = wrapc(y + sg * (t / 3 - 1), L) * L + wrapc(x + sg * (t % 3 - 1), L);
+            if (TRANS) {
+                const double z0 = sb[(int64_t)r * 2 * kMC + 2 * m16];
+                const double z1 = sb[(int64_t)r * 2 * kMC + 2 * m16 + 1];
+                bv[j] = (z1 > z0) ? z1 : z0;
+            } else {
+                bv[j] = sb[(int64_t)r * kMC + m16];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            dbp[h] += av[h];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[j], acc[h][j], 0, 0, 0);
+        }
+    }
+    OT *o = O + b * P;
+    // D element i of this lane: row co = 16 h + kq + 4 i, column ci = m16 at tap t0 + j
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = 16 * h + kq + 4 * i, ci = m16, t = t0 + j;
+                const int64_t idx = TRANS ? ((int64_t)ci * kMC + co) * 9 + t
+                                          : ((int64_t)co * kMC + ci) * 9 + t;
+                o[offw + idx] = (OT)acc[h][j][i];
+            }
+    if (t0 == 0) {
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            double v = dbp[h];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (kq == 0) o[offb + 16 * h + m16] = (OT)v;
+        }
+    }
+}
+
 // the max's routing of dL/dm (gm [nb][N][C], computed on the matrix cores)
 // into dL/dz: gz[q][2ci + a] = gm for the larger input a (first on a tie)
 __global__ void __launch_bounds__(kThreads)
@@ -356,16 +455,6 @@ k_c1_gdata(int nb, int L, int C, const double *__restrict__ gz, const double *__
     }
 }
 
-// canonical sizes with 16 channels
-constexpr int kMC = 16;
-constexpr int kConvT = kMC * kMC * 9;                  // V: 2304
-constexpr int kConv1 = 2 * kMC * 9;                    // W of block 1 (c_in = 1): 288
-constexpr int kConvK = 2 * kMC * kMC * 9;              // W of blocks 2..: 4608
-constexpr int kBlock1 = kConv1 + 2 * kMC + kConvT + kMC;          // 2640
-constexpr int kBlockK = kConvK + 2 * kMC + kConvT + kMC;          // blocks 2..: 6960
-constexpr int kPackFirst = kConvT + kMC;                          // packed block 1: 2320
-constexpr int kPackBlock = kBlockK;         // packed block k >= 2: same count, reordered
-static_assert(kBlock1 == 2640 && kPackFirst == 2320 && kPackBlock == 6960, "packing sizes");
 
 // offsets of block k's canonical V and W (c_in = 1 for k = 0, else 16)
 __host__ __device__ inline int64_t canon_V(int k)
@@ -579,7 +668,15 @@ void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsav
         const double *hk = k == 0 ? nullptr : usave + (int64_t)(k - 1) * plane;
         const int64_t wt = (int64_t)nb * (C * C * 9 + C);
         const int64_t wc = (int64_t)nb * (2 * C * o.cin * 9 + 2 * C);
-        if (odt == NQS_FP32) {
+        const dim3 gmm((unsigned)(((int64_t)nb * 3 + kThreads / 64 - 1) / (kThreads / 64)));
+        if (mfma_blocks(c)) {
+            if (odt == NQS_FP32)
+                NQS_LAUNCH((k_c1_wgrad_mma<float, true>), gmm, dim3(kThreads), 0, s, nb, L,
+                           (const double *)g, zk, o.V, o.v, c->P, (float *)O);
+            else
+                NQS_LAUNCH((k_c1_wgrad_mma<double, true>), gmm, dim3(kThreads), 0, s, nb, L,
+                           (const double *)g, zk, o.V, o.v, c->P, (double *)O);
+        } else if (odt == NQS_FP32) {
             NQS_LAUNCH(k_c1_wgrad<float>, dim3(grid_of(c, wt)), dim3(kThreads), 0, s, nb, L, C,
                        1, C, C, (const double *)g, zk, (const double *)nullptr, spins, o.V, o.v,
                        c->P, (float *)O);
@@ -597,7 +694,14 @@ void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsav
             NQS_LAUNCH(k_c1_gmax, dim3(grid_of(c, plane)), dim3(kThreads), 0, s, nb, L, C,
                        (const double *)g, w + o.V, zk, gz);
         }
-        if (odt == NQS_FP32) {
+        if (mfma_blocks(c) && k > 0) {
+            if (odt == NQS_FP32)
+                NQS_LAUNCH((k_c1_wgrad_mma<float, false>), gmm, dim3(kThreads), 0, s, nb, L,
+                           (const double *)gz, hk, o.W, o.a, c->P, (float *)O);
+            else
+                NQS_LAUNCH((k_c1_wgrad_mma<double, false>), gmm, dim3(kThreads), 0, s, nb, L,
+                           (const double *)gz, hk, o.W, o.a, c->P, (double *)O);
+        } else if (odt == NQS_FP32) {
             NQS_LAUNCH(k_c1_wgrad<float>, dim3(grid_of(c, wc)), dim3(kThreads), 0, s, nb, L, C,
                        0, 2 * C, o.cin, (const double *)gz, (const double *)nullptr, hk, spins,
                        o.W, o.a, c->P, (float *)O);
