@@ -115,6 +115,53 @@ __device__ inline void c1_origin(const C1Planes &pm, int64_t m, int L, int *s, i
     *qj = wrapc(y + bond_dy(t), L) * L + wrapc(x + bond_dx(t), L);
 }
 
+// Convolution and max-pool of the first block (one input channel, the
+// spins) with 16 channels: thread (plane, site) reads its 9 spins once and
+// forms all 32 z and 16 pooled m; the taps and biases sit in LDS.  Same
+// arithmetic order per output as k_c1_conv (bias, then taps 0..8).
+__global__ void __launch_bounds__(kThreads)
+k_c1_conv_first(const int8_t *__restrict__ spins, C1Planes pm, int64_t M, int L,
+                const double *__restrict__ W, const double *__restrict__ a,
+                double *__restrict__ mout, double *__restrict__ zsave)
+{
+    __shared__ double ws[2 * kMC * 9], as[2 * kMC];
+    for (int q = threadIdx.x; q < 2 * kMC * 9; q += kThreads) ws[q] = W[q];
+    for (int q = threadIdx.x; q < 2 * kMC; q += kThreads) as[q] = a[q];
+    __syncthreads();
+    const int N = L * L;
+    const int64_t total = c1_live(pm, M) * N;
+    for (int64_t mp = (int64_t)blockIdx.x * kThreads + threadIdx.x; mp < total;
+         mp += (int64_t)gridDim.x * kThreads) {
+        const int64_t m = mp / N;
+        const int p = (int)(mp - m * N);
+        const int x = p % L, y = p / L;
+        int s, qi, qj;
+        c1_origin(pm, m, L, &s, &qi, &qj);
+        const int8_t *sp = spins + (int64_t)s * N;
+        double h[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            int q = wrapc(y + t / 3 - 1, L) * L + wrapc(x + t % 3 - 1, L);
+            q = (q == qi) ? qj : ((q == qj) ? qi : q);
+            h[t] = (double)sp[q];
+        }
+#pragma unroll 4
+        for (int c = 0; c < kMC; ++c) {
+            double z0 = as[2 * c], z1 = as[2 * c + 1];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                z0 = fma(ws[(2 * c) * 9 + t], h[t], z0);
+                z1 = fma(ws[(2 * c + 1) * 9 + t], h[t], z1);
+            }
+            mout[mp * kMC + c] = (z1 > z0) ? z1 : z0;
+            if (zsave) {
+                zsave[mp * 2 * kMC + 2 * c] = z0;
+                zsave[mp * 2 * kMC + 2 * c + 1] = z1;
+            }
+        }
+    }
+}
+
 // Convolution and max-pool of one block: thread (plane, site, c) forms
 // z[2c], z[2c+1] and m[c].  in: [M][N][cin] (null: the spins of the plane).
 __global__ void __launch_bounds__(kThreads)
@@ -560,9 +607,14 @@ void block_forward(const nqs_ctx *c, int k, const int8_t *spins, C1Planes pm, in
         const double *pk = pt - (kConvK + 2 * kMC);
         f64mma_cnn1_conv(c, h, M, pk, pk + kConvK, mbuf, zsave, pm.qlen, pm.q_begin, s);
     } else {
-        NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L, C,
-                   o.cin, h, (const double *)c->w_canon + o.W, (const double *)c->w_canon + o.a,
-                   mbuf, zsave);
+        if (k == 0 && mm)
+            NQS_LAUNCH(k_c1_conv_first, dim3(grid_of(c, M * c->N)), dim3(kThreads), 0, s, spins,
+                       pm, M, L, (const double *)c->w_canon + o.W,
+                       (const double *)c->w_canon + o.a, mbuf, zsave);
+        else
+            NQS_LAUNCH(k_c1_conv, dim3(grid_of(c, work)), dim3(kThreads), 0, s, spins, pm, M, L,
+                       C, o.cin, h, (const double *)c->w_canon + o.W,
+                       (const double *)c->w_canon + o.a, mbuf, zsave);
     }
     if (mm) {
         f64mma_cnn1_convt(c, mbuf, M, pt, pt + kConvT, u, pm.qlen, pm.q_begin, s);
