@@ -266,3 +266,23 @@ def test_cnn1_vmc_reaches_exact_ground_energy_4x4(J2, tol):
     say("J2", J2, "first", e[0], "last 20 mean", tail, "ED", E0, "rel", (tail - E0) / abs(E0))
     assert abs(tail - E0) < tol * abs(E0)
     assert ctx.get_error() == 0
+
+
+@pytest.mark.parametrize("model", ["spin", "tj"])
+def test_cnn1_local_energy_without_marshall_sign(model):
+    """psi = the neuron product alone (marshall_sign = 0): only the network's
+    sign ratio weights the terms, in the spin and the t-J reductions."""
+    L, Kb, C, B = 6, 2, 16, 16
+    w = inputs.cnn1_weights(Kb, C, 0.2, 181, out_bias=1.0)
+    if model == "spin":
+        sp = inputs.spins_sz0(L, B, 182)
+        ctx = nqs.Context.cnn1(L, 1.0, 0.5, Kb, C, w, marshall_sign=False)
+        ref = oracle.cnn1_local_energy(L, 1.0, 0.5, Kb, C, w, sp, marshall=False)
+    else:
+        sp = inputs.spins_tj(L, B, 6, 182)
+        ctx = nqs.Context.cnn1_tj(L, 1.0, 0.4, Kb, C, w, marshall_sign=False)
+        ref = oracle.tj_cnn1_local_energy(L, 1.0, 0.4, Kb, C, w, sp, marshall=False)
+    e = ctx.local_energy(to_dev(sp)).cpu().numpy()
+    say(model, "no Marshall: max rel", rel_inf(e, ref))
+    assert rel_inf(e, ref) <= 1e-10
+    assert ctx.get_error() == 0
