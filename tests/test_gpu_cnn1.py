@@ -90,7 +90,7 @@ def test_cnn1_rayleigh_quotient_against_ed():
 
 @pytest.mark.parametrize("L,Kb,C,sigma,ob,B", [(4, 2, 4, 0.3, 0.0, 16), (6, 3, 3, 0.5, 0.0, 8),
                                                (10, 6, 8, 0.2, 0.0, 4), (8, 3, 16, 0.2, 0.0, 4),
-                                               (10, 6, 16, 0.1, 1.0, 3)])
+                                               (10, 6, 16, 0.1, 1.0, 3), (6, 1, 16, 0.3, 0.0, 5)])
 def test_cnn1_log_deriv(L, Kb, C, sigma, ob, B):
     say("log_deriv cnn1", L, Kb, C, B)
     w = inputs.cnn1_weights(Kb, C, sigma, 81, out_bias=ob)
