@@ -38,6 +38,7 @@ using mf::floatx4;
 using mf::Shape;
 
 constexpr int kNW = 4;
+constexpr int kXcd = 8;          // XCDs; workgroup b runs on XCD b % kXcd
 constexpr int kThreads = kNW * 64;
 constexpr int kRingRegs = 2;
 
@@ -324,10 +325,17 @@ k_net_inc(IncJobs jobs)
         for (int j = 1; j < kMaxConnJobs; ++j) jb = (u >= first[j]) ? j : jb;
         return jb;
     };
+    // XCD-contiguous ranges of the queue: consecutive items (mostly of one
+    // sample) stay on one XCD, whose L2 then serves that sample's cache
+    const int per_xcd = gridDim.x / kXcd;
+    const int xcd = blockIdx.x % kXcd, slot = blockIdx.x / kXcd;
+    const int64_t seg = (n_units + kXcd - 1) / kXcd;
+    const int64_t u_end = min(n_units, (xcd + 1) * seg);
     bf16x8 wa[S::KS][S::NH];
-    if (blockIdx.x < n_units) load_weights<C>(wa, jobs.job[job_of(blockIdx.x)].wa, lane);   // layer 2
+    if (xcd * seg + slot < u_end)                                                 // layer 2
+        load_weights<C>(wa, jobs.job[job_of(xcd * seg + slot)].wa, lane);
 
-    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
         const int jb = job_of(u);
         const IncParams &prm = jobs.job[jb];
         const int64_t unit = u - first[jb];
@@ -412,8 +420,8 @@ k_net_inc(IncJobs jobs)
             // may differ)
             if (!last)
                 load_weights<C>(wa, prm.wa + (int64_t)(k - 1) * wl_stride, lane);
-            else if (u + gridDim.x < n_units)
-                load_weights<C>(wa, jobs.job[job_of(u + gridDim.x)].wa, lane);
+            else if (u + per_xcd < u_end)
+                load_weights<C>(wa, jobs.job[job_of(u + per_xcd)].wa, lane);
             if (!last) ring_store<C>(ring, nxt, prm, roff[k - 1], roff[k], ax, ay,
                                      cache_s + (int64_t)(k - 1) * N * C);
             __syncthreads();
@@ -527,7 +535,8 @@ void mfma_inc_forward_jobs(const ConnJob *jobs, int n, hipStream_t s)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int64_t want = std::min<int64_t>(total_cap, (int64_t)jobs[0].c->n_cu * per_cu);
+    // persistent grid of resident workgroups, a multiple of the XCD count
+    const int64_t want = std::max<int64_t>((int64_t)jobs[0].c->n_cu * per_cu / kXcd * kXcd, kXcd);
     if (C == 32)
         NQS_LAUNCH((k_net_inc<32>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
     else
