@@ -176,6 +176,15 @@ nqs_status nqs_set_weights(nqs_ctx *ctx, const double *weights, int64_t n);
 nqs_status nqs_update_weights(nqs_ctx *ctx, const double *dtheta, double scale,
                               void *stream);
 
+/* Set the weights from a device vector theta (FP64 [P], canonical order)
+ * on the stream [Sec. 3.2: the parameters the amplitude is evaluated at]:
+ * copied into the context by a kernel, then every kernel family's packing
+ * rebuilt from it, as nqs_update_weights does.  Allocates nothing and never
+ * synchronises (capturable); the kernels then see exactly what
+ * nqs_set_weights of the same values gives them.  The caller keeps theta
+ * alive until the stream has run the copy.                                 */
+nqs_status nqs_set_weights_device(nqs_ctx *ctx, const double *theta, void *stream);
+
 /* The current weights (host FP64 [n], canonical order, n == P); waits for
  * the device.                                                               */
 nqs_status nqs_get_weights(nqs_ctx *ctx, double *weights, int64_t n);

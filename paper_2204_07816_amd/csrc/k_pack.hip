@@ -27,6 +27,15 @@ __global__ void k_axpy(double *__restrict__ w, const double *__restrict__ d, dou
     }
 }
 
+// w = theta (a kernel rather than a copy call, so that a captured graph holds
+// only kernel nodes)
+__global__ void k_copy_f64(double *__restrict__ w, const double *__restrict__ theta, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        w[i] = theta[i];
+}
+
 // offset of layer l in the canonical vector (layer 1 has one input channel)
 __device__ inline int64_t canon_off(int l, int C)
 {
@@ -157,11 +166,10 @@ int grid_of(int64_t n)
 
 }  // namespace
 
-void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipStream_t s)
+// every kernel family's packing rebuilt from the canonical vector w_canon
+static void device_repack(nqs_ctx *c, hipStream_t s)
 {
     const int K = c->K, C = c->C;
-    NQS_LAUNCH(k_axpy, dim3(grid_of(c->P)), dim3(kThreads), 0, s, c->w_canon, dtheta, scale,
-               c->P);
     if (c->net == kNetCnn1) {           // only the matrix-core packing of CNN1
         cnn1_pack_device(c, s);
         return;
@@ -178,6 +186,19 @@ void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipSt
         NQS_LAUNCH(k_pack_l1, dim3(grid_of(9 * C + K * C)), dim3(kThreads), 0, s,
                    (const double *)c->w_canon, K, C, c->w_l1);
     }
+}
+
+void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipStream_t s)
+{
+    NQS_LAUNCH(k_axpy, dim3(grid_of(c->P)), dim3(kThreads), 0, s, c->w_canon, dtheta, scale,
+               c->P);
+    device_repack(c, s);
+}
+
+void device_set_weights(nqs_ctx *c, const double *theta, hipStream_t s)
+{
+    NQS_LAUNCH(k_copy_f64, dim3(grid_of(c->P)), dim3(kThreads), 0, s, c->w_canon, theta, c->P);
+    device_repack(c, s);
 }
 
 }  // namespace nqs

@@ -372,11 +372,18 @@ bool stream_capturing(hipStream_t s)
 
 nqs_status ensure(DevBuf &b, size_t bytes, hipStream_t stream)
 {
+    const bool capturing = stream_capturing(stream);
+    if (capturing && b.gy) b.gy->captured = true;
     if (bytes <= b.bytes) return NQS_OK;
-    if (stream_capturing(stream)) return NQS_E_WORKSPACE;
+    if (capturing) return NQS_E_WORKSPACE;
     if (b.ptr) {
-        HIP_OK(hipDeviceSynchronize());
-        (void)hipFree(b.ptr);
+        if (b.gy && b.gy->captured) {
+            // a captured graph may still name this allocation: keep it
+            b.gy->bufs.push_back(b.ptr);
+        } else {
+            HIP_OK(hipDeviceSynchronize());
+            (void)hipFree(b.ptr);
+        }
         b.ptr = nullptr;
         b.bytes = 0;
     }
@@ -485,6 +492,7 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
     if (n_weights != (net == kNetCnn1 ? cnn1_params(K, C) : params_of(K, C)))
         return NQS_E_NPARAMS;
     nqs_ctx *c = new nqs_ctx();
+    c->ws.bind();
     c->L = L;
     c->N = L * L;
     c->K = K;
@@ -597,12 +605,9 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->ring_off);
     free_dev(c->cone_tab);
     free_dev(c->err);
-    DevBuf *bufs[] = {&c->ws.counts, &c->ws.ediag, &c->ws.offsets, &c->ws.qlen, &c->ws.queue,
-                      &c->ws.dlog,   &c->ws.fbase, &c->ws.hsum,    &c->ws.cache, &c->ws.plane_a,
-                      &c->ws.plane_b, &c->ws.zsave, &c->ws.hsave,  &c->ws.delta, &c->ws.sr,
-                      &c->ws.orows,   &c->ws.counter, &c->ws.flags};
-    for (DevBuf *b : bufs)
+    for (DevBuf *b : c->ws.all())
         if (b->ptr) (void)hipFree(b->ptr);
+    for (void *p : c->ws.gy.bufs) (void)hipFree(p);
     for (auto &e : c->events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -633,6 +638,15 @@ nqs_status nqs_update_weights(nqs_ctx *c, const double *dtheta, double scale, vo
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     device_update_weights(c, dtheta, scale, s);
+    return finish_call();
+}
+
+nqs_status nqs_set_weights_device(nqs_ctx *c, const double *theta, void *stream)
+{
+    if (!c || !theta) return NQS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    device_set_weights(c, theta, s);
     return finish_call();
 }
 

@@ -44,10 +44,20 @@ constexpr int kNetCnn1 = 1;
 constexpr int kErrSpin = 1;
 constexpr int kErrNonFinite = 2;
 
+// Superseded workspace allocations of a context.  Once any call on the
+// context has run under stream capture, a graph may hold the addresses of its
+// buffers, so a buffer that has to grow later keeps its old allocation here
+// (freed with the context) instead of freeing it.
+struct Graveyard {
+    bool captured = false;
+    std::vector<void *> bufs;
+};
+
 // Growable device buffer.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    Graveyard *gy = nullptr;    // the owning context's graveyard
 };
 
 struct Workspace {
@@ -71,6 +81,19 @@ struct Workspace {
     DevBuf flags;       // int32 per chain: accepted proposals of a Metropolis step
     DevBuf sgn;         // int8 [B] network sign of the samples (CNN1)
     DevBuf isign;       // int8 [capacity] network sign ratio per queue item (CNN1)
+    Graveyard gy;
+
+    std::vector<DevBuf *> all()
+    {
+        return {&counts, &ediag, &offsets, &qlen,  &queue, &dlog,  &fbase,   &hsum,
+                &cache,  &plane_a, &plane_b, &zsave, &hsave, &delta, &sr,    &orows,
+                &counter, &flags, &sgn,    &isign};
+    }
+    // every buffer files its superseded allocations with this workspace
+    void bind()
+    {
+        for (DevBuf *b : all()) b->gy = &gy;
+    }
 };
 
 }  // namespace nqs
@@ -284,6 +307,8 @@ void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t 
 // --- device-side parameter update (k_pack.hip) ---
 // theta += scale * dtheta (device FP64 [P]) and every packing rebuilt on the device
 void device_update_weights(nqs_ctx *c, const double *dtheta, double scale, hipStream_t s);
+// theta (device FP64 [P]) becomes the weights, every packing rebuilt on the device
+void device_set_weights(nqs_ctx *c, const double *theta, hipStream_t s);
 
 // --- Metropolis sampling (k_mcmc.hip) ---
 // queue[s] = (s, bond of proposal rnd[s]), qlen[0] = B

@@ -78,6 +78,7 @@ def load():
         "nqs_mcmc": [vp, vp, i64, i32, vp, vp, vp, i32, vp],
         "nqs_update_weights": [vp, vp, d, vp],
         "nqs_get_weights": [vp, vp, i64],
+        "nqs_set_weights_device": [vp, vp, vp],
         "nqs_auto_mode": [vp, P(i32)],
         "nqs_autotune": [vp, vp, i64, P(i32), vp],
         "nqs_tune_key": [i32, i32, i32, i32, d, ctypes.c_char_p, i64],
@@ -213,6 +214,14 @@ class Context:
             raise ValueError("dtheta must hold P values")
         _check(load().nqs_update_weights(self._h, _dev(dtheta, torch.float64, "dtheta"),
                                          float(scale), _stream()), "nqs_update_weights")
+
+    def set_weights_device(self, theta):
+        """theta (FP64 [P] device tensor, canonical order) becomes the weights,
+        on the current stream, with no host round trip or synchronisation."""
+        if theta.numel() != self.P:
+            raise ValueError("theta must hold P values")
+        _check(load().nqs_set_weights_device(self._h, _dev(theta, torch.float64, "theta"),
+                                             _stream()), "nqs_set_weights_device")
 
     def get_weights(self):
         """The current canonical weights (numpy FP64 [P])."""
@@ -408,21 +417,26 @@ def tune_lookup(path: str, key: str):
 class LogPsiFn(torch.autograd.Function):
     """log|psi(s)| as a differentiable function of the weights.
 
-    forward: nqs_log_psi; backward: per-sample O = d log|psi| / d theta from
-    the hand-written backward kernels (nqs_log_deriv, FP64), contracted with
-    the incoming gradient."""
+    forward: the weights set on the device from theta (nqs_set_weights_device:
+    no host round trip, no synchronisation), then nqs_log_psi; backward: the
+    same weights set again (the context may have been used with others in
+    between), per-sample O = d log|psi| / d theta from the hand-written
+    backward kernels (nqs_log_deriv, FP64), contracted with the incoming
+    gradient."""
 
     @staticmethod
     def forward(ctx_, theta, spins, nctx):
-        nctx.set_weights(theta.detach().cpu())
+        th = theta.detach().to(device=spins.device, dtype=torch.float64).contiguous()
+        nctx.set_weights_device(th)
         la = nctx.log_psi(spins, with_sign=False)
-        ctx_.save_for_backward(spins)
+        ctx_.save_for_backward(spins, th)
         ctx_.nctx = nctx
         ctx_.theta_device = theta.device
         return la
 
     @staticmethod
     def backward(ctx_, g):
-        (spins,) = ctx_.saved_tensors
+        spins, th = ctx_.saved_tensors
+        ctx_.nctx.set_weights_device(th)
         O = ctx_.nctx.log_deriv(spins, dtype="fp64")
         return (g.to(O.device, torch.float64) @ O).to(ctx_.theta_device), None, None

@@ -66,16 +66,45 @@ def test_log_deriv_finite_differences_24x24():
 
 
 def test_autograd_function():
+    """Two forwards at different weights on one context, then both backwards:
+    each sees its own weights (set on the device, no host round trip)."""
     L, K, C = 6, 2, 4
     w = inputs.weights(K, C, 0.4, 3)
+    w2 = inputs.weights(K, C, 0.3, 7)
     sp = inputs.spins_sz0(L, 5, 4)
     ctx = make_ctx(L, 0.5, K, C, w)
     theta = torch.tensor(w, requires_grad=True)
+    theta2 = torch.tensor(w2, device=DEV, requires_grad=True)
     la = nqs.LogPsiFn.apply(theta, to_dev(sp), ctx)
+    la2 = nqs.LogPsiFn.apply(theta2, to_dev(sp), ctx)
+    np.testing.assert_allclose(la.detach().cpu().numpy(), oracle.log_psi(L, K, C, w, sp)[0], rtol=1e-12)
+    np.testing.assert_allclose(la2.detach().cpu().numpy(), oracle.log_psi(L, K, C, w2, sp)[0], rtol=1e-12)
     g = torch.linspace(-1, 1, 5, dtype=torch.float64, device=DEV)
     (la * g).sum().backward()
+    (la2 * g * g).sum().backward()
     ref = g.cpu().numpy() @ oracle.log_deriv(L, K, C, w, sp)
+    ref2 = (g * g).cpu().numpy() @ oracle.log_deriv(L, K, C, w2, sp)
     np.testing.assert_allclose(theta.grad.numpy(), ref, rtol=1e-10, atol=1e-13)
+    assert theta2.grad.device.type == "cuda"
+    np.testing.assert_allclose(theta2.grad.cpu().numpy(), ref2, rtol=1e-10, atol=1e-13)
+
+
+def test_set_weights_device_equals_host_set():
+    """nqs_set_weights_device gives the kernels exactly what nqs_set_weights
+    gives them: log|psi|, E_loc and O bit for bit, in FP64 and BF16."""
+    L, K, C = 12, 3, 16
+    w = inputs.stress_weights(K, C, 1.0, 9)
+    w2 = inputs.stress_weights(K, C, 0.9, 10)
+    spd = to_dev(inputs.spins_sz0(L, 16, 11))
+    for dt in ("fp64", "bf16"):
+        a = make_ctx(L, 0.5, K, C, w, dtype=dt)
+        b = make_ctx(L, 0.5, K, C, w, dtype=dt)
+        a.set_weights(w2)
+        b.set_weights_device(torch.tensor(w2, device=DEV))
+        assert torch.equal(a.log_psi(spd)[0], b.log_psi(spd)[0])
+        assert torch.equal(a.local_energy(spd), b.local_energy(spd))
+        assert torch.equal(a.log_deriv(spd, dtype="fp64"), b.log_deriv(spd, dtype="fp64"))
+        assert np.array_equal(b.get_weights(), w2)
 
 
 # (S + 1e-4 I) condition numbers: ~4.7e3, ~60, ~110 (converged within 100 CG steps)
