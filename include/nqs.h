@@ -241,6 +241,24 @@ nqs_status nqs_sr_solve_recompute(nqs_ctx *ctx, const int8_t *spins,
                                   int64_t chunk_rows, double *dtheta,
                                   double *stats, void *stream);
 
+/* nqs_sr_solve for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, kernels and results (bit for bit) as nqs_sr_solve, with its
+ * workspace in a fixed 48 MiB array of device memory that the library holds
+ * on every device it runs on until the process ends, instead of the
+ * context's workspace.  Allocates nothing and never synchronises.
+ * Limit: the workspace of B samples and P parameters, 8 (5 P + 2 B + c P)
+ * bytes plus alignment with c = min(64, ceil(B / 64)) partial sums per
+ * column, must fit in 48 MiB (P = 65,056 with B = 4096 takes 36 MB);
+ * larger problems return NQS_E_WORKSPACE and enqueue nothing.  Every call on
+ * a device shares that device's array: calls that overlap on one device
+ * (other streams, other threads, other contexts) race and must be
+ * serialised by the caller.  Other errors as nqs_sr_solve.                */
+nqs_status nqs_sr_solve_noalloc(nqs_ctx *ctx, const void *O, nqs_dtype O_dtype,
+                                const double *e_loc, int64_t B, double diag_shift,
+                                int32_t n_iter, double *dtheta, double *stats,
+                                void *stream);
+
 /* Inspection of the integer stage [Sec. 5.4.1]: for every sample the count
  * of antiparallel bonds with J != 0 (t-J: of the pairs with an off-diagonal
  * term, see nqs_create_tj) (int32 [B]), exclusive offsets

@@ -72,6 +72,7 @@ def load():
         "nqs_log_deriv": [vp, vp, i64, vp, i32, vp],
         "nqs_sr_solve": [vp, vp, i32, vp, i64, d, i32, vp, vp, vp],
         "nqs_sr_solve_recompute": [vp, vp, i32, vp, i64, d, i32, i64, vp, vp, vp],
+        "nqs_sr_solve_noalloc": [vp, vp, i32, vp, i64, d, i32, vp, vp, vp],
         "nqs_connected": [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp],
         "nqs_log_ratios": [vp, vp, i64, i32, vp, i64, vp],
         "nqs_local_energy_multi": [vp, i32, i32, vp],
@@ -321,6 +322,25 @@ class Context:
                                    _dev(x, torch.float64, "dtheta"),
                                    _dev(st, torch.float64, "stats"), _stream()), "nqs_sr_solve")
         return x, st
+
+    def sr_solve_noalloc(self, O, e_loc, diag_shift: float = 1e-4, n_iter: int = 100, *,
+                         out, stats):
+        """nqs_sr_solve_noalloc: the SR solve with its workspace in the library's
+        fixed device array (no allocation anywhere: out and stats are
+        caller-provided FP64 [P] and [4] device tensors)."""
+        odt = {torch.float32: FP32, torch.float64: FP64}[O.dtype]
+        B = O.shape[0]
+        if O.dim() != 2 or O.shape[1] != self.P or e_loc.numel() != B:
+            raise ValueError("O must be [B, P] and e_loc [B]")
+        if out.numel() != self.P or stats.numel() < 4:
+            raise ValueError("out must hold P values and stats 4")
+        _check(load().nqs_sr_solve_noalloc(self._h, _dev(O, O.dtype, "O"), odt,
+                                           _dev(e_loc, torch.float64, "e_loc"), B,
+                                           float(diag_shift), int(n_iter),
+                                           _dev(out, torch.float64, "dtheta"),
+                                           _dev(stats, torch.float64, "stats"), _stream()),
+               "nqs_sr_solve_noalloc")
+        return out, stats
 
     def sr_solve_recompute(self, spins, e_loc, diag_shift: float = 1e-4, n_iter: int = 100,
                            dtype: str = "fp32", chunk_rows: int = 0, out=None, stats=None):
