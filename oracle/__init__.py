@@ -62,6 +62,9 @@ def _load():
         "oracle_cnn1_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
         "oracle_tj_cnn1_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d),
                                                ci]),
+        "oracle_sens_layers": (None, [ci, ci, ci, P(d), P(i8), P(d), P(d), P(d), P(d), P(d)]),
+        "oracle_dlog_sens": (None, [ci, ci, ci, P(d), P(i8), i64, P(i32), P(i32), i64, P(d),
+                                    ci]),
         "oracle_energy_stats": (None, [P(d), i64, P(d)]),
         "oracle_sr_cg": (None, [P(d), P(d), i64, i64, d, ci, P(d), P(d)]),
         "oracle_sr_dense": (ci, [P(d), P(d), i64, i64, d, P(d)]),
@@ -284,6 +287,33 @@ def cnn1_log_deriv(L: int, Kb: int, C: int, w, spins, nthreads: int = 0):
     _load().oracle_cnn1_log_deriv(L, Kb, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
                                   _p(O, ctypes.c_double), nthreads)
     return O
+
+
+def sens_layers(L: int, K: int, C: int, w, spins):
+    """Every layer of one configuration, arrays [K, C, L, L]: z, h = ln cosh z,
+    a = |b| + sum |W||h_in|, g = df/dh_k, d = df/dz_k (test support)."""
+    s = _spins(spins, L)[:1].copy()
+    w = np.ascontiguousarray(w, np.float64)
+    arrs = [np.zeros(K * C * L * L) for _ in range(5)]
+    _load().oracle_sens_layers(L, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8),
+                               *[_p(a, ctypes.c_double) for a in arrs])
+    return {k: a.reshape(K, C, L, L) for k, a in zip("zhagd", arrs)}
+
+
+def dlog_sens(L: int, K: int, C: int, w, spins, samples, bonds, nthreads: int = 0):
+    """Per item (samples[m], bonds[m]): [f(S')-f(S), S1_act, S2_act, S1_acc,
+    S1_lc, S2_acc] (bond < 0: the sample itself), the first-order rounding
+    sensitivities of nqs_oracle.h.  Returns float64 [M, 6]."""
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    sm = np.ascontiguousarray(samples, np.int32)
+    bd = np.ascontiguousarray(bonds, np.int32)
+    M = sm.shape[0]
+    out = np.zeros((M, 6))
+    _load().oracle_dlog_sens(L, K, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), s.shape[0],
+                             _p(sm, ctypes.c_int32), _p(bd, ctypes.c_int32), M,
+                             _p(out, ctypes.c_double), nthreads)
+    return out
 
 
 def energy_stats(e):

@@ -961,6 +961,208 @@ void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,
 }
 
 /* ------------------------------------------------------------------ */
+/* Rounding-error sensitivities (test support for reduced-precision     */
+/* evaluations of the network)                                          */
+/* ------------------------------------------------------------------ */
+
+/* Every layer of one configuration kept, channel-major [k][c][p], k = 0..K-1
+ * standing for layers 1..K:
+ *   z  pre-activation;  h = ln cosh z;
+ *   a  = |b| + sum |W| |h_in| (the magnitude an accumulation of z runs over);
+ *   g  = d f / d h_k (reverse mode; g = 1 on the last layer, whose values
+ *        are summed directly);
+ *   d  = d f / d z_k = g tanh z_k.                                          */
+typedef struct {
+    double *z, *h, *a, *g, *d;
+} sens_layers;
+
+static void sens_alloc(sens_layers *s, int K, int C, int N)
+{
+    const size_t n = (size_t)K * C * N;
+    s->z = (double *)malloc(sizeof(double) * n);
+    s->h = (double *)malloc(sizeof(double) * n);
+    s->a = (double *)malloc(sizeof(double) * n);
+    s->g = (double *)malloc(sizeof(double) * n);
+    s->d = (double *)malloc(sizeof(double) * n);
+}
+
+static void sens_free(sens_layers *s)
+{
+    free(s->z); free(s->h); free(s->a); free(s->g); free(s->d);
+}
+
+/* magnitude of a 3x3 circular accumulation: |b| + sum |W| |h_in|           */
+static void conv_layer_abs(int L, int cin, int cout, const double *W, const double *bias,
+                           const double *h_in, double *a_out)
+{
+    for (int co = 0; co < cout; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = fabs(bias[co]);
+                for (int ci = 0; ci < cin; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx) {
+                            int yy = wrap(y + ky - 1, L), xx = wrap(x + kx - 1, L);
+                            acc += fabs(W[((co * cin + ci) * 3 + ky) * 3 + kx]) *
+                                   fabs(h_in[(ci * L + yy) * L + xx]);
+                        }
+                a_out[(co * L + y) * L + x] = acc;
+            }
+}
+
+/* forward (keeping every layer) and reverse pass of one configuration;
+ * returns f.  h0: N scratch values for the spins as the first input.      */
+static double sens_pass(int L, int K, int C, const double *w, const int8_t *spins,
+                        sens_layers *s, double *h0)
+{
+    const int N = L * L;
+    const size_t plane = (size_t)C * N;
+    for (int i = 0; i < N; ++i) h0[i] = (double)spins[i];
+    for (int k = 0; k < K; ++k) {
+        int64_t wo, bo;
+        int cin;
+        layer_offsets(K, C, k, &wo, &bo, &cin);
+        const double *hin = (k == 0) ? h0 : s->h + (size_t)(k - 1) * plane;
+        conv_layer(L, cin, C, w + wo, w + bo, hin, s->z + (size_t)k * plane);
+        conv_layer_abs(L, cin, C, w + wo, w + bo, hin, s->a + (size_t)k * plane);
+        for (size_t q = 0; q < plane; ++q)
+            s->h[(size_t)k * plane + q] = ln_cosh(s->z[(size_t)k * plane + q]);
+    }
+    double f = 0.0;
+    for (size_t q = 0; q < plane; ++q) f += s->h[(size_t)(K - 1) * plane + q];
+    /* reverse: g_K = 1; d_k = g_k tanh z_k; g_{k-1} = W_k^T (*) d_k        */
+    for (size_t q = 0; q < plane; ++q) s->g[(size_t)(K - 1) * plane + q] = 1.0;
+    for (int k = K - 1; k >= 0; --k) {
+        double *g = s->g + (size_t)k * plane, *d = s->d + (size_t)k * plane;
+        const double *z = s->z + (size_t)k * plane;
+        for (size_t q = 0; q < plane; ++q) d[q] = g[q] * tanh(z[q]);
+        if (k == 0) break;
+        int64_t wo, bo;
+        int cin;
+        layer_offsets(K, C, k, &wo, &bo, &cin);
+        const double *W = w + wo;
+        double *gp = s->g + (size_t)(k - 1) * plane;
+        memset(gp, 0, sizeof(double) * plane);
+        for (int co = 0; co < C; ++co)
+            for (int ci = 0; ci < cin; ++ci)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const double wv = W[((co * cin + ci) * 3 + ky) * 3 + kx];
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x) {
+                                int yy = wrap(y + ky - 1, L), xx = wrap(x + kx - 1, L);
+                                gp[(ci * L + yy) * L + xx] += wv * d[(co * L + y) * L + x];
+                            }
+                    }
+    }
+    return f;
+}
+
+void oracle_sens_layers(int L, int K, int C, const double *w, const int8_t *spins,
+                        double *z, double *h, double *a, double *g, double *d)
+{
+    const int N = L * L;
+    const size_t n = (size_t)K * C * N;
+    sens_layers s;
+    sens_alloc(&s, K, C, N);
+    double *h0 = (double *)malloc(sizeof(double) * (size_t)N);
+    sens_pass(L, K, C, w, spins, &s, h0);
+    memcpy(z, s.z, sizeof(double) * n);
+    memcpy(h, s.h, sizeof(double) * n);
+    memcpy(a, s.a, sizeof(double) * n);
+    memcpy(g, s.g, sizeof(double) * n);
+    memcpy(d, s.d, sizeof(double) * n);
+    free(h0);
+    sens_free(&s);
+}
+
+/* Adds one value's coefficient to the sums: inside the changed region the
+ * two evaluations round independently (two terms), outside it they share
+ * one rounded value, which enters with the difference of the sensitivities. */
+static void sens_term(double vp, double v, double cp, double c, double *s1, double *s2)
+{
+    if (vp != v) {
+        const double t1 = fabs(cp * vp), t2 = fabs(c * v);
+        *s1 += t1 + t2;
+        *s2 += t1 * t1 + t2 * t2;
+    } else {
+        const double t = fabs((cp - c) * v);
+        *s1 += t;
+        *s2 += t * t;
+    }
+}
+
+void oracle_dlog_sens(int L, int K, int C, const double *w, const int8_t *spins, int64_t B,
+                      const int32_t *item_sample, const int32_t *item_bond, int64_t M,
+                      double *out, int nthreads)
+{
+    const int N = L * L;
+    const size_t plane = (size_t)C * N;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+    (void)B;
+#pragma omp parallel num_threads(nt)
+    {
+        sens_layers s0, s1;
+        sens_alloc(&s0, K, C, N);
+        sens_alloc(&s1, K, C, N);
+        double *h0 = (double *)malloc(sizeof(double) * (size_t)N);
+        int8_t *sp = (int8_t *)malloc((size_t)N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t m = 0; m < M; ++m) {
+            const int8_t *sb = spins + (int64_t)item_sample[m] * N;
+            double *o = out + m * 6;
+            const double f0 = sens_pass(L, K, C, w, sb, &s0, h0);
+            if (item_bond[m] < 0) {
+                /* the configuration itself: every value rounds once         */
+                double act1 = 0, act2 = 0, acc1 = 0, acc2 = 0, lc1 = 0;
+                for (int k = 0; k < K; ++k)
+                    for (size_t q = 0; q < plane; ++q) {
+                        const size_t i = (size_t)k * plane + q;
+                        const double th = fabs(s0.g[i] * s0.h[i]);
+                        const double tz = fabs(s0.d[i]) * s0.a[i];
+                        if (k < K - 1) { act1 += th; act2 += th * th; }
+                        acc1 += tz; acc2 += tz * tz;
+                        lc1 += th;
+                    }
+                o[0] = f0; o[1] = act1; o[2] = sqrt(act2); o[3] = acc1; o[4] = lc1;
+                o[5] = sqrt(acc2);
+                continue;
+            }
+            int si, sj;
+            oracle_bond_sites(L, item_bond[m], &si, &sj);
+            memcpy(sp, sb, (size_t)N);
+            sp[si] = sb[sj];
+            sp[sj] = sb[si];
+            const double f1 = sens_pass(L, K, C, w, sp, &s1, h0);
+            double act1 = 0, act2 = 0, acc1 = 0, acc2 = 0, lc1 = 0, lc2 = 0;
+            for (int k = 0; k < K; ++k)
+                for (size_t q = 0; q < plane; ++q) {
+                    const size_t i = (size_t)k * plane + q;
+                    if (k < K - 1) sens_term(s1.h[i], s0.h[i], s1.g[i], s0.g[i], &act1, &act2);
+                    sens_term(s1.h[i], s0.h[i], s1.g[i], s0.g[i], &lc1, &lc2);
+                    /* z: the accumulation's error scales with a, not |z|     */
+                    if (s1.z[i] != s0.z[i]) {
+                        const double t1 = fabs(s1.d[i]) * s1.a[i], t2 = fabs(s0.d[i]) * s0.a[i];
+                        acc1 += t1 + t2;
+                        acc2 += t1 * t1 + t2 * t2;
+                    } else {
+                        const double t = fabs(s1.d[i] - s0.d[i]) * s0.a[i];
+                        acc1 += t;
+                        acc2 += t * t;
+                    }
+                }
+            o[0] = f1 - f0; o[1] = act1; o[2] = sqrt(act2); o[3] = acc1; o[4] = lc1;
+            o[5] = sqrt(acc2);
+        }
+        free(sp);
+        free(h0);
+        sens_free(&s0);
+        sens_free(&s1);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Statistics and stochastic reconfiguration                            */
 /* ------------------------------------------------------------------ */
 

@@ -141,6 +141,34 @@ void oracle_tj_cnn1_local_energy(int L, double t, double J, int Kb, int C, const
 void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,
                       int64_t B, double *O, int nthreads);
 
+/* Rounding-error sensitivities of the network (test support: the bound a
+ * reduced-precision evaluation is checked against).  A value v that is
+ * rounded with relative error e (|e| <= u) moves f by (d f / d v) v e to
+ * first order, so the first-order error of an evaluation is bounded by u
+ * times the sum of |(d f / d v) v| over the values it rounds.
+ *
+ * oracle_sens_layers: every layer of one configuration, channel-major
+ * [k][c][p] (k = 0..K-1 for layers 1..K): z, h = ln cosh z,
+ * a = |b| + sum |W| |h_in| (magnitude of the accumulation of z),
+ * g = d f / d h_k (g = 1 on layer K), d = d f / d z_k = g tanh z_k.
+ *
+ * oracle_dlog_sens: for M items (sample, bond), out[m][0..5]:
+ *   [0] f(S') - f(S) (bond < 0: f(S) of the sample itself, below with only
+ *       the sample's own terms);
+ *   [1] S1_act = sum over layers 1..K-1 of the activation coefficients,
+ *   [2] sqrt(sum of their squares);
+ *   [3] S1_acc = same for the accumulations of z over layers 1..K with
+ *       coefficient |d| a, [5] sqrt(sum of their squares);
+ *   [4] S1_lc = same as [1] over layers 1..K (errors of ln cosh itself).
+ * Coefficients: where S' and S differ (v' != v) the two evaluations round
+ * independently, |g' v'| + |g v|; elsewhere they share the rounded value,
+ * |(g' - g) v|.                                                           */
+void oracle_sens_layers(int L, int K, int C, const double *w, const int8_t *spins,
+                        double *z, double *h, double *a, double *g, double *d);
+void oracle_dlog_sens(int L, int K, int C, const double *w, const int8_t *spins, int64_t B,
+                      const int32_t *item_sample, const int32_t *item_bond, int64_t M,
+                      double *out, int nthreads);
+
 /* Energy statistics: stats[0] = mean, stats[1] = variance (1/Ns).      */
 void oracle_energy_stats(const double *e_loc, int64_t B, double *stats);
 

@@ -76,3 +76,43 @@ def graph_replays_equal_eager(ctx, w, start, n=3, **kw):
     assert np.array_equal(run.weights, w_eager)
     assert torch.equal(run.spins, s_eager)
     del g
+
+
+def bf16_weights(w, K, C):
+    """The network the BF16 form evaluates: the 3x3 weights of layers 2..K
+    rounded to BF16 (nearest even, from the FP64 value); layer 1 and every
+    bias stay as given (those run in FP32, whose rounding the bound covers)."""
+    w = np.array(w, np.float64)
+    off = C * 9 + C
+    for _ in range(K - 1):
+        seg = w[off:off + C * C * 9]
+        m, e = np.frexp(seg)
+        w[off:off + C * C * 9] = np.ldexp(np.round(m * 256.0), e - 8)
+        off += C * C * 9 + C
+    return w
+
+
+# Rounding-error model of the reduced-precision forms (first order):
+#   activations of layers 1..K-1 rounded with relative error <= u_act
+#   (BF16, nearest even: 2^-8; split hi + lo BF16: 2^-16);
+#   each FP32 accumulation of z over n = 9C + 1 <= 289 terms: worst case
+#   gamma_289 = 289 * 2^-24 / (1 - 289 * 2^-24) times a = |b| + sum |W||h|,
+#   probabilistic sqrt(289) * 2^-24 * a;
+#   ln cosh evaluated with relative error <= eta.
+# Worst case:     u_act S1_act + gamma S1_acc + eta S1_lc
+# Probabilistic:  6 sqrt((u_act S2_act)^2 + (sqrt(289) 2^-24 S2_acc)^2) + eta S1_lc
+#   (independent, mean-zero rounding errors; Hoeffding's inequality puts the
+#   chance of exceeding it at 2 exp(-18) per value).
+U32 = 2.0 ** -24
+GAMMA_289 = 289 * U32 / (1 - 289 * U32)
+
+
+def rounding_bound(sens, u_act, eta, extra_rel=0.0):
+    """Per-item bound (the smaller of the worst-case and the probabilistic one)
+    from oracle.dlog_sens rows; extra_rel adds a relative error of the weights'
+    representation on every accumulation (split weights: 2^-16 twice)."""
+    s1a, s2a, s1z, s1l, s2z = sens[:, 1], sens[:, 2], sens[:, 3], sens[:, 4], sens[:, 5]
+    worst = 1.05 * (u_act * s1a + (GAMMA_289 + extra_rel) * s1z + eta * s1l)
+    prob = 6.0 * np.sqrt((u_act * s2a) ** 2 + ((np.sqrt(289.0) * U32 + extra_rel) * s2z) ** 2) \
+        + eta * s1l
+    return np.minimum(worst, prob)
