@@ -38,7 +38,8 @@
  *   - Limits: even L with 4 <= L <= 64; 1 <= K <= 16; 1 <= C <= 32 for the
  *     FP64/FP32 paths; C in {16, 32}, K >= 2 and L <= 36 for BF16 (its base
  *     pass keeps a whole layer of a configuration in one workgroup's
- *     accumulators, at most 1408 sites); B <= 131072 per call.
+ *     accumulators, at most 1408 sites); C = 32 and K >= 2 for BF16X3;
+ *     B <= 131072 per call.
  *
  * Errors
  *   - Argument problems found on the host are returned at once and nothing
@@ -78,12 +79,26 @@ typedef enum {
     NQS_E_UNSUPPORTED = 10  /* valid request this build does not implement     */
 } nqs_status;
 
-typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2 } nqs_dtype;
+/* Arithmetic of the convolutions of layers 2..K:
+ *   FP64      plain double precision (the paper's);
+ *   FP32      single precision on the vector ALU;
+ *   BF16      matrix cores, BF16 operands (weights and activations rounded to
+ *             nearest even), FP32 accumulation;
+ *   BF16X3    matrix cores, split BF16: every operand x is carried as a pair
+ *             hi = bf16(x), lo = bf16(x - hi) (|x - hi - lo| <= 2^-16 |x|)
+ *             and each product as hi*hi + hi*lo + lo*hi, three BF16 products
+ *             with FP32 accumulation (the bf16x3 scheme of Henry, Tang and
+ *             Heinecke, 2019).  32 channels only.
+ * Layer 1 (one input channel) runs in FP32 in the BF16 forms, FP64
+ * otherwise; ratios, sums and reductions are FP64 in every form.           */
+typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3 } nqs_dtype;
 
 /* How psi(S') is evaluated for the exchanged configurations [Sec. 5.4.1]:
  * FULL recomputes the whole network for every S'; INCREMENTAL recomputes only
- * the receptive-field cone of the exchanged pair (BF16 path only) and reads
- * the rest from the cached activations of S; AUTO lets the library choose. */
+ * the receptive-field cone of the exchanged pair (BF16 and BF16X3 forms; for
+ * BF16X3 only where no window of the cone wraps around the torus, L >= 2K+4)
+ * and reads the rest from the cached activations of S; AUTO lets the library
+ * choose. */
 typedef enum { NQS_AUTO = 0, NQS_FULL = 1, NQS_INCREMENTAL = 2 } nqs_mode;
 
 typedef struct {

@@ -43,12 +43,22 @@ using mf::floatx4;
 constexpr int C = 32;
 constexpr int KS = 9;           // K-steps (one tap of 32 channels each)
 constexpr int NH = 2;           // 16-channel output halves
-constexpr int kNW = 4;
-constexpr int kThreads = kNW * 64;
 constexpr int kRingRegs = 2;
 constexpr int kChunk = 16;      // bytes of one 8-channel chunk of a site
-constexpr int kChunks = 4;      // 16-byte chunks of channels per site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
+
+// The operand form: X = 1 plain BF16; X = 3 split BF16 (hi + lo of every
+// operand, three products per tap).  The split form's windows and cache hold
+// the lo parts as four more channel planes / chunks, twice the LDS, so it runs
+// one workgroup of eight waves per CU instead of three of four.
+template <int X>
+struct Form {
+    static constexpr int NW = X == 3 ? 8 : 4;          // waves per workgroup
+    static constexpr int kThreads = NW * 64;
+    static constexpr int CH = X == 3 ? 8 : 4;          // 16-byte chunks (planes) per site
+    static constexpr int SITE = CH * 8;                // BF16 values per cached site
+    static constexpr int WPE = X == 3 ? 2 : 3;         // waves per SIMD
+};
 constexpr int kMaxK = 16;
 constexpr int kMaxJobs = kMaxConnJobs;
 // layer-1 weights in LDS: for each of the 16 channel pairs a thread can own,
@@ -68,14 +78,16 @@ struct ConeParams {
     const int64_t *qlen;
     int64_t capacity;
     const bf16x8 *wa;          // layer k >= 2: [k-2][KS][NH][64 lanes]
+    const bf16x8 *wl;          // split form: the lo parts, same layout
     const float *w1;           // layer 1 [9][C]
     const float *bias;         // [K][C]
-    const uint16_t *cache;     // base-pass BF16 activations [B][K-1][N][C] (slot order)
+    const uint16_t *cache;     // base-pass BF16 activations [B][K-1][N][SITE] (slot order;
+                               // split form: the 32 hi values, then the 32 lo values)
     const double *hsum;        // base-pass per-site channel sums of layer K [B][N]
     double *dlog;
     int32_t *err;
     int ps_a, ps_b;            // plane strides (bytes) of the even- and odd-layer buffers
-    int buf_b;                 // byte offset of the odd-layer buffer (4 planes of ps_a)
+    int buf_b;                 // byte offset of the odd-layer buffer (CH planes of ps_a)
     const int32_t *ring;       // ring tables, one entry per site (see ring_chunk)
     // write-back launches only: the configuration S' of every item whose
     // chain has commit[chain] != 0 becomes the chain's base pass (the cone's
@@ -107,6 +119,11 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
 }
 
+__device__ __forceinline__ uint32_t pack_u16(uint16_t a, uint16_t b)
+{
+    return (uint32_t)a | ((uint32_t)b << 16);
+}
+
 struct Ring {
     u32x4 v[kRingRegs];
     int dst[kRingRegs];        // byte address in the window buffer, -1: none
@@ -118,15 +135,17 @@ struct RingTab {
 };
 
 // Table entries of the ring of W_{k+1} (entries [e0, e1) of the table, one
-// per site): chunk q = lt + i * kThreads reads entry e0 + q / 4.
+// per site): chunk q = lt + i * kThreads reads entry e0 + q / CH.
+template <int X>
 __device__ __forceinline__ void ring_tab_load(RingTab &t, const ConeParams &p, bool live, int e0,
                                               int e1, int lt)
 {
+    using F = Form<X>;
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i) {
-        const int q = lt + i * kThreads;
-        const bool ok = live && q < (e1 - e0) * kChunks;
-        const int e = p.ring[ok ? e0 + (q >> 2) : 0];
+        const int q = lt + i * F::kThreads;
+        const bool ok = live && q < (e1 - e0) * F::CH;
+        const int e = p.ring[ok ? e0 + q / F::CH : 0];
         t.ent[i] = ok ? e : -1;
     }
 }
@@ -134,24 +153,26 @@ __device__ __forceinline__ void ring_tab_load(RingTab &t, const ConeParams &p, b
 // Chunk c of ring entry `ent` (window index | (du mod L) << 16 | (dv mod L) << 24,
 // offsets from the anchor): .x element offset in the layer cache, .y byte
 // offset in the window buffer of plane stride ps.
+template <int X>
 __device__ __forceinline__ int2 ring_chunk(int ent, int c, int ax, int ay, int L, int ps)
 {
     uint32_t x = (uint32_t)(ax + ((ent >> 16) & 255));
     uint32_t y = (uint32_t)(ay + ((uint32_t)ent >> 24));
     x = min(x, x - (uint32_t)L);        // x, y < 2L: one conditional period
     y = min(y, y - (uint32_t)L);
-    return make_int2((int)(__umul24(y, (uint32_t)L) + x) * C + c * 8,
+    return make_int2((int)(__umul24(y, (uint32_t)L) + x) * Form<X>::SITE + c * 8,
                      (int)__umul24((uint32_t)c, (uint32_t)ps) + (ent & 0xffff) * kChunk);
 }
 
 // Issue the loads of the prefetched ring chunks named by `t`.
+template <int X>
 __device__ __forceinline__ void ring_fetch(Ring &r, const RingTab &t, int lt, int ax, int ay, int L,
                                            int ps, const uint16_t *layer_cache)
 {
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i) {
         const bool live = t.ent[i] >= 0;
-        const int2 sd = ring_chunk(live ? t.ent[i] : 0, lt & 3, ax, ay, L, ps);
+        const int2 sd = ring_chunk<X>(live ? t.ent[i] : 0, lt % Form<X>::CH, ax, ay, L, ps);
         r.v[i] = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
         r.dst[i] = live ? sd.y : -1;
     }
@@ -159,30 +180,45 @@ __device__ __forceinline__ void ring_fetch(Ring &r, const RingTab &t, int lt, in
 
 // Store the fetched chunks, then copy any chunks of entries [e0, e1) beyond
 // them directly.
+template <int X>
 __device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, int lt,
                                            unsigned char *buf, int e0, int e1, int ax, int ay,
                                            int L, int ps, const uint16_t *layer_cache)
 {
+    using F = Form<X>;
 #pragma unroll
     for (int i = 0; i < kRingRegs; ++i)
         if (r.dst[i] >= 0) *(u32x4 *)(buf + r.dst[i]) = r.v[i];
-    const int total = (e1 - e0) * kChunks;
-    for (int q = lt + kRingRegs * kThreads; q < total; q += kThreads) {
-        const int2 sd = ring_chunk(p.ring[e0 + (q >> 2)], q & 3, ax, ay, L, ps);
+    const int total = (e1 - e0) * F::CH;
+    for (int q = lt + kRingRegs * F::kThreads; q < total; q += F::kThreads) {
+        const int2 sd = ring_chunk<X>(p.ring[e0 + q / F::CH], q % F::CH, ax, ay, L, ps);
         *(u32x4 *)(buf + sd.y) = *(const u32x4 *)(layer_cache + (uint32_t)sd.x);
     }
 }
 
 // Weights of one layer (A operands, one 16-byte fragment per lane per
-// K-step and half).
-__device__ __forceinline__ void load_layer(bf16x8 (&wa)[KS][NH], const ConeParams &p, int k,
-                                           int lane)
+// K-step and half; the split form also the lo parts).
+template <int X>
+struct Weights {
+    bf16x8 hi[KS][NH];
+    bf16x8 lo[X == 3 ? KS : 1][NH];
+};
+
+template <int X>
+__device__ __forceinline__ void load_layer(Weights<X> &wt, const ConeParams &p, int k, int lane)
 {
     const bf16x8 *base = p.wa + (int64_t)(k - 2) * KS * NH * 64;
 #pragma unroll
     for (int j = 0; j < KS; ++j)
 #pragma unroll
-        for (int hh = 0; hh < NH; ++hh) wa[j][hh] = base[(j * NH + hh) * 64 + lane];
+        for (int hh = 0; hh < NH; ++hh) wt.hi[j][hh] = base[(j * NH + hh) * 64 + lane];
+    if (X == 3) {
+        const bf16x8 *bl = p.wl + (int64_t)(k - 2) * KS * NH * 64;
+#pragma unroll
+        for (int j = 0; j < KS; ++j)
+#pragma unroll
+            for (int hh = 0; hh < NH; ++hh) wt.lo[X == 3 ? j : 0][hh] = bl[(j * NH + hh) * 64 + lane];
+    }
 }
 
 // Everything one tile needs (wave-uniform): the tile's first position in R_k
@@ -196,14 +232,16 @@ struct TileArgs {
 };
 
 // NT tiles of one layer.  Inner layers store the BF16 activations into
-// W_{k+1}; the last layer accumulates the site sums.
-template <bool last, int NT, bool COMMIT>
-__device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const floatx4 (&bias)[NH],
+// W_{k+1} (split form: hi into planes 0..3, lo into planes 4..7); the last
+// layer accumulates the site sums.
+template <int X, bool last, int NT, bool COMMIT>
+__device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (&bias)[NH],
                                            const unsigned char *cur, unsigned char *nxt,
                                            uint16_t *wcache, double *whsum, int k,
                                            const TileArgs (&ta)[NT], int L, int K, int ax, int ay,
                                            const double *hsum_s, int g, int n16, double &fsum)
 {
+    using F = Form<X>;
     floatx4 acc[NT][NH];
     int ain[NT], aout[NT];
     bool valid[NT];
@@ -218,7 +256,7 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
         const int u = p - __mul24(v, ta[w].ex);
         const int u16 = u * kChunk;
         // tap (dx, dy) of output (u, v) is window site (u + 1 + dx, v + 1 + dy);
-        // lane group g reads plane g
+        // lane group g reads plane g (and plane 4 + g for the lo parts)
         ain[w] = __mul24(g, ta[w].psc) + __mul24(v, ta[w].p16) + u16;
         // output goes to W_{k+1} site (u + 2, v + 2)
         aout[w] = __mul24(g, ta[w].psn) + __mul24(v + 2, ta[w].q16) + u16 + 2 * kChunk;
@@ -236,10 +274,25 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
             for (int dx = 0; dx < 3; ++dx) {
                 const int j = dy * 3 + dx;
                 const bf16x8 bv = *(const bf16x8 *)(row + dx * kChunk);
+                if (X == 3) {
+                    // the split form's product order: lo*hi, hi*lo, hi*hi
+                    const bf16x8 bl = *(const bf16x8 *)(row + 4 * ta[w].psc + dx * kChunk);
 #pragma unroll
-                for (int hh = 0; hh < NH; ++hh)
-                    acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        wa[j][hh], bv, j == 0 ? bias[hh] : acc[w][hh], 0, 0, 0);
+                    for (int hh = 0; hh < NH; ++hh) {
+                        floatx4 c0 = j == 0 ? bias[hh] : acc[w][hh];
+                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.lo[X == 3 ? j : 0][hh],
+                                                                     bv, c0, 0, 0, 0);
+                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.hi[j][hh], bl, c0, 0, 0,
+                                                                     0);
+                        acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.hi[j][hh], bv,
+                                                                             c0, 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int hh = 0; hh < NH; ++hh)
+                        acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            wt.hi[j][hh], bv, j == 0 ? bias[hh] : acc[w][hh], 0, 0, 0);
+                }
             }
         }
     }
@@ -250,13 +303,32 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
         for (int hh = 0; hh < NH; ++hh)
 #pragma unroll
             for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[w][hh][r];
-        mf::ln_cosh_n<8>(zv, hv);
+        if (X == 3)
+            mf::ln_cosh_x3_n<8>(zv, hv);
+        else
+            mf::ln_cosh_n<8>(zv, hv);
         if (!last) {
-            if (valid[w]) {
+            if (X == 3) {
+                uint16_t hi[8], lo[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) mf::split_bf16(hv[r], &hi[r], &lo[r]);
+                if (valid[w]) {
+                    const u32x4 ph = {pack_u16(hi[0], hi[1]), pack_u16(hi[2], hi[3]),
+                                      pack_u16(hi[4], hi[5]), pack_u16(hi[6], hi[7])};
+                    const u32x4 pl = {pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
+                                      pack_u16(lo[4], lo[5]), pack_u16(lo[6], lo[7])};
+                    *(u32x4 *)(nxt + aout[w]) = ph;
+                    *(u32x4 *)(nxt + aout[w] + 4 * ta[w].psn) = pl;
+                    if (COMMIT) {
+                        *(u32x4 *)(wcache + site_w[w] * F::SITE + g * 8) = ph;
+                        *(u32x4 *)(wcache + site_w[w] * F::SITE + C + g * 8) = pl;
+                    }
+                }
+            } else if (valid[w]) {
                 const u32x4 pk = {pack_bf16(hv[0], hv[1]), pack_bf16(hv[2], hv[3]),
                                   pack_bf16(hv[4], hv[5]), pack_bf16(hv[6], hv[7])};
                 *(u32x4 *)(nxt + aout[w]) = pk;
-                if (COMMIT) *(u32x4 *)(wcache + site_w[w] * C + g * 8) = pk;
+                if (COMMIT) *(u32x4 *)(wcache + site_w[w] * F::SITE + g * 8) = pk;
             }
         } else {
             double part = 0.0;
@@ -272,15 +344,22 @@ __device__ __forceinline__ void cone_group(const bf16x8 (&wa)[KS][NH], const flo
     }
 }
 
-// Waves that work on a layer of ntiles tiles: small layers go to two waves, so
-// that the other two need not fetch that layer's weights.
-__device__ __forceinline__ int active_waves(int ntiles) { return ntiles <= 8 ? 2 : kNW; }
+// Waves that work on a layer of ntiles tiles.  Plain form: small layers go to
+// two waves, so that the other two need not fetch that layer's weights.  Split
+// form (eight waves, three times the matrix work per tile): one tile per wave
+// as far as the tiles go.
+template <int X>
+__device__ __forceinline__ int active_waves(int ntiles)
+{
+    if (X == 3) return ntiles < Form<X>::NW ? ntiles : Form<X>::NW;
+    return ntiles <= 8 ? 2 : Form<X>::NW;
+}
 
-// All tiles of layer k owned by this wave (tiles wave, wave + kNW, ...), one at
-// a time (three workgroups per CU supply the parallelism a second tile in
-// flight would), with the layer's weights in `wa`.
-template <bool last, bool COMMIT>
-__device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const float *bs,
+// All tiles of layer k owned by this wave (tiles wave, wave + nw, ...), one at
+// a time (the other workgroups / waves of the CU supply the parallelism a
+// second tile in flight would), with the layer's weights in `wt`.
+template <int X, bool last, bool COMMIT>
+__device__ __forceinline__ void cone_layer(const Weights<X> &wt, const float *bs,
                                            const unsigned char *cur, unsigned char *nxt,
                                            uint16_t *wcache, double *whsum, int psc,
                                            int psn, int k, int w0, int h0, int L, int K, int ax,
@@ -296,7 +375,7 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
     a.psc = psc;
     a.psn = psn;
     const int ntiles = (a.npos + 15) >> 4;
-    const int nw = active_waves(ntiles);
+    const int nw = active_waves<X>(ntiles);
     if (wave >= nw) return;
     // bias of this lane's output rows 16 hh + 4 g + r
     floatx4 bias[NH];
@@ -307,24 +386,29 @@ __device__ __forceinline__ void cone_layer(const bf16x8 (&wa)[KS][NH], const flo
     for (; t < ntiles; t += nw) {
         TileArgs ta[1] = {a};
         ta[0].p0 = t * 16;
-        cone_group<last, 1, COMMIT>(wa, bias, cur, nxt, wcache, whsum, k, ta, L, K, ax, ay,
-                                    hsum_s, g, n16, fsum);
+        cone_group<X, last, 1, COMMIT>(wt, bias, cur, nxt, wcache, whsum, k, ta, L, K, ax, ay,
+                                       hsum_s, g, n16, fsum);
     }
 }
 
-// Three workgroups per CU: 166 VGPRs and 46 KB of LDS (K = 8) each.
+// Plain form: three workgroups per CU, 166 VGPRs and 46 KB of LDS (K = 8)
+// each.  Split form: one workgroup of eight waves per CU (93 KB of LDS at
+// K = 8).
 // NJ: the number of jobs the launch can hold.  COMMIT: write-back launch (one
 // job): items whose chain is flagged in commit[] store the activations of
 // their cone into the cache and their site sums into hsum, so that the cache
 // becomes the base pass of S' (the arithmetic is the base pass's, so the
 // values are those a new base pass would give); other items are skipped.
 // Reads of the cache (ring, layer k) and writes (R_k, layer k) never meet.
-template <int NJ, bool COMMIT>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+template <int NJ, bool COMMIT, int X>
+__global__ void __launch_bounds__(Form<X>::kThreads)
+    __attribute__((amdgpu_waves_per_eu(Form<X>::WPE, Form<X>::WPE)))
 k_net_cone(ConeJobs jobs)
 {
+    using F = Form<X>;
+    constexpr int kThreads = F::kThreads;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    __shared__ double red[kNW];
+    __shared__ double red[F::NW];
 
     const int K = jobs.job[0].K;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -350,9 +434,10 @@ k_net_cone(ConeJobs jobs)
         for (int j = 1; j < NJ; ++j) jb = (u >= first[j]) ? j : jb;
         return jb;
     };
-    bf16x8 wa[KS][NH];
-    if (xcd * seg + slot < u_end) load_layer(wa, jobs.job[job_of(xcd * seg + slot)], 2, lane);
-    float *w1s = reinterpret_cast<float *>(lds + kChunks * (jobs.job[0].ps_a + jobs.job[0].ps_b));
+    Weights<X> wt;
+    if (xcd * seg + slot < u_end) load_layer<X>(wt, jobs.job[job_of(xcd * seg + slot)], 2, lane);
+    float *w1s =
+        reinterpret_cast<float *>(lds + F::CH * (jobs.job[0].ps_a + jobs.job[0].ps_b));
     float *bs = w1s + kW1Floats;   // bias of layer k at bs[(k - 2) C]
     int w1_job = -1;   // job whose layer-1 weights w1s holds
 
@@ -385,9 +470,10 @@ k_net_cone(ConeJobs jobs)
         const int ax = xi, ay = (tau == 3) ? wrap_l(yi - 1, L) : yi;
         const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
         const int8_t *sp = prm.spins + (int64_t)s * N;
-        const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * N * C;
+        const int64_t layer_el = (int64_t)N * F::SITE;   // cache values per layer
+        const uint16_t *cache_s = prm.cache + (int64_t)s * (K - 1) * layer_el;
         const double *hsum_s = prm.hsum + (int64_t)s * N;
-        uint16_t *wcache_s = COMMIT ? prm.cache_w + (int64_t)s * (K - 1) * N * C : nullptr;
+        uint16_t *wcache_s = COMMIT ? prm.cache_w + (int64_t)s * (K - 1) * layer_el : nullptr;
         double *whsum_s = COMMIT ? prm.hsum_w + (int64_t)s * N : nullptr;
 
         const int *roff = roff_j + tau * kMaxK;
@@ -395,10 +481,10 @@ k_net_cone(ConeJobs jobs)
         // ---- layer 1 (vector ALU) into W_2 (buffer A), two channels per thread ----
         RingTab tab;
         {
-            ring_tab_load(tab, prm, true, roff[0], roff[1], tid);
+            ring_tab_load<X>(tab, prm, true, roff[0], roff[1], tid);
             Ring ring;
-            ring_fetch(ring, tab, tid, ax, ay, L, prm.ps_a, cache_s);
-            ring_tab_load(tab, prm, K >= 3, roff[1], roff[K >= 3 ? 2 : 1], tid);
+            ring_fetch<X>(ring, tab, tid, ax, ay, L, prm.ps_a, cache_s);
+            ring_tab_load<X>(tab, prm, K >= 3, roff[1], roff[K >= 3 ? 2 : 1], tid);
             const int ex1 = w0 + 2, ey1 = h0 + 2;
             const int pos = tid >> 4, m = tid & 15;
             if (pos < ex1 * ey1) {
@@ -419,21 +505,35 @@ k_net_cone(ConeJobs jobs)
                     z0 = __builtin_fmaf(wm[t], sv[t], z0);
                     z1 = __builtin_fmaf(wm[10 + t], sv[t], z1);
                 }
-                const float h0v = mf::ln_cosh(z0);
-                const float h1v = mf::ln_cosh(z1);
                 const int p2 = ex1 + 4;                  // pitch of W_2 (its width)
-                *(uint32_t *)(lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk +
-                              (m & 3) * 4) = pack_bf16(h0v, h1v);
-                if (COMMIT)
-                    *(uint32_t *)(wcache_s + (gy * L + gx) * C + (m >> 2) * 8 + (m & 3) * 2) =
-                        pack_bf16(h0v, h1v);
+                unsigned char *dst =
+                    lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk + (m & 3) * 4;
+                uint16_t *cdst = COMMIT ? wcache_s + (gy * L + gx) * F::SITE + (m >> 2) * 8 +
+                                              (m & 3) * 2
+                                        : nullptr;
+                if (X == 3) {
+                    uint16_t h0u, l0u, h1u, l1u;
+                    mf::split_bf16(mf::ln_cosh_x3(z0), &h0u, &l0u);
+                    mf::split_bf16(mf::ln_cosh_x3(z1), &h1u, &l1u);
+                    *(uint32_t *)dst = pack_u16(h0u, h1u);
+                    *(uint32_t *)(dst + 4 * prm.ps_a) = pack_u16(l0u, l1u);
+                    if (COMMIT) {
+                        *(uint32_t *)cdst = pack_u16(h0u, h1u);
+                        *(uint32_t *)(cdst + C) = pack_u16(l0u, l1u);
+                    }
+                } else {
+                    const float h0v = mf::ln_cosh(z0);
+                    const float h1v = mf::ln_cosh(z1);
+                    *(uint32_t *)dst = pack_bf16(h0v, h1v);
+                    if (COMMIT) *(uint32_t *)cdst = pack_bf16(h0v, h1v);
+                }
             }
-            ring_store(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, prm.ps_a, cache_s);
+            ring_store<X>(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, prm.ps_a, cache_s);
         }
         // ring of W_{k+1}, fetched one layer ahead; its table entries two ahead
         Ring ring;
-        ring_fetch(ring, tab, tid, ax, ay, L, prm.ps_b, cache_s + (int64_t)(K >= 3 ? N * C : 0));
-        ring_tab_load(tab, prm, K >= 4, roff[K >= 4 ? 2 : 0], roff[K >= 4 ? 3 : 0], tid);
+        ring_fetch<X>(ring, tab, tid, ax, ay, L, prm.ps_b, cache_s + (K >= 3 ? layer_el : 0));
+        ring_tab_load<X>(tab, prm, K >= 4, roff[K >= 4 ? 2 : 0], roff[K >= 4 ? 3 : 0], tid);
         __syncthreads();
 
         double fsum = 0.0;
@@ -445,30 +545,30 @@ k_net_cone(ConeJobs jobs)
             // ring of W_{k+1} into the buffer W_{k-1} occupied, the ring of
             // W_{k+2} on its way, and the table entries of the ring of W_{k+3}
             if (k < K) {
-                ring_store(ring, prm, tid, nxt, roff[k - 1], roff[k], ax, ay, L, psn,
-                           cache_s + (int64_t)(k - 1) * N * C);
+                ring_store<X>(ring, prm, tid, nxt, roff[k - 1], roff[k], ax, ay, L, psn,
+                              cache_s + (int64_t)(k - 1) * layer_el);
                 if (k + 1 < K) {
                     // W_{k+2} lives in the buffer of W_k
-                    ring_fetch(ring, tab, tid, ax, ay, L, psc, cache_s + (int64_t)k * N * C);
+                    ring_fetch<X>(ring, tab, tid, ax, ay, L, psc, cache_s + (int64_t)k * layer_el);
                     const bool more = k + 2 < K;
-                    ring_tab_load(tab, prm, more, roff[more ? k + 1 : 0], roff[more ? k + 2 : 0],
-                                  tid);
+                    ring_tab_load<X>(tab, prm, more, roff[more ? k + 1 : 0],
+                                     roff[more ? k + 2 : 0], tid);
                 }
             }
-            uint16_t *wc = COMMIT ? wcache_s + (int64_t)(k - 1) * N * C : nullptr;
+            uint16_t *wc = COMMIT ? wcache_s + (int64_t)(k - 1) * layer_el : nullptr;
             if (k < K)
-                cone_layer<false, COMMIT>(wa, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0, L, K,
-                                          ax, ay, hsum_s, wave, g, n16, fsum);
+                cone_layer<X, false, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0,
+                                             L, K, ax, ay, hsum_s, wave, g, n16, fsum);
             else
-                cone_layer<true, COMMIT>(wa, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0, L, K,
-                                         ax, ay, hsum_s, wave, g, n16, fsum);
+                cone_layer<X, true, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, psc, psn, k, w0, h0,
+                                            L, K, ax, ay, hsum_s, wave, g, n16, fsum);
             // weights of the next layer if this wave works on it; after the last,
             // layer 2's of the next configuration (whose job may differ)
             if (k < K) {
                 const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
-                if (wave < active_waves(nt_next)) load_layer(wa, prm, k + 1, lane);
+                if (wave < active_waves<X>(nt_next)) load_layer<X>(wt, prm, k + 1, lane);
             } else if (u + per_xcd < u_end) {
-                load_layer(wa, jobs.job[job_of(u + per_xcd)], 2, lane);
+                load_layer<X>(wt, jobs.job[job_of(u + per_xcd)], 2, lane);
             }
             __syncthreads();
         }
@@ -478,7 +578,7 @@ k_net_cone(ConeJobs jobs)
         __syncthreads();
         if (tid == 0) {
             double v = 0.0;
-            for (int w = 0; w < kNW; ++w) v += red[w];
+            for (int w = 0; w < F::NW; ++w) v += red[w];
             if (!isfinite(v)) atomicOr(prm.err, kErrNonFinite);
             prm.dlog[unit] = v;
         }
@@ -505,7 +605,13 @@ inline void plane_strides(int K, int *ps_a, int *ps_b)
 
 bool cone_supported(const nqs_ctx *c)
 {
-    return c->C == 32 && c->K >= 2 && c->L >= 2 * c->K + 4 && mfma_supported(c) &&
+    return c->dtype == NQS_BF16 && c->C == 32 && c->K >= 2 && c->L >= 2 * c->K + 4 &&
+           mfma_supported(c) && cone_lds_bytes(c) <= 159 * 1024;
+}
+
+bool cone_x3_supported(const nqs_ctx *c)
+{
+    return c->dtype == NQS_BF16X3 && c->C == 32 && c->K >= 2 && c->L >= 2 * c->K + 4 &&
            cone_lds_bytes(c) <= 159 * 1024;
 }
 
@@ -513,7 +619,8 @@ size_t cone_lds_bytes(const nqs_ctx *c)
 {
     int a, b;
     plane_strides(c->K, &a, &b);
-    return (size_t)kChunks * (a + b) + sizeof(float) * (kW1Floats + kBiasFloats);
+    const int ch = c->dtype == NQS_BF16X3 ? Form<3>::CH : Form<1>::CH;
+    return (size_t)ch * (a + b) + sizeof(float) * (kW1Floats + kBiasFloats);
 }
 
 // Ring tables of the unwrapped geometry: for bond type tau and k = 1..K-1 the
@@ -550,6 +657,22 @@ nqs_status cone_build_ring_tables(nqs_ctx *c)
     return NQS_OK;
 }
 
+template <int NJ, bool COMMIT, int X>
+static void cone_launch_x(const ConeJobs &jp, const nqs_ctx *c0, size_t lds, hipStream_t s)
+{
+    const void *fn = (const void *)k_net_cone<NJ, COMMIT, X>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, Form<X>::kThreads, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    // persistent grid of resident workgroups, a multiple of the XCD count
+    const int64_t want = std::max<int64_t>((int64_t)c0->n_cu * per_cu / kXcd * kXcd, kXcd);
+    NQS_LAUNCH((k_net_cone<NJ, COMMIT, X>), dim3((unsigned)want), dim3(Form<X>::kThreads), lds,
+               s, jp);
+}
+
 // commit: null for the exchanged-configuration pass; else the write-back
 // launch (one job) for the chains flagged in commit[]
 static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipStream_t s)
@@ -568,6 +691,7 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
         p.qlen = jobs[i].qlen;
         p.capacity = jobs[i].capacity;
         p.wa = (const bf16x8 *)c->w_mfma;
+        p.wl = (const bf16x8 *)c->w_mfma_lo;
         p.w1 = c->w_l1;
         p.bias = c->w_l1 + 9 * C;
         p.cache = (const uint16_t *)jobs[i].cache;
@@ -578,34 +702,32 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
         for (int t = 0; t < 4; ++t)
             for (int k = 0; k < kMaxK; ++k) jp.ring_off[i][t][k] = c->cone_off[(size_t)t * kMaxK + k];
         plane_strides(c->K, &p.ps_a, &p.ps_b);
-        p.buf_b = kChunks * p.ps_a;
+        p.buf_b = (c->dtype == NQS_BF16X3 ? Form<3>::CH : Form<1>::CH) * p.ps_a;
         p.commit = commit;
         p.cache_w = (uint16_t *)jobs[i].cache;
         p.hsum_w = const_cast<double *>(jobs[i].hsum);
         total_cap += jobs[i].capacity;
     }
     if (total_cap <= 0) return;
-    const size_t lds = cone_lds_bytes(jobs[0].c);
+    const nqs_ctx *c0 = jobs[0].c;
+    const size_t lds = cone_lds_bytes(c0);
     // launches of one or two lattices use the two-job instantiation (fewer
     // scalar registers; a one-job instantiation spills)
-    const void *fn = commit ? (const void *)k_net_cone<2, true>
-                            : (n > 2 ? (const void *)k_net_cone<kMaxJobs, false>
-                                     : (const void *)k_net_cone<2, false>);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    // persistent grid of resident workgroups, a multiple of the XCD count
-    const int64_t want =
-        std::max<int64_t>((int64_t)jobs[0].c->n_cu * per_cu / kXcd * kXcd, kXcd);
+    if (c0->dtype == NQS_BF16X3) {
+        if (commit)
+            cone_launch_x<2, true, 3>(jp, c0, lds, s);
+        else if (n > 2)
+            cone_launch_x<kMaxJobs, false, 3>(jp, c0, lds, s);
+        else
+            cone_launch_x<2, false, 3>(jp, c0, lds, s);
+        return;
+    }
     if (commit)
-        NQS_LAUNCH((k_net_cone<2, true>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+        cone_launch_x<2, true, 1>(jp, c0, lds, s);
     else if (n > 2)
-        NQS_LAUNCH((k_net_cone<kMaxJobs, false>), dim3((unsigned)want), dim3(kThreads), lds, s,
-                   jp);
+        cone_launch_x<kMaxJobs, false, 1>(jp, c0, lds, s);
     else
-        NQS_LAUNCH((k_net_cone<2, false>), dim3((unsigned)want), dim3(kThreads), lds, s, jp);
+        cone_launch_x<2, false, 1>(jp, c0, lds, s);
 }
 
 void cone_forward_jobs(const ConnJob *jobs, int n, hipStream_t s) { cone_launch(jobs, n, nullptr, s); }

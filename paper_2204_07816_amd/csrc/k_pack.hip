@@ -115,7 +115,7 @@ __device__ inline int chan_of_slot_d(int q, int C)
 // BF16 A operands of layers 2..K: [l-1][j][h][lane][i]; lane l holds output
 // channel 16 h + l % 16 and the 8 reduction elements of lane group l / 16
 __global__ void k_pack_mfma(const double *__restrict__ w, int K, int C,
-                            uint16_t *__restrict__ wm)
+                            uint16_t *__restrict__ wm, uint16_t *__restrict__ wlo)
 {
     const int KS = (C == 32) ? 9 : 5, NH = C / 16;
     const int64_t per = (int64_t)KS * NH * 64 * 8, n = per * (K - 1);
@@ -137,8 +137,11 @@ __global__ void k_pack_mfma(const double *__restrict__ w, int K, int C,
             tap = 2 * j + (g >> 1);
             ci = (g & 1) * 8 + i;
         }
-        wm[q] = tap <= 8 ? bf16_rne_d(w[canon_off(l, C) + ((int64_t)co * C + ci) * 9 + tap])
-                         : (uint16_t)0;
+        const double wv = tap <= 8 ? w[canon_off(l, C) + ((int64_t)co * C + ci) * 9 + tap] : 0.0;
+        const uint16_t hi = bf16_rne_d(wv);
+        wm[q] = hi;
+        // split form: lo = bf16(W - hi), the difference exact in FP64
+        if (wlo) wlo[q] = bf16_rne_d(wv - (double)__uint_as_float((uint32_t)hi << 16));
     }
 }
 
@@ -179,10 +182,11 @@ static void device_repack(nqs_ctx *c, hipStream_t s)
     if (K > 1)
         NQS_LAUNCH(k_pack_bwd, dim3(grid_of((int64_t)9 * C * C * (K - 1))), dim3(kThreads), 0, s,
                    (const double *)c->w_canon, K, C, c->w_bwd64);
-    if (c->dtype == NQS_BF16) {
+    if (c->dtype == NQS_BF16 || c->dtype == NQS_BF16X3) {
         const int KS = (C == 32) ? 9 : 5;
         NQS_LAUNCH(k_pack_mfma, dim3(grid_of((int64_t)(K - 1) * KS * (C / 16) * 512)),
-                   dim3(kThreads), 0, s, (const double *)c->w_canon, K, C, c->w_mfma);
+                   dim3(kThreads), 0, s, (const double *)c->w_canon, K, C, c->w_mfma,
+                   c->dtype == NQS_BF16X3 ? c->w_mfma_lo : (uint16_t *)nullptr);
         NQS_LAUNCH(k_pack_l1, dim3(grid_of(9 * C + K * C)), dim3(kThreads), 0, s,
                    (const double *)c->w_canon, K, C, c->w_l1);
     }

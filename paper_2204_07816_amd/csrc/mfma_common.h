@@ -68,6 +68,71 @@ __device__ __forceinline__ void ln_cosh_n(const float *z, float *h)
     }
 }
 
+// ln cosh z in FP32 for the split (BF16X3) form, whose operands carry 16
+// significant bits: |z| < 0.5: s P(s), s = z^2, with P the degree-4 fit of
+// ln cosh(sqrt s)/s on [0, 0.25] (relative error 2.2e-9, 9e-8 once evaluated
+// in FP32); |z| >= 0.5: |z| - ln 2 + log1p(exp(-2|z|)) with the library's
+// FP32 exp and log1p (no cancellation: the result is >= 0.12 there; 7e-7
+// relative).
+// Contraction is off in these helpers: the base pass and the cone kernel must
+// round every intermediate identically, whatever code the inlined result
+// lands next to (a fused s * p - hi would change the lo part).
+__device__ __forceinline__ float ln_cosh_x3_small(float a)
+{
+#pragma clang fp contract(off)
+    const float s = a * a;
+    float p = __builtin_fmaf(0.0017842349592950431f, s, -0.006661991475716793f);
+    p = __builtin_fmaf(p, s, 0.02221489379770223f);
+    p = __builtin_fmaf(p, s, -0.08333310755059982f);
+    p = __builtin_fmaf(p, s, 0.49999999888185015f);
+    return s * p;
+}
+
+__device__ __forceinline__ float ln_cosh_x3_large(float a)
+{
+#pragma clang fp contract(off)
+    return (a - 0.69314718055994531f) + log1pf(expf(-2.0f * a));
+}
+
+// ln cosh of n values (split form) with a single wave-uniform test for the
+// large branch; every element gets the value ln_cosh_x3_small / _large gives.
+template <int n>
+__device__ __forceinline__ void ln_cosh_x3_n(const float *z, float *h)
+{
+    float amax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        const float a = fabsf(z[i]);
+        h[i] = ln_cosh_x3_small(a);
+        amax = fmaxf(amax, a);
+    }
+    if (__any(amax >= 0.5f)) {
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            const float a = fabsf(z[i]);
+            const float big = ln_cosh_x3_large(a);
+            h[i] = (a >= 0.5f) ? big : h[i];
+        }
+    }
+}
+
+__device__ __forceinline__ float ln_cosh_x3(float z)
+{
+    const float a = fabsf(z);
+    return a < 0.5f ? ln_cosh_x3_small(a) : ln_cosh_x3_large(a);
+}
+
+// Split of an FP32 value into BF16 hi + lo (both rounded to nearest even):
+// x - hi is exact in FP32, so |x - hi - lo| <= 2^-8 |x - hi| <= 2^-16 |x|.
+__device__ __forceinline__ void split_bf16(float x, uint16_t *hi, uint16_t *lo)
+{
+#pragma clang fp contract(off)
+    const __bf16 h = (__bf16)x;
+    *hi = __builtin_bit_cast(uint16_t, h);
+    *lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
+}
+
 // Channel permutation: physical slot q of a site holds logical channel
 // chan_of_slot(q).  MFMA lane group g (lanes 16g..16g+15) owns the slots of
 // chunk g, so its outputs are contiguous.

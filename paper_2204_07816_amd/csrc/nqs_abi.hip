@@ -133,11 +133,12 @@ nqs_status pack_weights(nqs_ctx *c)
     if ((st = upload(c->w_vec32, v32)) != NQS_OK) return st;
     if ((st = upload(c->w_bwd64, bw)) != NQS_OK) return st;
     if ((st = upload(c->w_canon, c->w_host)) != NQS_OK) return st;
-    if (c->dtype == NQS_BF16) {
+    if (c->dtype == NQS_BF16 || c->dtype == NQS_BF16X3) {
         // A operands of v_mfma_f32_16x16x32_bf16: lane l holds row m = l % 16
         // (output channel 16 h + m) and the 8 reduction elements (g = l/16, i)
-        // that pair with the B operand's 8 elements of lane group g.
-        std::vector<uint16_t> wm;
+        // that pair with the B operand's 8 elements of lane group g.  BF16X3
+        // also packs the lo parts: lo = bf16(W - hi), W - hi exact in FP64.
+        std::vector<uint16_t> wm, wlo;
         const int KS = (C == 32) ? 9 : 5, NH = C / 16;
         for (int l = 1; l < K; ++l)
             for (int j = 0; j < KS; ++j)
@@ -153,7 +154,15 @@ nqs_status pack_weights(nqs_ctx *c)
                                 tap = 2 * j + (g >> 1);
                                 ci = chan_of_slot_h<16>((g & 1) * 8 + i);
                             }
-                            wm.push_back(tap <= 8 ? bf16_rne(cn.W(l, co, ci, tap)) : (uint16_t)0);
+                            const double wv = tap <= 8 ? cn.W(l, co, ci, tap) : 0.0;
+                            const uint16_t hi = bf16_rne(wv);
+                            wm.push_back(hi);
+                            if (c->dtype == NQS_BF16X3) {
+                                uint32_t hb = (uint32_t)hi << 16;
+                                float hf;
+                                std::memcpy(&hf, &hb, 4);
+                                wlo.push_back(bf16_rne(wv - (double)hf));
+                            }
                         }
         std::vector<float> l1;
         for (int t = 0; t < 9; ++t)
@@ -162,6 +171,13 @@ nqs_status pack_weights(nqs_ctx *c)
             for (int co = 0; co < C; ++co) l1.push_back((float)cn.b(l, co));
         if ((st = upload(c->w_mfma, wm)) != NQS_OK) return st;
         if ((st = upload(c->w_l1, l1)) != NQS_OK) return st;
+        if (c->dtype == NQS_BF16X3) {
+            if ((st = upload(c->w_mfma_lo, wlo)) != NQS_OK) return st;
+            if (cone_x3_supported(c) && !c->cone_tab &&
+                (st = cone_build_ring_tables(c)) != NQS_OK)
+                return st;
+            return NQS_OK;
+        }
         if (!c->ring_tab && (st = mfma_build_ring_tables(c)) != NQS_OK) return st;
         if (cone_supported(c) && !c->cone_tab && (st = cone_build_ring_tables(c)) != NQS_OK)
             return st;
@@ -174,9 +190,23 @@ int64_t bonds_per_sample(const nqs_ctx *c)
     return (int64_t)2 * c->N * ((nn_moves(c) ? 1 : 0) + (nnn_moves(c) ? 1 : 0));
 }
 
+// whether the incremental cone form serves this context
+bool incremental_ok(const nqs_ctx *c)
+{
+    if (c->net != kNetLnCosh) return false;
+    if (c->dtype == NQS_BF16) return mfma_inc_supported(c);
+    if (c->dtype == NQS_BF16X3) return cone_x3_supported(c);
+    return false;
+}
+
 nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
 {
     if (m != NQS_AUTO) return m;
+    if (c->dtype == NQS_BF16X3) {
+        if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !incremental_ok(c)) ? NQS_FULL
+                                                                                       : c->tuned_mode;
+        return incremental_ok(c) ? NQS_INCREMENTAL : NQS_FULL;
+    }
     if (c->dtype != NQS_BF16) return NQS_FULL;
     if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !mfma_inc_supported(c)) ? NQS_FULL
                                                                                       : c->tuned_mode;
@@ -221,15 +251,57 @@ int64_t vec_chunk(const nqs_ctx *c, int64_t cap)
     return std::min(m, std::max<int64_t>(cap, 1));
 }
 
-// BF16 base pass: log-amplitudes, per-site sums and the activation cache of
-// the samples, in the context's workspace.
+size_t cache_bytes(const nqs_ctx *c, int64_t B)
+{
+    return std::max<size_t>(c->dtype == NQS_BF16X3 ? x3_cache_bytes(c, B) : mfma_cache_bytes(c, B),
+                            16);
+}
+
+// BF16 / BF16X3 base pass: log-amplitudes, per-site sums and the activation
+// cache of the samples, in the context's workspace.
 nqs_status bf16_base_stage(nqs_ctx *c, const int8_t *spins, int B, hipStream_t s)
 {
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
-    NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
-    mfma_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr, s);
+    NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
+    if (c->dtype == NQS_BF16X3)
+        x3_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr,
+                        nullptr, s);
+    else
+        mfma_base_forward(c, spins, B, (double *)w.fbase.ptr, (double *)w.hsum.ptr, w.cache.ptr,
+                          s);
+    return NQS_OK;
+}
+
+// BF16X3 full recomputation: buffers for chunks of `chunk` configurations
+nqs_status x3_full_reserve(nqs_ctx *c, int64_t chunk, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    NQS_TRY(ensure(w.plane_a, x3_plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.plane_b, x3_plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.hstmp, x3_sums_bytes(c, chunk), s));
+    return NQS_OK;
+}
+
+// The exchanged-configuration pass of a BF16X3 context on the queue in the
+// workspace (base pass already taken): the incremental cone or the full
+// recomputation in chunks.
+nqs_status x3_conn_stage(nqs_ctx *c, const int8_t *spins, nqs_mode mode, double *dlog,
+                         int64_t cap, hipStream_t s)
+{
+    Workspace &w = c->ws;
+    if (mode == NQS_INCREMENTAL) {
+        cone_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, cap,
+                     (double *)w.hsum.ptr, w.cache.ptr, dlog, s);
+        return NQS_OK;
+    }
+    const int64_t chunk = x3_chunk(c, cap);
+    NQS_TRY(x3_full_reserve(c, chunk, s));
+    for (int64_t q0 = 0; q0 < cap; q0 += chunk)
+        x3_conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
+                        std::min(chunk, cap - q0), (double *)w.hsum.ptr, dlog, w.plane_a.ptr,
+                        w.plane_b.ptr, w.hstmp.ptr, s);
     return NQS_OK;
 }
 
@@ -275,6 +347,22 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
     if (c->net == kNetCnn1) return cnn1_ratio_stage(c, spins, B, dlog, cap, s);
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
+    if (c->dtype == NQS_BF16X3) {
+        NQS_TRY(bf16_base_stage(c, spins, B, s));
+        if (mode == NQS_FULL) NQS_TRY(x3_full_reserve(c, x3_chunk(c, cap), s));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, s);
+        }
+        NQS_TRY(x3_conn_stage(c, spins, mode, dlog, cap, s));
+        if (c->timing) {
+            (void)hipEventRecord(e1, s);
+            c->events.push_back({e0, e1});
+        }
+        return NQS_OK;
+    }
     if (c->dtype == NQS_BF16) {
         NQS_TRY(bf16_base_stage(c, spins, B, s));
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -485,7 +573,7 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
     const int K = spec->n_layers, C = spec->channels;
     if (K < 1 || K > 16 || C < 1 || C > 32) return NQS_E_SPEC;
     if (spec->conv_dtype != NQS_FP64 && spec->conv_dtype != NQS_FP32 &&
-        spec->conv_dtype != NQS_BF16)
+        spec->conv_dtype != NQS_BF16 && spec->conv_dtype != NQS_BF16X3)
         return NQS_E_SPEC;
     if (spec->marshall_sign != 0 && spec->marshall_sign != 1) return NQS_E_SPEC;
     if (net == kNetCnn1 && spec->conv_dtype != NQS_FP64) return NQS_E_SPEC;
@@ -505,7 +593,7 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
     c->marshall = spec->marshall_sign;
     c->dtype = spec->conv_dtype;
     c->P = n_weights;
-    if (c->dtype == NQS_BF16 && !mfma_supported(c)) {
+    if ((c->dtype == NQS_BF16 && !mfma_supported(c)) || (c->dtype == NQS_BF16X3 && !x3_supported(c))) {
         delete c;
         return NQS_E_SPEC;
     }
@@ -600,6 +688,7 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->w_vec32);
     free_dev(c->w_bwd64);
     free_dev(c->w_mfma);
+    free_dev(c->w_mfma_lo);
     free_dev(c->w_l1);
     free_dev(c->ring_tab);
     free_dev(c->ring_off);
@@ -670,7 +759,6 @@ nqs_status nqs_auto_mode(const nqs_ctx *c, nqs_mode *mode)
 nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
 {
     if (!c || B_max < 0 || B_max > 131072) return NQS_E_ARG;
-    (void)mode;
     const int B = (int)B_max;
     hipStream_t s = nullptr;
     Workspace &w = c->ws;
@@ -690,7 +778,10 @@ nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
         NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
         NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
     } else if (c->dtype == NQS_BF16) {
-        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+        NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
+    } else if (c->dtype == NQS_BF16X3) {
+        NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
+        if (resolve_mode(c, mode) == NQS_FULL) NQS_TRY(x3_full_reserve(c, x3_chunk(c, cap), s));
     } else {
         const int64_t chunk = vec_chunk(c, std::max<int64_t>(cap, B));
         NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
@@ -721,8 +812,11 @@ nqs_status nqs_log_psi(nqs_ctx *c, const int8_t *spins, int64_t B, double *log_a
                               sign ? sign + b0 : nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
         }
     } else if (c->dtype == NQS_BF16) {
-        NQS_TRY(ensure(w.cache, std::max<size_t>(mfma_cache_bytes(c, B), 16), s));
+        NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
         mfma_base_forward(c, spins, (int)B, log_abs, (double *)w.hsum.ptr, w.cache.ptr, s);
+    } else if (c->dtype == NQS_BF16X3) {
+        NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
+        x3_base_forward(c, spins, (int)B, log_abs, (double *)w.hsum.ptr, w.cache.ptr, nullptr, s);
     } else {
         const int64_t chunk = vec_chunk(c, B);
         NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
@@ -743,7 +837,7 @@ nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *
     if (B > 0 && !e_loc) return NQS_E_ARG;
     if (mode != NQS_AUTO && mode != NQS_FULL && mode != NQS_INCREMENTAL) return NQS_E_ARG;
     const nqs_mode m = resolve_mode(c, mode);
-    if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+    if (m == NQS_INCREMENTAL && !incremental_ok(c))
         return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
@@ -767,7 +861,7 @@ nqs_status nqs_log_ratios(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode m
     const int64_t cap = bonds_per_sample(c) * B;
     if (capacity < cap) return NQS_E_ARG;
     const nqs_mode m = resolve_mode(c, mode);
-    if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+    if (m == NQS_INCREMENTAL && !incremental_ok(c))
         return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
@@ -877,6 +971,8 @@ nqs_status nqs_mcmc(nqs_ctx *c, int8_t *spins, int64_t B, int32_t n_steps,
     c->last_stream = s;
     if (B == 0 || n_steps == 0 || bonds_per_sample(c) == 0) return NQS_OK;
     const nqs_mode m = resolve_mode(c, mode);
+    if (m == NQS_INCREMENTAL && c->dtype == NQS_BF16X3 && !incremental_ok(c))
+        return NQS_E_UNSUPPORTED;
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.queue, sizeof(uint32_t) * B, s));
     NQS_TRY(ensure(w.qlen, sizeof(int64_t) * 4, s));
@@ -884,15 +980,14 @@ nqs_status nqs_mcmc(nqs_ctx *c, int8_t *spins, int64_t B, int32_t n_steps,
     uint32_t *queue = (uint32_t *)w.queue.ptr;
     int64_t *qlen = (int64_t *)w.qlen.ptr;
     double *dlog = (double *)w.dlog.ptr;
-    if (c->dtype == NQS_BF16 && m == NQS_INCREMENTAL && cone_supported(c)) {
+    if (m == NQS_INCREMENTAL && (cone_supported(c) || cone_x3_supported(c))) {
         // base pass once, kept current by write-back passes of the accepted chains
         NQS_TRY(ensure(w.flags, sizeof(int32_t) * B, s));
         int32_t *flag = (int32_t *)w.flags.ptr;
         NQS_TRY(bf16_base_stage(c, spins, (int)B, s));
         for (int32_t t = 0; t < n_steps; ++t) {
             launch_mcmc_propose(c, (int)B, rand_bond + (int64_t)t * B, queue, qlen, s);
-            mfma_conn_forward(c, NQS_INCREMENTAL, spins, queue, qlen, B, (double *)w.hsum.ptr,
-                              w.cache.ptr, dlog, nullptr, s);
+            cone_forward(c, spins, queue, qlen, B, (double *)w.hsum.ptr, w.cache.ptr, dlog, s);
             launch_mcmc_decide(c, spins, (int)B, queue, dlog, rand_u + (int64_t)t * B, flag,
                                accepted, false, s);
             cone_commit(c, spins, queue, qlen, B, (double *)w.hsum.ptr, w.cache.ptr, dlog, flag,
@@ -925,7 +1020,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
         NQS_TRY(check_common(c, jobs[i].spins, jobs[i].B));
         if (jobs[i].B > 0 && !jobs[i].e_loc) return NQS_E_ARG;
         const nqs_mode m = resolve_mode(c, mode);
-        if (m == NQS_INCREMENTAL && (c->dtype != NQS_BF16 || !mfma_inc_supported(c)))
+        if (m == NQS_INCREMENTAL && !incremental_ok(c))
             return NQS_E_UNSUPPORTED;
     }
     if (n == 0) return NQS_OK;
@@ -1000,24 +1095,32 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
     double ms_full = -1.0, ms_inc = -1.0;
     int best_nw = 0, best_mt = 0;
     nqs_mode best = NQS_FULL;
-    if (c->dtype == NQS_BF16) {
+    if (c->dtype == NQS_BF16 || c->dtype == NQS_BF16X3) {
         const int64_t cap = bonds_per_sample(c) * B;
         NQS_TRY(integer_stage(c, spins, (int)B, s));
         NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
         NQS_TRY(bf16_base_stage(c, spins, (int)B, s));
+        if (c->dtype == NQS_BF16X3) NQS_TRY(x3_full_reserve(c, x3_chunk(c, cap), s));
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        // one exchanged-configuration pass per candidate: a warm run, then two
-        // timed ones (ms per pass)
-        auto time_pass = [&](nqs_mode m, double *ms) -> nqs_status {
+        // one exchanged-configuration pass in form m
+        auto run = [&](nqs_mode m) {
+            if (c->dtype == NQS_BF16X3) {
+                (void)x3_conn_stage(c, spins, m, (double *)c->ws.dlog.ptr, cap, s);
+                return;
+            }
             const ConnJob j{c, spins, (const uint32_t *)c->ws.queue.ptr,
                             (const int64_t *)c->ws.qlen.ptr, cap, (const double *)c->ws.hsum.ptr,
                             c->ws.cache.ptr, (double *)c->ws.dlog.ptr};
             mfma_conn_forward_jobs(m, &j, 1, s);
+        };
+        // per candidate a warm run, then two timed ones (ms per pass)
+        auto time_pass = [&](nqs_mode m, double *ms) -> nqs_status {
+            run(m);
             HIP_OK(hipEventRecord(e0, s));
-            mfma_conn_forward_jobs(m, &j, 1, s);
-            mfma_conn_forward_jobs(m, &j, 1, s);
+            run(m);
+            run(m);
             HIP_OK(hipEventRecord(e1, s));
             HIP_OK(hipEventSynchronize(e1));
             float t = 0.f;
@@ -1025,8 +1128,9 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
             *ms = t / 2.0;
             return finish_call();
         };
-        int nw[8], mt[8];
-        const int nv = mfma_full_variants(c, nw, mt, 8);
+        int nw[8] = {0}, mt[8] = {0};
+        // the split form's full pass has a single shape
+        const int nv = c->dtype == NQS_BF16X3 ? 1 : mfma_full_variants(c, nw, mt, 8);
         const int keep_nw = c->full_nw, keep_mt = c->full_maxt;
         for (int i = 0; i < nv; ++i) {
             c->full_nw = nw[i];
@@ -1049,7 +1153,7 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
         c->full_nw = best_nw;
         c->full_maxt = best_mt;
         best = NQS_FULL;
-        if (mfma_inc_supported(c)) {
+        if (incremental_ok(c)) {
             const nqs_status st = time_pass(NQS_INCREMENTAL, &ms_inc);
             if (st != NQS_OK) {
                 (void)hipEventDestroy(e0);

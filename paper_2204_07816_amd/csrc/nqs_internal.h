@@ -81,13 +81,14 @@ struct Workspace {
     DevBuf flags;       // int32 per chain: accepted proposals of a Metropolis step
     DevBuf sgn;         // int8 [B] network sign of the samples (CNN1)
     DevBuf isign;       // int8 [capacity] network sign ratio per queue item (CNN1)
+    DevBuf hstmp;       // f64 per-site sums of full-recompute chunks (BF16X3)
     Graveyard gy;
 
     std::vector<DevBuf *> all()
     {
         return {&counts, &ediag, &offsets, &qlen,  &queue, &dlog,  &fbase,   &hsum,
                 &cache,  &plane_a, &plane_b, &zsave, &hsave, &delta, &sr,    &orows,
-                &counter, &flags, &sgn,    &isign};
+                &counter, &flags, &sgn,    &isign, &hstmp};
     }
     // every buffer files its superseded allocations with this workspace
     void bind()
@@ -115,6 +116,7 @@ struct nqs_ctx {
     float *w_vec32 = nullptr;     // vector-path packing, FP32
     double *w_bwd64 = nullptr;    // transposed packing for the backward data pass
     uint16_t *w_mfma = nullptr;   // BF16 MFMA A-operand packing, layers 2..K
+    uint16_t *w_mfma_lo = nullptr;  // BF16X3: the lo parts of the same packing
     float *w_l1 = nullptr;        // layer-1 weights + all biases, FP32, MFMA path
     int32_t *ring_tab = nullptr;  // incremental mode: ring lists per bond type and layer
     int32_t *ring_off = nullptr;
@@ -256,6 +258,24 @@ nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,
                   hipStream_t s);
+
+// --- split-BF16 (BF16X3) network kernels (k_x3.hip) ---
+bool x3_supported(const nqs_ctx *c);
+size_t x3_cache_bytes(const nqs_ctx *c, int64_t B);
+// base pass: f[B], hsum[B][N], cache [B][K-1][N][2C] (hi then lo of each site)
+void x3_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, double *hsum,
+                     void *cache, void *hs_tmp, hipStream_t s);
+// full recompute of queue items q0 .. q0+M-1 (items at or past qlen[0] skipped)
+void x3_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                     const int64_t *qlen, int64_t q0, int64_t M, const double *hsum,
+                     double *dlog, void *plane_a, void *plane_b, void *hs_tmp, hipStream_t s);
+// bytes of the full-recompute buffers of M configurations: two planes and the
+// per-site sums
+size_t x3_plane_bytes(const nqs_ctx *c, int64_t M);
+size_t x3_sums_bytes(const nqs_ctx *c, int64_t M);
+int64_t x3_chunk(const nqs_ctx *c, int64_t work);
+// incremental cone of the split form (k_net_cone.hip)
+bool cone_x3_supported(const nqs_ctx *c);
 
 // --- autotuner (tune.hip) ---
 std::string tune_cache_path();

@@ -158,7 +158,8 @@ bool write_cache(const std::string &path, const std::map<std::string, Entry> &m)
 
 std::string key_of(int L, int K, int C, nqs_dtype dt, double J2)
 {
-    const char *d = dt == NQS_BF16 ? "bf16" : (dt == NQS_FP32 ? "fp32" : "fp64");
+    const char *d = dt == NQS_BF16X3 ? "bf16x3"
+                    : dt == NQS_BF16 ? "bf16" : (dt == NQS_FP32 ? "fp32" : "fp64");
     char buf[96];
     std::snprintf(buf, sizeof buf, "gfx950 L=%d K=%d C=%d %s %s", L, K, C, d,
                   J2 != 0.0 ? "J2" : "J1only");

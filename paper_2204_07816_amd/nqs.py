@@ -15,9 +15,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnqs.so")
 
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
 AUTO, FULL, INCREMENTAL = 0, 1, 2
-_DTYPES = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_DTYPES = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
 _MODES = {"auto": AUTO, "full": FULL, "incremental": INCREMENTAL}
 
 STATUS = {
