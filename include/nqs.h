@@ -339,8 +339,9 @@ nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
  * exchanged-configuration pass is fastest here).  Runs the bond stage and
  * base pass of the B samples (device spins), then times the exchanged-
  * configuration pass in every available form -- full recompute with each
- * fitting tile variant, and the incremental receptive cone -- and makes AUTO
- * (and the full pass) use the fastest from then on.  The choice is stored in
+ * fitting tile variant, and the incremental receptive cone with each shape
+ * of its kernel (configurations per workgroup, waves) -- and makes AUTO
+ * (and the full pass and the cone kernel) use the fastest from then on.  The choice is stored in
  * the tune cache, a JSON file (NQS_TUNE_CACHE, else
  * $HOME/.cache/nqs/tune.json), under the key nqs_tune_key gives; contexts of
  * the same key created later read it.  FP64 / FP32 contexts have only the
@@ -357,9 +358,13 @@ nqs_status nqs_tune_key(int32_t L, int32_t K, int32_t C, nqs_dtype dtype,
 
 /* One entry of a tune-cache file (host only): NQS_OK with the entry when the
  * file parses and holds the key; NQS_E_ARG (outputs untouched) when it is
- * missing, malformed or lacks the key.                                     */
+ * missing, malformed or lacks the key.  cone_items / cone_waves (may be
+ * NULL): the tuned shape of the incremental cone kernel, configurations per
+ * workgroup and waves per workgroup (1 / 0: the one-configuration kernel;
+ * -1 / -1 when the entry has none).                                        */
 nqs_status nqs_tune_lookup(const char *path, const char *key, nqs_mode *mode,
-                           int32_t *full_nw, int32_t *full_maxt);
+                           int32_t *full_nw, int32_t *full_maxt, int32_t *cone_items,
+                           int32_t *cone_waves);
 
 /* Sticky device error word: synchronises the context's last stream, returns
  * the first device-detected status since the last call (host out), clears. */

@@ -585,6 +585,442 @@ k_net_cone(ConeJobs jobs)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lockstep form: G exchanged configurations per workgroup, layer by layer.
+//
+// The kernel above works on one configuration at a time, so every wave
+// re-reads a layer's A operands (18 KB plain, 36 KB split) for every
+// configuration it touches: the texture-address unit, not the matrix cores,
+// limits it.  Here a workgroup takes G consecutive queue items of one lattice
+// (mostly of one sample) and advances them together: each wave loads layer
+// k's weights once and works on the tiles of all G cones, so the weight
+// traffic per configuration falls by G.
+//
+// Each item has one frame in LDS, the rectangle R_{K+1} (2K + 4 sites square
+// for the largest bond box, CH channel planes of 16 bytes per site); window
+// W_k and output R_k of every layer are centred sub-rectangles of it, so a
+// layer is updated in place: the waves compute all their tiles of layer k
+// into registers, a barrier retires the reads of W_k, then the outputs and
+// the ring W_{k+1} \ R_k (prefetched from the sample's cache during the
+// compute) are written, and a second barrier opens layer k + 1.  Half the
+// LDS of the double-buffered windows is what lets G configurations share a
+// workgroup.  The per-site arithmetic (K-step order, products, ln cosh,
+// rounding, FP64 site sums) is the base pass's, as in the kernel above.
+// ---------------------------------------------------------------------------
+
+constexpr int kLsMaxK = 8;      // frames and register arrays are sized for K <= 8
+
+struct LsJob {
+    const int8_t *spins;
+    int L;
+    const uint32_t *queue;
+    const int64_t *qlen;
+    int64_t capacity;
+    const bf16x8 *wa, *wl;
+    const float *w1;            // layer 1 [9][C]
+    const float *bias;          // [K][C]
+    const uint16_t *cache;
+    const double *hsum;
+    double *dlog;
+    int32_t *err;
+};
+
+struct LsJobs {
+    LsJob job[kMaxJobs];
+    int n, K;
+    const int32_t *tab;         // frame ring tables (identical for every job of one K)
+    int16_t off[4][kMaxK];      // [tau][k - 1]: first entry of the ring W_{k+1} \ R_k; [tau][K - 1]: end
+};
+
+template <int X, int G, int NW>
+struct LsShape {
+    static constexpr int CH = Form<X>::CH;
+    static constexpr int SITE = Form<X>::SITE;
+    static constexpr int THREADS = NW * 64;
+    static constexpr int TILES_MAX = ((2 * kLsMaxK + 2) * (2 * kLsMaxK + 2) + 15) / 16;
+    static constexpr int MAXT = (G * TILES_MAX + NW - 1) / NW;    // tiles per wave and layer
+    static constexpr int RING_MAX = 16 * (kLsMaxK - 1) + 32;      // ring sites per item and layer
+    static constexpr int MAXR = (G * RING_MAX * CH + THREADS - 1) / THREADS;
+};
+
+// one batch item, kept in LDS
+struct LsItem {
+    int s, tau, ax, ay, qi, qj, live, pad;
+    int64_t unit;
+};
+
+__device__ __forceinline__ int box_w(int tau) { return tau == 1 ? 1 : 2; }
+__device__ __forceinline__ int box_h(int tau) { return tau == 0 ? 1 : 2; }
+
+// Prefix tables of one layer (LDS): first tile and first ring chunk of each
+// item, item after item.  Filled by thread 0 for the next layer between the
+// layer's two barriers, so no wave reads them while they change.
+template <int G>
+struct LsTab {
+    int tile[G + 1];
+    int ring[G + 1];
+};
+
+template <int X, int G>
+__device__ __forceinline__ void ls_fill_tab(LsTab<G> &t, const LsItem *items, const LsJobs &jobs,
+                                            int k, int K)
+{
+    t.tile[0] = 0;
+    t.ring[0] = 0;
+    for (int i = 0; i < G; ++i) {
+        const LsItem it = items[i];
+        const int ex = box_w(it.tau) + 2 * k, ey = box_h(it.tau) + 2 * k;
+        t.tile[i + 1] = t.tile[i] + (it.live ? (ex * ey + 15) >> 4 : 0);
+        // ring W_{k+1} \ R_k (none after the last layer)
+        t.ring[i + 1] = t.ring[i] + ((k < K && it.live)
+                                         ? (jobs.off[it.tau][k] - jobs.off[it.tau][k - 1]) * Form<X>::CH
+                                         : 0);
+    }
+}
+
+// item of entry q of a prefix table (q < tab[G])
+template <int G>
+__device__ __forceinline__ int ls_item_of(const int *tab, int q)
+{
+    int i = 0;
+    for (int j = 1; j < G; ++j) i = (q >= tab[j]) ? j : i;
+    return i;
+}
+
+template <int X, int G, int NW, int WPE>
+__global__ void __launch_bounds__(NW * 64)
+    __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_net_cone_ls(LsJobs jobs)
+{
+    using S = LsShape<X, G, NW>;
+    using F = Form<X>;
+    constexpr int kThreads = S::THREADS;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+
+    const int K = jobs.K;
+    const int FW = 2 * K + 4;                  // frame width and height (sites)
+    const int PB = FW * FW * kChunk;           // bytes of one channel plane of a frame
+    const int FB = S::CH * PB;                 // bytes of a frame
+    float *w1s = reinterpret_cast<float *>(lds + G * FB);
+    float *bs = w1s + kW1Floats;               // bias of layer k at bs[(k - 2) C]
+    LsItem *items = reinterpret_cast<LsItem *>(bs + (K - 1) * C);
+    double *red = reinterpret_cast<double *>(items + G);     // [NW][G]
+    LsTab<G> *tab = reinterpret_cast<LsTab<G> *>(red + NW * G);   // [2]: by layer parity
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, n16 = lane & 15;
+
+    // batches of one job each: job j holds ceil(n_j / G) batches (at most two jobs)
+    const int64_t n0 = jobs.n > 0 ? min(jobs.job[0].qlen[0], jobs.job[0].capacity) : 0;
+    const int64_t n1 = jobs.n > 1 ? min(jobs.job[1].qlen[0], jobs.job[1].capacity) : 0;
+    const int64_t nb0 = (n0 + G - 1) / G;
+    const int64_t n_batches = nb0 + (n1 + G - 1) / G;
+    const int per_xcd = gridDim.x / kXcd;
+    const int xcd = blockIdx.x % kXcd, slot = blockIdx.x / kXcd;
+    const int64_t seg = (n_batches + kXcd - 1) / kXcd;
+    const int64_t b_end = min(n_batches, (xcd + 1) * seg);
+
+    int w1_job = -1;
+
+    for (int64_t b = xcd * seg + slot; b < b_end; b += per_xcd) {
+        const int jb = b >= nb0 ? 1 : 0;
+        const LsJob &jp = jobs.job[jb];
+        const int L = jp.L, N = L * L;
+        const int64_t i0 = (b - (jb ? nb0 : 0)) * G;
+        const int64_t n_job = jb ? n1 : n0;
+        const int64_t layer_el = (int64_t)N * F::SITE;
+        // the previous batch's reads of its frames and tables are retired
+        // (it ended with a barrier); load this batch's items and tables
+        if (tid < G) {
+            LsItem it{};
+            const int64_t u = i0 + tid;
+            it.live = u < n_job;
+            it.unit = u;
+            if (it.live) {
+                const uint32_t e = jp.queue[u];
+                it.s = item_sample(e);
+                const int bd = item_bond(e), tau = bd & 3, q0 = bd >> 2;
+                const int xi = q0 % L, yi = q0 / L;
+                it.tau = tau;
+                it.qi = q0;
+                it.qj = wrap_l(yi + bond_dy(tau), L) * L + wrap_l(xi + bond_dx(tau), L);
+                it.ax = xi;
+                it.ay = (tau == 3) ? wrap_l(yi - 1, L) : yi;
+            }
+            items[tid] = it;
+        }
+        if (jb != w1_job) {
+            for (int q = tid; q < kW1Floats; q += kThreads) {
+                const int m = q / 20, r = q - 20 * (q / 20);
+                const int co = mf::chan_of_slot<C>(2 * m + (r >= 10 ? 1 : 0));
+                const int t = r >= 10 ? r - 10 : r;
+                w1s[q] = t < 9 ? jp.w1[t * C + co] : jp.bias[co];
+            }
+            for (int q = tid; q < (K - 1) * C; q += kThreads) bs[q] = jp.bias[C + q];
+            w1_job = jb;
+        }
+        __syncthreads();
+        // ring W_2 \ R_1 (prefix in tab[1].ring) and layer 2's tiles and ring (tab[0])
+        if (tid == 0) {
+            ls_fill_tab<X, G>(tab[1], items, jobs, 1, K);
+            ls_fill_tab<X, G>(tab[0], items, jobs, 2, K);
+        }
+
+        // ---- layer 1 (vector ALU) on R_1 of every item, two channels per unit ----
+        for (int q = tid; q < G * 256; q += kThreads) {
+            const int i = q >> 8, pos = (q >> 4) & 15, m = q & 15;
+            const LsItem it = items[i];
+            const int w0 = box_w(it.tau), h0 = box_h(it.tau);
+            const int ex1 = w0 + 2;
+            if (!it.live || pos >= ex1 * (h0 + 2)) continue;
+            const int u = pos % ex1, v = pos / ex1;
+            const int gx = wrap_l(it.ax + u - 1, L), gy = wrap_l(it.ay + v - 1, L);
+            const int8_t *sp = jp.spins + (int64_t)it.s * N;
+            float sv[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                int site = wrap_l(gy + t / 3 - 1, L) * L + wrap_l(gx + t % 3 - 1, L);
+                site = (site == it.qi) ? it.qj : ((site == it.qj) ? it.qi : site);
+                sv[t] = (float)sp[site];
+            }
+            const float *wm = w1s + 20 * m;
+            float z0 = wm[9], z1 = wm[19];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                z0 = __builtin_fmaf(wm[t], sv[t], z0);
+                z1 = __builtin_fmaf(wm[10 + t], sv[t], z1);
+            }
+            // R_1 sits at frame (K + u, K + v)
+            unsigned char *dst =
+                lds + i * FB + (m >> 2) * PB + ((K + v) * FW + K + u) * kChunk + (m & 3) * 4;
+            if (X == 3) {
+                uint16_t h0u, l0u, h1u, l1u;
+                mf::split_bf16(mf::ln_cosh_x3(z0), &h0u, &l0u);
+                mf::split_bf16(mf::ln_cosh_x3(z1), &h1u, &l1u);
+                *(uint32_t *)dst = pack_u16(h0u, h1u);
+                *(uint32_t *)(dst + 4 * PB) = pack_u16(l0u, l1u);
+            } else {
+                *(uint32_t *)dst = pack_bf16(mf::ln_cosh(z0), mf::ln_cosh(z1));
+            }
+        }
+        __syncthreads();                        // tables visible
+        // ring W_2 \ R_1 from the cache of layer 1
+        {
+            const int *rt = tab[1].ring;
+            const int total = rt[G];
+            for (int q = tid; q < total; q += kThreads) {
+                const int i = ls_item_of<G>(rt, q);
+                const LsItem it = items[i];
+                const int r = q - rt[i], e = r / S::CH, c = r - e * S::CH;
+                const int ent = jobs.tab[jobs.off[it.tau][0] + e];
+                const int fx = (ent >> 16) & 255, fy = (uint32_t)ent >> 24;
+                const int site = wrap_l(it.ay + fy - K - 1, L) * L + wrap_l(it.ax + fx - K - 1, L);
+                *(u32x4 *)(lds + i * FB + c * PB + (ent & 0xffff) * kChunk) =
+                    *(const u32x4 *)(jp.cache + (int64_t)it.s * (K - 1) * layer_el +
+                                     (int64_t)site * F::SITE + c * 8);
+            }
+        }
+        __syncthreads();
+
+        double fs[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) fs[i] = 0.0;
+
+        for (int k = 2; k <= K; ++k) {
+            const bool last = (k == K);
+            const LsTab<G> &tk = tab[k & 1 ? 1 : 0];
+            const int ntiles = tk.tile[G];
+            // ring W_{k+1} \ R_k of every item (cache of layer k), in flight
+            // during the compute
+            u32x4 rv[S::MAXR];
+            int rdst[S::MAXR];
+            const int rtotal = tk.ring[G];
+#pragma unroll
+            for (int r = 0; r < S::MAXR; ++r) {
+                const int q = tid + r * kThreads;
+                rdst[r] = -1;
+                if (q < rtotal) {
+                    const int i = ls_item_of<G>(tk.ring, q);
+                    const LsItem it = items[i];
+                    const int rr = q - tk.ring[i], e = rr / S::CH, c = rr - e * S::CH;
+                    const int ent = jobs.tab[jobs.off[it.tau][k - 1] + e];
+                    const int fx = (ent >> 16) & 255, fy = (uint32_t)ent >> 24;
+                    const int site =
+                        wrap_l(it.ay + fy - K - 1, L) * L + wrap_l(it.ax + fx - K - 1, L);
+                    rv[r] = *(const u32x4 *)(jp.cache + ((int64_t)it.s * (K - 1) + (k - 1)) * layer_el +
+                                             (int64_t)site * F::SITE + c * 8);
+                    rdst[r] = i * FB + c * PB + (ent & 0xffff) * kChunk;
+                }
+            }
+            // bias of this lane's output rows 16 hh + 4 g + r
+            floatx4 bias[NH];
+#pragma unroll
+            for (int hh = 0; hh < NH; ++hh)
+                bias[hh] = *(const floatx4 *)(bs + (k - 2) * C + 16 * hh + 4 * g);
+
+            // this wave's tiles: tile n is T = wave + n NW; per tile the LDS
+            // address of tap (0, 0), the output address (-1: not stored) and,
+            // in the last layer, the lattice site and item of the output
+            int a0[S::MAXT], oaddr[S::MAXT], osite[S::MAXT], oitem[S::MAXT];
+#pragma unroll
+            for (int n = 0; n < S::MAXT; ++n) {
+                const int T = wave + n * NW;
+                a0[n] = 0;
+                oaddr[n] = -1;
+                osite[n] = -1;
+                oitem[n] = 0;
+                if (T >= ntiles) continue;      // uniform over the wave
+                const int i = ls_item_of<G>(tk.tile, T);
+                const LsItem it = items[i];
+                const int ex = box_w(it.tau) + 2 * k, npos = ex * (box_h(it.tau) + 2 * k);
+                int p = (T - tk.tile[i]) * 16 + n16;
+                const bool valid = p < npos;
+                p = valid ? p : npos - 1;
+                // p / ex as (p * ceil(2^20 / ex)) >> 20: exact for ex <= 64, p < 66 ex
+                const uint32_t mul = ((1u << 20) + ex - 1) / ex;
+                const int v = (int)(((uint32_t)p * mul) >> 20), u = p - v * ex;
+                const int fx = K + 1 - k + u, fy = K + 1 - k + v;     // output site in the frame
+                a0[n] = i * FB + g * PB + ((fy - 1) * FW + fx - 1) * kChunk;
+                if (valid) {
+                    oaddr[n] = i * FB + g * PB + (fy * FW + fx) * kChunk;
+                    osite[n] = it.s * N + wrap_l(it.ay + fy - K - 1, L) * L +
+                               wrap_l(it.ax + fx - K - 1, L);
+                }
+                oitem[n] = i;
+            }
+            // taps outermost: the tap's A operands (streamed, the next tap's in
+            // flight) against every tile of the wave; per tile and half the
+            // accumulation order is the base pass's (bias, then taps 0..8)
+            floatx4 acc[S::MAXT][NH];
+            const bf16x8 *wbase = jp.wa + (int64_t)(k - 2) * KS * NH * 64 + lane;
+            const bf16x8 *lbase = jp.wl + (int64_t)(k - 2) * KS * NH * 64 + lane;
+            bf16x8 ah[NH], al[NH], nh[NH], nl[NH];
+#pragma unroll
+            for (int hh = 0; hh < NH; ++hh) {
+                ah[hh] = wbase[hh * 64];
+                if (X == 3) al[hh] = lbase[hh * 64];
+            }
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                if (j + 1 < KS) {
+#pragma unroll
+                    for (int hh = 0; hh < NH; ++hh) {
+                        nh[hh] = wbase[((j + 1) * NH + hh) * 64];
+                        if (X == 3) nl[hh] = lbase[((j + 1) * NH + hh) * 64];
+                    }
+                }
+                const int toff = ((j / 3) * FW + (j % 3)) * kChunk;
+#pragma unroll
+                for (int n = 0; n < S::MAXT; ++n) {
+                    if (wave + n * NW >= ntiles) continue;     // uniform
+                    const unsigned char *ap = lds + a0[n] + toff;
+                    const bf16x8 bv = *(const bf16x8 *)ap;
+                    if (X == 3) {
+                        const bf16x8 bl = *(const bf16x8 *)(ap + 4 * PB);
+#pragma unroll
+                        for (int hh = 0; hh < NH; ++hh) {
+                            floatx4 c0 = j == 0 ? bias[hh] : acc[n][hh];
+                            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[hh], bv, c0, 0, 0, 0);
+                            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[hh], bl, c0, 0, 0, 0);
+                            acc[n][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[hh], bv, c0, 0,
+                                                                                 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int hh = 0; hh < NH; ++hh)
+                            acc[n][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ah[hh], bv, j == 0 ? bias[hh] : acc[n][hh], 0, 0, 0);
+                    }
+                }
+                if (j + 1 < KS) {
+#pragma unroll
+                    for (int hh = 0; hh < NH; ++hh) {
+                        ah[hh] = nh[hh];
+                        if (X == 3) al[hh] = nl[hh];
+                    }
+                }
+            }
+            // epilogue: ln cosh, then BF16 (split: hi and lo) held for the
+            // in-place store, or the last layer's site sums
+            u32x4 oh[S::MAXT], ol[X == 3 ? S::MAXT : 1];
+#pragma unroll
+            for (int n = 0; n < S::MAXT; ++n) {
+                if (wave + n * NW >= ntiles) continue;         // uniform
+                float zv[8], hv[8];
+#pragma unroll
+                for (int hh = 0; hh < NH; ++hh)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[n][hh][r];
+                if (X == 3)
+                    mf::ln_cosh_x3_n<8>(zv, hv);
+                else
+                    mf::ln_cosh_n<8>(zv, hv);
+                if (!last) {
+                    if (X == 3) {
+                        uint16_t hi[8], lo[8];
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) mf::split_bf16(hv[r], &hi[r], &lo[r]);
+                        oh[n] = u32x4{pack_u16(hi[0], hi[1]), pack_u16(hi[2], hi[3]),
+                                      pack_u16(hi[4], hi[5]), pack_u16(hi[6], hi[7])};
+                        ol[X == 3 ? n : 0] = u32x4{pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
+                                                   pack_u16(lo[4], lo[5]), pack_u16(lo[6], lo[7])};
+                    } else {
+                        oh[n] = u32x4{pack_bf16(hv[0], hv[1]), pack_bf16(hv[2], hv[3]),
+                                      pack_bf16(hv[4], hv[5]), pack_bf16(hv[6], hv[7])};
+                    }
+                } else {
+                    double part = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) part += (double)hv[r];
+                    part += __shfl_xor(part, 16);
+                    part += __shfl_xor(part, 32);
+                    if (g == 0 && osite[n] >= 0) {
+                        const double d = part - jp.hsum[osite[n]];
+                        // item oitem[n]'s sum; compared, not indexed
+#pragma unroll
+                        for (int q = 0; q < G; ++q) fs[q] += (q == oitem[n]) ? d : 0.0;
+                    }
+                }
+            }
+            __syncthreads();                    // every read of W_k and of tab[k] is done
+            if (!last) {
+                if (tid == 0) ls_fill_tab<X, G>(tab[k & 1 ? 0 : 1], items, jobs, k + 1, K);
+#pragma unroll
+                for (int n = 0; n < S::MAXT; ++n)
+                    if (oaddr[n] >= 0) {
+                        *(u32x4 *)(lds + oaddr[n]) = oh[n];
+                        if (X == 3) *(u32x4 *)(lds + oaddr[n] + 4 * PB) = ol[X == 3 ? n : 0];
+                    }
+#pragma unroll
+                for (int r = 0; r < S::MAXR; ++r)
+                    if (rdst[r] >= 0) *(u32x4 *)(lds + rdst[r]) = rv[r];
+                __syncthreads();                // W_{k+1} and tab[k + 1] are complete
+            }
+        }
+
+        // ---- per-item sums: lanes, then waves in a fixed order ----
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            double v = fs[i];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave * G + i] = v;
+        }
+        __syncthreads();
+        if (tid < G) {
+            const LsItem it = items[tid];
+            if (it.live) {
+                double v = 0.0;
+                for (int w = 0; w < NW; ++w) v += red[w * G + tid];
+                if (!isfinite(v)) atomicOr(jp.err, kErrNonFinite);
+                jp.dlog[it.unit] = v;
+            }
+        }
+        // the items, sums, tables and frames of this batch stay in use until here
+        __syncthreads();
+    }
+}
+
 // row pitch (sites) of window W_k for a changed box of width w0: its width
 inline int win_pitch(int w0, int k) { return w0 + 2 * k + 2; }
 
@@ -626,9 +1062,44 @@ size_t cone_lds_bytes(const nqs_ctx *c)
 // Ring tables of the unwrapped geometry: for bond type tau and k = 1..K-1 the
 // sites of W_{k+1} = R_{k+2} outside R_k, as (index in W_{k+1}, whose pitch is
 // P_{k+1}) | (offset from the anchor modulo L) << 16 (x) and << 24 (y).
+// Ring tables of the lockstep kernel: for bond type tau and k = 1..K-1 the
+// sites of W_{k+1} = R_{k+2} outside R_k in frame coordinates (the frame is
+// R_{K+1} of the 2 x 2 box, 2K + 4 sites square; R_k of a w0 x h0 box starts
+// at K + 1 - k), as frame index | x << 16 | y << 24.
+static void ls_tables(int K, std::vector<int32_t> &ent, std::vector<int> &off)
+{
+    const int FW = 2 * K + 4;
+    off.assign((size_t)4 * kMaxK, 0);
+    for (int tau = 0; tau < 4; ++tau) {
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        for (int k = 1; k < K; ++k) {
+            off[(size_t)tau * kMaxK + (k - 1)] = (int)ent.size();
+            const int r0 = K + 1 - k, w0r = K - 1 - k;
+            for (int fy = w0r; fy < w0r + h0 + 2 * k + 4; ++fy)
+                for (int fx = w0r; fx < w0r + w0 + 2 * k + 4; ++fx) {
+                    if (fx >= r0 && fx < r0 + w0 + 2 * k && fy >= r0 && fy < r0 + h0 + 2 * k)
+                        continue;   // R_k
+                    ent.push_back((fy * FW + fx) | (fx << 16) | (fy << 24));
+                }
+        }
+        off[(size_t)tau * kMaxK + (K - 1)] = (int)ent.size();
+    }
+}
+
 nqs_status cone_build_ring_tables(nqs_ctx *c)
 {
     const int L = c->L, K = c->K;
+    if (K <= kLsMaxK) {
+        std::vector<int32_t> le;
+        ls_tables(K, le, c->ls_off);
+        if (c->ls_tab) (void)hipFree(c->ls_tab);
+        c->ls_tab = nullptr;
+        if (hipMalloc((void **)&c->ls_tab, std::max<size_t>(le.size(), 1) * 4) != hipSuccess)
+            return NQS_E_NOMEM;
+        if (!le.empty() &&
+            hipMemcpy(c->ls_tab, le.data(), le.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return NQS_E_HIP;
+    }
     std::vector<int32_t> ent;
     c->cone_off.assign((size_t)4 * kMaxK, 0);
     for (int tau = 0; tau < 4; ++tau) {
@@ -673,11 +1144,93 @@ static void cone_launch_x(const ConeJobs &jp, const nqs_ctx *c0, size_t lds, hip
                s, jp);
 }
 
+// bytes of LDS the lockstep kernel takes for G items
+static size_t ls_lds_bytes(int K, int X, int G, int NW)
+{
+    const size_t FW = 2 * (size_t)K + 4;
+    const size_t fb = (X == 3 ? Form<3>::CH : Form<1>::CH) * FW * FW * kChunk;
+    return G * fb + sizeof(float) * (kW1Floats + (size_t)(K - 1) * C) + G * sizeof(LsItem) +
+           (size_t)NW * G * sizeof(double) + 2 * sizeof(int) * 2 * (G + 1);
+}
+
+template <int X, int G, int NW, int WPE>
+static bool ls_launch_x(const LsJobs &jp, const nqs_ctx *c0, hipStream_t s)
+{
+    const size_t lds = ls_lds_bytes(c0->K, X, G, NW);
+    if (lds > 160 * 1024) return false;
+    const void *fn = (const void *)k_net_cone_ls<X, G, NW, WPE>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t want = std::max<int64_t>((int64_t)c0->n_cu * per_cu / kXcd * kXcd, kXcd);
+    NQS_LAUNCH((k_net_cone_ls<X, G, NW, WPE>), dim3((unsigned)want), dim3(NW * 64), lds, s, jp);
+    return true;
+}
+
+// The lockstep kernel's shapes (items per workgroup, waves); variant 0 is the
+// default of each form, the autotuner may pick another.
+struct LsVariant {
+    int G, NW, WPE;
+};
+const LsVariant kLsPlain[] = {{1, 4, 3}, {2, 8, 2}};
+const LsVariant kLsSplit[] = {{1, 4, 2}, {1, 8, 2}};
+
+static bool ls_launch(const ConnJob *jobs, int n, hipStream_t s)
+{
+    const nqs_ctx *c0 = jobs[0].c;
+    if (n > 2 || c0->K > kLsMaxK || c0->ls_tab == nullptr || c0->cone_variant < 0) return false;
+    LsJobs jp{};
+    jp.n = n;
+    jp.K = c0->K;
+    jp.tab = c0->ls_tab;
+    for (int t = 0; t < 4; ++t)
+        for (int k = 0; k < kMaxK; ++k) jp.off[t][k] = (int16_t)c0->ls_off[(size_t)t * kMaxK + k];
+    int64_t total_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        const nqs_ctx *c = jobs[i].c;
+        LsJob &p = jp.job[i];
+        p.spins = jobs[i].spins;
+        p.L = c->L;
+        p.queue = jobs[i].queue;
+        p.qlen = jobs[i].qlen;
+        p.capacity = jobs[i].capacity;
+        p.wa = (const bf16x8 *)c->w_mfma;
+        p.wl = (const bf16x8 *)c->w_mfma_lo;
+        p.w1 = c->w_l1;
+        p.bias = c->w_l1 + 9 * C;
+        p.cache = (const uint16_t *)jobs[i].cache;
+        p.hsum = jobs[i].hsum;
+        p.dlog = jobs[i].dlog;
+        p.err = c->err;
+        total_cap += jobs[i].capacity;
+    }
+    if (total_cap <= 0) return true;
+    const int v = c0->cone_variant;
+    if (c0->dtype == NQS_BF16X3) {
+        switch (v) {
+        case 0: return ls_launch_x<3, 1, 4, 2>(jp, c0, s);
+        case 1: return ls_launch_x<3, 1, 8, 2>(jp, c0, s);
+        default: return false;
+        }
+    }
+    switch (v) {
+    case 0: return ls_launch_x<1, 1, 4, 3>(jp, c0, s);
+    case 1: return ls_launch_x<1, 2, 8, 2>(jp, c0, s);
+    default: return false;
+    }
+}
+
 // commit: null for the exchanged-configuration pass; else the write-back
 // launch (one job) for the chains flagged in commit[]
 static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipStream_t s)
 {
     if (n <= 0) return;
+    // the lockstep kernel serves the exchanged-configuration pass where its
+    // frames fit (K <= 8); write-back launches and deeper networks take the
+    // one-configuration kernel
+    if (!commit && ls_launch(jobs, n, s)) return;
     ConeJobs jp{};
     jp.n = n;
     int64_t total_cap = 0;
@@ -749,4 +1302,36 @@ void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, 
     cone_forward_jobs(&j, 1, s);
 }
 
+}  // namespace nqs
+
+namespace nqs {
+int cone_variants(const nqs_ctx *c)
+{
+    if (c->K > kLsMaxK) return 0;
+    return c->dtype == NQS_BF16X3 ? (int)(sizeof(kLsSplit) / sizeof(kLsSplit[0]))
+                                  : (int)(sizeof(kLsPlain) / sizeof(kLsPlain[0]));
+}
+
+void cone_variant_shape(const nqs_ctx *c, int v, int *items, int *waves)
+{
+    if (v < 0 || v >= cone_variants(c)) {
+        // the one-configuration kernel
+        *items = 1;
+        *waves = 0;
+        return;
+    }
+    const LsVariant t = c->dtype == NQS_BF16X3 ? kLsSplit[v] : kLsPlain[v];
+    *items = t.G;
+    *waves = t.NW;
+}
+
+int cone_variant_of(const nqs_ctx *c, int items, int waves)
+{
+    for (int v = 0; v < cone_variants(c); ++v) {
+        int g, w;
+        cone_variant_shape(c, v, &g, &w);
+        if (g == items && w == waves) return v;
+    }
+    return -1;
+}
 }  // namespace nqs

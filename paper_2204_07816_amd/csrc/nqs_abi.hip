@@ -617,12 +617,13 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
     // an earlier autotuner choice for this configuration, if the cache has one
     {
         nqs_mode m;
-        int nw = 0, mt = 0;
-        if (tune_lookup(tune_cache_path(), tune_key(c), &m, &nw, &mt)) {
+        int nw = 0, mt = 0, ci = -1, cw = -1;
+        if (tune_lookup(tune_cache_path(), tune_key(c), &m, &nw, &mt, &ci, &cw)) {
             c->tuned = 1;
             c->tuned_mode = m;
             c->full_nw = nw;
             c->full_maxt = mt;
+            if (ci > 0) c->cone_variant = cone_variant_of(c, ci, cw);
         }
     }
     *out = c;
@@ -693,6 +694,7 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->ring_tab);
     free_dev(c->ring_off);
     free_dev(c->cone_tab);
+    free_dev(c->ls_tab);
     free_dev(c->err);
     for (DevBuf *b : c->ws.all())
         if (b->ptr) (void)hipFree(b->ptr);
@@ -1154,12 +1156,28 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
         c->full_maxt = best_mt;
         best = NQS_FULL;
         if (incremental_ok(c)) {
-            const nqs_status st = time_pass(NQS_INCREMENTAL, &ms_inc);
-            if (st != NQS_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
+            // every shape of the cone kernel where it serves (the lockstep
+            // shapes and the one-configuration kernel), else the one form
+            const bool cone = cone_supported(c) || cone_x3_supported(c);
+            const int nv_cone = cone ? cone_variants(c) : 0;
+            const int keep_v = c->cone_variant;
+            int best_v = keep_v;
+            for (int v = (nv_cone > 0 ? -1 : keep_v); v < std::max(nv_cone, keep_v + 1); ++v) {
+                c->cone_variant = v;
+                double ms;
+                const nqs_status st = time_pass(NQS_INCREMENTAL, &ms);
+                if (st != NQS_OK) {
+                    c->cone_variant = keep_v;
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return st;
+                }
+                if (ms_inc < 0.0 || ms < ms_inc) {
+                    ms_inc = ms;
+                    best_v = v;
+                }
             }
+            c->cone_variant = best_v;
             if (ms_inc < ms_full) best = NQS_INCREMENTAL;
         }
         (void)hipEventDestroy(e0);
@@ -1168,7 +1186,10 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
     c->tuned = 1;
     c->tuned_mode = best;
     // a cache that cannot be written leaves the choice with this context only
-    (void)tune_store(tune_cache_path(), tune_key(c), best, best_nw, best_mt, ms_full, ms_inc);
+    int ci = -1, cw = -1;
+    if (cone_supported(c) || cone_x3_supported(c)) cone_variant_shape(c, c->cone_variant, &ci, &cw);
+    (void)tune_store(tune_cache_path(), tune_key(c), best, best_nw, best_mt, ci, cw, ms_full,
+                     ms_inc);
     if (mode_out) *mode_out = best;
     return NQS_OK;
 }

@@ -122,6 +122,9 @@ struct nqs_ctx {
     int32_t *ring_off = nullptr;
     int32_t *cone_tab = nullptr;  // same, for the unwrapped-window kernel
     std::vector<int> cone_off;    // [4][16] entry offsets of cone_tab
+    int32_t *ls_tab = nullptr;    // frame ring tables of the lockstep cone kernel
+    std::vector<int> ls_off;      // [4][16] entry offsets of ls_tab
+    int cone_variant = -1;        // lockstep shape (items, waves); -1: one-configuration kernel
     // autotuner choice (from nqs_autotune or the tune cache)
     int tuned = 0;
     nqs_mode tuned_mode = NQS_FULL;
@@ -254,6 +257,12 @@ void cone_commit(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, c
                  int64_t capacity, double *hsum, void *cache, double *dlog, const int32_t *commit,
                  hipStream_t s);
 size_t cone_lds_bytes(const nqs_ctx *c);
+// number of lockstep shapes of the cone kernel for this context (0: K > 8);
+// shape v's items per workgroup and waves, and the variant of a shape (-1:
+// the one-configuration kernel, which is also variant -1)
+int cone_variants(const nqs_ctx *c);
+void cone_variant_shape(const nqs_ctx *c, int v, int *items, int *waves);
+int cone_variant_of(const nqs_ctx *c, int items, int waves);
 nqs_status cone_build_ring_tables(nqs_ctx *c);
 void cone_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue, const int64_t *qlen,
                   int64_t capacity, const double *hsum, const void *cache, double *dlog,
@@ -281,9 +290,9 @@ bool cone_x3_supported(const nqs_ctx *c);
 std::string tune_cache_path();
 std::string tune_key(const nqs_ctx *c);
 bool tune_lookup(const std::string &path, const std::string &key, nqs_mode *mode, int *nw,
-                 int *maxt);
+                 int *maxt, int *cone_items, int *cone_waves);
 bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, int nw, int maxt,
-                double ms_full, double ms_inc);
+                int cone_items, int cone_waves, double ms_full, double ms_inc);
 // tile variants (waves, tiles per wave) the full-recompute pass can use here
 int mfma_full_variants(const nqs_ctx *c, int *nw, int *maxt, int cap);
 

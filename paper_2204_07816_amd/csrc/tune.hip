@@ -6,7 +6,11 @@
 // Cache file: NQS_TUNE_CACHE if set, else $HOME/.cache/nqs/tune.json.  It is
 // one JSON object whose members are configurations:
 //   { "gfx950 L=36 K=8 C=32 bf16 J2": {"mode": "incremental", "full_nw": 8,
-//     "full_maxt": 11, "ms_full": 1234.5, "ms_incremental": 83.0}, ... }
+//     "full_maxt": 11, "cone_items": 6, "cone_waves": 4, "ms_full": 1234.5,
+//     "ms_incremental": 83.0}, ... }
+// cone_items / cone_waves: the shape of the incremental cone kernel (items
+// per workgroup and waves; 1 / 0 for the one-configuration kernel); entries
+// without them keep the default shape.
 // A missing, unreadable or malformed file counts as empty (defaults apply);
 // writing replaces the file through a temporary and a rename.
 #include <hip/hip_runtime.h>
@@ -29,6 +33,7 @@ namespace {
 struct Entry {
     std::string mode;          // "full" | "incremental"
     int full_nw = 0, full_maxt = 0;
+    int cone_items = -1, cone_waves = -1;   // -1: not tuned
     double ms_full = -1.0, ms_incremental = -1.0;
 };
 
@@ -90,6 +95,8 @@ bool parse_entry(Reader &r, Entry *e)
             if (!r.num(&v)) return false;
             if (k == "full_nw") e->full_nw = (int)v;
             else if (k == "full_maxt") e->full_maxt = (int)v;
+            else if (k == "cone_items") e->cone_items = (int)v;
+            else if (k == "cone_waves") e->cone_waves = (int)v;
             else if (k == "ms_full") e->ms_full = v;
             else if (k == "ms_incremental") e->ms_incremental = v;
         }
@@ -143,9 +150,10 @@ bool write_cache(const std::string &path, const std::map<std::string, Entry> &m)
         const Entry &e = kv.second;
         std::fprintf(f,
                      "  \"%s\": {\"mode\": \"%s\", \"full_nw\": %d, \"full_maxt\": %d, "
+                     "\"cone_items\": %d, \"cone_waves\": %d, "
                      "\"ms_full\": %.6g, \"ms_incremental\": %.6g}%s\n",
-                     kv.first.c_str(), e.mode.c_str(), e.full_nw, e.full_maxt, e.ms_full,
-                     e.ms_incremental, ++i < m.size() ? "," : "");
+                     kv.first.c_str(), e.mode.c_str(), e.full_nw, e.full_maxt, e.cone_items,
+                     e.cone_waves, e.ms_full, e.ms_incremental, ++i < m.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
     const bool ok = std::fclose(f) == 0;
@@ -179,7 +187,7 @@ std::string tune_cache_path()
 std::string tune_key(const nqs_ctx *c) { return key_of(c->L, c->K, c->C, c->dtype, c->J2); }
 
 bool tune_lookup(const std::string &path, const std::string &key, nqs_mode *mode, int *nw,
-                 int *maxt)
+                 int *maxt, int *cone_items, int *cone_waves)
 {
     std::map<std::string, Entry> m;
     if (!read_cache(path, &m)) return false;
@@ -188,11 +196,13 @@ bool tune_lookup(const std::string &path, const std::string &key, nqs_mode *mode
     *mode = it->second.mode == "incremental" ? NQS_INCREMENTAL : NQS_FULL;
     *nw = it->second.full_nw;
     *maxt = it->second.full_maxt;
+    if (cone_items) *cone_items = it->second.cone_items;
+    if (cone_waves) *cone_waves = it->second.cone_waves;
     return true;
 }
 
 bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, int nw, int maxt,
-                double ms_full, double ms_inc)
+                int cone_items, int cone_waves, double ms_full, double ms_inc)
 {
     std::map<std::string, Entry> m;
     read_cache(path, &m);   // a malformed cache is replaced
@@ -200,6 +210,8 @@ bool tune_store(const std::string &path, const std::string &key, nqs_mode mode, 
     e.mode = mode == NQS_INCREMENTAL ? "incremental" : "full";
     e.full_nw = nw;
     e.full_maxt = maxt;
+    e.cone_items = cone_items;
+    e.cone_waves = cone_waves;
     e.ms_full = ms_full;
     e.ms_incremental = ms_inc;
     m[key] = e;
@@ -219,14 +231,17 @@ extern "C" nqs_status nqs_tune_key(int32_t L, int32_t K, int32_t C, nqs_dtype dt
 }
 
 extern "C" nqs_status nqs_tune_lookup(const char *path, const char *key, nqs_mode *mode,
-                                      int32_t *full_nw, int32_t *full_maxt)
+                                      int32_t *full_nw, int32_t *full_maxt, int32_t *cone_items,
+                                      int32_t *cone_waves)
 {
     if (!path || !key || !mode || !full_nw || !full_maxt) return NQS_E_ARG;
     nqs_mode m;
-    int nw, mt;
-    if (!nqs::tune_lookup(path, key, &m, &nw, &mt)) return NQS_E_ARG;
+    int nw, mt, ci = -1, cw = -1;
+    if (!nqs::tune_lookup(path, key, &m, &nw, &mt, &ci, &cw)) return NQS_E_ARG;
     *mode = m;
     *full_nw = nw;
     *full_maxt = mt;
+    if (cone_items) *cone_items = ci;
+    if (cone_waves) *cone_waves = cw;
     return NQS_OK;
 }

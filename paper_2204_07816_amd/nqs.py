@@ -83,7 +83,8 @@ def load():
         "nqs_auto_mode": [vp, P(i32)],
         "nqs_autotune": [vp, vp, i64, P(i32), vp],
         "nqs_tune_key": [i32, i32, i32, i32, d, ctypes.c_char_p, i64],
-        "nqs_tune_lookup": [ctypes.c_char_p, ctypes.c_char_p, P(i32), P(i32), P(i32)],
+        "nqs_tune_lookup": [ctypes.c_char_p, ctypes.c_char_p, P(i32), P(i32), P(i32), P(i32),
+                            P(i32)],
         "nqs_get_error": [vp, P(i32)],
         "nqs_enable_timing": [vp, i32],
         "nqs_kernel_time": [vp, P(d), P(i64)],
@@ -426,12 +427,13 @@ def tune_lookup(path: str, key: str):
     """The tune-cache entry of key in the file at path, or None (missing file or
     key, malformed file).  Host only."""
     m, nw, mt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ci, cw = ctypes.c_int32(), ctypes.c_int32()
     code = load().nqs_tune_lookup(path.encode(), key.encode(), ctypes.byref(m), ctypes.byref(nw),
-                                  ctypes.byref(mt))
+                                  ctypes.byref(mt), ctypes.byref(ci), ctypes.byref(cw))
     if code != 0:
         return None
     return {"mode": {v: k for k, v in _MODES.items()}[m.value], "full_nw": nw.value,
-            "full_maxt": mt.value}
+            "full_maxt": mt.value, "cone_items": ci.value, "cone_waves": cw.value}
 
 
 class LogPsiFn(torch.autograd.Function):

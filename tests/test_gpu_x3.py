@@ -164,3 +164,33 @@ def test_x3_spec_limits():
     assert ctx.auto_mode() == "full"                      # cones wrap at 10x10, K = 4
     with pytest.raises(nqs.NqsError):
         ctx.local_energy(to_dev(inputs.spins_sz0(10, 2, 3)), mode="incremental")
+
+
+@pytest.mark.parametrize("dt", ["bf16", "bf16x3"])
+def test_every_cone_shape_gives_the_same_ratios(tmp_path, monkeypatch, dt):
+    """The cone kernel's shapes the autotuner chooses among (the one-
+    configuration kernel and the lockstep shapes, selected here through the
+    tune cache) run the same per-site arithmetic: their log ratios agree to
+    the FP64 summation order, and with full recomputation."""
+    import json
+    from paper_2204_07816_amd import nqs
+    L, J2, K, C = 16, 0.5, 6, 32
+    w = inputs.stress_weights(K, C, 1.1, 31)
+    sp = to_dev(inputs.spins_sz0(L, 6, 32))
+    shapes = [(1, 0), (1, 4), (2, 8)] if dt == "bf16" else [(1, 0), (1, 4), (1, 8)]
+    ref = None
+    for items, waves in shapes:
+        path = tmp_path / f"tune_{items}_{waves}.json"
+        path.write_text(json.dumps({nqs.tune_key(L, K, C, dt, J2): {
+            "mode": "incremental", "full_nw": 0, "full_maxt": 0, "cone_items": items,
+            "cone_waves": waves, "ms_full": -1, "ms_incremental": -1}}))
+        monkeypatch.setenv("NQS_TUNE_CACHE", str(path))
+        ctx = make_ctx(L, J2, K, C, w, dtype=dt)
+        d = ctx.log_ratios(sp, mode="incremental").cpu().numpy()
+        if ref is None:
+            ref = d
+            full = ctx.log_ratios(sp, mode="full").cpu().numpy()
+            assert np.all(np.abs(full - ref) <= 1e-12 * (1 + np.abs(ref)))
+        say(dt, "shape", items, waves, "max |diff|", np.abs(d - ref).max())
+        assert np.all(np.abs(d - ref) <= 1e-12 * (1 + np.abs(ref)))
+        assert ctx.get_error() == 0

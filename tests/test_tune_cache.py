@@ -33,12 +33,15 @@ def test_lookup_of_well_formed_cache(nqs, tmp_path):
     k2 = nqs.tune_key(10, 4, 16, "bf16", 0.5)
     p = tmp_path / "tune.json"
     p.write_text(json.dumps({
-        k1: {"mode": "incremental", "full_nw": 8, "full_maxt": 11, "ms_full": 900.5,
-             "ms_incremental": 83.0},
+        k1: {"mode": "incremental", "full_nw": 8, "full_maxt": 11, "cone_items": 6,
+             "cone_waves": 4, "ms_full": 900.5, "ms_incremental": 83.0},
         k2: {"mode": "full", "full_nw": 4, "full_maxt": 2, "ms_full": 3.5, "ms_incremental": 4.1},
     }, indent=1))
-    assert nqs.tune_lookup(str(p), k1) == {"mode": "incremental", "full_nw": 8, "full_maxt": 11}
-    assert nqs.tune_lookup(str(p), k2) == {"mode": "full", "full_nw": 4, "full_maxt": 2}
+    assert nqs.tune_lookup(str(p), k1) == {"mode": "incremental", "full_nw": 8, "full_maxt": 11,
+                                           "cone_items": 6, "cone_waves": 4}
+    # an entry without the cone kernel's shape keeps the default one
+    assert nqs.tune_lookup(str(p), k2) == {"mode": "full", "full_nw": 4, "full_maxt": 2,
+                                           "cone_items": -1, "cone_waves": -1}
     assert nqs.tune_lookup(str(p), nqs.tune_key(12, 6, 32, "bf16", 0.0)) is None
     assert nqs.tune_lookup(str(p), "") is None
 
