@@ -62,6 +62,11 @@ def _load():
         "oracle_cnn1_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
         "oracle_tj_cnn1_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d),
                                                ci]),
+        "oracle_cnn2_num_params": (i64, [ci, ci]),
+        "oracle_cnn2_log_psi": (None, [ci, ci, ci, P(d), ci, P(i8), i64, P(d), P(i8), ci]),
+        "oracle_cnn2_log_deriv": (None, [ci, ci, ci, P(d), P(i8), i64, P(d), ci]),
+        "oracle_tj_cnn2_local_energy": (None, [ci, d, d, ci, ci, P(d), ci, P(i8), i64, P(d),
+                                               ci]),
         "oracle_sens_layers": (None, [ci, ci, ci, P(d), P(i8), P(d), P(d), P(d), P(d), P(d)]),
         "oracle_dlog_sens": (None, [ci, ci, ci, P(d), P(i8), i64, P(i32), P(i32), i64, P(d),
                                     ci]),
@@ -289,6 +294,51 @@ def cnn1_log_deriv(L: int, Kb: int, C: int, w, spins, nthreads: int = 0):
     return O
 
 
+def cnn2_num_params(Kb: int, C: int) -> int:
+    return int(_load().oracle_cnn2_num_params(Kb, C))
+
+
+def cnn2_log_psi(L: int, Kb: int, C: int, w, spins, marshall: bool = True, nthreads: int = 0):
+    """CNN2 (Sec. 5.2, reading in nqs_oracle.h): (log|psi| [B], sign [B]).
+    Site values 0 (hole), +1 (up), -1 (down) select the embedding rows."""
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    assert w.shape[0] == cnn2_num_params(Kb, C)
+    B = s.shape[0]
+    la = np.zeros(B, np.float64)
+    sg = np.zeros(B, np.int8)
+    _load().oracle_cnn2_log_psi(L, Kb, C, _p(w, ctypes.c_double), int(marshall),
+                                _p(s, ctypes.c_int8), B, _p(la, ctypes.c_double),
+                                _p(sg, ctypes.c_int8), nthreads)
+    return la, sg
+
+
+def tj_cnn2_local_energy(L: int, t: float, J: float, Kb: int, C: int, w, spins,
+                         marshall: bool = True, nthreads: int = 0):
+    """t-J local energy (Sec. 6.1) with the CNN2 amplitude, sign included."""
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    assert w.shape[0] == cnn2_num_params(Kb, C)
+    B = s.shape[0]
+    e = np.zeros(B, np.float64)
+    _load().oracle_tj_cnn2_local_energy(L, t, J, Kb, C, _p(w, ctypes.c_double), int(marshall),
+                                        _p(s, ctypes.c_int8), B, _p(e, ctypes.c_double),
+                                        nthreads)
+    return e
+
+
+def cnn2_log_deriv(L: int, Kb: int, C: int, w, spins, nthreads: int = 0):
+    s = _spins(spins, L)
+    w = np.ascontiguousarray(w, np.float64)
+    B = s.shape[0]
+    P = cnn2_num_params(Kb, C)
+    assert w.shape[0] == P
+    O = np.zeros((B, P), np.float64)
+    _load().oracle_cnn2_log_deriv(L, Kb, C, _p(w, ctypes.c_double), _p(s, ctypes.c_int8), B,
+                                  _p(O, ctypes.c_double), nthreads)
+    return O
+
+
 def sens_layers(L: int, K: int, C: int, w, spins):
     """Every layer of one configuration, arrays [K, C, L, L]: z, h = ln cosh z,
     a = |b| + sum |W||h_in|, g = df/dh_k, d = df/dz_k (test support)."""
@@ -417,7 +467,12 @@ def cnn1_mcmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, rand_bond
                        lambda w_, s_: cnn1_log_psi(L, Kb, C, w_, s_)[0])
 
 
-def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms, oderiv=None):
+def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms, oderiv=None,
+         solve=None):
+    """solve(O, e, lam, n_iter) -> (x, rel_res, it) replaces sr_cg when given
+    (the same system solved with its sums taken in another order)."""
+    if solve is None:
+        solve = sr_cg
     w = np.array(w, np.float64)
     s = _spins(spins, L).reshape(-1, L, L).copy()
     means, variances = [], []
@@ -429,7 +484,7 @@ def _vmc(L, sampler, eloc, K, C, w, spins, n_iter, lr, lam, cg_iters, randoms, o
         means.append(m)
         variances.append(v)
         O = oderiv(w, s) if oderiv else log_deriv(L, K, C, w, s)
-        x, _, _ = sr_cg(O, e, lam, cg_iters)
+        x, _, _ = solve(O, e, lam, cg_iters)
         w = w - lr * x
     return np.array(means), np.array(variances), w, s
 
@@ -449,11 +504,11 @@ def vmc(L: int, J1: float, J2: float, K: int, C: int, w, spins, n_iter: int, ste
 
 
 def tj_vmc(L: int, t: float, J: float, K: int, C: int, w, spins, n_iter: int, lr: float,
-           lam: float, cg_iters: int, randoms):
+           lam: float, cg_iters: int, randoms, solve=None):
     """The same loop for the t-J model (tj_mcmc, tj_local_energy)."""
     return _vmc(L, lambda w, s, rb, ru: tj_mcmc(L, t, J, K, C, w, s, rb, ru),
                 lambda w, s: tj_local_energy(L, t, J, K, C, w, s),
-                K, C, w, spins, n_iter, lr, lam, cg_iters, randoms)
+                K, C, w, spins, n_iter, lr, lam, cg_iters, randoms, solve=solve)
 
 
 def cnn1_vmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, n_iter: int, lr: float,
@@ -464,6 +519,13 @@ def cnn1_vmc(L: int, J1: float, J2: float, Kb: int, C: int, w, spins, n_iter: in
                 lambda w, s: cnn1_local_energy(L, J1, J2, Kb, C, w, s, marshall=marshall),
                 Kb, C, w, spins, n_iter, lr, lam, cg_iters, randoms,
                 oderiv=lambda w, s: cnn1_log_deriv(L, Kb, C, w, s))
+
+
+def tj_cnn2_mcmc(L: int, t: float, J: float, Kb: int, C: int, w, spins, rand_bond, rand_u):
+    """The t-J sampler (tj_mcmc) with the CNN2 amplitude."""
+    types = [0, 1] if (t != 0.0 or J != 0.0) else []
+    return _metropolis(L, types, Kb, C, w, spins, rand_bond, rand_u,
+                       lambda w_, s_: cnn2_log_psi(L, Kb, C, w_, s_)[0])
 
 
 def tj_cnn1_mcmc(L: int, t: float, J: float, Kb: int, C: int, w, spins, rand_bond, rand_u):

@@ -872,6 +872,366 @@ void oracle_tj_cnn1_local_energy(int L, double t, double J, int Kb, int C, const
 }
 
 /* ------------------------------------------------------------------ */
+/* CNN2 (Sec. 5.2): CNN1's blocks behind an embedding of the site        */
+/* states, with a max-pool of stride one; a final convolution to one     */
+/* channel; output the product of the neurons                            */
+/* ------------------------------------------------------------------ */
+/* Reading (the block figure is missing): the state of site p selects an
+ * embedding row, e = 0 for a hole, 1 for an up and 2 for a down electron,
+ *   h0[c][p] = E[e(s_p)][c]                                   (C channels)
+ * and every block maps C channels to C channels:
+ *   z[co][p] = a[co] + sum_{ci,ky,kx} W[co][ci][ky][kx] h[ci][p + (ky-1, kx-1)]
+ *   m[c][p]  = max(z[c][p], z[(c+1) mod C][p])
+ *              (window 2 over the channels, stride 1; the last window takes
+ *               the first channel, copied after the last)
+ *   u[co][p] = v[co] + sum_{ci,ky,kx} V[ci][co][ky][kx] m[ci][p - (ky-1, kx-1)]
+ * then y[p] = b + sum_{c,ky,kx} F[c][ky][kx] u_K[c][p + (ky-1, kx-1)] and
+ * psi_net = prod_p y[p].  Lattice indices wrap mod L (the spatial padding
+ * copies the first rows and columns after the last).
+ * Canonical order: E[3][C]; per block W[C][C][3][3], a[C], V[C][C][3][3]
+ * (input channel first), v[C]; then F[C][3][3], b.                      */
+
+int64_t oracle_cnn2_num_params(int Kb, int C)
+{
+    if (Kb < 1 || C < 1) return 0;
+    return (int64_t)3 * C + (int64_t)Kb * (18 * (int64_t)C * C + 2 * C) + 9 * (int64_t)C + 1;
+}
+
+typedef struct {
+    int64_t W, a, V, v;
+} cnn2_block;
+
+static cnn2_block cnn2_offsets(int C, int k)
+{
+    cnn2_block o;
+    o.W = (int64_t)3 * C + (int64_t)k * (18 * (int64_t)C * C + 2 * C);
+    o.a = o.W + (int64_t)9 * C * C;
+    o.V = o.a + C;
+    o.v = o.V + (int64_t)9 * C * C;
+    return o;
+}
+
+static int64_t cnn2_final_offset(int Kb, int C) { return cnn2_offsets(C, Kb).W; }
+
+static int cnn2_class(int8_t s) { return s == 0 ? 0 : (s > 0 ? 1 : 2); }
+
+/* one block: h [C][N] -> z [C][N], m [C][N], u [C][N] */
+static void cnn2_block_forward(int L, int C, const double *w, cnn2_block o, const double *h,
+                               double *z, double *m, double *u)
+{
+    const int N = L * L;
+    for (int co = 0; co < C; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = w[o.a + co];
+                for (int ci = 0; ci < C; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx)
+                            acc += w[o.W + ((co * C + ci) * 3 + ky) * 3 + kx] *
+                                   h[ci * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                z[co * N + y * L + x] = acc;
+            }
+    for (int c = 0; c < C; ++c)
+        for (int p = 0; p < N; ++p) {
+            double z0 = z[c * N + p], z1 = z[((c + 1) % C) * N + p];
+            m[c * N + p] = (z1 > z0) ? z1 : z0;
+        }
+    for (int co = 0; co < C; ++co)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = w[o.v + co];
+                for (int ci = 0; ci < C; ++ci)
+                    for (int ky = 0; ky < 3; ++ky)
+                        for (int kx = 0; kx < 3; ++kx)
+                            acc += w[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] *
+                                   m[ci * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                u[co * N + y * L + x] = acc;
+            }
+}
+
+/* the final convolution C -> 1: y [N] from u [C][N] */
+static void cnn2_final(int L, int C, const double *w, int64_t fo, const double *u, double *yv)
+{
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            double acc = w[fo + 9 * C];
+            for (int c = 0; c < C; ++c)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx)
+                        acc += w[fo + (c * 3 + ky) * 3 + kx] *
+                               u[c * L * L + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+            yv[y * L + x] = acc;
+        }
+}
+
+typedef struct {
+    double *h0, *z, *m, *u, *y;   /* h0, y: one sample; z, m, u: Kb blocks each */
+} cnn2_state;
+
+static void cnn2_state_alloc(cnn2_state *st, int L, int Kb, int C)
+{
+    size_t cn = (size_t)L * L * C;
+    st->h0 = (double *)malloc(sizeof(double) * cn);
+    st->z = (double *)malloc(sizeof(double) * cn * Kb);
+    st->m = (double *)malloc(sizeof(double) * cn * Kb);
+    st->u = (double *)malloc(sizeof(double) * cn * Kb);
+    st->y = (double *)malloc(sizeof(double) * (size_t)L * L);
+}
+
+static void cnn2_state_free(cnn2_state *st)
+{
+    free(st->h0);
+    free(st->z);
+    free(st->m);
+    free(st->u);
+    free(st->y);
+}
+
+/* forward of one configuration, keeping every block's z, m, u */
+static void cnn2_forward(int L, int Kb, int C, const double *w, const int8_t *spins,
+                         cnn2_state *st)
+{
+    const int N = L * L;
+    const size_t cn = (size_t)C * N;
+    for (int c = 0; c < C; ++c)
+        for (int p = 0; p < N; ++p) st->h0[c * N + p] = w[cnn2_class(spins[p]) * C + c];
+    for (int k = 0; k < Kb; ++k) {
+        const double *h = (k == 0) ? st->h0 : st->u + (size_t)(k - 1) * cn;
+        cnn2_block_forward(L, C, w, cnn2_offsets(C, k), h, st->z + (size_t)k * cn,
+                           st->m + (size_t)k * cn, st->u + (size_t)k * cn);
+    }
+    cnn2_final(L, C, w, cnn2_final_offset(Kb, C), st->u + (size_t)(Kb - 1) * cn, st->y);
+}
+
+/* psi = M(s)^marshall * prod_p y[p]: log|psi| and sign */
+static double cnn2_amplitude(int L, int Kb, int C, const double *w, int marshall,
+                             const int8_t *spins, cnn2_state *st, int *sign)
+{
+    cnn2_forward(L, Kb, C, w, spins, st);
+    double f = 0.0;
+    int neg = 0;
+    for (int p = 0; p < L * L; ++p) {
+        f += log(fabs(st->y[p]));
+        neg += (st->y[p] < 0.0);
+    }
+    int sg = (neg % 2 == 0) ? 1 : -1;
+    if (marshall) sg *= oracle_marshall_sign(L, spins);
+    *sign = sg;
+    return f;
+}
+
+void oracle_cnn2_log_psi(int L, int Kb, int C, const double *w, int marshall,
+                         const int8_t *spins, int64_t B, double *log_abs, int8_t *sign,
+                         int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn2_state st;
+        cnn2_state_alloc(&st, L, Kb, C);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            int sg;
+            log_abs[s] = cnn2_amplitude(L, Kb, C, w, marshall, spins + s * N, &st, &sg);
+            if (sign) sign[s] = (int8_t)sg;
+        }
+        cnn2_state_free(&st);
+    }
+}
+
+/* t-J local energy (Sec. 6.1, Eq. tJ) with the CNN2 amplitude: the terms of
+ * tj_connected, each weighted by psi(S')/psi(s) including the network's sign. */
+void oracle_tj_cnn2_local_energy(int L, double t, double J, int Kb, int C, const double *w,
+                                 int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                                 int nthreads)
+{
+    const int N = L * L;
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn2_state st;
+        cnn2_state_alloc(&st, L, Kb, C);
+        int8_t *work = (int8_t *)malloc((size_t)N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s) {
+            const int8_t *sp = spins + s * N;
+            int m0;
+            double f0 = cnn2_amplitude(L, Kb, C, w, marshall, sp, &st, &m0);
+            double e = 0.0;
+            for (int bd = 0; bd < 4 * N; ++bd) {
+                int si, sj;
+                if (oracle_bond_sites(L, bd, &si, &sj) != 1) continue;
+                e += tj_diag_bond(J, sp[si], sp[sj]);
+                double h = tj_offdiag(t, J, sp, si, sj);
+                if (h == 0.0) continue;
+                memcpy(work, sp, (size_t)N);
+                work[si] = sp[sj];
+                work[sj] = sp[si];
+                int m1;
+                double f1 = cnn2_amplitude(L, Kb, C, w, marshall, work, &st, &m1);
+                e += h * (double)(m1 * m0) * exp(f1 - f0);
+            }
+            e_loc[s] = e;
+        }
+        free(work);
+        cnn2_state_free(&st);
+    }
+}
+
+/* O[p] = d log|psi| / d theta_p by reverse mode: dlog|psi|/dy = 1/y, then
+ * the final convolution, the blocks from the last to the first, and the
+ * embedding rows.  m[c] = max(z[c], z[c+1]) passes its gradient to z[c]
+ * unless z[c+1] is strictly larger.                                       */
+static void cnn2_log_deriv_one(int L, int Kb, int C, const double *w, const int8_t *spins,
+                               double *O, cnn2_state *st, double *gu, double *gm, double *gz,
+                               double *gh)
+{
+    const int N = L * L;
+    const size_t cn = (size_t)C * N;
+    cnn2_forward(L, Kb, C, w, spins, st);
+    /* final convolution */
+    const int64_t fo = cnn2_final_offset(Kb, C);
+    const double *uK = st->u + (size_t)(Kb - 1) * cn;
+    for (int c = 0; c < C; ++c)
+        for (int ky = 0; ky < 3; ++ky)
+            for (int kx = 0; kx < 3; ++kx) {
+                double acc = 0.0;
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x)
+                        acc += (1.0 / st->y[y * L + x]) *
+                               uK[c * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                O[fo + (c * 3 + ky) * 3 + kx] = acc;
+            }
+    {
+        double acc = 0.0;
+        for (int p = 0; p < N; ++p) acc += 1.0 / st->y[p];
+        O[fo + 9 * C] = acc;
+    }
+    for (int c = 0; c < C; ++c)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                double acc = 0.0;
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx)
+                        acc += w[fo + (c * 3 + ky) * 3 + kx] /
+                               st->y[wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                gu[c * N + y * L + x] = acc;
+            }
+    for (int k = Kb - 1; k >= 0; --k) {
+        cnn2_block o = cnn2_offsets(C, k);
+        const double *zk = st->z + (size_t)k * cn;
+        const double *mk = st->m + (size_t)k * cn;
+        const double *h = (k == 0) ? st->h0 : st->u + (size_t)(k - 1) * cn;
+        /* transposed convolution: dV, dv, and dL/dm */
+        for (int ci = 0; ci < C; ++ci)
+            for (int co = 0; co < C; ++co)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double acc = 0.0;
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x)
+                                acc += gu[co * N + y * L + x] *
+                                       mk[ci * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                        O[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] = acc;
+                    }
+        for (int co = 0; co < C; ++co) {
+            double acc = 0.0;
+            for (int p = 0; p < N; ++p) acc += gu[co * N + p];
+            O[o.v + co] = acc;
+        }
+        for (int ci = 0; ci < C; ++ci)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    double acc = 0.0;
+                    for (int co = 0; co < C; ++co)
+                        for (int ky = 0; ky < 3; ++ky)
+                            for (int kx = 0; kx < 3; ++kx)
+                                acc += w[o.V + ((ci * C + co) * 3 + ky) * 3 + kx] *
+                                       gu[co * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                    gm[ci * N + y * L + x] = acc;
+                }
+        /* the stride-one max: z[c] feeds m[c] (first input) and m[c-1]
+         * (second input) */
+        for (int c = 0; c < C; ++c) {
+            const int cn1 = (c + 1) % C, cp1 = (c + C - 1) % C;
+            for (int p = 0; p < N; ++p) {
+                double g = 0.0;
+                if (!(zk[cn1 * N + p] > zk[c * N + p])) g += gm[c * N + p];
+                if (zk[c * N + p] > zk[cp1 * N + p]) g += gm[cp1 * N + p];
+                gz[c * N + p] = g;
+            }
+        }
+        /* convolution: dW, da, and dL/dh */
+        for (int co = 0; co < C; ++co)
+            for (int ci = 0; ci < C; ++ci)
+                for (int ky = 0; ky < 3; ++ky)
+                    for (int kx = 0; kx < 3; ++kx) {
+                        double acc = 0.0;
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x)
+                                acc += gz[co * N + y * L + x] *
+                                       h[ci * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
+                        O[o.W + ((co * C + ci) * 3 + ky) * 3 + kx] = acc;
+                    }
+        for (int co = 0; co < C; ++co) {
+            double acc = 0.0;
+            for (int p = 0; p < N; ++p) acc += gz[co * N + p];
+            O[o.a + co] = acc;
+        }
+        for (int ci = 0; ci < C; ++ci)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    double acc = 0.0;
+                    for (int co = 0; co < C; ++co)
+                        for (int ky = 0; ky < 3; ++ky)
+                            for (int kx = 0; kx < 3; ++kx)
+                                acc += w[o.W + ((co * C + ci) * 3 + ky) * 3 + kx] *
+                                       gz[co * N + wrap(y - ky + 1, L) * L + wrap(x - kx + 1, L)];
+                    gh[ci * N + y * L + x] = acc;
+                }
+        memcpy(gu, gh, sizeof(double) * cn);
+    }
+    /* embedding rows: dE[e][c] = sum over the sites in state e */
+    for (int e = 0; e < 3; ++e)
+        for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int p = 0; p < N; ++p)
+                if (cnn2_class(spins[p]) == e) acc += gu[c * N + p];
+            O[e * C + c] = acc;
+        }
+}
+
+void oracle_cnn2_log_deriv(int L, int Kb, int C, const double *w, const int8_t *spins,
+                           int64_t B, double *O, int nthreads)
+{
+    const int N = L * L;
+    const int64_t P = oracle_cnn2_num_params(Kb, C);
+    int nt = threads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
+    {
+        cnn2_state st;
+        cnn2_state_alloc(&st, L, Kb, C);
+        size_t cn = (size_t)C * N;
+        double *gu = (double *)malloc(sizeof(double) * cn);
+        double *gm = (double *)malloc(sizeof(double) * cn);
+        double *gz = (double *)malloc(sizeof(double) * cn);
+        double *gh = (double *)malloc(sizeof(double) * cn);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < B; ++s)
+            cnn2_log_deriv_one(L, Kb, C, w, spins + s * N, O + s * P, &st, gu, gm, gz, gh);
+        free(gu);
+        free(gm);
+        free(gz);
+        free(gh);
+        cnn2_state_free(&st);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Log-derivatives by reverse-mode chain rule                           */
 /* ------------------------------------------------------------------ */
 

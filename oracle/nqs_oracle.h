@@ -136,6 +136,26 @@ void oracle_tj_cnn1_local_energy(int L, double t, double J, int Kb, int C, const
                                  int marshall, const int8_t *spins, int64_t B, double *e_loc,
                                  int nthreads);
 
+/* CNN2 [Sec. 5.2], read as: site states {hole, up, down} pick embedding rows
+ * E[3][C]; Kb blocks C -> C of a 3x3 circular convolution (W, a), a max over
+ * channels c and (c+1) mod C (window 2, stride 1, the first channel copied
+ * after the last) and a 3x3 circular transposed convolution (V, v); a final
+ * 3x3 circular convolution C -> 1 (F, b); psi = M(s)^marshall prod_p y[p].
+ * Canonical order: E, per block W, a, V, v, then F, b:
+ * 3C + Kb (18 C^2 + 2C) + 9C + 1 parameters.                               */
+int64_t oracle_cnn2_num_params(int Kb, int C);
+void oracle_cnn2_log_psi(int L, int Kb, int C, const double *w, int marshall,
+                         const int8_t *spins, int64_t B, double *log_abs, int8_t *sign,
+                         int nthreads);
+/* t-J local energy [Sec. 6.1] with the CNN2 amplitude (its sign included). */
+void oracle_tj_cnn2_local_energy(int L, double t, double J, int Kb, int C, const double *w,
+                                 int marshall, const int8_t *spins, int64_t B, double *e_loc,
+                                 int nthreads);
+/* O[s][p] = d log|psi(s)| / d theta_p by reverse mode; the max passes its
+ * gradient to channel c unless channel c+1 is strictly larger.          */
+void oracle_cnn2_log_deriv(int L, int Kb, int C, const double *w, const int8_t *spins,
+                           int64_t B, double *O, int nthreads);
+
 /* Per-sample log-derivatives O[s][p] = d f(s) / d theta_p, FP64, by the
  * reverse-mode chain rule through the network.                          */
 void oracle_log_deriv(int L, int K, int C, const double *w, const int8_t *spins,

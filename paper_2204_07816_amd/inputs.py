@@ -64,6 +64,31 @@ def cnn1_weights(Kb: int, C: int, sigma: float, seed: int, out_bias: float = 0.0
     return w
 
 
+def cnn2_num_params(Kb: int, C: int) -> int:
+    """Parameters of CNN2: an embedding of 3 site states into C channels, per
+    block two 3x3 convolutions C -> C with biases, and a final 3x3
+    convolution C -> 1 with a bias."""
+    return 3 * C + Kb * (18 * C * C + 2 * C) + 9 * C + 1
+
+
+def cnn2_weights(Kb: int, C: int, gain: float, seed: int, out_bias: float = 0.0) -> np.ndarray:
+    """CNN2 parameters in canonical order (E; per block W, a, V, v; F, b):
+    the embedding N(0, 1), every 3x3 tap N(0, gain^2 / (9C)) (fan-in scaled),
+    the biases N(0, 0.1^2), and out_bias added to the final bias (out_bias
+    of a few units keeps the output neurons away from the zeros of their
+    product)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    taps = gain / np.sqrt(9.0 * C)
+    out = [rng.normal(0.0, 1.0, 3 * C)]
+    for _ in range(Kb):
+        out += [rng.normal(0.0, taps, 9 * C * C), rng.normal(0.0, 0.1, C),
+                rng.normal(0.0, taps, 9 * C * C), rng.normal(0.0, 0.1, C)]
+    out += [rng.normal(0.0, taps, 9 * C), rng.normal(0.0, 0.1, 1) + out_bias]
+    w = np.concatenate(out).astype(np.float64)
+    assert w.shape[0] == cnn2_num_params(Kb, C)
+    return w
+
+
 def spins_sz0(L: int, B: int, seed: int) -> np.ndarray:
     """int8 [B, L, L] configurations, uniform over the Sz = 0 sector."""
     N = L * L

@@ -212,13 +212,19 @@ def test_tj_vmc_fp64_matches_oracle():
                                            lambda it: inputs.mcmc_randoms(123, it, T, B))
     say("energies gpu", got, "oracle", means)
     np.testing.assert_allclose(got, means, rtol=1e-9)
-    # The SR system (S + 1e-3 I) of this sector is ill-conditioned, so the
-    # two sides' FP64 reduction orders reach the weights amplified (about
-    # 3e-8 absolute after five updates of O(0.1) size); the samples, which
-    # every acceptance decision shapes, stay identical.
+    # The SR system (S + 1e-3 I) of this sector is ill-conditioned (condition
+    # ~8e3), so FP64 reduction order reaches the weights amplified: the
+    # oracle's own CG with its sums over the samples reversed or permuted
+    # moves them by 1e-8 to 3e-8 after these five updates (measured here on
+    # the CPU).  The device, which sums in its own order, is held to a small
+    # multiple of that drift; the samples, which every acceptance decision
+    # shapes, stay identical.
+    from test_oracle_vmc import tj_reorder_drift
+    drifts, w_cpu = tj_reorder_drift(oracle)
+    assert np.array_equal(w_cpu, w_ref)
     dw = np.abs(run.weights - w_ref).max()
-    say("max |w_gpu - w_oracle|", dw)
-    assert dw <= 1e-6 * np.abs(w_ref).max()
+    say("max |w_gpu - w_oracle|", dw, "oracle reorder drifts", drifts)
+    assert dw <= 4.0 * max(drifts)
     assert np.array_equal(d.cpu().numpy(), s_ref)
     assert ctx.get_error() == 0
 

@@ -21,3 +21,40 @@ def test_vmc_converges_to_exact_ground_energy(orc):
     assert abs(tail - E0) < 3e-3 * abs(E0), (tail, E0)
     assert means[0] > E0 + 1.0                      # it started far away
     assert variances[-20:].mean() < 0.1 * variances[0]
+
+
+def _tj_sector_run(orc, solve=None):
+    """Five SR updates on the 4x4 two-hole t-J sector (t = 1, J = 0.4)."""
+    L, K, C, B, T = 4, 2, 4, 96, 12
+    w = inputs.weights(K, C, 0.05, 121)
+    sp = inputs.spins_tj(L, B, 2, 122)
+    return orc.tj_vmc(L, 1.0, 0.4, K, C, w, sp, 5, 0.05, 1e-3, 100,
+                      lambda it: inputs.mcmc_randoms(123, it, T, B), solve=solve)
+
+
+def tj_reorder_drift(orc):
+    """How far the weights of the 4x4 two-hole t-J run move when the oracle's
+    own CG takes its sums over the samples in another order (reversed, and a
+    fixed permutation): the same system, solved in exact arithmetic to the
+    same iterate.  Returns (drifts, reference weights)."""
+    _, _, w0, s0 = _tj_sector_run(orc)
+    drifts = []
+    for order in (lambda n: np.arange(n)[::-1],
+                  lambda n: np.random.default_rng(5).permutation(n)):
+        def solve(O, e, lam, n_iter, order=order):
+            p = order(O.shape[0])
+            return orc.sr_cg(O[p].copy(), e[p].copy(), lam, n_iter)
+        _, _, w1, s1 = _tj_sector_run(orc, solve)
+        assert np.array_equal(s1, s0)               # every acceptance decision the same
+        drifts.append(float(np.abs(w1 - w0).max()))
+    return drifts, w0
+
+
+def test_tj_sr_update_moves_with_the_order_of_sums(orc):
+    """The sector's SR system (S + 1e-3 I, condition ~8e3 at the fifth step)
+    amplifies rounding: reordering the oracle's own sums moves the weights by
+    about 1e-8 to 3e-8 after five updates, while the samples stay identical.
+    A device run that sums in its own order cannot be held closer than
+    that."""
+    drifts, w0 = tj_reorder_drift(orc)
+    assert all(1e-10 < d < 1e-6 * np.abs(w0).max() for d in drifts), drifts
