@@ -173,6 +173,29 @@ nqs_status nqs_create_cnn1_tj(int32_t L, double t, double J, int32_t blocks, int
                               int32_t marshall_sign, const double *weights, int64_t n_weights,
                               nqs_ctx **out);
 
+/* The t-J model [Sec. 6.1, Eq. tJ; the terms and site values of
+ * nqs_create_tj] with the CNN2 amplitude [Sec. 5.2], computed in FP64.
+ * The block figure is not available; the network is read as: the state of
+ * site p (0 hole, +1 up, -1 down) selects the embedding row e = 0, 1, 2 of
+ * E[3][C]; each of `blocks` blocks maps C channels to C by
+ *   z = a + W (*) h   (3x3 circular convolution),
+ *   m[c] = max(z[c], z[(c+1) mod C])   (window 2 over the channels, stride
+ *           one, the first channel copied after the last),
+ *   u[co][p] = v[co] + sum V[ci][co][t] m[ci][p - off t]   (transposed);
+ * then y[p] = b + sum F[c][t] u[c][p + off t] and
+ * psi = M(s)^marshall_sign * prod_p y[p].
+ * weights: host FP64 [n_weights] in canonical order E[3][C]; per block
+ * W[C][C][3][3], a[C], V[C][C][3][3] (input channel first), v[C]; then
+ * F[C][3][3], b; n_weights = 3C + blocks (18 C^2 + 2C) + 9C + 1.
+ * channels must be 16 or 32 (every block convolution runs on the FP64
+ * matrix cores).  Entry points and modes as nqs_create_cnn1_tj; a max
+ * passes its gradient to channel c unless channel c+1 is strictly larger.
+ * Errors: NQS_E_SPEC (blocks outside 1..16, channels not 16 or 32,
+ * marshall_sign not 0/1), otherwise as nqs_create_cnn1.                   */
+nqs_status nqs_create_cnn2_tj(int32_t L, double t, double J, int32_t blocks, int32_t channels,
+                              int32_t marshall_sign, const double *weights, int64_t n_weights,
+                              nqs_ctx **out);
+
 /* Release the context and its device memory (synchronises the device).  */
 nqs_status nqs_destroy(nqs_ctx *ctx);
 

@@ -32,6 +32,7 @@ CFLAGS = [
 FILE_FLAGS = {
     "k_conv_f64mma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "k_cnn1.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "k_cnn2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -700,6 +700,13 @@ size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c)
     return sizeof(double) * (size_t)c->N * c->C * (3 * (size_t)c->K + 5);
 }
 
+void cnn1_deriv_planes(const nqs_ctx *c, int *zp, int *hp, int *wp)
+{
+    *zp = 2 * c->K;      // z of every block (2C channels)
+    *hp = c->K;          // u of every block
+    *wp = 5;             // m, g, gh, gz (2C)
+}
+
 void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
                      double *usave, double *work, void *O, nqs_dtype odt, hipStream_t s)
 {

@@ -56,8 +56,12 @@ struct ConvArgs {
 // MODE 1 (CNN1 convolution, COUT = 32): column 16 h + j holds z[2 j + h], so
 // one lane holds both inputs of a channel-pair max: out [M][N][16] gets
 // max(z[2j], z[2j+1]) (the second only when larger), zk (may be null) the z
-// in natural channel order [M][N][32].  MODE 2 (CNN1 transposed
-// convolution): out = z, no activation.
+// in natural channel order [M][N][32].  MODE 2 (transposed convolutions,
+// data gradients): out = z, no activation.  MODE 3 (CNN2 convolution): out
+// [M][N][COUT] gets m[c] = max(z[c], z[(c+1) mod COUT]) (the second only
+// when larger), zk (may be null) the z; channel c+1 sits in the next lane of
+// the same 16-lane row group, or for c = 16 h + 15 in lane 0 of the group
+// and the next 16-column tile.
 template <int COUT, int MODE = 0>
 __global__ void __launch_bounds__(kThreads)
 k_conv_mma(ConvArgs a)
@@ -144,6 +148,28 @@ k_conv_mma(ConvArgs a)
             }
         return;
     }
+    if constexpr (MODE == 3) {
+        const int lane_next = (lane & ~15) | ((m16 + 1) & 15);
+#pragma unroll
+        for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = p0 + mt * 16 + kq + 4 * i;   // same row in lane_next
+                double nb[NH];
+#pragma unroll
+                for (int h = 0; h < NH; ++h) nb[h] = __shfl(acc[mt][h][i], lane_next, 64);
+                if (p >= N) continue;
+#pragma unroll
+                for (int h = 0; h < NH; ++h) {
+                    const double z0 = acc[mt][h][i];
+                    const double z1 = m16 < 15 ? nb[h] : nb[(h + 1) % NH];
+                    const int64_t o = obase + (int64_t)p * COUT + 16 * h + m16;
+                    a.out[o] = (z1 > z0) ? z1 : z0;
+                    if (a.zk) a.zk[o] = z0;
+                }
+            }
+        return;
+    }
     if constexpr (MODE == 2) {
 #pragma unroll
         for (int mt = 0; mt < kMT; ++mt)
@@ -185,7 +211,10 @@ k_conv_mma(ConvArgs a)
 // GEMM over sites: M = co (C), N = (t, ci) (9C columns, ci fastest, so a
 // 16-column tile never straddles two taps), K = sites in steps of 4.  A wave
 // owns all C output channels and kNT consecutive column tiles of one sample.
-template <typename OT, int C>
+// TRANS (a transposed convolution u[co][p] = sum V[ci][co][t] h[p - off(t)][ci]):
+// dV[ci][co][t] = sum_p delta[p][co] h[p - off(t)][ci], stored input channel
+// first; the bias gradient as before.
+template <typename OT, int C, bool TRANS = false>
 __global__ void __launch_bounds__(kThreads)
 k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, int L, int B,
             int64_t P, int64_t woff, OT *__restrict__ O)
@@ -211,8 +240,8 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
         tok[j] = tile < NTILE;
         const int col = (tok[j] ? tile : 0) * 16;
         const int t = col / C;
-        tdy[j] = t / 3 - 1;
-        tdx[j] = t % 3 - 1;
+        tdy[j] = TRANS ? 1 - t / 3 : t / 3 - 1;
+        tdx[j] = TRANS ? 1 - t % 3 : t % 3 - 1;
         tci[j] = col % C + m16;
     }
     double4_t acc[NH][kNT];
@@ -277,7 +306,9 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int co = 16 * h + kq + 4 * i;
-                o[((int64_t)co * C + tci[j]) * 9 + t] = (OT)acc[h][j][i];
+                const int64_t idx = TRANS ? ((int64_t)tci[j] * C + co) * 9 + t
+                                          : ((int64_t)co * C + tci[j]) * 9 + t;
+                o[idx] = (OT)acc[h][j][i];
             }
     }
     if (wg == 0) {
@@ -346,27 +377,72 @@ void f64mma_cnn1_plain(const nqs_ctx *c, const double *in, int64_t M, int Cin, c
     NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
 }
 
+// CNN2 convolution C -> C with the stride-one channel max in the epilogue
+// (MODE 3): m into out, z into zsave (may be null)
+void f64mma_cnn2_conv(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                      const double *bias, double *out, double *zsave, const int64_t *qlen,
+                      int64_t q_begin, hipStream_t s)
+{
+    if (M <= 0) return;
+    ConvArgs a{in, w, bias, out, zsave, qlen, q_begin, M, c->L, c->C, 0};
+    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
+    if (c->C == 32)
+        NQS_LAUNCH((k_conv_mma<32, 3>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    else
+        NQS_LAUNCH((k_conv_mma<16, 3>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
+// convolution Cin -> Cout (16 or 32) with an optional bias and no activation
+// (MODE 2): transposed convolutions as convolutions with flipped, transposed
+// taps, and the data gradients of the backward
+void f64mma_linear(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cout,
+                   const double *w, const double *bias, double *out, const int64_t *qlen,
+                   int64_t q_begin, hipStream_t s)
+{
+    if (M <= 0) return;
+    ConvArgs a{in, w, bias, out, nullptr, qlen, q_begin, M, c->L, Cin, 0};
+    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
+    if (Cout == 32)
+        NQS_LAUNCH((k_conv_mma<32, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    else
+        NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
 bool f64mma_wgrad_ok(int C) { return C == 16 || C == 32; }
 
-void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
+namespace {
+template <bool TRANS>
+void wgrad_launch(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
                   void *O, nqs_dtype odt, hipStream_t s)
 {
-    if (B <= 0) return;
     const int C = c->C;
     const int wps = (9 * C / 16 + kNT - 1) / kNT;
     const int64_t blocks = ((int64_t)B * wps + kThreads / 64 - 1) / (kThreads / 64);
     const dim3 g((unsigned)blocks), b(kThreads);
     if (C == 32) {
         if (odt == NQS_FP32)
-            NQS_LAUNCH((k_wgrad_mma<float, 32>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (float *)O);
+            NQS_LAUNCH((k_wgrad_mma<float, 32, TRANS>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (float *)O);
         else
-            NQS_LAUNCH((k_wgrad_mma<double, 32>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (double *)O);
+            NQS_LAUNCH((k_wgrad_mma<double, 32, TRANS>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (double *)O);
     } else {
         if (odt == NQS_FP32)
-            NQS_LAUNCH((k_wgrad_mma<float, 16>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (float *)O);
+            NQS_LAUNCH((k_wgrad_mma<float, 16, TRANS>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (float *)O);
         else
-            NQS_LAUNCH((k_wgrad_mma<double, 16>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (double *)O);
+            NQS_LAUNCH((k_wgrad_mma<double, 16, TRANS>), g, b, 0, s, hin, delta, c->L, B, c->P, woff, (double *)O);
     }
+}
+}  // namespace
+
+void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
+                  void *O, nqs_dtype odt, hipStream_t s, bool trans)
+{
+    if (B <= 0) return;
+    if (trans)
+        wgrad_launch<true>(c, hin, delta, B, woff, O, odt, s);
+    else
+        wgrad_launch<false>(c, hin, delta, B, woff, O, odt, s);
 }
 
 }  // namespace nqs

@@ -173,8 +173,8 @@ int grid_of(int64_t n)
 static void device_repack(nqs_ctx *c, hipStream_t s)
 {
     const int K = c->K, C = c->C;
-    if (c->net == kNetCnn1) {           // only the matrix-core packing of CNN1
-        cnn1_pack_device(c, s);
+    if (const BlockNet *bn = block_net(c)) {   // only the packing of a block network
+        bn->pack_device(c, s);
         return;
     }
     NQS_LAUNCH(k_pack_vec, dim3(grid_of(c->P)), dim3(kThreads), 0, s, (const double *)c->w_canon,

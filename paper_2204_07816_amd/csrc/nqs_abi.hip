@@ -14,6 +14,22 @@
 
 using namespace nqs;
 
+namespace nqs {
+
+const BlockNet kCnn1Net{cnn1_params,       cnn1_plane_bytes,  cnn1_chunk,
+                        cnn1_base_forward, cnn1_conn_forward, cnn1_packed_doubles,
+                        cnn1_pack_device,  cnn1_deriv_planes, cnn1_deriv_rows};
+const BlockNet kCnn2Net{cnn2_params,       cnn2_plane_bytes,  cnn2_chunk,
+                        cnn2_base_forward, cnn2_conn_forward, cnn2_packed_doubles,
+                        cnn2_pack_device,  cnn2_deriv_planes, cnn2_deriv_rows};
+
+const BlockNet *block_net(const nqs_ctx *c)
+{
+    return c->net == kNetCnn1 ? &kCnn1Net : (c->net == kNetCnn2 ? &kCnn2Net : nullptr);
+}
+
+}  // namespace nqs
+
 namespace {
 
 #define HIP_OK(x)                                   \
@@ -22,6 +38,7 @@ namespace {
     } while (0)
 
 int64_t params_of(int K, int C) { return (int64_t)(C * 9 + C) + (int64_t)(K - 1) * (C * C * 9 + C); }
+
 
 // FP64 -> BF16, round to nearest even (via FP32, with the double-rounding
 // case resolved against the exact midpoint).
@@ -97,16 +114,16 @@ nqs_status upload(T *&dst, const std::vector<T> &src)
 
 nqs_status pack_weights(nqs_ctx *c)
 {
-    if (c->net == kNetCnn1) {
+    if (const BlockNet *bn = block_net(c)) {
         // canonical vector, plus the matrix-core packing built from it on the device
         nqs_status st = upload(c->w_canon, c->w_host);
-        const size_t np = cnn1_packed_doubles(c);
+        const size_t np = bn->packed_doubles(c);
         if (st != NQS_OK || np == 0) return st;
         if (!c->w_vec64 && hipMalloc((void **)&c->w_vec64, np * sizeof(double)) != hipSuccess) {
             c->w_vec64 = nullptr;
             return NQS_E_NOMEM;
         }
-        cnn1_pack_device(c, nullptr);
+        bn->pack_device(c, nullptr);
         HIP_OK(hipDeviceSynchronize());
         return NQS_OK;
     }
@@ -305,20 +322,21 @@ nqs_status x3_conn_stage(nqs_ctx *c, const int8_t *spins, nqs_mode mode, double 
     return NQS_OK;
 }
 
-// CNN1: base pass (log|psi_net| and sign of the samples), then every queue
-// item recomputed in full: dlog[item] and the sign ratio in ws.isign.
-nqs_status cnn1_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, double *dlog, int64_t cap,
-                            hipStream_t s)
+// Block networks (CNN1, CNN2): base pass (log|psi_net| and sign of the
+// samples), then every queue item recomputed in full: dlog[item] and the
+// sign ratio in ws.isign.
+nqs_status block_ratio_stage(nqs_ctx *c, const BlockNet *bn, const int8_t *spins, int B,
+                             double *dlog, int64_t cap, hipStream_t s)
 {
     Workspace &w = c->ws;
-    const int64_t chunk = cnn1_chunk(c, std::max<int64_t>(cap, B));
+    const int64_t chunk = bn->chunk(c, std::max<int64_t>(cap, B));
     NQS_TRY(ensure(w.sgn, std::max(B, 1), s));
     NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
-    NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
-    NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.plane_a, bn->plane_bytes(c, chunk), s));
+    NQS_TRY(ensure(w.plane_b, bn->plane_bytes(c, chunk), s));
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
-        cnn1_base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+        bn->base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
                           (int8_t *)w.sgn.ptr + b0, nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -328,7 +346,7 @@ nqs_status cnn1_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, double *dlog
         (void)hipEventRecord(e0, s);
     }
     for (int64_t q0 = 0; q0 < cap; q0 += chunk)
-        cnn1_conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
+        bn->conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
                           std::min(chunk, cap - q0), (const double *)w.fbase.ptr,
                           (const int8_t *)w.sgn.ptr, dlog, (int8_t *)w.isign.ptr, w.plane_a.ptr,
                           w.plane_b.ptr, s);
@@ -345,7 +363,7 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
 {
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
-    if (c->net == kNetCnn1) return cnn1_ratio_stage(c, spins, B, dlog, cap, s);
+    if (const BlockNet *bn = block_net(c)) return block_ratio_stage(c, bn, spins, B, dlog, cap, s);
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
     if (c->dtype == NQS_BF16X3) {
         NQS_TRY(bf16_base_stage(c, spins, B, s));
@@ -493,8 +511,11 @@ namespace {
 // deltas per sample, at most 8 GB
 int64_t deriv_chunk(const nqs_ctx *c, int64_t B)
 {
-    if (c->net == kNetCnn1) {
-        const int64_t n = (int64_t)(((size_t)8 << 30) / cnn1_deriv_bytes_per_sample(c));
+    if (const BlockNet *bn = block_net(c)) {
+        int zp, hp, wp;
+        bn->deriv_planes(c, &zp, &hp, &wp);
+        const size_t per = sizeof(double) * (size_t)c->N * c->C * (zp + hp + wp);
+        const int64_t n = (int64_t)(((size_t)8 << 30) / per);
         return std::max<int64_t>(1, std::min<int64_t>(n, B));
     }
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;   // one FP64 plane
@@ -507,10 +528,12 @@ nqs_status deriv_reserve(nqs_ctx *c, int64_t chunk, hipStream_t s)
 {
     Workspace &w = c->ws;
     const size_t plane = sizeof(double) * (size_t)c->N * c->C;
-    if (c->net == kNetCnn1) {
-        NQS_TRY(ensure(w.zsave, plane * 2 * c->K * chunk, s));
-        NQS_TRY(ensure(w.hsave, plane * c->K * chunk, s));
-        NQS_TRY(ensure(w.delta, plane * 5 * chunk, s));
+    if (const BlockNet *bn = block_net(c)) {
+        int zp, hp, wp;
+        bn->deriv_planes(c, &zp, &hp, &wp);
+        NQS_TRY(ensure(w.zsave, plane * zp * chunk, s));
+        NQS_TRY(ensure(w.hsave, plane * hp * chunk, s));
+        NQS_TRY(ensure(w.delta, plane * wp * chunk, s));
         return NQS_OK;
     }
     const size_t saved = plane * std::max(c->K - 1, 1) * chunk;
@@ -529,8 +552,8 @@ void deriv_rows(const nqs_ctx *c, const int8_t *spins, int64_t B, int64_t chunk,
     const size_t esz = odt == NQS_FP32 ? sizeof(float) : sizeof(double);
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
-        if (c->net == kNetCnn1) {
-            cnn1_deriv_rows(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr,
+        if (const BlockNet *bn = block_net(c)) {
+            bn->deriv_rows(c, spins + b0 * c->N, nb, (double *)w.zsave.ptr,
                             (double *)w.hsave.ptr, (double *)w.delta.ptr,
                             (unsigned char *)O + (size_t)b0 * c->P * esz, odt, s);
             continue;
@@ -576,9 +599,12 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
         spec->conv_dtype != NQS_BF16 && spec->conv_dtype != NQS_BF16X3)
         return NQS_E_SPEC;
     if (spec->marshall_sign != 0 && spec->marshall_sign != 1) return NQS_E_SPEC;
-    if (net == kNetCnn1 && spec->conv_dtype != NQS_FP64) return NQS_E_SPEC;
-    if (n_weights != (net == kNetCnn1 ? cnn1_params(K, C) : params_of(K, C)))
-        return NQS_E_NPARAMS;
+    if (net != kNetLnCosh && spec->conv_dtype != NQS_FP64) return NQS_E_SPEC;
+    if (net == kNetCnn2 && !cnn2_supported(K, C)) return NQS_E_SPEC;
+    const int64_t want = net == kNetCnn1   ? cnn1_params(K, C)
+                         : net == kNetCnn2 ? cnn2_params(K, C)
+                                           : params_of(K, C);
+    if (n_weights != want) return NQS_E_NPARAMS;
     nqs_ctx *c = new nqs_ctx();
     c->ws.bind();
     c->L = L;
@@ -672,6 +698,14 @@ nqs_status nqs_create_cnn1_tj(int32_t L, double t, double J, int32_t blocks, int
 {
     const nqs_cnn_spec spec{blocks, channels, marshall_sign, NQS_FP64};
     return create_ctx(L, kModelTJ, kNetCnn1, J, 0.0, t, &spec, weights, n_weights, out);
+}
+
+nqs_status nqs_create_cnn2_tj(int32_t L, double t, double J, int32_t blocks, int32_t channels,
+                              int32_t marshall_sign, const double *weights, int64_t n_weights,
+                              nqs_ctx **out)
+{
+    const nqs_cnn_spec spec{blocks, channels, marshall_sign, NQS_FP64};
+    return create_ctx(L, kModelTJ, kNetCnn2, J, 0.0, t, &spec, weights, n_weights, out);
 }
 
 nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec,
@@ -773,12 +807,12 @@ nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
     NQS_TRY(ensure(w.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
-    if (c->net == kNetCnn1) {
-        const int64_t chunk = cnn1_chunk(c, std::max<int64_t>(cap, B));
+    if (const BlockNet *bn = block_net(c)) {
+        const int64_t chunk = bn->chunk(c, std::max<int64_t>(cap, B));
         NQS_TRY(ensure(w.sgn, std::max(B, 1), s));
         NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
-        NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
-        NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_a, bn->plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, bn->plane_bytes(c, chunk), s));
     } else if (c->dtype == NQS_BF16) {
         NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
     } else if (c->dtype == NQS_BF16X3) {
@@ -803,14 +837,14 @@ nqs_status nqs_log_psi(nqs_ctx *c, const int8_t *spins, int64_t B, double *log_a
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)B * c->N, s));
     launch_marshall(c, spins, (int)B, sign, s);
-    if (c->net == kNetCnn1) {
-        const int64_t chunk = cnn1_chunk(c, B);
+    if (const BlockNet *bn = block_net(c)) {
+        const int64_t chunk = bn->chunk(c, B);
         NQS_TRY(ensure(w.sgn, (size_t)B, s));
-        NQS_TRY(ensure(w.plane_a, cnn1_plane_bytes(c, chunk), s));
-        NQS_TRY(ensure(w.plane_b, cnn1_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_a, bn->plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.plane_b, bn->plane_bytes(c, chunk), s));
         for (int64_t b0 = 0; b0 < B; b0 += chunk) {
             const int nb = (int)std::min<int64_t>(chunk, B - b0);
-            cnn1_base_forward(c, spins + b0 * c->N, nb, log_abs + b0, (int8_t *)w.sgn.ptr + b0,
+            bn->base_forward(c, spins + b0 * c->N, nb, log_abs + b0, (int8_t *)w.sgn.ptr + b0,
                               sign ? sign + b0 : nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
         }
     } else if (c->dtype == NQS_BF16) {
@@ -850,7 +884,7 @@ nqs_status nqs_local_energy(nqs_ctx *c, const int8_t *spins, int64_t B, double *
     NQS_TRY(log_ratio_stage(c, spins, (int)B, m, (double *)c->ws.dlog.ptr, cap, s));
     launch_energy_reduce(c, spins, (int)B, (int64_t *)c->ws.offsets.ptr,
                          (uint32_t *)c->ws.queue.ptr, (double *)c->ws.dlog.ptr,
-                         c->net == kNetCnn1 ? (const int8_t *)c->ws.isign.ptr : nullptr,
+                         block_net(c) ? (const int8_t *)c->ws.isign.ptr : nullptr,
                          (double *)c->ws.ediag.ptr, e_loc, c->err, s);
     return finish_call();
 }
@@ -1014,7 +1048,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     for (int i = 0; i < n; ++i) {
         nqs_ctx *c = jobs[i].ctx;
         if (!c) return NQS_E_ARG;
-        if (c->net == kNetCnn1) return NQS_E_UNSUPPORTED;
+        if (block_net(c)) return NQS_E_UNSUPPORTED;
         if (c->K != jobs[0].ctx->K || c->C != jobs[0].ctx->C || c->dtype != jobs[0].ctx->dtype)
             return NQS_E_SPEC;
         for (int j = 0; j < i; ++j)
@@ -1090,7 +1124,7 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
 {
     NQS_TRY(check_common(c, spins, B));
     if (B == 0) return NQS_E_ARG;
-    if (c->net == kNetCnn1) return NQS_E_UNSUPPORTED;
+    if (block_net(c)) return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stream_capturing(s)) return NQS_E_WORKSPACE;
     c->last_stream = s;

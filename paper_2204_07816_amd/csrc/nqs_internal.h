@@ -34,11 +34,14 @@ constexpr int kModelSpin = 0;
 constexpr int kModelTJ = 1;
 
 // Network family of a context: the ln cosh CNN (K layers of 3x3 circular
-// convolutions with ln cosh, summed) or CNN1 (K blocks of convolution,
+// convolutions with ln cosh, summed), CNN1 (K blocks of convolution,
 // max-pool over channel pairs and transposed convolution; product of the
-// output neurons) [Sec. 5.2].
+// output neurons) or CNN2 (an embedding of the site states, K blocks with a
+// stride-one channel max, a final convolution to one channel; product of its
+// neurons) [Sec. 5.2].
 constexpr int kNetLnCosh = 0;
 constexpr int kNetCnn1 = 1;
+constexpr int kNetCnn2 = 2;
 
 // Device-side sticky error codes (ORed bits, mapped to nqs_status on read).
 constexpr int kErrSpin = 1;
@@ -208,8 +211,18 @@ void f64mma_conv(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cou
                  const int64_t *qlen, int64_t q_begin, hipStream_t s);
 bool f64mma_wgrad_ok(int C);
 // Rows O[s][woff ...] of a C -> C layer: weights [co][ci][t] then bias [co].
+// trans: a transposed convolution's weights, [ci][co][t] then bias [co].
 void f64mma_wgrad(const nqs_ctx *c, const double *hin, const double *delta, int B, int64_t woff,
-                  void *O, nqs_dtype odt, hipStream_t s);
+                  void *O, nqs_dtype odt, hipStream_t s, bool trans = false);
+// convolution Cin -> Cout (16 or 32), optional bias, no activation
+void f64mma_linear(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cout,
+                   const double *w, const double *bias, double *out, const int64_t *qlen,
+                   int64_t q_begin, hipStream_t s);
+// CNN2 convolution C -> C (16 or 32) with the stride-one channel max: m into
+// out, z into zsave (may be null)
+void f64mma_cnn2_conv(const nqs_ctx *c, const double *in, int64_t M, const double *w,
+                      const double *bias, double *out, double *zsave, const int64_t *qlen,
+                      int64_t q_begin, hipStream_t s);
 
 // --- one lattice's share of a multi-lattice exchanged-configuration launch ---
 constexpr int kMaxConnJobs = 8;
@@ -331,6 +344,48 @@ size_t cnn1_deriv_bytes_per_sample(const nqs_ctx *c);
 // O rows of nb samples; zsave: K*2*nb*N*C, usave: K*nb*N*C, work: 5*nb*N*C doubles
 void cnn1_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
                      double *usave, double *work, void *O, nqs_dtype odt, hipStream_t s);
+
+// --- CNN2 network family (k_cnn2.hip), FP64, C = 16 or 32 ---
+bool cnn2_supported(int Kb, int C);
+int64_t cnn2_params(int Kb, int C);
+size_t cnn2_plane_bytes(const nqs_ctx *c, int64_t planes);
+int64_t cnn2_chunk(const nqs_ctx *c, int64_t work);
+void cnn2_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, int8_t *sgn,
+                       int8_t *sign_pub, void *pa, void *pb, hipStream_t s);
+void cnn2_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                       const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
+                       const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
+                       hipStream_t s);
+size_t cnn2_packed_doubles(const nqs_ctx *c);
+void cnn2_pack_device(const nqs_ctx *c, hipStream_t s);
+void cnn2_deriv_planes(const nqs_ctx *c, int *zp, int *hp, int *wp);
+void cnn2_deriv_rows(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
+                     double *hsave, double *work, void *O, nqs_dtype odt, hipStream_t s);
+
+// A block network (CNN1, CNN2): an FP64 forward over planes [M][N][C] of
+// samples or queue items, every exchanged configuration recomputed in full,
+// a sign carried by the network, and a per-sample backward whose buffers
+// hold zp, hp and wp planes of N*C doubles per sample.
+struct BlockNet {
+    int64_t (*params)(int Kb, int C);
+    size_t (*plane_bytes)(const nqs_ctx *c, int64_t planes);
+    int64_t (*chunk)(const nqs_ctx *c, int64_t work);
+    void (*base_forward)(const nqs_ctx *c, const int8_t *spins, int B, double *f, int8_t *sgn,
+                         int8_t *sign_pub, void *pa, void *pb, hipStream_t s);
+    void (*conn_forward)(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                         const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
+                         const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
+                         hipStream_t s);
+    size_t (*packed_doubles)(const nqs_ctx *c);
+    void (*pack_device)(const nqs_ctx *c, hipStream_t s);
+    void (*deriv_planes)(const nqs_ctx *c, int *zp, int *hp, int *wp);
+    void (*deriv_rows)(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
+                       double *hsave, double *work, void *O, nqs_dtype odt, hipStream_t s);
+};
+// the context's block network, null for the ln cosh CNN
+const BlockNet *block_net(const nqs_ctx *c);
+void cnn1_deriv_planes(const nqs_ctx *c, int *zp, int *hp, int *wp);
+
 void launch_energy_stats(const double *e_loc, int B, double *stats, hipStream_t s);
 
 // --- device-side parameter update (k_pack.hip) ---

@@ -62,6 +62,7 @@ def load():
         "nqs_create_tj": [i32, d, d, P(CnnSpec), vp, i64, P(vp)],
         "nqs_create_cnn1": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_create_cnn1_tj": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
+        "nqs_create_cnn2_tj": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_destroy": [vp],
         "nqs_num_params": [vp, P(i64)],
         "nqs_set_weights": [vp, vp, i64],
@@ -131,7 +132,7 @@ def num_params(K: int, C: int) -> int:
 
 class Context:
     """One lattice + network (nqs_create / nqs_create_tj / nqs_create_cnn1 /
-    nqs_destroy)."""
+    nqs_create_cnn1_tj / nqs_create_cnn2_tj / nqs_destroy)."""
 
     def __init__(self, L: int, J1: float, J2: float, K: int, C: int, weights,
                  dtype: str = "fp64", marshall_sign: bool = True, *,
@@ -153,6 +154,12 @@ class Context:
                 _check(lib.nqs_create_cnn1_tj(L, tj_hop, J1, K, C, 1 if marshall_sign else 0,
                                               ctypes.c_void_p(w.data_ptr()), w.numel(),
                                               ctypes.byref(h)), "nqs_create_cnn1_tj")
+        elif net == "cnn2":
+            if dtype != "fp64" or tj_hop is None or J2 != 0.0:
+                raise ValueError("CNN2 contexts are FP64 t-J contexts")
+            _check(lib.nqs_create_cnn2_tj(L, tj_hop, J1, K, C, 1 if marshall_sign else 0,
+                                          ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                          ctypes.byref(h)), "nqs_create_cnn2_tj")
         elif tj_hop is None:
             _check(lib.nqs_create(L, J1, J2, ctypes.byref(spec), ctypes.c_void_p(w.data_ptr()),
                                   w.numel(), ctypes.byref(h)), "nqs_create")
@@ -178,6 +185,13 @@ class Context:
                 marshall_sign: bool = True) -> "Context":
         """A t-J context with the CNN1 amplitude (nqs_create_cnn1_tj), FP64."""
         return cls(L, J, 0.0, blocks, C, weights, "fp64", marshall_sign, tj_hop=t, net="cnn1")
+
+    @classmethod
+    def cnn2_tj(cls, L: int, t: float, J: float, blocks: int, C: int, weights,
+                marshall_sign: bool = True) -> "Context":
+        """A t-J context with the CNN2 amplitude (nqs_create_cnn2_tj), FP64,
+        C = 16 or 32."""
+        return cls(L, J, 0.0, blocks, C, weights, "fp64", marshall_sign, tj_hop=t, net="cnn2")
 
     @classmethod
     def tj(cls, L: int, t: float, J: float, K: int, C: int, weights, dtype: str = "fp64",
