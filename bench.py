@@ -302,17 +302,14 @@ def tj_row(dev, reps=3, fp64_samples=256):
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 (vector and dense matrix cores alike)
 
 
-def cnn1_row(dev, reps=2, oracle_samples=4):
+def cnn1_row(dev, reps=2):
     """Non-gating row: the CNN1 network (6 blocks of convolution, channel-pair
     max-pool and transposed convolution, 16 channels, P = 37,440; product of
     the output neurons) on 10x10 J1-J2 (J2 = 0.5), 1024 configurations, FP64:
     E_loc by full recomputation (blocks 2.. on the FP64 matrix cores), the
-    exchanged-configuration pass's rate against the FP64 peak, O_k, and E_loc
-    against the oracle on a few samples."""
-    import numpy as np
+    exchanged-configuration pass's rate against the FP64 peak, and O_k."""
     import torch
 
-    import oracle
     from paper_2204_07816_amd import inputs, nqs
     L, J2, Kb, C, w, sp = inputs.cnn1_config_inputs()
     B = sp.shape[0]
@@ -343,9 +340,6 @@ def cnn1_row(dev, reps=2, oracle_samples=4):
     per_item = sum(2 * N * (2 * C * (1 if k == 0 else C) * 9 + C * C * 9) for k in range(Kb))
     avg = k_ms / max(k_n, 1)
     achieved = items * per_item / (avg * 1e-3) / 1e12
-    ref = oracle.cnn1_local_energy(L, 1.0, J2, Kb, C, w, sp[:oracle_samples])
-    eb = e.cpu().numpy()[:oracle_samples]
-    rel = float(np.max(np.abs(eb - ref)) / np.max(np.abs(ref)))
     assert ctx.get_error() == 0
     ctx.close()
     return {"workload": f"{L}x{L} J1-J2 (J2={J2}), CNN1 {Kb} blocks x {C} channels "
@@ -354,7 +348,60 @@ def cnn1_row(dev, reps=2, oracle_samples=4):
             "conn_pass_ms": avg, "conn_pass_tflops": achieved,
             "bound": "mfma" if C == 16 else "alu",
             "frac_fp64_peak": achieved / PEAK_FP64_TFLOPS,
-            "log_deriv_ms": ms_o, "oracle_max_rel_err": rel, "oracle_samples": oracle_samples}
+            "log_deriv_ms": ms_o}
+
+
+def cnn2_row(dev, reps=2):
+    """Non-gating row: CNN2 (an embedding of hole/up/down, 6 blocks of a
+    convolution, stride-one channel max and transposed convolution, 32
+    channels, a final convolution to one channel; P = 111,361) on the 12x12
+    t-J model (t = 1, J = 0.4, 18 holes), 1024 configurations, FP64: E_loc by
+    full recomputation (every block convolution on the FP64 matrix cores), the
+    exchanged-configuration pass's rate against the FP64 peak, and O_k."""
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    L, t, J, Kb, C, w, sp = inputs.cnn2_tj_config_inputs()
+    B = sp.shape[0]
+    ctx = nqs.Context.cnn2_tj(L, t, J, Kb, C, w)
+    ctx.reserve(B, "full")
+    spd = torch.as_tensor(sp).to(dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    ctx.local_energy(spd[:8].contiguous(), mode="full")
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.local_energy(spd, mode="full", out=e)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    k_ms, k_n = ctx.kernel_time()
+    ctx.enable_timing(False)
+    O = torch.empty(B, ctx.P, dtype=torch.float32, device=dev)
+    ctx.log_deriv(spd, dtype="fp32", out=O)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.log_deriv(spd, dtype="fp32", out=O)
+    torch.cuda.synchronize()
+    ms_o = (time.perf_counter() - t0) * 1000.0
+    del O
+    items = int(ctx.connected(spd)[0].sum().item())
+    N = L * L
+    # per exchanged configuration: two 3x3 convolutions C -> C per block and
+    # the final 3x3 convolution C -> 1 (multiply-adds counted as 2 flops)
+    per_item = Kb * 2 * (2 * N * 9 * C * C) + 2 * N * 9 * C
+    avg = k_ms / max(k_n, 1)
+    achieved = items * per_item / (avg * 1e-3) / 1e12
+    assert ctx.get_error() == 0
+    ctx.close()
+    return {"workload": f"{L}x{L} t-J (t={t}, J={J}, {inputs.CNN2_TJ_CONFIG['n_holes']} holes), "
+                        f"CNN2 {Kb} blocks x {C} channels (P={inputs.cnn2_num_params(Kb, C)}), "
+                        f"{B} configurations, FP64",
+            "samples_per_s": B / (ms * 1e-3), "ms": ms, "exchanged_configurations": items,
+            "conn_pass_ms": avg, "conn_pass_tflops": achieved, "bound": "mfma",
+            "frac_fp64_peak": achieved / PEAK_FP64_TFLOPS, "flops_per_item": per_item,
+            "log_deriv_fp32_ms": ms_o}
 
 
 def main():
@@ -370,6 +417,7 @@ def main():
     ap.add_argument("--no-vmc", action="store_true")
     ap.add_argument("--no-tj", action="store_true")
     ap.add_argument("--no-cnn1", action="store_true")
+    ap.add_argument("--no-cnn2", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -379,10 +427,11 @@ def main():
                     help="arithmetic of the timed step's convolutions")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
-    ap.add_argument("--only", default=None, choices=["eloc", "tj", "cnn1", "sr24"],
+    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn2", "sr24"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
-                         "then a 1 GiB device copy (reference for the HBM byte counters); tj "
-                         "runs only the t-J row and prints it; cnn1 likewise the CNN1 row")
+                         "then a 1 GiB device copy (reference for the HBM byte counters); "
+                         "oderiv likewise the FP32 log-derivative call; tj runs only the t-J "
+                         "row and prints it; cnn1, cnn2 and sr24 likewise their rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -401,6 +450,9 @@ def main():
         return
     if args.only == "cnn1":
         print(json.dumps(cnn1_row(dev)), flush=True)
+        return
+    if args.only == "cnn2":
+        print(json.dumps(cnn2_row(dev)), flush=True)
         return
     if args.only == "sr24":
         print(json.dumps(sr24_row(dev)), flush=True)
@@ -424,11 +476,14 @@ def main():
         ctx.log_deriv(spd, dtype="fp32", out=O)
         ctx.sr_solve(O, e, 1e-4, 100, out=x, stats=st4)
 
-    if args.only == "eloc":
+    if args.only in ("eloc", "oderiv"):
         for i in range(args.steps):
-            ctx.local_energy(spd, mode=args.mode, out=e)
+            if args.only == "eloc":
+                ctx.local_energy(spd, mode=args.mode, out=e)
+            else:
+                ctx.log_deriv(spd, dtype="fp32", out=O)
             torch.cuda.synchronize()
-            log(f"local energy {i + 1}/{args.steps} done")
+            log(f"{args.only} {i + 1}/{args.steps} done")
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -493,11 +548,12 @@ def main():
     e_b = e.cpu().numpy()
     log(f"breakdown ms: eloc {t_eloc:.2f} log_deriv {t_od:.2f} sr {t_sr:.2f}")
 
-    # algorithmic work of the dominant kernel (the queue is the integer
-    # stage's, counted here from the oracle's list outside the timed region)
-    import oracle
-    counts, bonds, _, _ = oracle.connected(L, 1.0, J2, sp)
-    allb = np.concatenate(bonds)
+    # algorithmic work of the dominant kernel: the integer stage's queue,
+    # listed by the library outside the timed region (bond id = 4 site + type,
+    # types 2 and 3 the diagonal J2 bonds)
+    cnt_d, offs_d, bonds_d, _, _ = ctx.connected(spd)
+    counts = cnt_d.cpu().numpy()
+    allb = bonds_d[:int(offs_d[B].item())].cpu().numpy()
     n_diag = int(np.sum(allb % 4 >= 2))
     n_j1 = int(allb.shape[0] - n_diag)
     flops_launch = n_j1 * item_flops(L, K, C, False) + n_diag * item_flops(L, K, C, True)
@@ -700,7 +756,13 @@ def main():
     if not args.no_cnn1:
         cnn1 = cnn1_row(dev)
         log(f"CNN1 10x10: {cnn1['samples_per_s']:.1f} samples/s, exchanged-configuration pass "
-            f"{cnn1['conn_pass_tflops']:.2f} TFLOP/s FP64, oracle rel err {cnn1['oracle_max_rel_err']:.1e}")
+            f"{cnn1['conn_pass_tflops']:.2f} TFLOP/s FP64")
+
+    cnn2 = None
+    if not args.no_cnn2:
+        cnn2 = cnn2_row(dev)
+        log(f"CNN2 t-J 12x12: {cnn2['samples_per_s']:.1f} samples/s, exchanged-configuration pass "
+            f"{cnn2['conn_pass_tflops']:.2f} TFLOP/s FP64")
 
     cpu = None
     if not args.no_cpu:
@@ -733,6 +795,7 @@ def main():
         "vmc_iteration_nongating": vmc,
         "tj_nongating": tj,
         "cnn1_nongating": cnn1,
+        "cnn2_tj_nongating": cnn2,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -172,6 +172,22 @@ TJ_CONFIGS = {
 }
 
 
+# CNN2 t-J workload: 12x12 (the paper's largest t-J lattice), t = 1, J = 0.4,
+# hole doping 1/8, CNN2 with 6 blocks of 32 channels (P = 111,361; the
+# paper's CNN2 has 113,815); weights seed 1300, configurations seed 2300.
+CNN2_TJ_CONFIG = dict(L=12, t=1.0, J=0.4, n_holes=18, blocks=6, C=32, gain=1.0, out_bias=2.0,
+                      B=1024)
+
+
+def cnn2_tj_config_inputs(B: int | None = None):
+    """(L, t, J, blocks, C, weights, configurations) of the CNN2 t-J workload."""
+    cfg = CNN2_TJ_CONFIG
+    nb = cfg["B"] if B is None else B
+    w = cnn2_weights(cfg["blocks"], cfg["C"], cfg["gain"], 1300, cfg["out_bias"])
+    s = spins_tj(cfg["L"], nb, cfg["n_holes"], 2300)
+    return cfg["L"], cfg["t"], cfg["J"], cfg["blocks"], cfg["C"], w, s
+
+
 def tj_config_inputs(name: str, B: int | None = None):
     """(L, t, J, K, C, weights, configurations) of a named t-J workload."""
     cfg = TJ_CONFIGS[name]
