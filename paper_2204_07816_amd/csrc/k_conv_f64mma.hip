@@ -4,7 +4,7 @@
 // every output element is an FP64 fused multiply-add chain.  They serve the
 // plain FP64 network (base and exchanged configurations alike, so the two
 // sides of a log-ratio still run identical arithmetic), the forward pass that
-// saves pre-activations, the backward data pass, and the weight gradients
+// saves tanh of the pre-activations, the backward data pass, and the weight gradients
 // that form the rows of O [Sec. 3.2].
 //
 // Operand layout of v_mfma_f64_16x16x4f64 (64 lanes, lane l):
@@ -20,7 +20,14 @@ namespace {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kMT = 4;            // 16-site M-tiles per wave (64 sites)
+#ifndef NQS_CONV_MT
+#define NQS_CONV_MT 4
+#endif
+#ifndef NQS_CONV_PF
+#define NQS_CONV_PF 0
+#endif
+constexpr int kMT = NQS_CONV_MT;  // 16-site M-tiles per wave
+constexpr bool kPF = NQS_CONV_PF; // fetch the next K-block's operands before this one's MFMAs
 constexpr int kNT = 3;            // 16-column N-tiles per weight-gradient wave
 
 __device__ inline int wrapi(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
@@ -40,7 +47,7 @@ struct ConvArgs {
     const double *w;         // [9][Cin][Cout]
     const double *bias;      // [Cout] or null
     double *out;             // [M][N][Cout]
-    double *zk;              // epi 1: saved z [M][N][Cout]; epi 2: z_{k-1} for tanh
+    double *zk;              // epi 1: saved tanh z [M][N][Cout]; epi 2: tanh z_{k-1}; MODE 1, 3: z
     const int64_t *qlen;     // exchanged-configuration queue length (null: all M live)
     int64_t q_begin;
     int64_t M;
@@ -51,8 +58,8 @@ struct ConvArgs {
 // for 64 sites x COUT channels per wave.  GEMM: M = sites, N = co, K = (t, ci)
 // in steps of 4; within a 16-channel block, lane group kq at sub-step s takes
 // channel 4 kq + s, so each lane reads 4 consecutive channels of a site.
-// epi 0: ln cosh; 1: ln cosh and save z; 2: z * tanh(zk) (backward data pass);
-// 3: tanh z (the last layer's delta).
+// epi 0: ln cosh; 1: ln cosh and save tanh z in zk; 2: z * zk (backward data
+// pass, zk the saved tanh); 3: tanh z (the last layer's delta).
 // MODE 1 (CNN1 convolution, COUT = 32): column 16 h + j holds z[2 j + h], so
 // one lane holds both inputs of a channel-pair max: out [M][N][16] gets
 // max(z[2j], z[2j+1]) (the second only when larger), zk (may be null) the z
@@ -62,31 +69,38 @@ struct ConvArgs {
 // when larger), zk (may be null) the z; channel c+1 sits in the next lane of
 // the same 16-lane row group, or for c = 16 h + 15 in lane 0 of the group
 // and the next 16-column tile.
-template <int COUT, int MODE = 0>
+template <int COUT, int MODE, int CIN>
 __global__ void __launch_bounds__(kThreads)
 k_conv_mma(ConvArgs a)
 {
     constexpr int NH = COUT / 16;
-    const int L = a.L, N = L * L, Cin = a.Cin;
+    constexpr int NCB = CIN / 16;               // 16-channel K-blocks per tap
+    constexpr int NSTEP = 9 * NCB;
+    const int L = a.L, N = L * L;
     const int lane = threadIdx.x & 63;
     const int m16 = lane & 15, kq = lane >> 4;
-    const int ntile = (N + 16 * kMT - 1) / (16 * kMT);
     const int64_t wave_id = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     int64_t live = a.M;
     if (a.qlen) {
         const int64_t left = a.qlen[0] - a.q_begin;
         live = left < 0 ? 0 : (left < a.M ? left : a.M);
     }
-    const int64_t plane = wave_id / ntile;
-    if (plane >= live) return;
-    const int p0 = (int)(wave_id - plane * ntile) * 16 * kMT;
-    const double *inp = a.in + plane * (int64_t)N * Cin;
-
+    // The planes' sites form one index space g = plane * N + p, tiled in runs
+    // of 16 kMT that may span two planes, so no lattice size leaves part of a
+    // tile idle; planes are contiguous, so element (g, c) of any [M][N][X]
+    // array sits at g X + c.
+    const int64_t total = live * N;
+    const int64_t g0 = wave_id * 16 * kMT;
+    if (g0 >= total) return;
+    const double *inr[kMT];          // this lane's A-row plane
     int sx[kMT], sy[kMT];
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt) {
-        int p = p0 + mt * 16 + m16;
-        if (p >= N) p = N - 1;
+        int64_t g = g0 + mt * 16 + m16;
+        if (g >= total) g = total - 1;
+        const int64_t pl = g / N;
+        const int p = (int)(g - pl * N);
+        inr[mt] = a.in + pl * (int64_t)N * CIN;
         sy[mt] = p / L;
         sx[mt] = p - sy[mt] * L;
     }
@@ -97,53 +111,80 @@ k_conv_mma(ConvArgs a)
 #pragma unroll
         for (int mt = 0; mt < kMT; ++mt) acc[mt][h] = (double4_t){b, b, b, b};
     }
-    for (int t = 0; t < 9; ++t) {
+    // operands of K-block kb (tap t = kb / NCB, channels c0 .. c0 + 15): this
+    // lane's 4 consecutive input channels at each of its kMT sites, and the
+    // 4 x NH weights of its column
+    auto fetch = [&](int kb, double (&av)[kMT][4], double (&bv)[4][NH]) {
+        const int t = kb / NCB, c0 = (kb - t * NCB) * 16;
         const int dy = t / 3 - 1, dx = t % 3 - 1;
-        int site[kMT];
+        const int cb = c0 + 4 * kq;
 #pragma unroll
-        for (int mt = 0; mt < kMT; ++mt)
-            site[mt] = wrapi(sy[mt] + dy, L) * L + wrapi(sx[mt] + dx, L);
-        const double *wt = a.w + (int64_t)t * Cin * COUT;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            const int cb = c0 + 4 * kq;
-            double av[kMT][4], bv[4][NH];
+        for (int mt = 0; mt < kMT; ++mt) {
+            const int site = wrapi(sy[mt] + dy, L) * L + wrapi(sx[mt] + dx, L);
+            const double2 *src = reinterpret_cast<const double2 *>(inr[mt] + (int64_t)site * CIN + cb);
+            const double2 u = src[0], v = src[1];
+            av[mt][0] = u.x;
+            av[mt][1] = u.y;
+            av[mt][2] = v.x;
+            av[mt][3] = v.y;
+        }
+        const double *wt = a.w + ((int64_t)t * CIN + cb) * COUT + m16;
 #pragma unroll
-            for (int mt = 0; mt < kMT; ++mt) {
-                const double2 *src = reinterpret_cast<const double2 *>(inp + (int64_t)site[mt] * Cin + cb);
-                const double2 u = src[0], v = src[1];
-                av[mt][0] = u.x;
-                av[mt][1] = u.y;
-                av[mt][2] = v.x;
-                av[mt][3] = v.y;
-            }
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int h = 0; h < NH; ++h) bv[s][h] = wt[s * COUT + 16 * h];
+    };
+    auto mma = [&](const double (&av)[kMT][4], const double (&bv)[4][NH]) {
 #pragma unroll
-                for (int h = 0; h < NH; ++h) bv[s][h] = wt[(int64_t)(cb + s) * COUT + 16 * h + m16];
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+                    acc[mt][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt][s], bv[s][h],
+                                                                      acc[mt][h], 0, 0, 0);
+    };
+    if constexpr (kPF) {
+        double av[kMT][4], bv[4][NH];
+        fetch(0, av, bv);
+#pragma unroll
+        for (int kb = 0; kb < NSTEP; ++kb) {
+            double an[kMT][4], bn[4][NH];
+            if (kb + 1 < NSTEP) fetch(kb + 1, an, bn);
+            mma(av, bv);
+            if (kb + 1 < NSTEP) {
 #pragma unroll
                 for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
-                    for (int h = 0; h < NH; ++h)
-                        acc[mt][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt][s], bv[s][h],
-                                                                          acc[mt][h], 0, 0, 0);
+                    for (int q = 0; q < 4; ++q) av[mt][q] = an[mt][q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) bv[q][h] = bn[q][h];
+            }
+        }
+    } else {
+        for (int kb = 0; kb < NSTEP; ++kb) {
+            double av[kMT][4], bv[4][NH];
+            fetch(kb, av, bv);
+            mma(av, bv);
         }
     }
-    const int64_t obase = plane * (int64_t)N * COUT;
+    // D element i of tile mt in this lane: site g0 + 16 mt + kq + 4 i, column
+    // 16 h + m16
     if constexpr (MODE == 1) {
         static_assert(COUT == 32, "channel pairs span the two 16-column tiles");
 #pragma unroll
         for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = p0 + mt * 16 + kq + 4 * i;
-                if (p >= N) continue;
+                const int64_t g = g0 + mt * 16 + kq + 4 * i;
+                if (g >= total) continue;
                 const double z0 = acc[mt][0][i], z1 = acc[mt][1][i];
-                a.out[plane * (int64_t)N * 16 + (int64_t)p * 16 + m16] = (z1 > z0) ? z1 : z0;
+                a.out[g * 16 + m16] = (z1 > z0) ? z1 : z0;
                 if (a.zk) {
-                    a.zk[obase + (int64_t)p * 32 + 2 * m16] = z0;
-                    a.zk[obase + (int64_t)p * 32 + 2 * m16 + 1] = z1;
+                    a.zk[g * 32 + 2 * m16] = z0;
+                    a.zk[g * 32 + 2 * m16 + 1] = z1;
                 }
             }
         return;
@@ -154,16 +195,16 @@ k_conv_mma(ConvArgs a)
         for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = p0 + mt * 16 + kq + 4 * i;   // same row in lane_next
+                const int64_t g = g0 + mt * 16 + kq + 4 * i;   // same row in lane_next
                 double nb[NH];
 #pragma unroll
                 for (int h = 0; h < NH; ++h) nb[h] = __shfl(acc[mt][h][i], lane_next, 64);
-                if (p >= N) continue;
+                if (g >= total) continue;
 #pragma unroll
                 for (int h = 0; h < NH; ++h) {
                     const double z0 = acc[mt][h][i];
                     const double z1 = m16 < 15 ? nb[h] : nb[(h + 1) % NH];
-                    const int64_t o = obase + (int64_t)p * COUT + 16 * h + m16;
+                    const int64_t o = g * COUT + 16 * h + m16;
                     a.out[o] = (z1 > z0) ? z1 : z0;
                     if (a.zk) a.zk[o] = z0;
                 }
@@ -175,42 +216,71 @@ k_conv_mma(ConvArgs a)
         for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = p0 + mt * 16 + kq + 4 * i;
-                if (p >= N) continue;
+                const int64_t g = g0 + mt * 16 + kq + 4 * i;
+                if (g >= total) continue;
 #pragma unroll
-                for (int h = 0; h < NH; ++h)
-                    a.out[obase + (int64_t)p * COUT + 16 * h + m16] = acc[mt][h][i];
+                for (int h = 0; h < NH; ++h) a.out[g * COUT + 16 * h + m16] = acc[mt][h][i];
             }
         return;
     }
+    if (a.epi == 2) {
+        // backward data pass: z times the saved tanh of the layer below
+#pragma unroll
+        for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t g = g0 + mt * 16 + kq + 4 * i;
+                if (g >= total) continue;
+#pragma unroll
+                for (int h = 0; h < NH; ++h) {
+                    const int64_t o = g * COUT + 16 * h + m16;
+                    a.out[o] = acc[mt][h][i] * a.zk[o];
+                }
+            }
+        return;
+    }
+    // The transcendental epilogues run in two phases: z leaves the
+    // accumulators first, then each element is re-read (by the lane that
+    // wrote it) and transformed in a rolled loop, so no accumulator is live
+    // across the math library's code.
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int p = p0 + mt * 16 + kq + 4 * i;
-            if (p >= N) continue;
+            const int64_t g = g0 + mt * 16 + kq + 4 * i;
+            if (g >= total) continue;
 #pragma unroll
-            for (int h = 0; h < NH; ++h) {
-                const int64_t o = obase + (int64_t)p * COUT + 16 * h + m16;
-                const double z = acc[mt][h][i];
-                if (a.epi >= 2) {
-                    // one tanh call site: epi 3 writes tanh z, epi 2 z tanh(zk)
-                    const double th = tanh(a.epi == 3 ? z : a.zk[o]);
-                    a.out[o] = a.epi == 3 ? th : z * th;
-                } else {
-                    if (a.epi == 1) a.zk[o] = z;
-                    a.out[o] = ln_cosh_d(z);
-                }
-            }
+            for (int h = 0; h < NH; ++h) a.out[g * COUT + 16 * h + m16] = acc[mt][h][i];
         }
+#pragma unroll 1
+    for (int e = 0; e < kMT * 4 * NH; ++e) {
+        const int mt = e / (4 * NH), i = (e / NH) % 4, h = e % NH;
+        const int64_t g = g0 + mt * 16 + kq + 4 * i;
+        if (g >= total) continue;
+        const int64_t o = g * COUT + 16 * h + m16;
+        const double z = a.out[o];
+        if (a.epi == 3) {
+            a.out[o] = tanh(z);
+        } else if (a.epi == 1) {
+            double th;
+            a.out[o] = ln_cosh_tanh(z, &th);
+            a.zk[o] = th;
+        } else {
+            a.out[o] = ln_cosh_d(z);
+        }
+    }
 }
 
 // Weight and bias gradients of one layer with C input and output channels,
 // per sample:  dW[co][ci][t] = sum_p delta[p][co] h[p + off(t)][ci],
 //              db[co] = sum_p delta[p][co].
 // GEMM over sites: M = co (C), N = (t, ci) (9C columns, ci fastest, so a
-// 16-column tile never straddles two taps), K = sites in steps of 4.  A wave
-// owns all C output channels and kNT consecutive column tiles of one sample.
+// 16-column tile never straddles two taps), K = sites in steps of 4.  A
+// column group of kNT consecutive 16-column tiles of one sample is shared by
+// two waves of a workgroup, one per half of the site range; the second half's
+// partial sums pass through LDS and the first adds them (lo + hi, a fixed
+// order), so rows stay deterministic.  A workgroup holds two column groups
+// (one idle pair when a sample has an odd number of groups).
 // TRANS (a transposed convolution u[co][p] = sum V[ci][co][t] h[p - off(t)][ci]):
 // dV[ci][co][t] = sum_p delta[p][co] h[p - off(t)][ci], stored input channel
 // first; the bias gradient as before.
@@ -221,14 +291,17 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
 {
     constexpr int NH = C / 16;
     constexpr int NTILE = 9 * C / 16;
-    constexpr int WPS = (NTILE + kNT - 1) / kNT;   // waves per sample
+    constexpr int WPS = (NTILE + kNT - 1) / kNT;   // column groups per sample
+    constexpr int GPS = (WPS + 1) / 2;             // workgroups per sample
+    constexpr int NRED = NH * kNT * 4 + NH;        // partials per lane
+    __shared__ double red[2][NRED][64];
     const int N = L * L;
     const int lane = threadIdx.x & 63;
     const int m16 = lane & 15, kq = lane >> 4;
-    const int64_t wave_id = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    const int64_t s = wave_id / WPS;
-    if (s >= B) return;
-    const int wg = (int)(wave_id - s * WPS);
+    const int w = threadIdx.x >> 6, cgl = w >> 1, kh = w & 1;
+    const int64_t s = blockIdx.x / GPS;            // the grid holds B * GPS workgroups
+    const int wg = (int)(blockIdx.x - s * GPS) * 2 + cgl;
+    const bool active = wg < WPS;
     const double *dl = delta + s * (int64_t)N * C;
     const double *hs = hin + s * (int64_t)N * C;
 
@@ -265,36 +338,62 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
             bv[j] = hs[(int64_t)r * C + tci[j]];
         }
     };
-    const int y0 = kq / L, x0 = kq - (kq / L) * L;
-    int y = y0, x = x0;                        // site of position p0 + kq
-    double av[NH], bv[kNT];
-    fetch(kq, y, x, av, bv);
-    // the operands of step p0 + 4 are fetched while the matrix cores work on
-    // p0 (the last step fetches step 0's again, unused, so that the loop has
-    // no branch)
-    for (int p0 = 0; p0 < N; p0 += 4) {
-        int xn = x + 4, yn = y;                // L >= 4: at most one row end
-        if (xn >= L) {
-            xn -= L;
-            ++yn;
-        }
-        const bool more = p0 + 4 < N;
-        double an[NH], bn[kNT];
-        fetch(more ? p0 + 4 + kq : kq, more ? yn : y0, more ? xn : x0, an, bn);
+    // this wave's half of the sites, [pb, pe), both multiples of 4 (N is)
+    const int mid = (N / 2) & ~3;
+    const int pb = kh ? mid : 0, pe = kh ? N : mid;
+    if (active && pb < pe) {
+        const int y0 = (pb + kq) / L, x0 = (pb + kq) - ((pb + kq) / L) * L;
+        int y = y0, x = x0;                    // site of position p0 + kq
+        double av[NH], bv[kNT];
+        fetch(pb + kq, y, x, av, bv);
+        // the operands of step p0 + 4 are fetched while the matrix cores work
+        // on p0 (the last step fetches the first step's again, unused, so that
+        // the loop has no branch)
+        for (int p0 = pb; p0 < pe; p0 += 4) {
+            int xn = x + 4, yn = y;            // L >= 4: at most one row end
+            if (xn >= L) {
+                xn -= L;
+                ++yn;
+            }
+            const bool more = p0 + 4 < pe;
+            double an[NH], bn[kNT];
+            fetch(more ? p0 + 4 + kq : pb + kq, more ? yn : y0, more ? xn : x0, an, bn);
 #pragma unroll
-        for (int h = 0; h < NH; ++h) dbp[h] += av[h];
+            for (int h = 0; h < NH; ++h) dbp[h] += av[h];
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+#pragma unroll
+                for (int j = 0; j < kNT; ++j)
+                    acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[j], acc[h][j], 0, 0, 0);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) av[h] = an[h];
+#pragma unroll
+            for (int j = 0; j < kNT; ++j) bv[j] = bn[j];
+            x = xn;
+            y = yn;
+        }
+    }
+    // the second half hands its partial sums to the first
+    if (kh == 1) {
 #pragma unroll
         for (int h = 0; h < NH; ++h)
 #pragma unroll
             for (int j = 0; j < kNT; ++j)
-                acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[j], acc[h][j], 0, 0, 0);
 #pragma unroll
-        for (int h = 0; h < NH; ++h) av[h] = an[h];
+                for (int i = 0; i < 4; ++i) red[cgl][(h * kNT + j) * 4 + i][lane] = acc[h][j][i];
 #pragma unroll
-        for (int j = 0; j < kNT; ++j) bv[j] = bn[j];
-        x = xn;
-        y = yn;
+        for (int h = 0; h < NH; ++h) red[cgl][NH * kNT * 4 + h][lane] = dbp[h];
     }
+    __syncthreads();
+    if (kh == 1 || !active) return;
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int j = 0; j < kNT; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[h][j][i] += red[cgl][(h * kNT + j) * 4 + i][lane];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) dbp[h] += red[cgl][NH * kNT * 4 + h][lane];
     OT *o = O + s * P + woff;
     // D element i of this lane: co = 16 h + kq + 4 i, column ci = tci[j]
 #pragma unroll
@@ -326,18 +425,28 @@ k_wgrad_mma(const double *__restrict__ hin, const double *__restrict__ delta, in
 
 bool f64mma_conv_ok(int Cin, int Cout) { return (Cin == 16 || Cin == 32) && (Cout == 16 || Cout == 32); }
 
+// one launch of k_conv_mma<COUT, MODE, Cin> over M planes
+template <int COUT, int MODE>
+void conv_launch(const nqs_ctx *c, const ConvArgs &a, hipStream_t s)
+{
+    const int64_t tiles = (a.M * c->N + 16 * kMT - 1) / (16 * kMT);
+    const int64_t blocks = (tiles + kThreads / 64 - 1) / (kThreads / 64);
+    if (a.Cin == 32)
+        NQS_LAUNCH((k_conv_mma<COUT, MODE, 32>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    else
+        NQS_LAUNCH((k_conv_mma<COUT, MODE, 16>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+}
+
 void f64mma_conv(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cout,
                  const double *w, const double *bias, double *out, int epi, double *zk,
                  const int64_t *qlen, int64_t q_begin, hipStream_t s)
 {
     if (M <= 0) return;
     ConvArgs a{in, w, bias, out, zk, qlen, q_begin, M, c->L, Cin, epi};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
     if (Cout == 32)
-        NQS_LAUNCH((k_conv_mma<32>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<32, 0>(c, a, s);
     else
-        NQS_LAUNCH((k_conv_mma<16>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<16, 0>(c, a, s);
 }
 
 // CNN1 with 16 channels: the convolution 16 -> 32 with the channel-pair max
@@ -349,9 +458,7 @@ void f64mma_cnn1_conv(const nqs_ctx *c, const double *in, int64_t M, const doubl
 {
     if (M <= 0) return;
     ConvArgs a{in, w, bias, out, zsave, qlen, q_begin, M, c->L, 16, 0};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
-    NQS_LAUNCH((k_conv_mma<32, 1>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    conv_launch<32, 1>(c, a, s);
 }
 
 void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const double *w,
@@ -360,9 +467,7 @@ void f64mma_cnn1_convt(const nqs_ctx *c, const double *in, int64_t M, const doub
 {
     if (M <= 0) return;
     ConvArgs a{in, w, bias, out, nullptr, qlen, q_begin, M, c->L, 16, 0};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
-    NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    conv_launch<16, 2>(c, a, s);
 }
 
 // plain convolution Cin (16 or 32) -> 16 with no bias and no activation
@@ -372,9 +477,7 @@ void f64mma_cnn1_plain(const nqs_ctx *c, const double *in, int64_t M, int Cin, c
 {
     if (M <= 0) return;
     ConvArgs a{in, w, nullptr, out, nullptr, nullptr, 0, M, c->L, Cin, 0};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
-    NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    conv_launch<16, 2>(c, a, s);
 }
 
 // CNN2 convolution C -> C with the stride-one channel max in the epilogue
@@ -385,12 +488,10 @@ void f64mma_cnn2_conv(const nqs_ctx *c, const double *in, int64_t M, const doubl
 {
     if (M <= 0) return;
     ConvArgs a{in, w, bias, out, zsave, qlen, q_begin, M, c->L, c->C, 0};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
     if (c->C == 32)
-        NQS_LAUNCH((k_conv_mma<32, 3>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<32, 3>(c, a, s);
     else
-        NQS_LAUNCH((k_conv_mma<16, 3>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<16, 3>(c, a, s);
 }
 
 // convolution Cin -> Cout (16 or 32) with an optional bias and no activation
@@ -402,12 +503,10 @@ void f64mma_linear(const nqs_ctx *c, const double *in, int64_t M, int Cin, int C
 {
     if (M <= 0) return;
     ConvArgs a{in, w, bias, out, nullptr, qlen, q_begin, M, c->L, Cin, 0};
-    const int64_t ntile = (c->N + 16 * kMT - 1) / (16 * kMT);
-    const int64_t blocks = (M * ntile + kThreads / 64 - 1) / (kThreads / 64);
     if (Cout == 32)
-        NQS_LAUNCH((k_conv_mma<32, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<32, 2>(c, a, s);
     else
-        NQS_LAUNCH((k_conv_mma<16, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+        conv_launch<16, 2>(c, a, s);
 }
 
 bool f64mma_wgrad_ok(int C) { return C == 16 || C == 32; }
@@ -418,8 +517,8 @@ void wgrad_launch(const nqs_ctx *c, const double *hin, const double *delta, int 
                   void *O, nqs_dtype odt, hipStream_t s)
 {
     const int C = c->C;
-    const int wps = (9 * C / 16 + kNT - 1) / kNT;
-    const int64_t blocks = ((int64_t)B * wps + kThreads / 64 - 1) / (kThreads / 64);
+    const int wps = (9 * C / 16 + kNT - 1) / kNT;            // column groups per sample
+    const int64_t blocks = (int64_t)B * ((wps + 1) / 2);       // two groups per workgroup
     const dim3 g((unsigned)blocks), b(kThreads);
     if (C == 32) {
         if (odt == NQS_FP32)

@@ -125,8 +125,13 @@ k_layer1(const int8_t *__restrict__ spins, PlaneMap pm, int64_t M, int L, int C,
             T z = w[9 * C + co];
 #pragma unroll
             for (int t = 0; t < 9; ++t) z = fma(w[t * C + co], sv[t], z);
-            if (zsave) zsave[mp * C + co] = (double)z;
-            out[mp * C + co] = ln_cosh(z);
+            if (zsave) {
+                double th;
+                out[mp * C + co] = (T)ln_cosh_tanh((double)z, &th);
+                zsave[mp * C + co] = th;
+            } else {
+                out[mp * C + co] = ln_cosh(z);
+            }
         }
     }
 }
@@ -151,8 +156,9 @@ void layer1_launch(const nqs_ctx *c, const int8_t *spins, PlaneMap pm, int64_t M
 
 // Layers 2..K and the backward data pass: out[m][p][co] = epi(bias[co] +
 // sum_{t, ci} W[t][ci][co] in[m][p + off(t)][ci]).  epi: 0 = ln cosh,
-// 1 = ln cosh and save z to zk[m][p][co], 2 = multiply by tanh(zk[m][p][co])
-// (no bias), 3 = tanh z (the last layer's delta, d ln cosh z / dz).  Saved pre-activations are laid out [layer][plane][site][channel].
+// 1 = ln cosh and save tanh z to zk[m][p][co], 2 = multiply by zk[m][p][co]
+// (the saved tanh; no bias), 3 = tanh z (the last layer's delta, d ln cosh z
+// / dz).  Saved values are laid out [layer][plane][site][channel].
 template <typename T, int CPT>
 __global__ void __launch_bounds__(kThreads)
 k_layer(const T *__restrict__ in, int64_t M, int L, int Cin, int Cout,
@@ -196,12 +202,15 @@ k_layer(const T *__restrict__ in, int64_t M, int L, int Cin, int Cout,
         } else if (epi == 2) {
             const double *zp = zk + mp * Cout + co0;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) o[j] = acc[j] * (T)tanh(zp[j]);
-        } else {
-            if (epi == 1) {
+            for (int j = 0; j < CPT; ++j) o[j] = acc[j] * (T)zp[j];
+        } else if (epi == 1) {
 #pragma unroll
-                for (int j = 0; j < CPT; ++j) zk[mp * Cout + co0 + j] = (double)acc[j];
+            for (int j = 0; j < CPT; ++j) {
+                double th;
+                o[j] = (T)ln_cosh_tanh((double)acc[j], &th);
+                zk[mp * Cout + co0 + j] = th;
             }
+        } else {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) o[j] = ln_cosh(acc[j]);
         }
@@ -338,12 +347,13 @@ k_wgrad1(const int8_t *__restrict__ spins, const double *__restrict__ delta, int
 }
 
 // delta_K = tanh(z_K)  (d f / d h_K = 1, d ln cosh z / dz = tanh z)
-__global__ void k_delta_last(const double *__restrict__ zK, int64_t total,
+// the last layer's delta when it is layer 1: the saved tanh z
+__global__ void k_delta_last(const double *__restrict__ thK, int64_t total,
                              double *__restrict__ delta)
 {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x)
-        delta[g] = tanh(zK[g]);
+        delta[g] = thK[g];
 }
 
 template <typename T>
@@ -502,7 +512,7 @@ void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zs
 {
     if (B <= 0) return;
     const int N = c->N, C = c->C, K = c->K;
-    const int64_t layer = (int64_t)B * N * C;   // one layer of saved z or h: [B][N][C]
+    const int64_t layer = (int64_t)B * N * C;   // one layer of saved tanh z or h: [B][N][C]
     double *cur = delta_a, *nxt = delta_b;
     std::vector<int64_t> woff(K);   // layer offsets in the canonical parameter vector
     int64_t off = 0;

@@ -27,6 +27,20 @@ __host__ __device__ inline uint32_t pack_item(int sample, int bond) {
 __host__ __device__ inline int item_sample(uint32_t e) { return (int)(e >> kBondBits); }
 __host__ __device__ inline int item_bond(uint32_t e) { return (int)(e & ((1u << kBondBits) - 1)); }
 
+// ln cosh z and tanh z from one expm1, for the forward pass of the backward
+// (which keeps tanh z, the derivative of ln cosh, for the data gradient):
+// with m = expm1(-2|z|), tanh|z| = -m / (2 + m) at full relative precision,
+// and ln cosh z = |z| + log1p(m / 2) to a few ulp of |z| in absolute terms
+// (the pass needs ln cosh only as the next layer's input, where an absolute
+// error at FP64 rounding level is what any order of the sums gives).
+__device__ inline double ln_cosh_tanh(double z, double *th)
+{
+    const double a = fabs(z);
+    const double m = expm1(-2.0 * a);
+    *th = copysign(-m / (2.0 + m), z);
+    return a + log1p(0.5 * m);
+}
+
 // Hamiltonian of a context: the J1-J2 spin model [Sec. 6.1, Eq. J1J2] or
 // the t-J model [Sec. 6.1, Eq. tJ] (site values +1 / -1 / 0, nearest-
 // neighbour bonds only, J held in J1).
@@ -75,7 +89,7 @@ struct Workspace {
     DevBuf cache;       // activations of the base pass (dtype-dependent)
     DevBuf plane_a;     // scratch planes for the vector path
     DevBuf plane_b;
-    DevBuf zsave;       // f64 pre-activations for the backward pass
+    DevBuf zsave;       // f64 saved values of the backward pass (tanh z; z for CNN1/CNN2)
     DevBuf hsave;       // f64 activations for the backward pass
     DevBuf delta;       // f64 backward deltas
     DevBuf sr;          // SR vectors
@@ -191,8 +205,8 @@ void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                       const int64_t *qlen, int64_t q_begin, int64_t q_count, const double *hsum,
                       double *dlog, void *plane_a, void *plane_b, hipStream_t s);
 size_t vec_plane_bytes(const nqs_ctx *c, int64_t items);
-// Backward: O[B][P] from the saved pre-activations.
-// forward of B samples for the backward: z and h = ln cosh z of layers
+// Backward: O[B][P] from the saved activations and tanh of the pre-activations.
+// forward of B samples for the backward: tanh z and h = ln cosh z of layers
 // 1..K-1 into zsave / hsave ([layer][B][N][C] FP64 each), and the last
 // layer's delta tanh z_K into delta_last
 void vec_deriv_forward(const nqs_ctx *c, const int8_t *spins, int B, double *zsave,
@@ -204,8 +218,9 @@ void vec_backward(const nqs_ctx *c, const int8_t *spins, int B, const double *zs
 
 // --- FP64 matrix-core layer and weight-gradient kernels (k_conv_f64mma.hip) ---
 bool f64mma_conv_ok(int Cin, int Cout);
-// epi 0: ln cosh; 1: ln cosh + save z to zk; 2: z * tanh(zk).  qlen (may be
-// null) bounds the live planes to qlen[0] - q_begin.
+// epi 0: ln cosh; 1: ln cosh + save tanh z to zk; 2: z * zk (zk the saved
+// tanh); 3: tanh z.  qlen (may be null) bounds the live planes to qlen[0] -
+// q_begin.
 void f64mma_conv(const nqs_ctx *c, const double *in, int64_t M, int Cin, int Cout,
                  const double *w, const double *bias, double *out, int epi, double *zk,
                  const int64_t *qlen, int64_t q_begin, hipStream_t s);
