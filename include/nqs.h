@@ -196,6 +196,19 @@ nqs_status nqs_create_cnn2_tj(int32_t L, double t, double J, int32_t blocks, int
                               int32_t marshall_sign, const double *weights, int64_t n_weights,
                               nqs_ctx **out);
 
+/* Matrix-core calibration (no context): `workgroups` workgroups of 4 waves
+ * each run `iters` x 8 independent MFMA instructions from registers only
+ * (kind 0: v_mfma_f32_16x16x32_bf16; kind 1: v_mfma_f64_16x16x4f64), timed
+ * with HIP events on `stream` after one warm-up launch.  *ms (host) is the
+ * timed launch and *tflops (host) the sustained rate.  It measures what the
+ * matrix cores deliver under full load, beside the published dense peaks the
+ * roofline fractions are quoted against.  Allocates and frees a small device
+ * buffer and synchronises the stream.  Errors: NQS_E_ARG (kind not 0/1,
+ * workgroups outside 1..2^20, iters < 1, null outputs), NQS_E_WORKSPACE
+ * (stream under capture), NQS_E_NOMEM, NQS_E_HIP.                          */
+nqs_status nqs_mfma_rate(int32_t kind, int64_t workgroups, int32_t iters, double *ms,
+                         double *tflops, void *stream);
+
 /* Release the context and its device memory (synchronises the device).  */
 nqs_status nqs_destroy(nqs_ctx *ctx);
 

@@ -20,14 +20,7 @@ namespace {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-#ifndef NQS_CONV_MT
-#define NQS_CONV_MT 4
-#endif
-#ifndef NQS_CONV_PF
-#define NQS_CONV_PF 0
-#endif
-constexpr int kMT = NQS_CONV_MT;  // 16-site M-tiles per wave
-constexpr bool kPF = NQS_CONV_PF; // fetch the next K-block's operands before this one's MFMAs
+constexpr int kMT = 4;            // 16-site M-tiles per wave (64 sites)
 constexpr int kNT = 3;            // 16-column N-tiles per weight-gradient wave
 
 __device__ inline int wrapi(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
@@ -144,31 +137,12 @@ k_conv_mma(ConvArgs a)
                     acc[mt][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt][s], bv[s][h],
                                                                       acc[mt][h], 0, 0, 0);
     };
-    if constexpr (kPF) {
+    // (fetching the next K-block's operands before this one's MFMAs, in
+    // registers, measured no faster: three waves per SIMD hide the latency)
+    for (int kb = 0; kb < NSTEP; ++kb) {
         double av[kMT][4], bv[4][NH];
-        fetch(0, av, bv);
-#pragma unroll
-        for (int kb = 0; kb < NSTEP; ++kb) {
-            double an[kMT][4], bn[4][NH];
-            if (kb + 1 < NSTEP) fetch(kb + 1, an, bn);
-            mma(av, bv);
-            if (kb + 1 < NSTEP) {
-#pragma unroll
-                for (int mt = 0; mt < kMT; ++mt)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) av[mt][q] = an[mt][q];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int h = 0; h < NH; ++h) bv[q][h] = bn[q][h];
-            }
-        }
-    } else {
-        for (int kb = 0; kb < NSTEP; ++kb) {
-            double av[kMT][4], bv[4][NH];
-            fetch(kb, av, bv);
-            mma(av, bv);
-        }
+        fetch(kb, av, bv);
+        mma(av, bv);
     }
     // D element i of tile mt in this lane: site g0 + 16 mt + kq + 4 i, column
     // 16 h + m16

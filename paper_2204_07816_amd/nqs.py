@@ -63,6 +63,7 @@ def load():
         "nqs_create_cnn1": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_create_cnn1_tj": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
         "nqs_create_cnn2_tj": [i32, d, d, i32, i32, i32, vp, i64, P(vp)],
+        "nqs_mfma_rate": [i32, i64, i32, P(d), P(d), vp],
         "nqs_destroy": [vp],
         "nqs_num_params": [vp, P(i64)],
         "nqs_set_weights": [vp, vp, i64],
@@ -428,6 +429,15 @@ def local_energy_multi(jobs, mode: str = "auto"):
         arr[i] = ElocJob(ctx.handle.value, sp.value, B, _dev(e, torch.float64, "e_loc").value)
     _check(load().nqs_local_energy_multi(arr, len(jobs), _MODES[mode], _stream()),
            "nqs_local_energy_multi")
+
+
+def mfma_rate(kind: str = "bf16", workgroups: int = 4096, iters: int = 4000):
+    """Sustained matrix-core rate of a register-only MFMA loop (nqs_mfma_rate):
+    (launch ms, TFLOP/s); kind "bf16" (16x16x32) or "fp64" (16x16x4)."""
+    ms, tf = ctypes.c_double(), ctypes.c_double()
+    _check(load().nqs_mfma_rate({"bf16": 0, "fp64": 1}[kind], workgroups, iters,
+                                ctypes.byref(ms), ctypes.byref(tf), _stream()), "nqs_mfma_rate")
+    return ms.value, tf.value
 
 
 def tune_key(L: int, K: int, C: int, dtype: str, J2: float) -> str:

@@ -137,3 +137,12 @@ def test_create_cnn1_tj_rejects_bad_arguments(lib):
     assert lib.nqs_create_cnn1_tj(4, 1.0, 0.4, 2, 4, 1, buf, 671, ctypes.byref(h)) == 4
     assert lib.nqs_create_cnn1_tj(4, float("inf"), 0.4, 2, 4, 1, buf, 672, ctypes.byref(h)) == 1
     assert not h.value
+
+
+def test_mfma_rate_rejects_bad_arguments(lib):
+    """nqs_mfma_rate checks its arguments before touching the device."""
+    ms, tf = ctypes.c_double(), ctypes.c_double()
+    for kind, wg, it in ((2, 16, 10), (0, 0, 10), (1, 16, 0), (0, 1 << 21, 10)):
+        assert lib.nqs_mfma_rate(kind, ctypes.c_int64(wg), it, ctypes.byref(ms),
+                                 ctypes.byref(tf), None) == 1          # NQS_E_ARG
+    assert lib.nqs_mfma_rate(0, ctypes.c_int64(16), 10, None, ctypes.byref(tf), None) == 1
