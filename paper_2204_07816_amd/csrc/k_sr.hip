@@ -43,22 +43,56 @@ __device__ double block_sum(double v, double *sh)
     return r;
 }
 
+// 16-byte vectors of O: VW consecutive elements (4 FP32 or 2 FP64)
+template <typename OT, int VW> struct Vec;
+template <> struct Vec<float, 4> {
+    typedef float4 T;
+    static __device__ inline void get(const float *q, double (&o)[4])
+    {
+        const float4 v = *reinterpret_cast<const float4 *>(q);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+};
+template <> struct Vec<double, 2> {
+    static __device__ inline void get(const double *q, double (&o)[2])
+    {
+        const double2 v = *reinterpret_cast<const double2 *>(q);
+        o[0] = v.x; o[1] = v.y;
+    }
+};
+template <typename OT> struct Vec<OT, 1> {
+    static __device__ inline void get(const OT *q, double (&o)[1]) { o[0] = (double)q[0]; }
+};
+
 // part[c][p] = sum_{s in chunk c} (O[s][p] - sub[p]) * wt[s]   (sub / wt may be null)
-template <typename OT>
+// Each thread owns VW consecutive columns (one 16-byte load per row when
+// P is a multiple of VW); every column still sums its rows in order.
+template <typename OT, int VW>
 __global__ void __launch_bounds__(kThreads)
 k_colsum(const OT *__restrict__ O, int64_t B, int64_t P, const double *__restrict__ sub,
          const double *__restrict__ wt, int64_t rows_per_chunk, double *__restrict__ part,
          const SrCtl *ctl)
 {
     if (ctl && ctl->done) return;
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t p = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VW;
     if (p >= P) return;
     const int64_t s0 = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t s1 = min(B, s0 + rows_per_chunk);
-    const double m = sub ? sub[p] : 0.0;
-    double acc = 0.0;
-    for (int64_t s = s0; s < s1; ++s) acc = fma(ld(O, s * P + p) - m, wt ? wt[s] : 1.0, acc);
-    part[(int64_t)blockIdx.y * P + p] = acc;
+    double m[VW], acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+        m[q] = sub ? sub[p + q] : 0.0;
+        acc[q] = 0.0;
+    }
+    for (int64_t s = s0; s < s1; ++s) {
+        double o[VW];
+        Vec<OT, VW>::get(O + s * P + p, o);
+        const double ws = wt ? wt[s] : 1.0;
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] = fma(o[q] - m[q], ws, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < VW; ++q) part[(int64_t)blockIdx.y * P + p + q] = acc[q];
 }
 
 // out[p] = scale * sum_c part[c][p] (+ lam * v[p])
@@ -74,20 +108,82 @@ __global__ void k_colsum_final(const double *__restrict__ part, int nchunk, int6
     out[p] = acc * scale + (v ? lam * v[p] : 0.0);
 }
 
-// u[s] = sum_p (O[s][p] - obar[p]) v[p]: one block per row
-template <typename OT>
+// u[s] = sum_p (O[s][p] - obar[p]) v[p]: kRows rows per block, each thread
+// taking VW consecutive elements per step (16-byte loads of O); the FP64
+// vectors obar and v are read once per step for all the block's rows.  Each
+// row's sum has the same order whatever the number of rows per block.
+constexpr int kRows = 4;
+
+template <typename OT, int VW>
 __global__ void __launch_bounds__(kThreads)
-k_rowdot(const OT *__restrict__ O, int64_t P, const double *__restrict__ obar,
+k_rowdot(const OT *__restrict__ O, int64_t nrows, int64_t P, const double *__restrict__ obar,
          const double *__restrict__ v, double *__restrict__ u, const SrCtl *ctl)
 {
-    __shared__ double sh[kThreads];
+    __shared__ double sh[kRows][kThreads];
     if (ctl->done) return;
-    const int64_t s = blockIdx.x;
-    const OT *row = O + s * P;
-    double acc = 0.0;
-    for (int64_t p = threadIdx.x; p < P; p += kThreads) acc = fma(ld(row, p) - obar[p], v[p], acc);
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) u[s] = acc;
+    const int64_t s0 = (int64_t)blockIdx.x * kRows;
+    const int nr = (int)min((int64_t)kRows, nrows - s0);
+    double acc[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) acc[r] = 0.0;
+    for (int64_t p = (int64_t)threadIdx.x * VW; p < P; p += (int64_t)kThreads * VW) {
+        double ob[VW], vv[VW];
+#pragma unroll
+        for (int q = 0; q < VW; ++q) {
+            ob[q] = obar[p + q];
+            vv[q] = v[p + q];
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            if (r >= nr) break;
+            double o[VW];
+            Vec<OT, VW>::get(O + (s0 + r) * P + p, o);
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[r] = fma(o[q] - ob[q], vv[q], acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) sh[r][threadIdx.x] = acc[r];
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) sh[r][threadIdx.x] += sh[r][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < nr) u[s0 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// launches of the two streaming passes, 16-byte loads when P allows them
+template <typename OT>
+constexpr int vec_width() { return 16 / (int)sizeof(OT); }
+
+template <typename OT>
+void launch_colsum(dim3 grid_rows, int64_t P, hipStream_t s, const OT *O, int64_t B,
+                   const double *sub, const double *wt, int64_t rpc, double *part,
+                   const SrCtl *ctl)
+{
+    constexpr int VW = vec_width<OT>();
+    if (P % VW == 0) {
+        const dim3 g((unsigned)((P / VW + kThreads - 1) / kThreads), grid_rows.y);
+        NQS_LAUNCH((k_colsum<OT, VW>), g, dim3(kThreads), 0, s, O, B, P, sub, wt, rpc, part, ctl);
+    } else {
+        const dim3 g((unsigned)((P + kThreads - 1) / kThreads), grid_rows.y);
+        NQS_LAUNCH((k_colsum<OT, 1>), g, dim3(kThreads), 0, s, O, B, P, sub, wt, rpc, part, ctl);
+    }
+}
+
+template <typename OT>
+void launch_rowdot(int64_t nrows, int64_t P, hipStream_t s, const OT *O, const double *obar,
+                   const double *v, double *u, const SrCtl *ctl)
+{
+    constexpr int VW = vec_width<OT>();
+    const dim3 g((unsigned)((nrows + kRows - 1) / kRows));
+    if (P % VW == 0)
+        NQS_LAUNCH((k_rowdot<OT, VW>), g, dim3(kThreads), 0, s, O, nrows, P, obar, v, u, ctl);
+    else
+        NQS_LAUNCH((k_rowdot<OT, 1>), g, dim3(kThreads), 0, s, O, nrows, P, obar, v, u, ctl);
 }
 
 // partial dot products a.b, one value per block
@@ -329,14 +425,13 @@ void sr_solve_t(const OT *O, const double *e, int64_t B, int64_t P, double lam, 
 
     NQS_LAUNCH(k_center, dim3(1), dim3(1024), 0, s, e, B, d, ctl);
     // column means
-    NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P,
-                       (const double *)nullptr, (const double *)nullptr, l.rows_per_chunk, part,
-                       (const SrCtl *)nullptr);
+    launch_colsum<OT>(cgrid, P, s, O, B, (const double *)nullptr, (const double *)nullptr,
+                      l.rows_per_chunk, part, (const SrCtl *)nullptr);
     NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
                        invB, 0.0, (const double *)nullptr, obar, (const SrCtl *)nullptr);
     // F = Obar^T (E - Ebar) / B
-    NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P, obar, d,
-                       l.rows_per_chunk, part, (const SrCtl *)nullptr);
+    launch_colsum<OT>(cgrid, P, s, O, B, obar, d, l.rows_per_chunk, part,
+                      (const SrCtl *)nullptr);
     NQS_LAUNCH(k_colsum_final, dim3(fgrid), dim3(kThreads), 0, s, part, (int)l.nchunk, P,
                        invB, 0.0, (const double *)nullptr, F, (const SrCtl *)nullptr);
     NQS_LAUNCH(k_init, dim3(vgrid), dim3(kThreads), 0, s, x, r, p, F, P);
@@ -345,10 +440,8 @@ void sr_solve_t(const OT *O, const double *e, int64_t B, int64_t P, double lam, 
     NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, ctl);
     for (int it = 0; it < n_iter; ++it) {
         // Ap = Obar^T (Obar p) / B + lambda p
-        NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)B), dim3(kThreads), 0, s, O, P, obar, p,
-                           u, ctl);
-        NQS_LAUNCH((k_colsum<OT>), cgrid, dim3(kThreads), 0, s, O, B, P, obar, u,
-                           l.rows_per_chunk, part, ctl);
+        launch_rowdot<OT>(B, P, s, O, obar, p, u, ctl);
+        launch_colsum<OT>(cgrid, P, s, O, B, obar, u, l.rows_per_chunk, part, ctl);
         cg_tail(l, P, invB, lam, x, r, p, ap, part, w, ctl, it, s);
     }
     if (stats) NQS_LAUNCH(k_stats_out, dim3(1), dim3(1), 0, s, ctl, stats);
@@ -399,8 +492,8 @@ void sr_solve_rows_t(const SrRows &rows, OT *obuf, int64_t chunk, const double *
     // partial column sums of rows [r0, r0 + nb) into their reduction blocks
     auto colsum = [&](int64_t r0, int nb, const double *sub, const double *wt, const SrCtl *c) {
         const dim3 g(fgrid, (unsigned)((nb + rpc - 1) / rpc));
-        NQS_LAUNCH((k_colsum<OT>), g, dim3(kThreads), 0, s, (const OT *)obuf, (int64_t)nb, P, sub,
-                   wt ? wt + r0 : wt, rpc, part + (r0 / rpc) * P, c);
+        launch_colsum<OT>(g, P, s, (const OT *)obuf, (int64_t)nb, sub, wt ? wt + r0 : wt, rpc,
+                          part + (r0 / rpc) * P, c);
     };
 
     NQS_LAUNCH(k_center, dim3(1), dim3(1024), 0, s, e, B, d, ctl);
@@ -418,8 +511,7 @@ void sr_solve_rows_t(const SrRows &rows, OT *obuf, int64_t chunk, const double *
     NQS_LAUNCH(k_dot_final, dim3(1), dim3(kThreads), 0, s, dot, (int)l.ndot, ctl);
     for (int it = 0; it < n_iter; ++it) {
         pass([&](int64_t r0, int nb) {
-            NQS_LAUNCH((k_rowdot<OT>), dim3((unsigned)nb), dim3(kThreads), 0, s,
-                       (const OT *)obuf, P, obar, p, u + r0, ctl);
+            launch_rowdot<OT>(nb, P, s, (const OT *)obuf, obar, p, u + r0, ctl);
         });
         pass([&](int64_t r0, int nb) { colsum(r0, nb, obar, u, ctl); });
         cg_tail(l, P, invB, lam, x, r, p, ap, part, w, ctl, it, s);
