@@ -588,8 +588,8 @@ def main():
                 "mfma_instruction_tflops": ach * (3 if form == "bf16x3" else 1),
                 "sustained_peak": SUSTAINED["bf16_tflops"] / (3 if form == "bf16x3" else 1),
                 "frac_of_sustained": ach * (3 if form == "bf16x3" else 1) / SUSTAINED["bf16_tflops"],
-                "sustained_note": "sustained_peak: the BF16 MFMA rate of a register-only loop "
-                                  "of independent MFMAs on this device (nqs_mfma_rate), per "
+                "sustained_note": "sustained_peak: the BF16 MFMA rate a register-only loop of "
+                                  "independent MFMAs reaches on this device (nqs_mfma_rate), per "
                                   "algorithmic flop of this form"}
 
     roofline = roofline_of(args.form, k_ms, k_n)

@@ -2,10 +2,10 @@
 
 Every .hip file under csrc/ is compiled to an object in parallel, then linked
 into one shared library next to this file.  Packed FP32 instructions are
-disabled for the device code.  The FP64 matrix-core kernels are built with
-the VGPR form of the MFMA instructions: with accumulators in AGPRs the
-compiler copies them to and from VGPRs on every step of the weight-gradient
-loop.
+disabled for the device code.  The matrix-core kernels whose accumulators
+the compiler would otherwise place in AGPRs are built with the VGPR form of
+the MFMA instructions: with accumulators in AGPRs it copies them to and from
+VGPRs inside the loops.
 """
 from __future__ import annotations
 
@@ -33,6 +33,9 @@ FILE_FLAGS = {
     "k_conv_f64mma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "k_cnn1.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "k_cnn2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "calib.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "k_conv_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "k_x3.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -10,13 +10,18 @@ namespace nqs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kAcc = 8;   // independent accumulators per wave
+constexpr int kAcc = 16;  // independent accumulators per wave
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
-__global__ void __launch_bounds__(kThreads) k_rate_f64(double *out, int iters)
+// Two waves per SIMD with the accumulators in VGPRs (the file is built with
+// the VGPR form of the MFMA instructions): with accumulators in AGPRs the
+// compiler copied every accumulator out and back on each iteration, and the
+// loop measured the copies (1.46 PFLOP/s BF16) instead of the matrix cores.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_rate_f64(double *out, int iters)
 {
     double4_t acc[kAcc];
 #pragma unroll
@@ -33,7 +38,8 @@ __global__ void __launch_bounds__(kThreads) k_rate_f64(double *out, int iters)
     out[(int64_t)blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_rate_bf16(double *out, int iters)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_rate_bf16(double *out, int iters)
 {
     floatx4 acc[kAcc];
 #pragma unroll
