@@ -354,6 +354,47 @@ def cnn1_row(dev, reps=2):
             "log_deriv_ms": ms_o}
 
 
+def cmp10_row(dev, reps=3):
+    """Non-gating row: the precision comparison workload (10x10 J1-J2, J2 =
+    0.5, CNN 4x3x3x16, weights N(0, 0.02^2), 8192 configurations): E_loc per
+    pass in the FP64, FP32 and BF16 GPU forms (BF16 autotuned on 256 samples),
+    each form's mean and largest per-sample error against the FP64 GPU form."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    L, J2, K, C, w, sp = inputs.config_inputs("cmp10")
+    B = sp.shape[0]
+    spd = torch.as_tensor(sp).to(dev)
+    out = {"workload": f"{L}x{L} J1-J2 (J2={J2}), CNN {K}x3x3x{C}, {B} configurations, weights "
+                       "N(0, 0.02^2)", "forms": {}}
+    ref = None
+    for form in ("fp64", "fp32", "bf16"):
+        ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype=form)
+        mode = ctx.autotune(spd[:256].contiguous()) if form == "bf16" else "full"
+        ctx.reserve(B, mode)
+        e = torch.empty(B, dtype=torch.float64, device=dev)
+        ctx.local_energy(spd, mode=mode, out=e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.local_energy(spd, mode=mode, out=e)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        ev = e.cpu().numpy()
+        assert ctx.get_error() == 0
+        ctx.close()
+        row = {"mode": mode, "ms": ms, "samples_per_s": B / (ms * 1e-3)}
+        if ref is None:
+            ref = ev
+        else:
+            row["mean_rel_err_vs_fp64"] = float(abs(ev.mean() - ref.mean()) / abs(ref.mean()))
+            row["max_sample_rel_err_vs_fp64"] = float(np.max(np.abs(ev - ref)) /
+                                                      np.max(np.abs(ref)))
+        out["forms"][form] = row
+    return out
+
+
 def cnn2_row(dev, reps=2):
     """Non-gating row: CNN2 (an embedding of hole/up/down, 6 blocks of a
     convolution, stride-one channel max and transposed convolution, 32
@@ -422,6 +463,7 @@ def main():
     ap.add_argument("--no-tj", action="store_true")
     ap.add_argument("--no-cnn1", action="store_true")
     ap.add_argument("--no-cnn2", action="store_true")
+    ap.add_argument("--no-cmp10", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -431,11 +473,11 @@ def main():
                     help="arithmetic of the timed step's convolutions")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
-    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn2", "sr24"],
+    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn2", "sr24", "cmp10"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); "
                          "oderiv likewise the FP32 log-derivative call; tj runs only the t-J "
-                         "row and prints it; cnn1, cnn2 and sr24 likewise their rows")
+                         "row and prints it; cnn1, cnn2, sr24 and cmp10 likewise their rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -468,6 +510,9 @@ def main():
         return
     if args.only == "sr24":
         print(json.dumps(sr24_row(dev)), flush=True)
+        return
+    if args.only == "cmp10":
+        print(json.dumps(cmp10_row(dev)), flush=True)
         return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
@@ -781,6 +826,14 @@ def main():
         log(f"CNN2 t-J 12x12: {cnn2['samples_per_s']:.1f} samples/s, exchanged-configuration pass "
             f"{cnn2['conn_pass_tflops']:.2f} TFLOP/s FP64")
 
+    cmp10 = None
+    if not args.no_cmp10:
+        cmp10 = cmp10_row(dev)
+        f = cmp10["forms"]
+        log(f"10x10 precision comparison: fp64 {f['fp64']['samples_per_s']:.0f}, fp32 "
+            f"{f['fp32']['samples_per_s']:.0f}, bf16 {f['bf16']['samples_per_s']:.0f} samples/s "
+            f"(bf16 mean rel err {f['bf16']['mean_rel_err_vs_fp64']:.1e})")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(L, J2, K, C, w, sp, float(counts.mean()))
@@ -813,6 +866,7 @@ def main():
         "tj_nongating": tj,
         "cnn1_nongating": cnn1,
         "cnn2_tj_nongating": cnn2,
+        "cmp10_nongating": cmp10,
         "roofline": roofline,
         "mfma_sustained_tflops": SUSTAINED,
         "cpu_baseline": cpu,
