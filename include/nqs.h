@@ -254,7 +254,9 @@ nqs_status nqs_log_psi(nqs_ctx *ctx, const int8_t *spins, int64_t B,
 nqs_status nqs_local_energy(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                             double *e_loc, nqs_mode mode, void *stream);
 
-/* Batch mean and variance (1/Ns) of e_loc: stats FP64 [2], device.         */
+/* Batch mean and variance (1/Ns) of e_loc [Sec. 3.2: the energy estimate
+ * over the samples and its variance]: stats FP64 [2], device.  Two-stage
+ * fixed-order FP64 sums.                                                    */
 nqs_status nqs_energy_stats(nqs_ctx *ctx, const double *e_loc, int64_t B,
                             double *stats, void *stream);
 
@@ -324,7 +326,9 @@ nqs_status nqs_connected(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                          void *stream);
 
 /* The log-amplitude differences f(S') - f(s) of every exchanged
- * configuration, FP64 [capacity], in the order of nqs_connected.            */
+ * configuration [Sec. 5.4.1: the network forwards of the exchanged
+ * configurations, which take over 95% of the time], FP64 [capacity], in the
+ * order of nqs_connected.                                                   */
 nqs_status nqs_log_ratios(nqs_ctx *ctx, const int8_t *spins, int64_t B,
                           nqs_mode mode, double *dlog, int64_t capacity,
                           void *stream);

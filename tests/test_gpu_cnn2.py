@@ -181,3 +181,35 @@ def test_cnn2_empty_batch():
     assert la.numel() == 0 and sg.numel() == 0
     assert ctx.log_deriv(empty, dtype="fp64").shape == (0, ctx.P)
     assert ctx.get_error() == 0
+
+
+def test_cnn2_largest_lattice_and_degenerate_sectors():
+    """64x64 (the largest lattice) log|psi| and a 20x20 local energy against
+    the oracle; a lattice of holes only (no term at all: E_loc = 0) and a
+    single electron (hops only, no exchange) on 8x8."""
+    Kb, C = 2, 16
+    w = inputs.cnn2_weights(Kb, C, 1.0, 291, out_bias=2.0)
+    sp = inputs.spins_tj(64, 2, 512, 292)
+    ctx = c2_ctx(64, Kb, C, w)
+    la, sg = ctx.log_psi(to_dev(sp))
+    ol, os_ = oracle.cnn2_log_psi(64, Kb, C, w, sp)
+    np.testing.assert_allclose(la.cpu().numpy(), ol, rtol=1e-12)
+    assert np.array_equal(sg.cpu().numpy(), os_)
+    sp32 = inputs.spins_tj(20, 2, 50, 293)
+    c32 = c2_ctx(20, Kb, C, w)
+    e = c32.local_energy(to_dev(sp32)).cpu().numpy()
+    ref = oracle.tj_cnn2_local_energy(20, T_HOP, J_EX, Kb, C, w, sp32)
+    say("20x20 cnn2 E_loc max rel", rel_inf(e, ref))
+    assert rel_inf(e, ref) <= 1e-10
+    c8 = c2_ctx(8, Kb, C, w)
+    holes = np.zeros((3, 8, 8), np.int8)
+    one = np.zeros((3, 8, 8), np.int8)
+    one[0, 0, 0], one[1, 3, 5], one[2, 7, 7] = 1, -1, 1
+    e0 = c8.local_energy(to_dev(holes)).cpu().numpy()
+    assert np.array_equal(e0, np.zeros(3))
+    e1 = c8.local_energy(to_dev(one)).cpu().numpy()
+    r1 = oracle.tj_cnn2_local_energy(8, T_HOP, J_EX, Kb, C, w, one)
+    say("single electron E_loc", e1, "oracle", r1)
+    assert rel_inf(e1, r1) <= 1e-10
+    for c in (ctx, c32, c8):
+        assert c.get_error() == 0
