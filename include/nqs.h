@@ -155,8 +155,9 @@ nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec
  * output, a max passes its gradient to the larger input, the first on a
  * tie), nqs_sr_solve, nqs_sr_solve_recompute, nqs_energy_stats,
  * nqs_connected, nqs_set_weights, nqs_update_weights, nqs_get_weights,
- * nqs_reserve.  nqs_local_energy_multi and nqs_autotune return
- * NQS_E_UNSUPPORTED, and INCREMENTAL mode does too.  An output neuron of
+ * nqs_reserve, nqs_local_energy_multi (lattice after lattice) and
+ * nqs_autotune (FULL, the only form).  INCREMENTAL mode returns
+ * NQS_E_UNSUPPORTED.  An output neuron of
  * exactly 0 makes log|psi| infinite: NQS_E_NONFINITE.
  * Errors: NQS_E_LATTICE, NQS_E_SPEC (blocks or channels outside 1..16 /
  * 1..32, marshall_sign not 0/1), NQS_E_NPARAMS, NQS_E_ARG as nqs_create.  */
@@ -358,9 +359,10 @@ nqs_status nqs_mcmc(nqs_ctx *ctx, int8_t *spins, int64_t B, int32_t n_steps,
  * lattices with unwrapped cones share the cone kernel and the others the
  * general incremental kernel), then each lattice's FP64 ratio sums are
  * taken, so every lattice's energies equal its single-lattice call's.
- * FP64 / FP32 contexts run lattice after lattice; CNN1 contexts are
- * refused (NQS_E_UNSUPPORTED).  Errors as nqs_local_energy, checked for
- * every job before any work is queued.                                    */
+ * FP64 / FP32 contexts and CNN1 / CNN2 contexts (every job of one network
+ * family) run lattice after lattice.  Errors as nqs_local_energy, checked
+ * for every job before any work is queued; NQS_E_SPEC for jobs of different
+ * shape, dtype or network family.                                          */
 typedef struct {
     nqs_ctx *ctx;
     const int8_t *spins;
@@ -385,7 +387,8 @@ nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
  * the tune cache, a JSON file (NQS_TUNE_CACHE, else
  * $HOME/.cache/nqs/tune.json), under the key nqs_tune_key gives; contexts of
  * the same key created later read it.  FP64 / FP32 contexts have only the
- * full form.  Synchronises the stream; NQS_E_WORKSPACE while the stream is
+ * full form; CNN1 / CNN2 contexts too, and for them nothing is timed or
+ * stored (FULL is returned).  Synchronises the stream; NQS_E_WORKSPACE while the stream is
  * capturing; NQS_E_ARG for B = 0.  mode_out (host) may be null.  A cache
  * file that cannot be written is not an error.                             */
 nqs_status nqs_autotune(nqs_ctx *ctx, const int8_t *spins, int64_t B,

@@ -1048,8 +1048,8 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     for (int i = 0; i < n; ++i) {
         nqs_ctx *c = jobs[i].ctx;
         if (!c) return NQS_E_ARG;
-        if (block_net(c)) return NQS_E_UNSUPPORTED;
-        if (c->K != jobs[0].ctx->K || c->C != jobs[0].ctx->C || c->dtype != jobs[0].ctx->dtype)
+        if (c->K != jobs[0].ctx->K || c->C != jobs[0].ctx->C || c->dtype != jobs[0].ctx->dtype ||
+            c->net != jobs[0].ctx->net)
             return NQS_E_SPEC;
         for (int j = 0; j < i; ++j)
             if (jobs[j].ctx == c) return NQS_E_ARG;   // one workspace per job
@@ -1062,7 +1062,7 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     if (n == 0) return NQS_OK;
     hipStream_t s = (hipStream_t)stream;
     if (jobs[0].ctx->dtype != NQS_BF16) {
-        // the vector-ALU (FP64 / FP32) path runs lattice after lattice
+        // the FP64 / FP32 forms and the block networks run lattice after lattice
         for (int i = 0; i < n; ++i)
             NQS_TRY(nqs_local_energy(jobs[i].ctx, jobs[i].spins, jobs[i].B, jobs[i].e_loc, mode,
                                      stream));
@@ -1124,10 +1124,17 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
 {
     NQS_TRY(check_common(c, spins, B));
     if (B == 0) return NQS_E_ARG;
-    if (block_net(c)) return NQS_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stream_capturing(s)) return NQS_E_WORKSPACE;
     c->last_stream = s;
+    if (block_net(c)) {
+        // CNN1 / CNN2: full recomputation is the only form (nothing to time
+        // or to keep in the cache)
+        c->tuned = 1;
+        c->tuned_mode = NQS_FULL;
+        if (mode_out) *mode_out = NQS_FULL;
+        return NQS_OK;
+    }
     double ms_full = -1.0, ms_inc = -1.0;
     int best_nw = 0, best_mt = 0;
     nqs_mode best = NQS_FULL;

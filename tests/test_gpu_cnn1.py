@@ -15,7 +15,8 @@ against the oracle.  The block architecture is a reading of a missing figure
 * a CNN1 VMC iteration captured in a HIP graph equals the eager iterations;
 * trained by the VMC loop on 4x4, CNN1 reaches the exact ground energy (0.3%
   at J2 = 0, 2% at J2 = 0.5);
-* incremental mode, the multi-lattice call and the autotuner are refused.
+* incremental mode is refused; the autotuner answers FULL, and the multi-lattice
+  call runs CNN1 lattices one after another, equal to the single calls.
 """
 import numpy as np
 import pytest
@@ -169,13 +170,17 @@ def test_cnn1_refusals():
     sp = to_dev(inputs.spins_sz0(L, 4, 122))
     ctx = c1_ctx(L, Kb, C, w)
     e = torch.empty(4, dtype=torch.float64, device=DEV)
-    for call in (lambda: ctx.local_energy(sp, mode="incremental"),
-                 lambda: ctx.autotune(sp),
-                 lambda: nqs.local_energy_multi([(ctx, sp, e)], mode="full")):
-        with pytest.raises(nqs.NqsError) as info:
-            call()
-        assert info.value.code == 10            # NQS_E_UNSUPPORTED
-    assert ctx.auto_mode() == "full"
+    with pytest.raises(nqs.NqsError) as info:
+        ctx.local_energy(sp, mode="incremental")
+    assert info.value.code == 10                # NQS_E_UNSUPPORTED
+    # the autotuner answers the only form; the multi-lattice call runs the
+    # lattices one after another and equals the single calls
+    assert ctx.autotune(sp) == "full" and ctx.auto_mode() == "full"
+    other = c1_ctx(8, Kb, C, inputs.cnn1_weights(Kb, C, 0.3, 123))
+    sp8 = to_dev(inputs.spins_sz0(8, 3, 124))
+    e8 = torch.empty(3, dtype=torch.float64, device=DEV)
+    nqs.local_energy_multi([(ctx, sp, e), (other, sp8, e8)], mode="full")
+    assert torch.equal(e, ctx.local_energy(sp)) and torch.equal(e8, other.local_energy(sp8))
     assert ctx.get_error() == 0
 
 

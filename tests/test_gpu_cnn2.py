@@ -15,8 +15,9 @@ oracle/nqs_oracle.h); these tests pin the GPU to the oracle's CNN2.
 * Metropolis chains equal the oracle's bit for bit; SR on recomputed O equals
   SR on stored O; the device weight update equals setting the weights; a VMC
   iteration captured in a HIP graph equals the eager iterations;
-* incremental mode, the multi-lattice call, the autotuner, other channel
-  counts and wrong parameter counts are refused.
+* incremental mode, other channel counts, wrong parameter counts and a
+  multi-lattice call mixing network families are refused; the autotuner
+  answers FULL and the multi-lattice call equals the single calls.
 """
 import numpy as np
 import pytest
@@ -148,12 +149,20 @@ def test_cnn2_refusals():
     sp = to_dev(inputs.spins_tj(L, 4, 4, 262))
     ctx = c2_ctx(L, Kb, C, w)
     e = torch.empty(4, dtype=torch.float64, device=DEV)
-    for call in (lambda: ctx.local_energy(sp, mode="incremental"),
-                 lambda: ctx.autotune(sp),
-                 lambda: nqs.local_energy_multi([(ctx, sp, e)], mode="full")):
-        with pytest.raises(nqs.NqsError) as info:
-            call()
-        assert info.value.code == 10            # NQS_E_UNSUPPORTED
+    with pytest.raises(nqs.NqsError) as info:
+        ctx.local_energy(sp, mode="incremental")
+    assert info.value.code == 10                # NQS_E_UNSUPPORTED
+    assert ctx.autotune(sp) == "full" and ctx.auto_mode() == "full"
+    other = c2_ctx(8, Kb, C, w)
+    sp8 = to_dev(inputs.spins_tj(8, 3, 8, 264))
+    e8 = torch.empty(3, dtype=torch.float64, device=DEV)
+    nqs.local_energy_multi([(ctx, sp, e), (other, sp8, e8)], mode="full")
+    assert torch.equal(e, ctx.local_energy(sp)) and torch.equal(e8, other.local_energy(sp8))
+    # jobs of different network families are refused
+    lc = nqs.Context.tj(L, T_HOP, J_EX, Kb, C, inputs.weights(Kb, C, 0.1, 265))
+    with pytest.raises(nqs.NqsError) as info:
+        nqs.local_energy_multi([(ctx, sp, e), (lc, sp, torch.empty_like(e))], mode="full")
+    assert info.value.code == 3                 # NQS_E_SPEC
     with pytest.raises(nqs.NqsError) as info:
         c2_ctx(L, Kb, 8, inputs.cnn2_weights(Kb, 8, 1.0, 263))
     assert info.value.code == 3                 # NQS_E_SPEC
