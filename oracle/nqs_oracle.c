@@ -21,6 +21,12 @@
  *     is parity unpinned against the paper (the functions are pinned
  *     against torch's conv2d / conv_transpose2d / autograd and the exact
  *     diagonalisation).
+ *   - CNN2 (Sec. 5.2: CNN1's block behind an embedding of the site states,
+ *     the max-pooling at stride one with the first channel copied after the
+ *     last, a final convolution to one channel, product of neurons) in the
+ *     reading stated in nqs_oracle.h; parity unpinned against the paper for
+ *     the same reason (pinned against torch, symmetries and the t-J exact
+ *     diagonalisation).
  *   - t-J model: Sec. 6.1, Eq. (tJ), with the fermions encoded by the
  *     Jordan-Wigner transformation along the site order i = y*L + x.
  *   - O_loc = per-sample log-derivative and the SR update: Sec. 3.2 and
