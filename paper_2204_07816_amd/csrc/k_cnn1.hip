@@ -633,6 +633,296 @@ void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t 
         block_forward(c, k, spins, pm, M, k == 0 ? nullptr : pa, pb, pa, nullptr, s);
 }
 
+// ---- exchanged configurations by the receptive cone ----
+//
+// Exchanging the pair (q_i, q_j) changes the spins of a w0 x h0 box.  Number
+// the stencils l = 1 .. 2K (block b's convolution is layer 2b - 1, its
+// transposed convolution layer 2b, each 3x3 on the torus): the output of
+// layer l differs from the sample's only on R_l, the box widened by l sites.
+// So log|psi(S')| - log|psi(S)| = sum over R_2K of log|u'_K| - log|u_K|, and
+// the sign ratio is the parity of the change in negative neurons on R_2K.
+//
+// One workgroup per queue item.  A square frame of side 4K + 4 (the box
+// widened by F = 2K + 1) holds in LDS the 16 FP64 channels of the current
+// layer's input; layer l reads the frame on R_{l+1} and forms R_l as tiles of
+// 16 sites x 16 channels on v_mfma_f64_16x16x4f64, with the operand layout,
+// packed taps and MFMA order of the full pass (k_conv_mma), so every neuron
+// of the cone is bit-identical to the full recomputation's; the layer's taps
+// sit in LDS after the frame, laid out so that each lane reads its four B
+// operands of a tap and column block as 32 contiguous bytes.  The results wait
+// in registers until every wave has read the frame, then replace R_l in
+// place, and the ring R_{l+2} \ R_l is filled from the sample's activations
+// of layer l, kept by the base pass ([2K][B][N][16]: m_1, u_1, m_2, ...).
+// Layer 1 (one input channel) runs on the vector ALU from the exchanged
+// spins, with the full pass's FMA order.  Needs 16 channels, K <= 6 (the
+// register staging) and L >= 4K + 4 (the frame does not overlap itself).
+constexpr int kConeMaxK = 6;
+constexpr int kConeNW = 8;
+constexpr int kConeThreads = kConeNW * 64;
+constexpr int kConeStage = 5;   // staged tiles per wave: R_11 has 36 tiles at K = 6
+
+struct C1ConeArgs {
+    const int8_t *spins;        // [B][N]
+    const uint32_t *queue;
+    const int64_t *qlen;
+    int64_t cap;
+    const double *wpack;        // the forward's packed taps
+    const double *w1;           // block 1, canonical: W [32][9], then a [32]
+    const double *cache;        // [2K][B][N][16]
+    int64_t B;
+    double *dlog;
+    int8_t *isign;
+    int32_t *err;
+    int L, K;
+};
+
+// byte offset of 16-byte chunk c (channels 2c, 2c + 1) of frame site f; the
+// chunks of a site are rotated by f mod 8, so 8 lanes reading one chunk
+// position of 8 consecutive sites hit 8 different bank groups
+__device__ inline int fr_off(int f, int c) { return f * 128 + ((c ^ (f & 7)) << 4); }
+
+// packed taps of layer l: W[t][ci][col] (ncol columns) and its bias
+__device__ inline const double *c1_layer_taps(const double *wp, int l, int *ncol)
+{
+    const int k = (l - 1) >> 1;                      // 0-based block
+    const double *blk = k == 0 ? wp : wp + kPackFirst + (int64_t)(k - 1) * kPackBlock;
+    if (l & 1) {                                     // convolution of block k >= 1
+        *ncol = 2 * kMC;
+        return blk;
+    }
+    *ncol = kMC;                                     // transposed convolution
+    return k == 0 ? blk : blk + kConvK + 2 * kMC;
+}
+
+// layer l's taps into LDS: wl[((t NH + h) 64 + lane) 4 + s] = W[t][4 kq + s][16 h + m16]
+// (lane = 16 kq + m16), all threads of the workgroup
+__device__ inline void c1_stage_taps(const double *wt, int ncol, double *wl, int tid)
+{
+    const int nh = ncol >> 4, total = 9 * nh * 256;
+    for (int q = tid; q < total; q += kConeThreads) {
+        const int sub = q & 3, ln = (q >> 2) & 63, th = q >> 8;
+        const int t = th / nh, h = th - t * nh;
+        wl[q] = wt[(t * kMC + 4 * (ln >> 4) + sub) * ncol + 16 * h + (ln & 15)];
+    }
+}
+
+// one tile: fm = frame site of this lane's A row; D element i: row kq + 4 i,
+// column 16 h + m16
+template <int NH>
+__device__ inline void c1_tile(const unsigned char *fr, const double *wl, int fm, int P,
+                               int lane, const double (&bias)[2], double4_t (&acc)[2])
+{
+    const int kq = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) acc[h] = (double4_t){bias[h], bias[h], bias[h], bias[h]};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int f = fm + (t / 3 - 1) * P + (t % 3 - 1);
+        const double2 u0 = *(const double2 *)(fr + fr_off(f, 2 * kq));
+        const double2 u1 = *(const double2 *)(fr + fr_off(f, 2 * kq + 1));
+        const double av[4] = {u0.x, u0.y, u1.x, u1.y};
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const double2 *wp = (const double2 *)(wl + ((t * NH + h) * 64 + lane) * 4);
+            const double2 w0 = wp[0], w1 = wp[1];
+            const double bv[4] = {w0.x, w0.y, w1.x, w1.y};
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub)
+                acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[sub], bv[sub], acc[h], 0, 0, 0);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kConeThreads)
+k_c1_cone(C1ConeArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char fr[];
+    __shared__ double red[kConeNW];
+    __shared__ int nred[kConeNW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m16 = lane & 15, kq = lane >> 4;
+    const int L = a.L, N = L * L, K = a.K, F = 2 * K + 1, P = 4 * K + 4;
+    const int64_t n_items = min(a.qlen[0], a.cap);
+    // XCD-contiguous ranges of the queue (the grid is a multiple of 8)
+    const int per_xcd = gridDim.x / 8;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    const int64_t seg = (n_items + 7) / 8;
+    const int64_t u_end = min(n_items, (xcd + 1) * seg);
+    double *wl = reinterpret_cast<double *>(fr + (size_t)P * P * 128);   // the layer's taps
+    double bias[2];
+
+    for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
+        const uint32_t e = a.queue[u];
+        const int s = item_sample(e), b = item_bond(e), tau = b & 3, i0 = b >> 2;
+        const int xi = i0 % L, yi = i0 / L;
+        const int qi = i0, qj = wrapc(yi + bond_dy(tau), L) * L + wrapc(xi + bond_dx(tau), L);
+        const int ax = xi, ay = (tau == 3) ? wrapc(yi - 1, L) : yi;
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        const int8_t *sp = a.spins + (int64_t)s * N;
+        // lattice site of frame position (fx, fy): ax - F + fx lies in (-L, 2L)
+        auto site_of = [&](int fx, int fy) {
+            int x = ax - F + fx, y = ay - F + fy;
+            x += x < 0 ? L : (x >= L ? -L : 0);
+            y += y < 0 ? L : (y >= L ? -L : 0);
+            return y * L + x;
+        };
+        // ring R_{l+2} \ R_l of the frame from the cache of layer l
+        auto ring_fill = [&](int l) {
+            const int wr = w0 + 2 * l + 4, hr = h0 + 2 * l + 4;
+            const int total = wr * hr * 8;
+            const double *src = a.cache + ((int64_t)(l - 1) * a.B + s) * N * kMC;
+            // chunk q: its value (loaded for every q, from site 0 when not
+            // needed) and its LDS offset, -1 when not needed
+            auto fetch = [&](int q, double2 &v, int &d) {
+                const int p = q >> 3, c = q & 7;
+                const int py = p / wr, px = p - py * wr;
+                const bool inner = (unsigned)(px - 2) < (unsigned)(w0 + 2 * l) &&
+                                   (unsigned)(py - 2) < (unsigned)(h0 + 2 * l);
+                const bool live = q < total && !inner;
+                const int fx = F - l - 2 + px, fy = F - l - 2 + py;
+                const int site = live ? site_of(fx, fy) : 0;
+                v = *(const double2 *)(src + (int64_t)site * kMC + 2 * c);
+                d = live ? fr_off(fy * P + fx, c) : -1;
+            };
+            for (int q0 = tid; q0 < total; q0 += 4 * kConeThreads) {
+                double2 v0, v1, v2, v3;
+                int d0, d1, d2, d3;
+                fetch(q0, v0, d0);
+                fetch(q0 + kConeThreads, v1, d1);
+                fetch(q0 + 2 * kConeThreads, v2, d2);
+                fetch(q0 + 3 * kConeThreads, v3, d3);
+                if (d0 >= 0) *(double2 *)(fr + d0) = v0;
+                if (d1 >= 0) *(double2 *)(fr + d1) = v1;
+                if (d2 >= 0) *(double2 *)(fr + d2) = v2;
+                if (d3 >= 0) *(double2 *)(fr + d3) = v3;
+            }
+        };
+
+        // layer 1 on R_1 from the exchanged spins: thread (site, pooled channel j)
+        {
+            const int w1 = w0 + 2, n1 = w1 * (h0 + 2);
+            if (tid < n1 * kMC) {
+                const int p = tid >> 4, j = tid & 15;
+                const int py = p / w1, px = p - py * w1;
+                const int fx = F - 1 + px, fy = F - 1 + py;
+                double z0 = a.w1[2 * kMC * 9 + 2 * j], z1 = a.w1[2 * kMC * 9 + 2 * j + 1];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    int q = site_of(fx + t % 3 - 1, fy + t / 3 - 1);
+                    q = (q == qi) ? qj : ((q == qj) ? qi : q);
+                    const double hv = (double)sp[q];
+                    z0 = fma(a.w1[(2 * j) * 9 + t], hv, z0);
+                    z1 = fma(a.w1[(2 * j + 1) * 9 + t], hv, z1);
+                }
+                *(double *)(fr + fr_off(fy * P + fx, j >> 1) + (j & 1) * 8) = (z1 > z0) ? z1 : z0;
+            }
+        }
+        ring_fill(1);
+        {
+            int nc;
+            const double *wt = c1_layer_taps(a.wpack, 2, &nc);
+            c1_stage_taps(wt, nc, wl, tid);
+            bias[0] = wt[9 * kMC * nc + m16];
+        }
+        __syncthreads();
+
+        double dl = 0.0;
+        int dneg = 0;
+        for (int l = 2; l <= 2 * K; ++l) {
+            const bool conv = l & 1;
+            const int wd = w0 + 2 * l, hd = h0 + 2 * l, nl = wd * hd;
+            const int ntiles = (nl + 15) >> 4;
+            const uint32_t mul = ((1u << 20) + wd - 1) / wd;
+            auto frame_of = [&](int p) {   // frame site of position p of R_l
+                const int v = (int)(((uint32_t)p * mul) >> 20);
+                return (F - l + v) * P + (F - l + p - v * wd);
+            };
+            double st[kConeStage][4];
+            int j = 0;
+            for (int ti = wave; ti < ntiles; ti += kConeNW, ++j) {
+                const int fm = frame_of(min(ti * 16 + m16, nl - 1));
+                double4_t acc[2];
+                double out[4];
+                if (conv) {
+                    c1_tile<2>(fr, wl, fm, P, lane, bias, acc);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) out[i] = (acc[1][i] > acc[0][i]) ? acc[1][i] : acc[0][i];
+                } else {
+                    c1_tile<1>(fr, wl, fm, P, lane, bias, acc);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) out[i] = acc[0][i];
+                }
+                if (l < 2 * K) {
+#pragma unroll
+                    for (int jj = 0; jj < kConeStage; ++jj)
+                        if (jj == j)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) st[jj][i] = out[i];
+                } else {
+                    // the last layer: log|u'| - log|u| and the sign change
+                    const double *ub = a.cache + ((int64_t)(2 * K - 1) * a.B + s) * N * kMC;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int p = ti * 16 + kq + 4 * i;
+                        if (p >= nl) continue;
+                        const int v = (int)(((uint32_t)p * mul) >> 20);
+                        const double u0 = ub[(int64_t)site_of(F - l + p - v * wd, F - l + v) * kMC + m16];
+                        dl += log(fabs(out[i])) - log(fabs(u0));
+                        dneg += (out[i] < 0.0) - (u0 < 0.0);
+                    }
+                }
+            }
+            if (l == 2 * K) break;
+            __syncthreads();                 // every read of the frame and taps for layer l is done
+            {
+                int nc;
+                const double *wt = c1_layer_taps(a.wpack, l + 1, &nc);
+                c1_stage_taps(wt, nc, wl, tid);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) bias[h] = h < (nc >> 4) ? wt[9 * kMC * nc + 16 * h + m16] : 0.0;
+            }
+            j = 0;
+            for (int ti = wave; ti < ntiles; ti += kConeNW, ++j) {
+#pragma unroll
+                for (int jj = 0; jj < kConeStage; ++jj)
+                    if (jj == j)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int p = ti * 16 + kq + 4 * i;
+                            if (p < nl)
+                                *(double *)(fr + fr_off(frame_of(p), m16 >> 1) + (m16 & 1) * 8) =
+                                    st[jj][i];
+                        }
+            }
+            ring_fill(l);
+            __syncthreads();
+        }
+        // fixed-order sums over the lanes, then over the waves
+        for (int off = 32; off > 0; off >>= 1) {
+            dl += __shfl_xor(dl, off);
+            dneg += __shfl_xor(dneg, off);
+        }
+        if (lane == 0) {
+            red[wave] = dl;
+            nred[wave] = dneg;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = 0.0;
+            int n = 0;
+            for (int w = 0; w < kConeNW; ++w) {
+                v += red[w];
+                n += nred[w];
+            }
+            if (!isfinite(v)) atomicOr(a.err, kErrNonFinite);
+            a.dlog[u] = v;
+            a.isign[u] = (n & 1) ? (int8_t)-1 : (int8_t)1;
+        }
+        __syncthreads();                     // red and the frame are free again
+    }
+}
+
 }  // namespace
 
 int64_t cnn1_params(int Kb, int C)
@@ -677,6 +967,55 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
     NQS_LAUNCH(k_c1_final, dim3((unsigned)M), dim3(kThreads), 0, s, pm, M, c->N * c->C,
                (const double *)pa, dlog + q0, isign + q0, (int8_t *)nullptr, fbase, sbase,
                c->err);
+}
+
+bool cnn1_cone_ok(const nqs_ctx *c)
+{
+    return c->net == kNetCnn1 && c->C == kMC && c->K >= 1 && c->K <= kConeMaxK &&
+           c->L >= 4 * c->K + 4;
+}
+
+size_t cnn1_cache_bytes(const nqs_ctx *c, int64_t B)
+{
+    return sizeof(double) * (size_t)2 * c->K * (size_t)B * c->N * kMC;
+}
+
+void cnn1_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
+                              int8_t *sgn, void *pa, void *pb, double *cache, int64_t B,
+                              int64_t b0, hipStream_t s)
+{
+    if (nb <= 0) return;
+    const C1Planes pm{nullptr, 0, nullptr};
+    const size_t plane = (size_t)c->N * kMC, bytes = sizeof(double) * plane * nb;
+    double *u = (double *)pa, *m = (double *)pb;
+    for (int k = 0; k < c->K; ++k) {
+        block_forward(c, k, spins, pm, nb, k == 0 ? nullptr : u, m, u, nullptr, s);
+        (void)hipMemcpyAsync(cache + ((size_t)(2 * k) * B + b0) * plane, m, bytes,
+                             hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(cache + ((size_t)(2 * k + 1) * B + b0) * plane, u, bytes,
+                             hipMemcpyDeviceToDevice, s);
+    }
+    NQS_LAUNCH(k_c1_final, dim3(nb), dim3(kThreads), 0, s, pm, (int64_t)nb, c->N * c->C,
+               (const double *)u, f, sgn, (int8_t *)nullptr, (const double *)nullptr,
+               (const int8_t *)nullptr, c->err);
+}
+
+void cnn1_cone_forward(const nqs_ctx *c, const int8_t *spins, int64_t B, const uint32_t *queue,
+                       const int64_t *qlen, int64_t cap, const double *cache, double *dlog,
+                       int8_t *isign, hipStream_t s)
+{
+    if (cap <= 0) return;
+    const C1ConeArgs a{spins, queue, qlen,     cap,   c->w_vec64, c->w_canon,
+                       cache,  B,     dlog,     isign, c->err,     c->L,
+                       c->K};
+    const int P = 4 * c->K + 4;
+    const size_t lds = (size_t)P * P * 128 + sizeof(double) * kConvK;   // frame, taps
+    (void)hipFuncSetAttribute((const void *)k_c1_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    // one workgroup of eight waves per CU (registers); a multiple of 8 for the
+    // XCD ranges
+    const int grid = std::max(8, c->n_cu / 8 * 8);
+    NQS_LAUNCH(k_c1_cone, dim3(grid), dim3(kConeThreads), lds, s, a);
 }
 
 size_t cnn1_packed_doubles(const nqs_ctx *c)

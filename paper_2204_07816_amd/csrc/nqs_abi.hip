@@ -18,10 +18,14 @@ namespace nqs {
 
 const BlockNet kCnn1Net{cnn1_params,       cnn1_plane_bytes,  cnn1_chunk,
                         cnn1_base_forward, cnn1_conn_forward, cnn1_packed_doubles,
-                        cnn1_pack_device,  cnn1_deriv_planes, cnn1_deriv_rows};
+                        cnn1_pack_device,  cnn1_deriv_planes, cnn1_deriv_rows,
+                        cnn1_cone_ok,      cnn1_cache_bytes,  cnn1_base_forward_cached,
+                        cnn1_cone_forward};
 const BlockNet kCnn2Net{cnn2_params,       cnn2_plane_bytes,  cnn2_chunk,
                         cnn2_base_forward, cnn2_conn_forward, cnn2_packed_doubles,
-                        cnn2_pack_device,  cnn2_deriv_planes, cnn2_deriv_rows};
+                        cnn2_pack_device,  cnn2_deriv_planes, cnn2_deriv_rows,
+                        nullptr,           nullptr,           nullptr,
+                        nullptr};
 
 const BlockNet *block_net(const nqs_ctx *c)
 {
@@ -210,6 +214,7 @@ int64_t bonds_per_sample(const nqs_ctx *c)
 // whether the incremental cone form serves this context
 bool incremental_ok(const nqs_ctx *c)
 {
+    if (const BlockNet *bn = block_net(c)) return bn->cone_ok && bn->cone_ok(c);
     if (c->net != kNetLnCosh) return false;
     if (c->dtype == NQS_BF16) return mfma_inc_supported(c);
     if (c->dtype == NQS_BF16X3) return cone_x3_supported(c);
@@ -219,6 +224,17 @@ bool incremental_ok(const nqs_ctx *c)
 nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
 {
     if (m != NQS_AUTO) return m;
+    if (block_net(c)) {
+        if (!incremental_ok(c)) return NQS_FULL;
+        if (c->tuned) return c->tuned_mode;
+        // positions of the cone (R_1 .. R_2K of a 2x2 box) against 2K full layers
+        double inc = 0.0, full = 0.0;
+        for (int l = 1; l <= 2 * c->K; ++l) {
+            inc += (2.0 + 2 * l) * (2.0 + 2 * l);
+            full += (double)c->N;
+        }
+        return inc < 0.7 * full ? NQS_INCREMENTAL : NQS_FULL;
+    }
     if (c->dtype == NQS_BF16X3) {
         if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !incremental_ok(c)) ? NQS_FULL
                                                                                        : c->tuned_mode;
@@ -326,18 +342,26 @@ nqs_status x3_conn_stage(nqs_ctx *c, const int8_t *spins, nqs_mode mode, double 
 // samples), then every queue item recomputed in full: dlog[item] and the
 // sign ratio in ws.isign.
 nqs_status block_ratio_stage(nqs_ctx *c, const BlockNet *bn, const int8_t *spins, int B,
-                             double *dlog, int64_t cap, hipStream_t s)
+                             nqs_mode mode, double *dlog, int64_t cap, hipStream_t s)
 {
     Workspace &w = c->ws;
-    const int64_t chunk = bn->chunk(c, std::max<int64_t>(cap, B));
+    const bool cone = mode == NQS_INCREMENTAL && incremental_ok(c);
+    const int64_t chunk = bn->chunk(c, std::max<int64_t>(cone ? B : cap, B));
     NQS_TRY(ensure(w.sgn, std::max(B, 1), s));
     NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
     NQS_TRY(ensure(w.plane_a, bn->plane_bytes(c, chunk), s));
     NQS_TRY(ensure(w.plane_b, bn->plane_bytes(c, chunk), s));
+    if (cone) NQS_TRY(ensure(w.cache, bn->cache_bytes(c, B), s));
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
-        bn->base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
-                          (int8_t *)w.sgn.ptr + b0, nullptr, w.plane_a.ptr, w.plane_b.ptr, s);
+        if (cone)
+            bn->base_forward_cached(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+                                    (int8_t *)w.sgn.ptr + b0, w.plane_a.ptr, w.plane_b.ptr,
+                                    (double *)w.cache.ptr, B, b0, s);
+        else
+            bn->base_forward(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+                              (int8_t *)w.sgn.ptr + b0, nullptr, w.plane_a.ptr, w.plane_b.ptr,
+                              s);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -345,11 +369,15 @@ nqs_status block_ratio_stage(nqs_ctx *c, const BlockNet *bn, const int8_t *spins
         (void)hipEventCreate(&e1);
         (void)hipEventRecord(e0, s);
     }
-    for (int64_t q0 = 0; q0 < cap; q0 += chunk)
-        bn->conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
-                          std::min(chunk, cap - q0), (const double *)w.fbase.ptr,
-                          (const int8_t *)w.sgn.ptr, dlog, (int8_t *)w.isign.ptr, w.plane_a.ptr,
-                          w.plane_b.ptr, s);
+    if (cone)
+        bn->cone_forward(c, spins, B, (const uint32_t *)w.queue.ptr, (const int64_t *)w.qlen.ptr,
+                         cap, (const double *)w.cache.ptr, dlog, (int8_t *)w.isign.ptr, s);
+    else
+        for (int64_t q0 = 0; q0 < cap; q0 += chunk)
+            bn->conn_forward(c, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, q0,
+                              std::min(chunk, cap - q0), (const double *)w.fbase.ptr,
+                              (const int8_t *)w.sgn.ptr, dlog, (int8_t *)w.isign.ptr,
+                              w.plane_a.ptr, w.plane_b.ptr, s);
     if (c->timing) {
         (void)hipEventRecord(e1, s);
         c->events.push_back({e0, e1});
@@ -363,7 +391,8 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
 {
     Workspace &w = c->ws;
     NQS_TRY(ensure(w.fbase, sizeof(double) * std::max(B, 1), s));
-    if (const BlockNet *bn = block_net(c)) return block_ratio_stage(c, bn, spins, B, dlog, cap, s);
+    if (const BlockNet *bn = block_net(c))
+        return block_ratio_stage(c, bn, spins, B, mode, dlog, cap, s);
     NQS_TRY(ensure(w.hsum, sizeof(double) * (size_t)std::max(B, 1) * c->N, s));
     if (c->dtype == NQS_BF16X3) {
         NQS_TRY(bf16_base_stage(c, spins, B, s));
@@ -1128,12 +1157,45 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
     if (stream_capturing(s)) return NQS_E_WORKSPACE;
     c->last_stream = s;
     if (block_net(c)) {
-        // CNN1 / CNN2: full recomputation is the only form (nothing to time
-        // or to keep in the cache)
+        // CNN1 / CNN2: where the receptive cone serves, the whole log-ratio pass
+        // (base pass included: the incremental one also keeps the activations)
+        // is timed in both forms; otherwise full recomputation is the only
+        // form.  Nothing goes to the tune cache, whose keys do not name the
+        // network family.
+        nqs_mode best = NQS_FULL;
+        if (incremental_ok(c)) {
+            const int64_t cap = bonds_per_sample(c) * B;
+            NQS_TRY(integer_stage(c, spins, (int)B, s));
+            NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+            double *dl = (double *)c->ws.dlog.ptr;
+            hipEvent_t e0, e1;
+            HIP_OK(hipEventCreate(&e0));
+            HIP_OK(hipEventCreate(&e1));
+            double ms[2] = {0.0, 0.0};
+            const nqs_mode form[2] = {NQS_FULL, NQS_INCREMENTAL};
+            nqs_status st = NQS_OK;
+            for (int i = 0; i < 2 && st == NQS_OK; ++i) {
+                st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
+                if (st != NQS_OK) break;
+                (void)hipEventRecord(e0, s);
+                st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
+                (void)hipEventRecord(e1, s);
+                if (st != NQS_OK) break;
+                (void)hipEventSynchronize(e1);
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ms[i] = t;
+                st = finish_call();
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            NQS_TRY(st);
+            best = ms[1] < ms[0] ? NQS_INCREMENTAL : NQS_FULL;
+        }
         c->tuned = 1;
-        c->tuned_mode = NQS_FULL;
-        if (mode_out) *mode_out = NQS_FULL;
-        return NQS_OK;
+        c->tuned_mode = best;
+        if (mode_out) *mode_out = best;
+        return finish_call();
     }
     double ms_full = -1.0, ms_inc = -1.0;
     int best_nw = 0, best_mt = 0;

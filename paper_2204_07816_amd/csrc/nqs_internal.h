@@ -343,6 +343,18 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
                        const int64_t *qlen, int64_t q0, int64_t M, const double *fbase,
                        const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
                        hipStream_t s);
+// exchanged configurations by the receptive cone (16 channels, K <= 6,
+// L >= 4K + 4): the base pass also keeps every layer's activations
+// (cache [2K][B][N][16], samples b0 .. b0 + nb - 1 of B; f and sgn of those
+// samples), then one launch gives dlog and isign of queue items 0 .. cap - 1
+bool cnn1_cone_ok(const nqs_ctx *c);
+size_t cnn1_cache_bytes(const nqs_ctx *c, int64_t B);
+void cnn1_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
+                              int8_t *sgn, void *pa, void *pb, double *cache, int64_t B,
+                              int64_t b0, hipStream_t s);
+void cnn1_cone_forward(const nqs_ctx *c, const int8_t *spins, int64_t B, const uint32_t *queue,
+                       const int64_t *qlen, int64_t cap, const double *cache, double *dlog,
+                       int8_t *isign, hipStream_t s);
 // matrix-core packing of blocks 2.. (16 channels): its size in doubles (0
 // when the vector kernels serve) and its rebuild from w_canon into w_vec64
 size_t cnn1_packed_doubles(const nqs_ctx *c);
@@ -396,6 +408,16 @@ struct BlockNet {
     void (*deriv_planes)(const nqs_ctx *c, int *zp, int *hp, int *wp);
     void (*deriv_rows)(const nqs_ctx *c, const int8_t *spins, int nb, double *zsave,
                        double *hsave, double *work, void *O, nqs_dtype odt, hipStream_t s);
+    // the incremental form (null: none): whether it serves c, the size of its
+    // activation cache, the base pass that fills it, the exchanged pass
+    bool (*cone_ok)(const nqs_ctx *c);
+    size_t (*cache_bytes)(const nqs_ctx *c, int64_t B);
+    void (*base_forward_cached)(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
+                                int8_t *sgn, void *pa, void *pb, double *cache, int64_t B,
+                                int64_t b0, hipStream_t s);
+    void (*cone_forward)(const nqs_ctx *c, const int8_t *spins, int64_t B, const uint32_t *queue,
+                         const int64_t *qlen, int64_t cap, const double *cache, double *dlog,
+                         int8_t *isign, hipStream_t s);
 };
 // the context's block network, null for the ln cosh CNN
 const BlockNet *block_net(const nqs_ctx *c);

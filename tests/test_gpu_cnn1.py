@@ -15,8 +15,10 @@ against the oracle.  The block architecture is a reading of a missing figure
 * a CNN1 VMC iteration captured in a HIP graph equals the eager iterations;
 * trained by the VMC loop on 4x4, CNN1 reaches the exact ground energy (0.3%
   at J2 = 0, 2% at J2 = 0.5);
-* incremental mode is refused; the autotuner answers FULL, and the multi-lattice
-  call runs CNN1 lattices one after another, equal to the single calls.
+* where the receptive cone does not serve (fewer than 16 channels, or L below
+  4K + 4; the cone's own tests are in test_gpu_cnn1_cone.py) incremental mode
+  is refused and the autotuner answers FULL; the multi-lattice call runs CNN1
+  lattices one after another, equal to the single calls.
 """
 import numpy as np
 import pytest
