@@ -23,8 +23,9 @@ with its own stress error; the plain FP64 GPU form is timed on all 1024
 samples.  Further non-gating rows: the mixed-lattice workload (12x12, 16x16,
 20x20) through one multi-lattice call, SR at 24x24 (P = 46,560, B = 4096, 100
 iterations), SR with O recomputed, Metropolis steps, a graph-replayed VMC
-iteration, the t-J local energy (12x12, hole doping 1/8) and the CNN1
-network (10x10, FP64).  The FP64 CPU oracle is timed on the host cores on a
+iteration, the t-J local energy (12x12, hole doping 1/8), the CNN1
+network (10x10, FP64; 36x36 by full recomputation and by the receptive cone)
+and CNN2 (t-J 12x12).  The FP64 CPU oracle is timed on the host cores on a
 bounded sample.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -354,6 +355,82 @@ def cnn1_row(dev, reps=2):
             "log_deriv_ms": ms_o}
 
 
+def cnn1_cone_flops(L, Kb, C, bonds):
+    """Algorithmic FLOPs of the CNN1 receptive-cone pass over the given bond
+    ids: layer l (block b's convolution is layer 2b - 1, its transposed
+    convolution layer 2b) forms the box of the exchanged pair widened by l
+    sites, |R_l| = (w0 + 2l)(h0 + 2l), at 2 * 9 * c_in * c_out per site."""
+    import numpy as np
+    tau = np.asarray(bonds) & 3
+    total = 0
+    for t, (w0, h0) in enumerate(((2, 1), (1, 2), (2, 2), (2, 2))):
+        n = int((tau == t).sum())
+        per = 0
+        for l in range(1, 2 * Kb + 1):
+            if l == 1:
+                f = 2 * 9 * 1 * 2 * C
+            elif l % 2:
+                f = 2 * 9 * C * 2 * C
+            else:
+                f = 2 * 9 * C * C
+            per += (w0 + 2 * l) * (h0 + 2 * l) * f
+        total += n * per
+    return total
+
+
+def cnn1_36_row(dev, reps=2):
+    """Non-gating row: CNN1 (6 blocks x 16 channels) on 36x36 J1-J2 (J2 =
+    0.5), the paper's largest lattice for this network, 128 configurations,
+    FP64: E_loc by full recomputation and by the receptive cone, the cone
+    kernel's rate against the FP64 peak, and the largest relative difference
+    of the two forms' E_loc."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    L, J2, Kb, C, w, sp = inputs.cnn1_36_config_inputs()
+    B = sp.shape[0]
+    ctx = nqs.Context.cnn1(L, 1.0, J2, Kb, C, w)
+    spd = torch.as_tensor(sp).to(dev)
+    out = {"workload": f"{L}x{L} J1-J2 (J2={J2}), CNN1 {Kb} blocks x {C} channels "
+                       f"(P={inputs.cnn1_num_params(Kb, C)}), {B} configurations, FP64"}
+    es = {}
+    for mode in ("full", "incremental"):
+        ctx.reserve(B, mode)
+        e = torch.empty(B, dtype=torch.float64, device=dev)
+        ctx.local_energy(spd, mode=mode, out=e)
+        torch.cuda.synchronize()
+        ctx.enable_timing(True)
+        ctx.kernel_time()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.local_energy(spd, mode=mode, out=e)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        k_ms, k_n = ctx.kernel_time()
+        ctx.enable_timing(False)
+        es[mode] = e.cpu().numpy()
+        out[mode] = {"samples_per_s": B / (ms * 1e-3), "ms": ms,
+                     "conn_pass_ms": k_ms / max(k_n, 1)}
+    _, offs, bonds, _, _ = ctx.connected(spd)
+    n = int(offs[-1].item())
+    bonds = bonds[:n].cpu().numpy()
+    flops = cnn1_cone_flops(L, Kb, C, bonds)
+    tf = flops / (out["incremental"]["conn_pass_ms"] * 1e-3) / 1e12
+    out["exchanged_configurations"] = n
+    out["cone_flops_per_item"] = flops / max(n, 1)
+    out["speedup_incremental_vs_full"] = out["full"]["ms"] / out["incremental"]["ms"]
+    out["cone_kernel"] = {"name": "k_c1_cone", "bound": "mfma", "tflops": tf,
+                          "frac_fp64_peak": tf / PEAK_FP64_TFLOPS,
+                          "frac_fp64_sustained": tf / SUSTAINED["fp64_tflops"]}
+    ref = es["full"]
+    out["eloc_max_rel_diff_incremental_vs_full"] = float(
+        np.max(np.abs(es["incremental"] - ref)) / np.max(np.abs(ref)))
+    assert ctx.get_error() == 0
+    ctx.close()
+    return out
+
+
 def cmp10_row(dev, reps=3):
     """Non-gating row: the precision comparison workload (10x10 J1-J2, J2 =
     0.5, CNN 4x3x3x16, weights N(0, 0.02^2), 8192 configurations): E_loc per
@@ -462,6 +539,7 @@ def main():
     ap.add_argument("--no-vmc", action="store_true")
     ap.add_argument("--no-tj", action="store_true")
     ap.add_argument("--no-cnn1", action="store_true")
+    ap.add_argument("--no-cnn1-36", action="store_true")
     ap.add_argument("--no-cnn2", action="store_true")
     ap.add_argument("--no-cmp10", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
@@ -473,7 +551,8 @@ def main():
                     help="arithmetic of the timed step's convolutions")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
-    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn2", "sr24", "cmp10"],
+    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn1_36", "cnn2", "sr24",
+                             "cmp10"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); "
                          "oderiv likewise the FP32 log-derivative call; tj runs only the t-J "
@@ -504,6 +583,9 @@ def main():
         return
     if args.only == "cnn1":
         print(json.dumps(cnn1_row(dev)), flush=True)
+        return
+    if args.only == "cnn1_36":
+        print(json.dumps(cnn1_36_row(dev)), flush=True)
         return
     if args.only == "cnn2":
         print(json.dumps(cnn2_row(dev)), flush=True)
@@ -819,6 +901,12 @@ def main():
         cnn1 = cnn1_row(dev)
         log(f"CNN1 10x10: {cnn1['samples_per_s']:.1f} samples/s, exchanged-configuration pass "
             f"{cnn1['conn_pass_tflops']:.2f} TFLOP/s FP64")
+    cnn1_36 = None
+    if not args.no_cnn1_36:
+        cnn1_36 = cnn1_36_row(dev)
+        log(f"CNN1 36x36: full {cnn1_36['full']['samples_per_s']:.1f}, cone "
+            f"{cnn1_36['incremental']['samples_per_s']:.1f} samples/s, cone kernel "
+            f"{cnn1_36['cone_kernel']['tflops']:.2f} TFLOP/s FP64")
 
     cnn2 = None
     if not args.no_cnn2:
@@ -865,6 +953,7 @@ def main():
         "vmc_iteration_nongating": vmc,
         "tj_nongating": tj,
         "cnn1_nongating": cnn1,
+        "cnn1_36x36_nongating": cnn1_36,
         "cnn2_tj_nongating": cnn2,
         "cmp10_nongating": cmp10,
         "roofline": roofline,

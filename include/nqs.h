@@ -150,14 +150,23 @@ nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec
  * n_weights = sum_k (2C c_in 9 + 2C + 9 C^2 + C).
  * Entry points serving CNN1 contexts: nqs_log_psi (sign = M^marshall times
  * the sign of the neuron product), nqs_local_energy, nqs_log_ratios and
- * nqs_mcmc (FULL or AUTO mode; the per-item sign ratio of the network enters
- * E_loc), nqs_log_deriv (d log|psi| / d theta by a backward pass: 1/u at the
+ * nqs_mcmc (the per-item sign ratio of the network enters E_loc),
+ * nqs_log_deriv (d log|psi| / d theta by a backward pass: 1/u at the
  * output, a max passes its gradient to the larger input, the first on a
  * tie), nqs_sr_solve, nqs_sr_solve_recompute, nqs_energy_stats,
  * nqs_connected, nqs_set_weights, nqs_update_weights, nqs_get_weights,
  * nqs_reserve, nqs_local_energy_multi (lattice after lattice) and
- * nqs_autotune (FULL, the only form).  INCREMENTAL mode returns
- * NQS_E_UNSUPPORTED.  An output neuron of
+ * nqs_autotune.  Modes: FULL recomputes every exchanged configuration;
+ * INCREMENTAL (channels = 16, blocks <= 6, L >= 4 blocks + 4; otherwise
+ * NQS_E_UNSUPPORTED) recomputes only the receptive cone -- stencil l of the
+ * network (block b's convolution is stencil 2b - 1, its transposed
+ * convolution 2b) changes only within l sites of the exchanged pair -- from
+ * every layer's activations of the base pass, kept in the workspace
+ * (2 blocks B N 16 doubles), with the full pass's arithmetic for every
+ * neuron; AUTO takes the autotuner's choice, else INCREMENTAL where the
+ * cone's positions are below 70% of the full pass's.  nqs_autotune times
+ * both forms where the cone serves (FULL is the only form elsewhere) and
+ * stores nothing in the tune cache.  An output neuron of
  * exactly 0 makes log|psi| infinite: NQS_E_NONFINITE.
  * Errors: NQS_E_LATTICE, NQS_E_SPEC (blocks or channels outside 1..16 /
  * 1..32, marshall_sign not 0/1), NQS_E_NPARAMS, NQS_E_ARG as nqs_create.  */
@@ -189,8 +198,10 @@ nqs_status nqs_create_cnn1_tj(int32_t L, double t, double J, int32_t blocks, int
  * W[C][C][3][3], a[C], V[C][C][3][3] (input channel first), v[C]; then
  * F[C][3][3], b; n_weights = 3C + blocks (18 C^2 + 2C) + 9C + 1.
  * channels must be 16 or 32 (every block convolution runs on the FP64
- * matrix cores).  Entry points and modes as nqs_create_cnn1_tj; a max
- * passes its gradient to channel c unless channel c+1 is strictly larger.
+ * matrix cores).  Entry points as nqs_create_cnn1_tj, in FULL and AUTO
+ * modes (INCREMENTAL: NQS_E_UNSUPPORTED; nqs_autotune answers FULL and
+ * stores nothing); a max passes its gradient to channel c unless channel
+ * c+1 is strictly larger.
  * Errors: NQS_E_SPEC (blocks outside 1..16, channels not 16 or 32,
  * marshall_sign not 0/1), otherwise as nqs_create_cnn1.                   */
 nqs_status nqs_create_cnn2_tj(int32_t L, double t, double J, int32_t blocks, int32_t channels,
@@ -387,8 +398,10 @@ nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
  * the tune cache, a JSON file (NQS_TUNE_CACHE, else
  * $HOME/.cache/nqs/tune.json), under the key nqs_tune_key gives; contexts of
  * the same key created later read it.  FP64 / FP32 contexts have only the
- * full form; CNN1 / CNN2 contexts too, and for them nothing is timed or
- * stored (FULL is returned).  Synchronises the stream; NQS_E_WORKSPACE while the stream is
+ * full form.  CNN1 contexts where the receptive cone serves have both
+ * forms, timed over the whole log-ratio pass; other CNN1 and CNN2 contexts
+ * have the full form only; for block networks nothing is stored in the
+ * cache.  Synchronises the stream; NQS_E_WORKSPACE while the stream is
  * capturing; NQS_E_ARG for B = 0.  mode_out (host) may be null.  A cache
  * file that cannot be written is not an error.                             */
 nqs_status nqs_autotune(nqs_ctx *ctx, const int8_t *spins, int64_t B,

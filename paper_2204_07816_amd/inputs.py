@@ -164,6 +164,19 @@ def cnn1_config_inputs(B: int | None = None):
     return cfg["L"], cfg["J2"], cfg["blocks"], cfg["C"], w, spins_sz0(cfg["L"], nb, 2200)
 
 
+# CNN1 on 36x36 J1-J2 (J2 = 0.5), the paper's largest lattice for CNN1, same
+# network and weight recipe as above; 128 configurations.
+CNN1_36_CONFIG = dict(L=36, J2=0.5, blocks=6, C=16, sigma=0.05, out_bias=1.0, B=128)
+
+
+def cnn1_36_config_inputs(B: int | None = None):
+    """(L, J2, blocks, C, weights, spins) of the 36x36 CNN1 workload."""
+    cfg = CNN1_36_CONFIG
+    nb = cfg["B"] if B is None else B
+    w = cnn1_weights(cfg["blocks"], cfg["C"], cfg["sigma"], 1210, cfg["out_bias"])
+    return cfg["L"], cfg["J2"], cfg["blocks"], cfg["C"], w, spins_sz0(cfg["L"], nb, 2210)
+
+
 # t-J workloads (t = 1, J = 0.4, hole doping 1/8, the parameters of the
 # paper's t-J runs): seeds weights 1100 + index, spins 2100 + index.
 TJ_CONFIGS = {

@@ -21,6 +21,8 @@ factor 64, 64 eps sqrt(N C) (|f(S)| + |f(S')|), plus 1e-10.
   sampled items against the oracle, E_loc against the full pass;
 * edge cases: a Neel state (every J1 bond exchanged), a ferromagnet (no
   items), the AUTO choice, refusals below 4K + 4;
+* the t-J model with the CNN1 amplitude (hops and spin exchanges, 12x12 at
+  hole doping 1/8) against the oracle;
 * Metropolis chains in INCREMENTAL mode equal the oracle's; the autotuner
   times both forms; a VMC iteration captured in a HIP graph (the cone pass
   and the cache copies inside) equals the eager iterations.
@@ -171,6 +173,24 @@ def test_cone_edge_cases():
     with pytest.raises(nqs.NqsError) as info:
         c8.local_energy(to_dev(inputs.spins_sz0(L, 2, 234)), mode="incremental")
     assert info.value.code == 10
+    assert ctx.get_error() == 0
+
+
+@pytest.mark.parametrize("marshall", [True, False])
+def test_cone_tj_local_energy_matches_oracle(marshall):
+    # t-J with the CNN1 amplitude on 12x12 (hole doping 1/8): hops and spin
+    # exchanges both swap the values of two neighbouring sites, so the same
+    # cone serves them; the network's sign ratio meets the Jordan-Wigner sign
+    L, Kb, B, t, J = 12, 2, 3, 1.0, 0.4
+    w = inputs.cnn1_weights(Kb, C16, 0.3, 271, out_bias=1.0)
+    sp = inputs.spins_tj(L, B, 18, 272)
+    ctx = nqs.Context.cnn1_tj(L, t, J, Kb, C16, w, marshall_sign=marshall)
+    d = to_dev(sp)
+    e = ctx.local_energy(d, mode="incremental").cpu().numpy()
+    ref = oracle.tj_cnn1_local_energy(L, t, J, Kb, C16, w, sp, marshall=marshall)
+    say("t-J cnn1 cone: max rel", rel_inf(e, ref))
+    assert rel_inf(e, ref) <= 1e-10
+    assert torch.equal(ctx.local_energy(d), ctx.local_energy(d, mode="incremental"))
     assert ctx.get_error() == 0
 
 
