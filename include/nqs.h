@@ -162,8 +162,9 @@ nqs_status nqs_create_tj(int32_t L, double t, double J, const nqs_cnn_spec *spec
  * network (block b's convolution is stencil 2b - 1, its transposed
  * convolution 2b) changes only within l sites of the exchanged pair -- from
  * every layer's activations of the base pass, kept in the workspace
- * (2 blocks B N 16 doubles), with the full pass's arithmetic for every
- * neuron; AUTO takes the autotuner's choice, else INCREMENTAL where the
+ * ((2 blocks - 1) B N 16 doubles, and per site of the last layer the sum of
+ * log|u| and the count of negative neurons), with the full pass's
+ * arithmetic for every neuron; AUTO takes the autotuner's choice, else INCREMENTAL where the
  * cone's positions are below 70% of the full pass's.  nqs_autotune times
  * both forms where the cone serves (FULL is the only form elsewhere) and
  * stores nothing in the tune cache.  An output neuron of

@@ -652,10 +652,37 @@ void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t 
 // operands of a tap and column block as 32 contiguous bytes.  The results wait
 // in registers until every wave has read the frame, then replace R_l in
 // place, and the ring R_{l+2} \ R_l is filled from the sample's activations
-// of layer l, kept by the base pass ([2K][B][N][16]: m_1, u_1, m_2, ...).
-// Layer 1 (one input channel) runs on the vector ALU from the exchanged
-// spins, with the full pass's FMA order.  Needs 16 channels, K <= 6 (the
-// register staging) and L >= 4K + 4 (the frame does not overlap itself).
+// of layer l, kept by the base pass (cache: [2K-1][B][N][16], m_1, u_1, m_2,
+// ..., m_K; then per site the sum of log|u_K| over the channels, [B][N]
+// FP64, and the count of negative u_K, [B][N] int32).  Each wave fetches the
+// ring and the next layer's taps as soon as its tiles are done, so the loads
+// run while the other waves finish; the stores follow the barrier.  On the
+// last layer each neuron of R_2K adds log|u'| and the region's sites
+// subtract their base sums.  Layer 1 (one input channel) runs on the vector
+// ALU from the exchanged spins, with the full pass's FMA order.  Needs 16
+// channels, K <= 6 (the register staging; the ring fits 4 chunks per
+// thread) and L >= 4K + 4 (the frame does not overlap itself).
+// Per site of the last layer's output u [M][N][16]: the sum of log|u| over
+// the channels and the count of negative neurons.
+__global__ void __launch_bounds__(kThreads)
+k_c1_site_sums(const double *__restrict__ u, int64_t n_sites, double *__restrict__ slog,
+               int *__restrict__ nneg)
+{
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n_sites;
+         q += (int64_t)gridDim.x * kThreads) {
+        const double *v = u + q * kMC;
+        double acc = 0.0;
+        int n = 0;
+#pragma unroll
+        for (int c = 0; c < kMC; ++c) {
+            acc += log(fabs(v[c]));
+            n += v[c] < 0.0;
+        }
+        slog[q] = acc;
+        nneg[q] = n;
+    }
+}
+
 constexpr int kConeMaxK = 6;
 constexpr int kConeNW = 8;
 constexpr int kConeThreads = kConeNW * 64;
@@ -668,7 +695,7 @@ struct C1ConeArgs {
     int64_t cap;
     const double *wpack;        // the forward's packed taps
     const double *w1;           // block 1, canonical: W [32][9], then a [32]
-    const double *cache;        // [2K][B][N][16]
+    const double *cache;        // [2K-1][B][N][16], then slog [B][N], then nneg (int32) [B][N]
     int64_t B;
     double *dlog;
     int8_t *isign;
@@ -694,20 +721,42 @@ __device__ inline const double *c1_layer_taps(const double *wp, int l, int *ncol
     return k == 0 ? blk : blk + kConvK + 2 * kMC;
 }
 
-// layer l's taps into LDS: wl[((t NH + h) 64 + lane) 4 + s] = W[t][4 kq + s][16 h + m16]
-// (lane = 16 kq + m16), all threads of the workgroup
-__device__ inline void c1_stage_taps(const double *wt, int ncol, double *wl, int tid)
+// A layer's taps in LDS: wl[((t NH + h) 64 + lane) 4 + s] = W[t][4 kq + s][16 h + m16]
+// (lane = 16 kq + m16), at most 9 entries per thread (q = tid + r kConeThreads),
+// fetched into tv (entries beyond the layer's: not stored), and its bias
+struct C1Taps {
+    double tv[9];
+    double bias[2];
+    int total;
+};
+
+__device__ inline void c1_taps_fetch(C1Taps &tp, const double *wp, int l, int tid, int m16)
 {
-    const int nh = ncol >> 4, total = 9 * nh * 256;
-    for (int q = tid; q < total; q += kConeThreads) {
+    int ncol;
+    const double *wt = c1_layer_taps(wp, l, &ncol);
+    const int nh = ncol >> 4;
+    tp.total = 9 * nh * 256;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int q = min(tid + r * kConeThreads, tp.total - 1);
         const int sub = q & 3, ln = (q >> 2) & 63, th = q >> 8;
         const int t = th / nh, h = th - t * nh;
-        wl[q] = wt[(t * kMC + 4 * (ln >> 4) + sub) * ncol + 16 * h + (ln & 15)];
+        tp.tv[r] = wt[(t * kMC + 4 * (ln >> 4) + sub) * ncol + 16 * h + (ln & 15)];
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) tp.bias[h] = wt[9 * kMC * ncol + 16 * min(h, nh - 1) + m16];
 }
 
-// one tile: fm = frame site of this lane's A row; D element i: row kq + 4 i,
-// column 16 h + m16
+__device__ inline void c1_taps_store(const C1Taps &tp, double *wl, int tid)
+{
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+        if (tid + r * kConeThreads < tp.total) wl[tid + r * kConeThreads] = tp.tv[r];
+}
+
+// One tile: fm = frame site of this lane's A row; D element i: row kq + 4 i,
+// column 16 h + m16; the taps and K-steps in the full pass's order (fully
+// unrolled: the compiler reads the operands of all taps ahead).
 template <int NH>
 __device__ inline void c1_tile(const unsigned char *fr, const double *wl, int fm, int P,
                                int lane, const double (&bias)[2], double4_t (&acc)[2])
@@ -750,7 +799,6 @@ k_c1_cone(C1ConeArgs a)
     const int64_t seg = (n_items + 7) / 8;
     const int64_t u_end = min(n_items, (xcd + 1) * seg);
     double *wl = reinterpret_cast<double *>(fr + (size_t)P * P * 128);   // the layer's taps
-    double bias[2];
 
     for (int64_t u = xcd * seg + slot; u < u_end; u += per_xcd) {
         const uint32_t e = a.queue[u];
@@ -767,37 +815,44 @@ k_c1_cone(C1ConeArgs a)
             y += y < 0 ? L : (y >= L ? -L : 0);
             return y * L + x;
         };
-        // ring R_{l+2} \ R_l of the frame from the cache of layer l
-        auto ring_fill = [&](int l) {
-            const int wr = w0 + 2 * l + 4, hr = h0 + 2 * l + 4;
-            const int total = wr * hr * 8;
+        // ring R_{l+2} \ R_l of the frame: its 4 (w0 + 2l + 4) + 4 (h0 + 2l)
+        // sites (two rows above and below R_l, full width, then two columns
+        // left and right of it) in 8 chunks each, chunk q = tid + r kConeThreads
+        // (at most 4 per thread): values from the cache of layer l, offsets
+        // in the frame (-1: none)
+        double2 rv0, rv1, rv2, rv3;
+        int rd0, rd1, rd2, rd3;
+        auto ring_fetch = [&](int l) {
+            const int W = w0 + 2 * l + 4, H = h0 + 2 * l + 4, hi = h0 + 2 * l;
+            const int total = (4 * W + 4 * hi) * 8;
             const double *src = a.cache + ((int64_t)(l - 1) * a.B + s) * N * kMC;
-            // chunk q: its value (loaded for every q, from site 0 when not
-            // needed) and its LDS offset, -1 when not needed
-            auto fetch = [&](int q, double2 &v, int &d) {
-                const int p = q >> 3, c = q & 7;
-                const int py = p / wr, px = p - py * wr;
-                const bool inner = (unsigned)(px - 2) < (unsigned)(w0 + 2 * l) &&
-                                   (unsigned)(py - 2) < (unsigned)(h0 + 2 * l);
-                const bool live = q < total && !inner;
+            auto one = [&](int q, double2 &v, int &d) {
+                const int rs = q >> 3, c = q & 7;
+                const int band = (rs >= W) + (rs >= 2 * W) + (rs >= 3 * W);
+                const int rr = rs - 4 * W, col = rr & 3;
+                const bool bands = rs < 4 * W;
+                const int px = bands ? rs - band * W : (col < 2 ? col : W - 4 + col);
+                const int py = bands ? (band < 2 ? band : H - 4 + band) : 2 + (rr >> 2);
+                const bool live = q < total;
                 const int fx = F - l - 2 + px, fy = F - l - 2 + py;
                 const int site = live ? site_of(fx, fy) : 0;
                 v = *(const double2 *)(src + (int64_t)site * kMC + 2 * c);
                 d = live ? fr_off(fy * P + fx, c) : -1;
             };
-            for (int q0 = tid; q0 < total; q0 += 4 * kConeThreads) {
-                double2 v0, v1, v2, v3;
-                int d0, d1, d2, d3;
-                fetch(q0, v0, d0);
-                fetch(q0 + kConeThreads, v1, d1);
-                fetch(q0 + 2 * kConeThreads, v2, d2);
-                fetch(q0 + 3 * kConeThreads, v3, d3);
-                if (d0 >= 0) *(double2 *)(fr + d0) = v0;
-                if (d1 >= 0) *(double2 *)(fr + d1) = v1;
-                if (d2 >= 0) *(double2 *)(fr + d2) = v2;
-                if (d3 >= 0) *(double2 *)(fr + d3) = v3;
-            }
+            one(tid, rv0, rd0);
+            one(tid + kConeThreads, rv1, rd1);
+            one(tid + 2 * kConeThreads, rv2, rd2);
+            one(tid + 3 * kConeThreads, rv3, rd3);
         };
+        auto ring_store = [&]() {
+            if (rd0 >= 0) *(double2 *)(fr + rd0) = rv0;
+            if (rd1 >= 0) *(double2 *)(fr + rd1) = rv1;
+            if (rd2 >= 0) *(double2 *)(fr + rd2) = rv2;
+            if (rd3 >= 0) *(double2 *)(fr + rd3) = rv3;
+        };
+        C1Taps tp;
+        ring_fetch(1);
+        c1_taps_fetch(tp, a.wpack, 2, tid, m16);
 
         // layer 1 on R_1 from the exchanged spins: thread (site, pooled channel j)
         {
@@ -818,13 +873,9 @@ k_c1_cone(C1ConeArgs a)
                 *(double *)(fr + fr_off(fy * P + fx, j >> 1) + (j & 1) * 8) = (z1 > z0) ? z1 : z0;
             }
         }
-        ring_fill(1);
-        {
-            int nc;
-            const double *wt = c1_layer_taps(a.wpack, 2, &nc);
-            c1_stage_taps(wt, nc, wl, tid);
-            bias[0] = wt[9 * kMC * nc + m16];
-        }
+        ring_store();
+        c1_taps_store(tp, wl, tid);
+        double bias[2] = {tp.bias[0], tp.bias[1]};
         __syncthreads();
 
         double dl = 0.0;
@@ -838,7 +889,45 @@ k_c1_cone(C1ConeArgs a)
                 const int v = (int)(((uint32_t)p * mul) >> 20);
                 return (F - l + v) * P + (F - l + p - v * wd);
             };
+            // last layer: the base sums of this thread's sites of R_2K (loads
+            // issued before the matrix work)
+            double bsum = 0.0;
+            int bneg = 0;
+            if (l == 2 * K) {
+                const double *slog = a.cache + (int64_t)(2 * K - 1) * a.B * N * kMC + (int64_t)s * N;
+                const int *nneg = reinterpret_cast<const int *>(
+                                      a.cache + (int64_t)(2 * K - 1) * a.B * N * kMC + a.B * N) +
+                                  (int64_t)s * N;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int p = tid + r * kConeThreads;
+                    if (p < nl) {
+                        const int v = (int)(((uint32_t)p * mul) >> 20);
+                        const int site = site_of(F - l + p - v * wd, F - l + v);
+                        bsum += slog[site];
+                        bneg += nneg[site];
+                    }
+                }
+            }
             double st[kConeStage][4];
+            // the result of this wave's j-th tile (ti = wave + 8 j): staged, or
+            // on the last layer its log|u'| and negative neurons
+            auto take = [&](int j, int ti, const double (&out)[4]) {
+                if (l < 2 * K) {
+#pragma unroll
+                    for (int jj = 0; jj < kConeStage; ++jj)
+                        if (jj == j)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) st[jj][i] = out[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (ti * 16 + kq + 4 * i >= nl) continue;
+                        dl += log(fabs(out[i]));
+                        dneg += out[i] < 0.0;
+                    }
+                }
+            };
             int j = 0;
             for (int ti = wave; ti < ntiles; ti += kConeNW, ++j) {
                 const int fm = frame_of(min(ti * 16 + m16, nl - 1));
@@ -853,35 +942,18 @@ k_c1_cone(C1ConeArgs a)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) out[i] = acc[0][i];
                 }
-                if (l < 2 * K) {
-#pragma unroll
-                    for (int jj = 0; jj < kConeStage; ++jj)
-                        if (jj == j)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) st[jj][i] = out[i];
-                } else {
-                    // the last layer: log|u'| - log|u| and the sign change
-                    const double *ub = a.cache + ((int64_t)(2 * K - 1) * a.B + s) * N * kMC;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int p = ti * 16 + kq + 4 * i;
-                        if (p >= nl) continue;
-                        const int v = (int)(((uint32_t)p * mul) >> 20);
-                        const double u0 = ub[(int64_t)site_of(F - l + p - v * wd, F - l + v) * kMC + m16];
-                        dl += log(fabs(out[i])) - log(fabs(u0));
-                        dneg += (out[i] < 0.0) - (u0 < 0.0);
-                    }
-                }
+                take(j, ti, out);
             }
-            if (l == 2 * K) break;
+            if (l == 2 * K) {
+                dl -= bsum;
+                dneg -= bneg;
+                break;
+            }
+            // this wave's tiles are done: the ring of W_{l+1} and the next
+            // layer's taps on their way while the other waves finish
+            ring_fetch(l);
+            c1_taps_fetch(tp, a.wpack, l + 1, tid, m16);
             __syncthreads();                 // every read of the frame and taps for layer l is done
-            {
-                int nc;
-                const double *wt = c1_layer_taps(a.wpack, l + 1, &nc);
-                c1_stage_taps(wt, nc, wl, tid);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) bias[h] = h < (nc >> 4) ? wt[9 * kMC * nc + 16 * h + m16] : 0.0;
-            }
             j = 0;
             for (int ti = wave; ti < ntiles; ti += kConeNW, ++j) {
 #pragma unroll
@@ -895,7 +967,10 @@ k_c1_cone(C1ConeArgs a)
                                     st[jj][i];
                         }
             }
-            ring_fill(l);
+            ring_store();
+            c1_taps_store(tp, wl, tid);
+            bias[0] = tp.bias[0];
+            bias[1] = tp.bias[1];
             __syncthreads();
         }
         // fixed-order sums over the lanes, then over the waves
@@ -975,9 +1050,11 @@ bool cnn1_cone_ok(const nqs_ctx *c)
            c->L >= 4 * c->K + 4;
 }
 
+// stencils 1 .. 2K-1 [2K-1][B][N][16], then slog [B][N] FP64, nneg [B][N] int32
 size_t cnn1_cache_bytes(const nqs_ctx *c, int64_t B)
 {
-    return sizeof(double) * (size_t)2 * c->K * (size_t)B * c->N * kMC;
+    const size_t bn = (size_t)B * c->N;
+    return sizeof(double) * ((size_t)(2 * c->K - 1) * bn * kMC + bn) + sizeof(int) * bn;
 }
 
 void cnn1_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
@@ -992,9 +1069,16 @@ void cnn1_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, dou
         block_forward(c, k, spins, pm, nb, k == 0 ? nullptr : u, m, u, nullptr, s);
         (void)hipMemcpyAsync(cache + ((size_t)(2 * k) * B + b0) * plane, m, bytes,
                              hipMemcpyDeviceToDevice, s);
-        (void)hipMemcpyAsync(cache + ((size_t)(2 * k + 1) * B + b0) * plane, u, bytes,
-                             hipMemcpyDeviceToDevice, s);
+        if (k + 1 < c->K)
+            (void)hipMemcpyAsync(cache + ((size_t)(2 * k + 1) * B + b0) * plane, u, bytes,
+                                 hipMemcpyDeviceToDevice, s);
     }
+    // the last layer: per-site sums of log|u| and negative counts
+    double *slog = cache + (size_t)(2 * c->K - 1) * B * plane;
+    int *nneg = reinterpret_cast<int *>(slog + (size_t)B * c->N);
+    const int64_t sites = (int64_t)nb * c->N;
+    NQS_LAUNCH(k_c1_site_sums, dim3(grid_of(c, sites)), dim3(kThreads), 0, s, (const double *)u,
+               sites, slog + (size_t)b0 * c->N, nneg + (size_t)b0 * c->N);
     NQS_LAUNCH(k_c1_final, dim3(nb), dim3(kThreads), 0, s, pm, (int64_t)nb, c->N * c->C,
                (const double *)u, f, sgn, (int8_t *)nullptr, (const double *)nullptr,
                (const int8_t *)nullptr, c->err);

@@ -344,9 +344,11 @@ void cnn1_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *qu
                        const int8_t *sbase, double *dlog, int8_t *isign, void *pa, void *pb,
                        hipStream_t s);
 // exchanged configurations by the receptive cone (16 channels, K <= 6,
-// L >= 4K + 4): the base pass also keeps every layer's activations
-// (cache [2K][B][N][16], samples b0 .. b0 + nb - 1 of B; f and sgn of those
-// samples), then one launch gives dlog and isign of queue items 0 .. cap - 1
+// L >= 4K + 4): the base pass also keeps the activations (cache: stencils
+// 1 .. 2K-1 [2K-1][B][N][16], then per site of the last layer the sum of
+// log|u| [B][N] and the negative count [B][N] int32; samples b0 .. b0+nb-1
+// of B; f and sgn of those samples), then one launch gives dlog and isign of
+// queue items 0 .. cap - 1
 bool cnn1_cone_ok(const nqs_ctx *c);
 size_t cnn1_cache_bytes(const nqs_ctx *c, int64_t B);
 void cnn1_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
