@@ -642,7 +642,8 @@ void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t 
 // So log|psi(S')| - log|psi(S)| = sum over R_2K of log|u'_K| - log|u_K|, and
 // the sign ratio is the parity of the change in negative neurons on R_2K.
 //
-// One workgroup per queue item.  A square frame of side 4K + 4 (the box
+// One workgroup of 12 waves (three per SIMD) per queue item.  A square
+// frame of side 4K + 4 (the box
 // widened by F = 2K + 1) holds in LDS the 16 FP64 channels of the current
 // layer's input; layer l reads the frame on R_{l+1} and forms R_l as tiles of
 // 16 sites x 16 channels on v_mfma_f64_16x16x4f64, with the operand layout,
@@ -660,7 +661,7 @@ void blocks_forward(const nqs_ctx *c, const int8_t *spins, C1Planes pm, int64_t 
 // last layer each neuron of R_2K adds log|u'| and the region's sites
 // subtract their base sums.  Layer 1 (one input channel) runs on the vector
 // ALU from the exchanged spins, with the full pass's FMA order.  Needs 16
-// channels, K <= 6 (the register staging; the ring fits 4 chunks per
+// channels, K <= 6 (the register staging; the ring fits 3 chunks per
 // thread) and L >= 4K + 4 (the frame does not overlap itself).
 // Per site of the last layer's output u [M][N][16]: the sum of log|u| over
 // the channels and the count of negative neurons.
@@ -684,9 +685,10 @@ k_c1_site_sums(const double *__restrict__ u, int64_t n_sites, double *__restrict
 }
 
 constexpr int kConeMaxK = 6;
-constexpr int kConeNW = 8;
+constexpr int kConeNW = 12;
 constexpr int kConeThreads = kConeNW * 64;
-constexpr int kConeStage = 5;   // staged tiles per wave: R_11 has 36 tiles at K = 6
+constexpr int kConeStage = 3;   // staged tiles per wave: R_11 has 36 tiles at K = 6
+constexpr int kConeTapSlots = (9 * 2 * 256 + kConeThreads - 1) / kConeThreads;   // taps per thread
 
 struct C1ConeArgs {
     const int8_t *spins;        // [B][N]
@@ -722,10 +724,10 @@ __device__ inline const double *c1_layer_taps(const double *wp, int l, int *ncol
 }
 
 // A layer's taps in LDS: wl[((t NH + h) 64 + lane) 4 + s] = W[t][4 kq + s][16 h + m16]
-// (lane = 16 kq + m16), at most 9 entries per thread (q = tid + r kConeThreads),
+// (lane = 16 kq + m16), at most kConeTapSlots entries per thread (q = tid + r kConeThreads),
 // fetched into tv (entries beyond the layer's: not stored), and its bias
 struct C1Taps {
-    double tv[9];
+    double tv[kConeTapSlots];
     double bias[2];
     int total;
 };
@@ -737,7 +739,7 @@ __device__ inline void c1_taps_fetch(C1Taps &tp, const double *wp, int l, int ti
     const int nh = ncol >> 4;
     tp.total = 9 * nh * 256;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < kConeTapSlots; ++r) {
         const int q = min(tid + r * kConeThreads, tp.total - 1);
         const int sub = q & 3, ln = (q >> 2) & 63, th = q >> 8;
         const int t = th / nh, h = th - t * nh;
@@ -750,7 +752,7 @@ __device__ inline void c1_taps_fetch(C1Taps &tp, const double *wp, int l, int ti
 __device__ inline void c1_taps_store(const C1Taps &tp, double *wl, int tid)
 {
 #pragma unroll
-    for (int r = 0; r < 9; ++r)
+    for (int r = 0; r < kConeTapSlots; ++r)
         if (tid + r * kConeThreads < tp.total) wl[tid + r * kConeThreads] = tp.tv[r];
 }
 
@@ -782,7 +784,7 @@ __device__ inline void c1_tile(const unsigned char *fr, const double *wl, int fm
     }
 }
 
-__global__ void __launch_bounds__(kConeThreads)
+__global__ void __launch_bounds__(kConeThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_c1_cone(C1ConeArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char fr[];
@@ -820,8 +822,8 @@ k_c1_cone(C1ConeArgs a)
         // left and right of it) in 8 chunks each, chunk q = tid + r kConeThreads
         // (at most 4 per thread): values from the cache of layer l, offsets
         // in the frame (-1: none)
-        double2 rv0, rv1, rv2, rv3;
-        int rd0, rd1, rd2, rd3;
+        double2 rv0, rv1, rv2;
+        int rd0, rd1, rd2;   // 3 x 768 >= 1664 ring chunks (K = 6)
         auto ring_fetch = [&](int l) {
             const int W = w0 + 2 * l + 4, H = h0 + 2 * l + 4, hi = h0 + 2 * l;
             const int total = (4 * W + 4 * hi) * 8;
@@ -842,13 +844,11 @@ k_c1_cone(C1ConeArgs a)
             one(tid, rv0, rd0);
             one(tid + kConeThreads, rv1, rd1);
             one(tid + 2 * kConeThreads, rv2, rd2);
-            one(tid + 3 * kConeThreads, rv3, rd3);
         };
         auto ring_store = [&]() {
             if (rd0 >= 0) *(double2 *)(fr + rd0) = rv0;
             if (rd1 >= 0) *(double2 *)(fr + rd1) = rv1;
             if (rd2 >= 0) *(double2 *)(fr + rd2) = rv2;
-            if (rd3 >= 0) *(double2 *)(fr + rd3) = rv3;
         };
         C1Taps tp;
         ring_fetch(1);
@@ -899,7 +899,7 @@ k_c1_cone(C1ConeArgs a)
                                       a.cache + (int64_t)(2 * K - 1) * a.B * N * kMC + a.B * N) +
                                   (int64_t)s * N;
 #pragma unroll
-                for (int r = 0; r < 2; ++r) {
+                for (int r = 0; r < (676 + kConeThreads - 1) / kConeThreads; ++r) {
                     const int p = tid + r * kConeThreads;
                     if (p < nl) {
                         const int v = (int)(((uint32_t)p * mul) >> 20);
@@ -1096,8 +1096,8 @@ void cnn1_cone_forward(const nqs_ctx *c, const int8_t *spins, int64_t B, const u
     const size_t lds = (size_t)P * P * 128 + sizeof(double) * kConvK;   // frame, taps
     (void)hipFuncSetAttribute((const void *)k_c1_cone, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    // one workgroup of eight waves per CU (registers); a multiple of 8 for the
-    // XCD ranges
+    // one workgroup of twelve waves per CU (LDS); a multiple of 8 for the XCD
+    // ranges
     const int grid = std::max(8, c->n_cu / 8 * 8);
     NQS_LAUNCH(k_c1_cone, dim3(grid), dim3(kConeThreads), lds, s, a);
 }
