@@ -19,6 +19,7 @@ factor 64, 64 eps sqrt(N C) (|f(S)| + |f(S')|), plus 1e-10.
 * 36x36 with 6 blocks (the paper's largest lattice and CNN1 depth): every item
   against the full recomputation on the GPU (itself pinned to the oracle),
   sampled items against the oracle, E_loc against the full pass;
+* the smallest lattice the cone serves at K = 4 and 5 (L = 4K + 4);
 * edge cases: a Neel state (every J1 bond exchanged), a ferromagnet (no
   items), the AUTO choice, refusals below 4K + 4;
 * the t-J model with the CNN1 amplitude (hops and spin exchanges, 12x12 at
@@ -143,6 +144,33 @@ def test_cone_36x36_six_blocks():
     e_full = ctx.local_energy(d, mode="full")
     say("  eloc rel", rel_inf(e_inc.cpu().numpy(), e_full.cpu().numpy()))
     assert rel_inf(e_inc.cpu().numpy(), e_full.cpu().numpy()) <= 1e-10
+    assert ctx.get_error() == 0
+
+
+@pytest.mark.parametrize("L,Kb,J2", [(20, 4, 0.5), (24, 5, 0.0)])
+def test_cone_minimal_lattice_per_depth(L, Kb, J2):
+    # L = 4K + 4, the smallest lattice the cone serves at this depth: the frame
+    # spans the whole width, and K = 4, 5 give other staging and ring sizes
+    B = 2
+    w = inputs.cnn1_weights(Kb, C16, 0.1, 281 + Kb, out_bias=1.0)
+    sp = inputs.spins_sz0(L, B, 282 + Kb)
+    ctx = c1_ctx(L, Kb, w, J2=J2)
+    d = to_dev(sp)
+    inc = ctx.log_ratios(d, mode="incremental").cpu().numpy()
+    full = ctx.log_ratios(d, mode="full").cpu().numpy()
+    sample, bond = items_of(ctx, d)
+    n = len(sample)
+    fb = ctx.log_psi(d)[0].cpu().numpy()
+    assert np.all(np.abs(inc[:n] - full[:n]) <= item_tol(L, fb[sample], fb[sample] + full[:n]))
+    rng = np.random.default_rng(283)
+    pick = np.unique(np.concatenate([rng.choice(n, 8, replace=False), [0, n - 1]]))
+    f0, f1 = oracle_items(L, Kb, w, sp, sample[pick], bond[pick])
+    err = np.abs(inc[pick] - (f1 - f0))
+    say("L", L, "K", Kb, "items", n, "sampled vs oracle", err.max())
+    assert np.all(err <= item_tol(L, f0, f1))
+    e_inc = ctx.local_energy(d, mode="incremental").cpu().numpy()
+    e_full = ctx.local_energy(d, mode="full").cpu().numpy()
+    assert rel_inf(e_inc, e_full) <= 1e-10
     assert ctx.get_error() == 0
 
 
