@@ -95,10 +95,16 @@ typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3 } nqs_dt
 
 /* How psi(S') is evaluated for the exchanged configurations [Sec. 5.4.1]:
  * FULL recomputes the whole network for every S'; INCREMENTAL recomputes only
- * the receptive-field cone of the exchanged pair (BF16 and BF16X3 forms; for
- * BF16X3 only where no window of the cone wraps around the torus, L >= 2K+4)
- * and reads the rest from the cached activations of S; AUTO lets the library
- * choose. */
+ * the receptive-field cone of the exchanged pair and reads the rest from the
+ * cached activations of S; AUTO lets the library choose.  INCREMENTAL serves
+ * the BF16 form, the BF16X3 form where no window of the cone wraps around the
+ * torus (L >= 2K + 4), and the FP64 form with 16 or 32 channels, 2 <= K <= 8
+ * and L >= 2K + 4 (elsewhere NQS_E_UNSUPPORTED).  The FP64 cone forms every
+ * neuron with the full pass's arithmetic, in the same order, so the two
+ * differ only in the order of the final sum over sites; its cache holds
+ * layers 1 .. K-1 of the samples, (K-1) B N C doubles (at most 16 GiB per
+ * fill: larger batches are taken in chunks of samples).  For FP64 contexts
+ * AUTO is FULL until nqs_autotune has measured the cone faster. */
 typedef enum { NQS_AUTO = 0, NQS_FULL = 1, NQS_INCREMENTAL = 2 } nqs_mode;
 
 typedef struct {
@@ -253,8 +259,10 @@ nqs_status nqs_set_weights_device(nqs_ctx *ctx, const double *theta, void *strea
  * the device.                                                               */
 nqs_status nqs_get_weights(nqs_ctx *ctx, double *weights, int64_t n);
 
-/* Pre-allocate workspace for batches up to B_max in the given mode, so that
- * later calls allocate nothing (and may be captured into a hipGraph).    */
+/* Pre-allocate workspace for batches up to B_max in the given mode (AUTO:
+ * the mode AUTO resolves to now; the incremental forms' activation caches
+ * are reserved when the mode is INCREMENTAL), so that later calls allocate
+ * nothing (and may be captured into a hipGraph).                          */
 nqs_status nqs_reserve(nqs_ctx *ctx, int64_t B_max, nqs_mode mode);
 
 /* log|psi(s)| (FP64 [B]) and the sign of psi (int8 [B], may be NULL)
@@ -398,8 +406,10 @@ nqs_status nqs_auto_mode(const nqs_ctx *ctx, nqs_mode *mode);
  * (and the full pass and the cone kernel) use the fastest from then on.  The choice is stored in
  * the tune cache, a JSON file (NQS_TUNE_CACHE, else
  * $HOME/.cache/nqs/tune.json), under the key nqs_tune_key gives; contexts of
- * the same key created later read it.  FP64 / FP32 contexts have only the
- * full form.  CNN1 contexts where the receptive cone serves have both
+ * the same key created later read it.  FP64 contexts where the FP64 cone
+ * serves have both forms, timed over the whole log-ratio pass (base pass
+ * included: the incremental one also keeps the activations); other FP64 and
+ * all FP32 contexts have only the full form.  CNN1 contexts where the receptive cone serves have both
  * forms, timed over the whole log-ratio pass; other CNN1 and CNN2 contexts
  * have the full form only; for block networks nothing is stored in the
  * cache.  Synchronises the stream; NQS_E_WORKSPACE while the stream is

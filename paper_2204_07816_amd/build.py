@@ -36,6 +36,7 @@ FILE_FLAGS = {
     "calib.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "k_conv_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "k_x3.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "k_net_cone64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -468,6 +468,27 @@ void vec_base_forward(const nqs_ctx *c, const int8_t *spins, int B, double *f, d
         base_forward_t<double>(c, spins, B, f, hsum, plane_a, plane_b, s);
 }
 
+void vec_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
+                             double *hsum, void *plane, double *cache, int64_t cB, hipStream_t s)
+{
+    if (nb <= 0) return;
+    // the same launches as the plain FP64 base pass, with h_1 .. h_{K-1}
+    // written into their cache slots and h_K into the plane
+    const PlaneMap pm{nullptr, 0, nullptr};
+    const int C = c->C;
+    const int64_t slot = cB * c->N * C;
+    double *h = cache;
+    layer1_launch<double>(c, spins, pm, nb, layer_w<double>(c, 0), h, nullptr, s);
+    for (int k = 1; k < c->K; ++k) {
+        const double *wl = layer_w<double>(c, k);
+        double *out = (k + 1 < c->K) ? h + slot : (double *)plane;
+        layer_launch<double>(c, h, nb, C, C, wl, wl + 9 * C * C, out, 0, nullptr, pm, s);
+        h = out;
+    }
+    NQS_LAUNCH((k_final<double>), dim3(nb), dim3(kThreads), 0, s, (const double *)h, (int64_t)nb,
+               c->N, C, pm, c->L, f, hsum, (const double *)nullptr, (double *)nullptr, c->err);
+}
+
 void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
                       const int64_t *qlen, int64_t q_begin, int64_t q_count, const double *hsum,
                       double *dlog, void *plane_a, void *plane_b, hipStream_t s)

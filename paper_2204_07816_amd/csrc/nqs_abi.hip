@@ -218,6 +218,7 @@ bool incremental_ok(const nqs_ctx *c)
     if (c->net != kNetLnCosh) return false;
     if (c->dtype == NQS_BF16) return mfma_inc_supported(c);
     if (c->dtype == NQS_BF16X3) return cone_x3_supported(c);
+    if (c->dtype == NQS_FP64) return cone64_ok(c);
     return false;
 }
 
@@ -240,6 +241,10 @@ nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
                                                                                        : c->tuned_mode;
         return incremental_ok(c) ? NQS_INCREMENTAL : NQS_FULL;
     }
+    if (c->dtype == NQS_FP64)
+        // the FP64 cone only by request or by the autotuner's measurement
+        return (c->tuned && c->tuned_mode == NQS_INCREMENTAL && incremental_ok(c)) ? NQS_INCREMENTAL
+                                                                                 : NQS_FULL;
     if (c->dtype != NQS_BF16) return NQS_FULL;
     if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !mfma_inc_supported(c)) ? NQS_FULL
                                                                                       : c->tuned_mode;
@@ -420,6 +425,33 @@ nqs_status log_ratio_stage(nqs_ctx *c, const int8_t *spins, int B, nqs_mode mode
         }
         mfma_conn_forward(c, mode, spins, (uint32_t *)w.queue.ptr, (int64_t *)w.qlen.ptr, cap,
                           (double *)w.hsum.ptr, w.cache.ptr, dlog, nullptr, s);
+        if (c->timing) {
+            (void)hipEventRecord(e1, s);
+            c->events.push_back({e0, e1});
+        }
+        return NQS_OK;
+    }
+    if (mode == NQS_INCREMENTAL && incremental_ok(c)) {
+        // FP64 receptive cone: per chunk of samples the base pass, which also
+        // keeps the activations, then the cone over that chunk's queue items
+        const int64_t chunk = std::min(vec_chunk(c, B), cone64_chunk(c, B));
+        NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
+        NQS_TRY(ensure(w.cache, cone64_cache_bytes(c, chunk), s));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+        }
+        for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+            const int nb = (int)std::min<int64_t>(chunk, B - b0);
+            vec_base_forward_cached(c, spins + b0 * c->N, nb, (double *)w.fbase.ptr + b0,
+                                    (double *)w.hsum.ptr + b0 * c->N, w.plane_a.ptr,
+                                    (double *)w.cache.ptr, chunk, s);
+            if (c->timing && b0 == 0) (void)hipEventRecord(e0, s);
+            cone64_forward(c, spins, (const uint32_t *)w.queue.ptr, (const int64_t *)w.qlen.ptr,
+                           cap, (const double *)w.cache.ptr, chunk, b0, nb,
+                           (const double *)w.hsum.ptr, dlog, s);
+        }
         if (c->timing) {
             (void)hipEventRecord(e1, s);
             c->events.push_back({e0, e1});
@@ -673,7 +705,9 @@ nqs_status create_ctx(int32_t L, int model, int net, double J1, double J2, doubl
     {
         nqs_mode m;
         int nw = 0, mt = 0, ci = -1, cw = -1;
-        if (tune_lookup(tune_cache_path(), tune_key(c), &m, &nw, &mt, &ci, &cw)) {
+        // (block networks store no choices; their keys would match the ln
+        // cosh CNN's of the same shape)
+        if (!block_net(c) && tune_lookup(tune_cache_path(), tune_key(c), &m, &nw, &mt, &ci, &cw)) {
             c->tuned = 1;
             c->tuned_mode = m;
             c->full_nw = nw;
@@ -842,6 +876,8 @@ nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
         NQS_TRY(ensure(w.isign, std::max<int64_t>(cap, 1), s));
         NQS_TRY(ensure(w.plane_a, bn->plane_bytes(c, chunk), s));
         NQS_TRY(ensure(w.plane_b, bn->plane_bytes(c, chunk), s));
+        if (resolve_mode(c, mode) == NQS_INCREMENTAL && incremental_ok(c))
+            NQS_TRY(ensure(w.cache, bn->cache_bytes(c, B), s));
     } else if (c->dtype == NQS_BF16) {
         NQS_TRY(ensure(w.cache, cache_bytes(c, B), s));
     } else if (c->dtype == NQS_BF16X3) {
@@ -851,6 +887,9 @@ nqs_status nqs_reserve(nqs_ctx *c, int64_t B_max, nqs_mode mode)
         const int64_t chunk = vec_chunk(c, std::max<int64_t>(cap, B));
         NQS_TRY(ensure(w.plane_a, vec_plane_bytes(c, chunk), s));
         NQS_TRY(ensure(w.plane_b, vec_plane_bytes(c, chunk), s));
+        if (resolve_mode(c, mode) == NQS_INCREMENTAL && incremental_ok(c))
+            NQS_TRY(ensure(w.cache, cone64_cache_bytes(
+                                        c, std::min(vec_chunk(c, B), cone64_chunk(c, B))), s));
     }
     return NQS_OK;
 }
@@ -1148,6 +1187,41 @@ nqs_status nqs_local_energy_multi(const nqs_eloc_job *jobs, int32_t n, nqs_mode 
     return finish_call();
 }
 
+namespace {
+// ms[0], ms[1]: one whole log-ratio pass (bond stage excluded, base pass
+// included) in the FULL and INCREMENTAL forms, each after a warm run
+nqs_status time_ratio_forms(nqs_ctx *c, const int8_t *spins, int64_t B, hipStream_t s,
+                            double ms[2])
+{
+    const int64_t cap = bonds_per_sample(c) * B;
+    NQS_TRY(integer_stage(c, spins, (int)B, s));
+    NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
+    double *dl = (double *)c->ws.dlog.ptr;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    ms[0] = ms[1] = 0.0;
+    const nqs_mode form[2] = {NQS_FULL, NQS_INCREMENTAL};
+    nqs_status st = NQS_OK;
+    for (int i = 0; i < 2 && st == NQS_OK; ++i) {
+        st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
+        if (st != NQS_OK) break;
+        (void)hipEventRecord(e0, s);
+        st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
+        (void)hipEventRecord(e1, s);
+        if (st != NQS_OK) break;
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        ms[i] = t;
+        st = finish_call();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+}  // namespace
+
 nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mode_out,
                         void *stream)
 {
@@ -1164,38 +1238,26 @@ nqs_status nqs_autotune(nqs_ctx *c, const int8_t *spins, int64_t B, nqs_mode *mo
         // network family.
         nqs_mode best = NQS_FULL;
         if (incremental_ok(c)) {
-            const int64_t cap = bonds_per_sample(c) * B;
-            NQS_TRY(integer_stage(c, spins, (int)B, s));
-            NQS_TRY(ensure(c->ws.dlog, sizeof(double) * std::max<int64_t>(cap, 1), s));
-            double *dl = (double *)c->ws.dlog.ptr;
-            hipEvent_t e0, e1;
-            HIP_OK(hipEventCreate(&e0));
-            HIP_OK(hipEventCreate(&e1));
-            double ms[2] = {0.0, 0.0};
-            const nqs_mode form[2] = {NQS_FULL, NQS_INCREMENTAL};
-            nqs_status st = NQS_OK;
-            for (int i = 0; i < 2 && st == NQS_OK; ++i) {
-                st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
-                if (st != NQS_OK) break;
-                (void)hipEventRecord(e0, s);
-                st = log_ratio_stage(c, spins, (int)B, form[i], dl, cap, s);
-                (void)hipEventRecord(e1, s);
-                if (st != NQS_OK) break;
-                (void)hipEventSynchronize(e1);
-                float t = 0.f;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                ms[i] = t;
-                st = finish_call();
-            }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            NQS_TRY(st);
+            double ms[2];
+            NQS_TRY(time_ratio_forms(c, spins, B, s, ms));
             best = ms[1] < ms[0] ? NQS_INCREMENTAL : NQS_FULL;
         }
         c->tuned = 1;
         c->tuned_mode = best;
         if (mode_out) *mode_out = best;
         return finish_call();
+    }
+    if (c->dtype == NQS_FP64 && incremental_ok(c)) {
+        // the FP64 ln cosh CNN where its receptive cone serves: the whole
+        // log-ratio pass timed in both forms, the choice stored in the cache
+        double ms[2];
+        NQS_TRY(time_ratio_forms(c, spins, B, s, ms));
+        const nqs_mode best = ms[1] < ms[0] ? NQS_INCREMENTAL : NQS_FULL;
+        c->tuned = 1;
+        c->tuned_mode = best;
+        (void)tune_store(tune_cache_path(), tune_key(c), best, 0, 0, -1, -1, ms[0], ms[1]);
+        if (mode_out) *mode_out = best;
+        return NQS_OK;
     }
     double ms_full = -1.0, ms_inc = -1.0;
     int best_nw = 0, best_mt = 0;

@@ -205,6 +205,20 @@ void vec_conn_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *que
                       const int64_t *qlen, int64_t q_begin, int64_t q_count, const double *hsum,
                       double *dlog, void *plane_a, void *plane_b, hipStream_t s);
 size_t vec_plane_bytes(const nqs_ctx *c, int64_t items);
+// FP64 receptive cone of the ln cosh CNN (k_net_cone64.hip): 16 or 32
+// channels, 2 <= K <= 8, L >= 2K + 4.  The base pass of nb samples also keeps
+// h_1 .. h_{K-1} in the cache, [K-1][cB][N][C] (the nb samples at the start
+// of each slot; plane: one plane of nb samples); then one launch gives dlog
+// of the queue items of samples b0 .. b0 + nb - 1 among items 0 .. cap - 1
+// (those samples' activations in the cache, hsum of all samples).
+bool cone64_ok(const nqs_ctx *c);
+size_t cone64_cache_bytes(const nqs_ctx *c, int64_t cB);
+int64_t cone64_chunk(const nqs_ctx *c, int64_t B);
+void vec_base_forward_cached(const nqs_ctx *c, const int8_t *spins, int nb, double *f,
+                             double *hsum, void *plane, double *cache, int64_t cB, hipStream_t s);
+void cone64_forward(const nqs_ctx *c, const int8_t *spins, const uint32_t *queue,
+                    const int64_t *qlen, int64_t cap, const double *cache, int64_t cB, int64_t b0,
+                    int64_t nb, const double *hsum, double *dlog, hipStream_t s);
 // Backward: O[B][P] from the saved activations and tanh of the pre-activations.
 // forward of B samples for the backward: tanh z and h = ln cosh z of layers
 // 1..K-1 into zsave / hsave ([layer][B][N][C] FP64 each), and the last
