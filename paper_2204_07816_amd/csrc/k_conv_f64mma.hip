@@ -25,15 +25,6 @@ constexpr int kNT = 3;            // 16-column N-tiles per weight-gradient wave
 
 __device__ inline int wrapi(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
 
-// ln cosh z in FP64, the same form as the vector-ALU layers: expm1/log1p
-// below |z| = 1, |z| - ln 2 + log1p(exp(-2|z|)) above.
-__device__ inline double ln_cosh_d(double z)
-{
-    const double a = fabs(z);
-    if (a > 1.0) return a - 0.69314718055994530942 + log1p(exp(-2.0 * a));
-    const double e = expm1(a);
-    return log1p(e * e / (2.0 + 2.0 * e));
-}
 
 struct ConvArgs {
     const double *in;        // [M][N][Cin]
@@ -240,7 +231,7 @@ k_conv_mma(ConvArgs a)
             a.out[o] = ln_cosh_tanh(z, &th);
             a.zk[o] = th;
         } else {
-            a.out[o] = ln_cosh_d(z);
+            a.out[o] = ln_cosh_fwd(z);
         }
     }
 }

@@ -22,16 +22,11 @@ constexpr int kThreads = 256;
 
 __device__ inline int wrapi(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
 
-// ln cosh z.  With e = expm1(|z|): cosh|z| - 1 = e^2 / (2 (1 + e)), so
-// ln cosh z = log1p(e^2 / (2 + 2e)) keeps full relative precision at small
-// |z|; for |z| > 1 the form |z| - ln 2 + log1p(exp(-2|z|)) avoids overflow.
-__device__ inline double ln_cosh(double z)
-{
-    const double a = fabs(z);
-    if (a > 1.0) return a - 0.69314718055994530942 + log1p(exp(-2.0 * a));
-    const double e = expm1(a);
-    return log1p(e * e / (2.0 + 2.0 * e));
-}
+// ln cosh z: FP64 in the shared branch-free form; FP32 with e = expm1(|z|),
+// cosh|z| - 1 = e^2 / (2 (1 + e)), so ln cosh z = log1p(e^2 / (2 + 2e)) keeps
+// full relative precision at small |z|, and for |z| > 1 the form
+// |z| - ln 2 + log1p(exp(-2|z|)) avoids overflow.
+__device__ inline double ln_cosh(double z) { return ln_cosh_fwd(z); }
 __device__ inline float ln_cosh(float z)
 {
     const float a = fabsf(z);

@@ -39,7 +39,8 @@ constexpr int kNW = 8;
 constexpr int kThreads = kNW * 64;
 constexpr int kXcd = 8;
 constexpr int kMaxK64 = 8;
-constexpr int kStage = 3;       // tiles per wave: R_K has 21 tiles at K = 8
+// tiles per wave and layer: R_K of a 2 x 2 box has 21 tiles at K = 8
+constexpr int kStage = (21 + kNW - 1) / kNW;
 
 struct Cone64Args {
     const int8_t *spins;        // [B][N]
@@ -56,15 +57,6 @@ struct Cone64Args {
 };
 
 __device__ inline int wrapc(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
-
-// ln cosh in FP64, the full pass's form
-__device__ inline double ln_cosh64(double z)
-{
-    const double a = fabs(z);
-    if (a > 1.0) return a - 0.69314718055994530942 + log1p(exp(-2.0 * a));
-    const double e = expm1(a);
-    return log1p(e * e / (2.0 + 2.0 * e));
-}
 
 // byte offset of 16-byte chunk c (channels 2c, 2c + 1) of frame site f; the
 // C / 2 chunks of a site are rotated by the site index, so lanes reading one
@@ -114,32 +106,42 @@ __device__ inline void c64_mma(const Ops<C> &o, double4_t (&acc)[C / 16])
 
 // One tile of layer k (16 sites from frame site fm of this lane's A row):
 // h = ln cosh(bias + W (*) input), D element i of column block h: row kq + 4 i,
-// channel 16 h + m16.  The K-blocks run in the full pass's order; the next
-// block's operands are read before this block's MFMAs issue.
+// channel 16 h + m16.  The K-blocks run in the full pass's order; each
+// block's operands are read two blocks before its MFMAs issue (the weights'
+// latency from L2 exceeds one block's MFMA time), in three register sets
+// that take turns over a loop rolled by three blocks (9 NB is a multiple of 3).
 template <int C>
 __device__ inline void c64_tile(const unsigned char *fr, const double *wl, const double *bias,
                                 int fm, int P, int kq, int m16, double (&out)[C / 16][4])
 {
     constexpr int NB = C / 16;
+    constexpr int NKB = 9 * NB;
     double4_t acc[NB];
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
         const double b = bias[16 * h + m16];
         acc[h] = (double4_t){b, b, b, b};
     }
-    Ops<C> cur, nxt;
-    c64_fetch<C>(fr, wl, fm, P, kq, m16, 0, cur);
+    Ops<C> o0, o1, o2;
+    c64_fetch<C>(fr, wl, fm, P, kq, m16, 0, o0);
+    c64_fetch<C>(fr, wl, fm, P, kq, m16, 1, o1);
 #pragma unroll 1
-    for (int kb = 0; kb < 9 * NB - 1; ++kb) {
-        c64_fetch<C>(fr, wl, fm, P, kq, m16, kb + 1, nxt);
-        c64_mma<C>(cur, acc);
-        cur = nxt;
+    for (int kb = 0; kb < NKB - 3; kb += 3) {
+        c64_fetch<C>(fr, wl, fm, P, kq, m16, kb + 2, o2);
+        c64_mma<C>(o0, acc);
+        c64_fetch<C>(fr, wl, fm, P, kq, m16, kb + 3, o0);
+        c64_mma<C>(o1, acc);
+        c64_fetch<C>(fr, wl, fm, P, kq, m16, kb + 4, o1);
+        c64_mma<C>(o2, acc);
     }
-    c64_mma<C>(cur, acc);
+    c64_fetch<C>(fr, wl, fm, P, kq, m16, NKB - 1, o2);
+    c64_mma<C>(o0, acc);
+    c64_mma<C>(o1, acc);
+    c64_mma<C>(o2, acc);
 #pragma unroll
     for (int h = 0; h < NB; ++h)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[h][i] = ln_cosh64(acc[h][i]);
+        for (int i = 0; i < 4; ++i) out[h][i] = ln_cosh_fwd(acc[h][i]);
 }
 
 template <int C>
@@ -151,7 +153,7 @@ k_net_cone64(Cone64Args a)
     // ring chunks per thread: the largest ring, R_{K+1} \ R_{K-1} of a 2 x 2
     // box, has 16 K + 16 sites
     constexpr int RS = ((16 * kMaxK64 + 16) * CHK + kThreads - 1) / kThreads;
-    static_assert(RS >= 3 && RS <= 5, "ring slots are five named registers");
+    static_assert(RS <= 5, "ring slots are five named registers");
     extern __shared__ __attribute__((aligned(16))) unsigned char fr[];
     __shared__ double red[kNW];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -207,15 +209,17 @@ k_net_cone64(Cone64Args a)
         };
         auto ring_load = [&](int l) __attribute__((always_inline)) {
             ring_one(l, 0, rv0, rd0);
-            ring_one(l, 1, rv1, rd1);
-            ring_one(l, 2, rv2, rd2);
+            if constexpr (RS > 1) ring_one(l, 1, rv1, rd1);
+            if constexpr (RS > 2) ring_one(l, 2, rv2, rd2);
             if constexpr (RS > 3) ring_one(l, 3, rv3, rd3);
             if constexpr (RS > 4) ring_one(l, 4, rv4, rd4);
         };
         auto ring_store = [&]() __attribute__((always_inline)) {
             if (rd0 >= 0) *(double2 *)(fr + rd0) = rv0;
-            if (rd1 >= 0) *(double2 *)(fr + rd1) = rv1;
-            if (rd2 >= 0) *(double2 *)(fr + rd2) = rv2;
+            if constexpr (RS > 1)
+                if (rd1 >= 0) *(double2 *)(fr + rd1) = rv1;
+            if constexpr (RS > 2)
+                if (rd2 >= 0) *(double2 *)(fr + rd2) = rv2;
             if constexpr (RS > 3)
                 if (rd3 >= 0) *(double2 *)(fr + rd3) = rv3;
             if constexpr (RS > 4)
@@ -237,7 +241,7 @@ k_net_cone64(Cone64Args a)
                     site = (site == qi) ? qj : ((site == qj) ? qi : site);
                     z = fma(a.w[t * C + co], (double)sp[site], z);
                 }
-                *(double *)(fr + fo<C>(fy * P + fx, co >> 1) + (co & 1) * 8) = ln_cosh64(z);
+                *(double *)(fr + fo<C>(fy * P + fx, co >> 1) + (co & 1) * 8) = ln_cosh_fwd(z);
             }
         }
         ring_load(1);
@@ -255,38 +259,34 @@ k_net_cone64(Cone64Args a)
                 const int v = (int)(((uint32_t)p * mul) >> 20);
                 return (F - k + v) * P + (F - k + p - v * wd);
             };
+            // this wave's tiles ti = wave + kNW jj, results staged in
+            // registers until every wave has read the frame
             double st[kStage][NB][4];
-            int j = 0;
-            for (int ti = wave; ti < ntiles; ti += kNW, ++j) {
-                double out[NB][4];
-                c64_tile<C>(fr, wl, bias, frame_of(min(ti * 16 + m16, nl - 1)), P, kq, m16, out);
 #pragma unroll
-                for (int jj = 0; jj < kStage; ++jj)
-                    if (jj == j)
-#pragma unroll
-                        for (int h = 0; h < NB; ++h)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) st[jj][h][i] = out[h][i];
+            for (int jj = 0; jj < kStage; ++jj) {
+                const int ti = wave + kNW * jj;
+                if (ti < ntiles)
+                    c64_tile<C>(fr, wl, bias, frame_of(min(ti * 16 + m16, nl - 1)), P, kq, m16,
+                                st[jj]);
             }
             if (k < K) ring_load(k);
             __syncthreads();                 // every read of the frame for layer k is done
-            j = 0;
-            for (int ti = wave; ti < ntiles; ti += kNW, ++j) {
 #pragma unroll
-                for (int jj = 0; jj < kStage; ++jj)
-                    if (jj == j)
+            for (int jj = 0; jj < kStage; ++jj) {
+                const int ti = wave + kNW * jj;
+                if (ti < ntiles)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int p = ti * 16 + kq + 4 * i;
-                            if (p < nl) {
-                                const int f = frame_of(p);
+                    for (int i = 0; i < 4; ++i) {
+                        const int p = ti * 16 + kq + 4 * i;
+                        if (p < nl) {
+                            const int f = frame_of(p);
 #pragma unroll
-                                for (int h = 0; h < NB; ++h) {
-                                    const int co = 16 * h + m16;
-                                    *(double *)(fr + fo<C>(f, co >> 1) + (co & 1) * 8) = st[jj][h][i];
-                                }
+                            for (int h = 0; h < NB; ++h) {
+                                const int co = 16 * h + m16;
+                                *(double *)(fr + fo<C>(f, co >> 1) + (co & 1) * 8) = st[jj][h][i];
                             }
                         }
+                    }
             }
             if (k < K) ring_store();
             __syncthreads();

@@ -27,10 +27,45 @@ __host__ __device__ inline uint32_t pack_item(int sample, int bond) {
 __host__ __device__ inline int item_sample(uint32_t e) { return (int)(e >> kBondBits); }
 __host__ __device__ inline int item_bond(uint32_t e) { return (int)(e & ((1u << kBondBits) - 1)); }
 
+// log(1 + v) for -1/2 <= v <= 0, the range the FP64 ln cosh needs (v =
+// expm1(-2|z|) / 2), to about 2 ulp.  With m = 1 + v (its rounding c = v -
+// (m - 1) kept exactly) and m2 = m or 2m in [1/sqrt 2, sqrt 2):
+// log m2 = 2 atanh s = 2s (1 + s^2/3 + s^4/5 + ...), s = (m2 - 1)/(m2 + 1),
+// |s| <= 0.1716, where the first term left out, s^22 / 23, is below 1e-18
+// relative; then log(1 + v) = log m2 - [m < 1/sqrt 2] ln 2 + c / m.  The
+// general log1p carries extended-precision steps this range does not need
+// (113 FP64 instructions against about 25).
+__device__ inline double log1p_neg(double v)
+{
+    const double m = 1.0 + v;
+    const double c = v - (m - 1.0);
+    const bool lo = m < 0.70710678118654752440;
+    const double m2 = lo ? 2.0 * m : m;
+    const double num = m2 - 1.0, den = m2 + 1.0;
+    double y = __builtin_amdgcn_rcp(den);
+    y = fma(fma(-den, y, 1.0), y, y);
+    double s = num * y;
+    s = fma(fma(-den, s, num), y, s);
+    const double w = s * s;
+    double p = 1.0 / 21;
+    p = fma(p, w, 1.0 / 19);
+    p = fma(p, w, 1.0 / 17);
+    p = fma(p, w, 1.0 / 15);
+    p = fma(p, w, 1.0 / 13);
+    p = fma(p, w, 1.0 / 11);
+    p = fma(p, w, 1.0 / 9);
+    p = fma(p, w, 1.0 / 7);
+    p = fma(p, w, 1.0 / 5);
+    p = fma(p, w, 1.0 / 3);
+    const double s2 = 2.0 * s;
+    const double lg = fma(s2 * w, p, s2);
+    return (lo ? lg - 0.69314718055994530942 : lg) + c * __builtin_amdgcn_rcp(m);
+}
+
 // ln cosh z and tanh z from one expm1, for the forward pass of the backward
 // (which keeps tanh z, the derivative of ln cosh, for the data gradient):
 // with m = expm1(-2|z|), tanh|z| = -m / (2 + m) at full relative precision,
-// and ln cosh z = |z| + log1p(m / 2) to a few ulp of |z| in absolute terms
+// and ln cosh z = |z| + log(1 + m / 2) to a few ulp of |z| in absolute terms
 // (the pass needs ln cosh only as the next layer's input, where an absolute
 // error at FP64 rounding level is what any order of the sums gives).
 __device__ inline double ln_cosh_tanh(double z, double *th)
@@ -38,7 +73,18 @@ __device__ inline double ln_cosh_tanh(double z, double *th)
     const double a = fabs(z);
     const double m = expm1(-2.0 * a);
     *th = copysign(-m / (2.0 + m), z);
-    return a + log1p(0.5 * m);
+    return a + log1p_neg(0.5 * m);
+}
+
+// ln cosh z in FP64 for the forward passes: the same |z| + log(1 + m / 2),
+// m = expm1(-2|z|), so a forward and the backward's forward give equal
+// activations.  No branch: the lanes of a wave never run two forms (a
+// two-branch form with relative precision at small |z| costs twice the FP64
+// instructions where a wave's lanes take both).
+__device__ inline double ln_cosh_fwd(double z)
+{
+    const double a = fabs(z);
+    return a + log1p_neg(0.5 * expm1(-2.0 * a));
 }
 
 // Hamiltonian of a context: the J1-J2 spin model [Sec. 6.1, Eq. J1J2] or
