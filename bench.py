@@ -20,7 +20,8 @@ in log amplitude, its mean energy over 16 samples must lie within 1e-5
 log ratios are below FP64 resolution, so any form passes there; that check is
 reported too.)  The plain BF16 form is timed beside it as a non-gating row
 with its own stress error; the plain FP64 GPU form is timed on all 1024
-samples.  Further non-gating rows: the mixed-lattice workload (12x12, 16x16,
+samples, in full and by its receptive cone (FP64 matrix cores; every
+neuron bit-identical to the full pass).  Further non-gating rows: the mixed-lattice workload (12x12, 16x16,
 20x20) through one multi-lattice call, SR at 24x24 (P = 46,560, B = 4096, 100
 iterations), SR with O recomputed, Metropolis steps, a graph-replayed VMC
 iteration, the t-J local energy (12x12, hole doping 1/8), the CNN1
@@ -551,11 +552,12 @@ def main():
                     help="arithmetic of the timed step's convolutions")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
-    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "tj", "cnn1", "cnn1_36", "cnn2", "sr24",
-                             "cmp10"],
+    ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "eloc64", "tj", "cnn1", "cnn1_36",
+                                                     "cnn2", "sr24", "cmp10"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); "
-                         "oderiv likewise the FP32 log-derivative call; tj runs only the t-J "
+                         "oderiv likewise the FP32 log-derivative call; eloc64 likewise the "
+                         "FP64 local-energy call in --mode; tj runs only the t-J "
                          "row and prints it; cnn1, cnn2, sr24 and cmp10 likewise their rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -598,6 +600,17 @@ def main():
         return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
+    if args.only == "eloc64":
+        c64 = nqs.Context(L, 1.0, J2, K, C, w, dtype="fp64")
+        c64.reserve(B, args.mode)
+        spd = torch.as_tensor(sp).to(dev)
+        e = torch.empty(B, dtype=torch.float64, device=dev)
+        for i in range(args.steps):
+            c64.local_energy(spd, mode=args.mode, out=e)
+            torch.cuda.synchronize()
+            log(f"eloc64 ({args.mode}) {i + 1}/{args.steps} done")
+        assert c64.get_error() == 0
+        return
     log(f"workload 36x36 K={K} C={C} B={B}, form {args.form}")
     spd = torch.as_tensor(sp).to(dev)
     ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype=args.form)
@@ -784,6 +797,38 @@ def main():
                 "note": "at the workload's weights the log ratios are below FP64 resolution, "
                         "so this comparison cannot fail; the gate is precision_gate"}
         log(f"fp64 plain: {fp64['samples_per_s']:.2f} samples/s, {args.form} mean rel err {rel:.3e}")
+        # the FP64 receptive cone on the same samples: whole call, and the cone
+        # kernel's algorithmic FP64 rate (item_flops over the queue)
+        c64.reserve(nsub, "incremental")
+        e64i = torch.empty_like(e64)
+        c64.local_energy(sub[:4], mode="incremental", out=e64i[:4])
+        torch.cuda.synchronize()
+        c64.kernel_time()
+        c64.enable_timing(True)
+        ev0.record()
+        c64.local_energy(sub, mode="incremental", out=e64i)
+        ev1.record()
+        torch.cuda.synchronize()
+        c64.enable_timing(False)
+        t64i = ev0.elapsed_time(ev1)
+        ki_ms, ki_n = c64.kernel_time()
+        _, offs64, bonds64, _, _ = c64.connected(sub)
+        b64 = bonds64[:int(offs64[-1].item())].cpu().numpy()
+        nd64 = int(np.sum(b64 % 4 >= 2))
+        fl64 = (b64.shape[0] - nd64) * item_flops(L, K, C, False) + nd64 * item_flops(L, K, C, True)
+        tf64 = fl64 / (ki_ms / max(ki_n, 1) * 1e-3) / 1e12
+        e64in = e64i.cpu().numpy()
+        fp64["incremental"] = {
+            "samples_per_s": nsub / (t64i * 1e-3), "ms": t64i,
+            "speedup_vs_full": t64 / t64i,
+            "eloc_max_rel_diff_vs_full": float(np.max(np.abs(e64in - e64n)) / np.max(np.abs(e64n))),
+            "cone_kernel": {"name": "k_net_cone64<32>", "bound": "mfma", "ms": ki_ms / max(ki_n, 1),
+                            "items": int(b64.shape[0]), "flops": fl64, "tflops": tf64,
+                            "frac_fp64_peak": tf64 / PEAK_FP64_TFLOPS,
+                            "frac_fp64_sustained": tf64 / SUSTAINED["fp64_tflops"]}}
+        log(f"fp64 cone: {fp64['incremental']['samples_per_s']:.1f} samples/s "
+            f"({fp64['incremental']['speedup_vs_full']:.2f}x full), kernel {tf64:.1f} TFLOP/s "
+            f"({tf64 / PEAK_FP64_TFLOPS:.3f} of peak)")
         c64.close()
 
     gate, stress_other = None, None

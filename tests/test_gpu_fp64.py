@@ -166,3 +166,30 @@ def test_exhaustive_all_states_4x4_gpu(dtype, tol):
         pick = np.random.default_rng(3).choice(1 << 16, size=1024, replace=False)
         ref = oracle.local_energy(L, 1.0, J2, K, C, w, spins[pick])
         assert rel_inf(e[pick], ref) <= 1e-10
+
+
+def test_fp64_ln_cosh_to_a_few_ulp():
+    """The FP64 forward's ln cosh itself: a single 1-channel layer with zero
+    taps has z = b at every site, so log|psi| = N ln cosh(b) exactly (equal
+    per-site values sum exactly in pairs).  Against an 80-bit long-double
+    evaluation of |b| + log1p(expm1(-2|b|)/2), every b from 1e-8 to 700 (both
+    signs, the 1/sqrt 2 switch of the short logarithm at |b| = 0.4407, large
+    |b| where ln cosh b = |b| - ln 2) lies within 4 ulp of max(|b|, ln cosh b)."""
+    L = 4
+    bs = np.concatenate([np.geomspace(1e-8, 700.0, 160), -np.geomspace(3e-4, 35.0, 40),
+                         [0.0, 0.44068, 0.44069, 0.5, 1.0, 18.4, 20.0]])
+    sp = to_dev(inputs.spins_sz0(L, 1, 91))
+    got = np.empty(len(bs))
+    for i, b in enumerate(bs):
+        w = np.zeros(inputs.num_params(1, 1))
+        w[9] = b
+        ctx = make_ctx(L, 0.0, 1, 1, w)
+        la, _ = ctx.log_psi(sp)
+        got[i] = la.cpu().numpy()[0] / (L * L)
+        ctx.close()
+    a = np.abs(bs).astype(np.longdouble)
+    ref = a + np.log1p(np.expm1(-2 * a) / 2)
+    scale = np.maximum(np.abs(bs), np.abs(ref.astype(np.float64)))
+    ulps = np.abs((got - ref).astype(np.float64)) / np.maximum(np.spacing(scale), 5e-324)
+    say("ln cosh max error", ulps.max(), "ulp at b =", bs[np.argmax(ulps)])
+    assert ulps.max() <= 4.0
