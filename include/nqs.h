@@ -103,8 +103,7 @@ typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3 } nqs_dt
  * neuron with the full pass's arithmetic, in the same order, so the two
  * differ only in the order of the final sum over sites; its cache holds
  * layers 1 .. K-1 of the samples, (K-1) B N C doubles (at most 16 GiB per
- * fill: larger batches are taken in chunks of samples).  For FP64 contexts
- * AUTO is FULL until nqs_autotune has measured the cone faster. */
+ * fill: larger batches are taken in chunks of samples). */
 typedef enum { NQS_AUTO = 0, NQS_FULL = 1, NQS_INCREMENTAL = 2 } nqs_mode;
 
 typedef struct {

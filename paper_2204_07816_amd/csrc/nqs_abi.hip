@@ -225,12 +225,14 @@ bool incremental_ok(const nqs_ctx *c)
 nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
 {
     if (m != NQS_AUTO) return m;
-    if (block_net(c)) {
+    if (block_net(c) || c->dtype == NQS_FP64) {
         if (!incremental_ok(c)) return NQS_FULL;
         if (c->tuned) return c->tuned_mode;
-        // positions of the cone (R_1 .. R_2K of a 2x2 box) against 2K full layers
+        // positions of the cone (R_1 .. R_S of a 2x2 box, S stencils: 2K for a
+        // block network, K for the ln cosh CNN) against S full layers
+        const int S = block_net(c) ? 2 * c->K : c->K;
         double inc = 0.0, full = 0.0;
-        for (int l = 1; l <= 2 * c->K; ++l) {
+        for (int l = 1; l <= S; ++l) {
             inc += (2.0 + 2 * l) * (2.0 + 2 * l);
             full += (double)c->N;
         }
@@ -241,10 +243,6 @@ nqs_mode resolve_mode(const nqs_ctx *c, nqs_mode m)
                                                                                        : c->tuned_mode;
         return incremental_ok(c) ? NQS_INCREMENTAL : NQS_FULL;
     }
-    if (c->dtype == NQS_FP64)
-        // the FP64 cone only by request or by the autotuner's measurement
-        return (c->tuned && c->tuned_mode == NQS_INCREMENTAL && incremental_ok(c)) ? NQS_INCREMENTAL
-                                                                                 : NQS_FULL;
     if (c->dtype != NQS_BF16) return NQS_FULL;
     if (c->tuned) return (c->tuned_mode == NQS_INCREMENTAL && !mfma_inc_supported(c)) ? NQS_FULL
                                                                                       : c->tuned_mode;

@@ -24,7 +24,7 @@ N C terms, the bound is 1e-11 + 64 eps sqrt(N C) (|f(S)| + |f(S')|).
 * a batch of two cache fills (1026 samples of 64x64 at 32 channels: 1024 per
   fill): every E_loc equals that of a call on the sample's own fill's part;
 * edge cases: a Neel state (every J1 bond exchanged), a ferromagnet (no
-  items), AUTO stays FULL until measured, refusals (L < 2K + 4, 8 channels,
+  items), AUTO picks the cone by the work estimate, refusals (L < 2K + 4, 8 channels,
   FP32, K = 1);
 * the t-J model's ln cosh network (hops and exchanges) against the oracle;
 * Metropolis chains in INCREMENTAL mode equal the oracle's;
@@ -197,8 +197,10 @@ def test_cone64_edges():
     say("edges", e, ref)
     assert rel_inf(e, ref) <= 1e-10
     assert e[1] == pytest.approx(L * L * 1.5 / 2, rel=1e-15)   # no items
-    # AUTO is FULL until the autotuner has measured the cone
-    assert ctx.auto_mode() == "full"
+    # AUTO: the cone's positions (16 + 36 + 64) are below 70% of the full
+    # pass's (3 x 100), and an AUTO call runs it
+    assert ctx.auto_mode() == "incremental"
+    assert torch.equal(ctx.local_energy(d), ctx.local_energy(d, mode="incremental"))
     assert ctx.local_energy(to_dev(np.zeros((0, L, L), np.int8)), mode="incremental").numel() == 0
     # refusals: below 2K + 4, 8 channels, FP32, a single layer
     for (LL, KK, CC, dt) in [(10, 4, 16, "fp64"), (10, 3, 8, "fp64"), (10, 3, 16, "fp32"),
