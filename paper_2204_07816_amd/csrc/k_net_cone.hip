@@ -47,17 +47,19 @@ constexpr int kRingRegs = 2;
 constexpr int kChunk = 16;      // bytes of one 8-channel chunk of a site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
 
-// The operand form: X = 1 plain BF16; X = 3 split BF16 (hi + lo of every
+// The operand form: X = 1 plain BF16; X = 3, 4 split BF16 (hi + lo of every
 // operand, three products per tap).  The split form's windows and cache hold
-// the lo parts as four more channel planes / chunks, twice the LDS, so it runs
-// one workgroup of eight waves per CU instead of three of four.
+// the lo parts as four more channel planes / chunks, twice the LDS: X = 3
+// runs one workgroup of eight waves per CU, X = 4 (where two workgroups' LDS
+// fits, K <= 7) two of four, which keeps two configurations in flight per CU
+// (1.5x at K = 6).
 template <int X>
 struct Form {
     static constexpr int NW = X == 3 ? 8 : 4;          // waves per workgroup
     static constexpr int kThreads = NW * 64;
-    static constexpr int CH = X == 3 ? 8 : 4;          // 16-byte chunks (planes) per site
+    static constexpr int CH = X >= 3 ? 8 : 4;          // 16-byte chunks (planes) per site
     static constexpr int SITE = CH * 8;                // BF16 values per cached site
-    static constexpr int WPE = X == 3 ? 2 : 3;         // waves per SIMD
+    static constexpr int WPE = X >= 3 ? 2 : 3;         // waves per SIMD
 };
 constexpr int kMaxK = 16;
 constexpr int kMaxJobs = kMaxConnJobs;
@@ -201,7 +203,7 @@ __device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, i
 template <int X>
 struct Weights {
     bf16x8 hi[KS][NH];
-    bf16x8 lo[X == 3 ? KS : 1][NH];
+    bf16x8 lo[X >= 3 ? KS : 1][NH];
 };
 
 template <int X>
@@ -212,12 +214,12 @@ __device__ __forceinline__ void load_layer(Weights<X> &wt, const ConeParams &p, 
     for (int j = 0; j < KS; ++j)
 #pragma unroll
         for (int hh = 0; hh < NH; ++hh) wt.hi[j][hh] = base[(j * NH + hh) * 64 + lane];
-    if (X == 3) {
+    if (X >= 3) {
         const bf16x8 *bl = p.wl + (int64_t)(k - 2) * KS * NH * 64;
 #pragma unroll
         for (int j = 0; j < KS; ++j)
 #pragma unroll
-            for (int hh = 0; hh < NH; ++hh) wt.lo[X == 3 ? j : 0][hh] = bl[(j * NH + hh) * 64 + lane];
+            for (int hh = 0; hh < NH; ++hh) wt.lo[X >= 3 ? j : 0][hh] = bl[(j * NH + hh) * 64 + lane];
     }
 }
 
@@ -274,13 +276,13 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
             for (int dx = 0; dx < 3; ++dx) {
                 const int j = dy * 3 + dx;
                 const bf16x8 bv = *(const bf16x8 *)(row + dx * kChunk);
-                if (X == 3) {
+                if (X >= 3) {
                     // the split form's product order: lo*hi, hi*lo, hi*hi
                     const bf16x8 bl = *(const bf16x8 *)(row + 4 * ta[w].psc + dx * kChunk);
 #pragma unroll
                     for (int hh = 0; hh < NH; ++hh) {
                         floatx4 c0 = j == 0 ? bias[hh] : acc[w][hh];
-                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.lo[X == 3 ? j : 0][hh],
+                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.lo[X >= 3 ? j : 0][hh],
                                                                      bv, c0, 0, 0, 0);
                         c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.hi[j][hh], bl, c0, 0, 0,
                                                                      0);
@@ -303,12 +305,12 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
         for (int hh = 0; hh < NH; ++hh)
 #pragma unroll
             for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[w][hh][r];
-        if (X == 3)
+        if (X >= 3)
             mf::ln_cosh_x3_n<8>(zv, hv);
         else
             mf::ln_cosh_n<8>(zv, hv);
         if (!last) {
-            if (X == 3) {
+            if (X >= 3) {
                 uint16_t hi[8], lo[8];
 #pragma unroll
                 for (int r = 0; r < 8; ++r) mf::split_bf16(hv[r], &hi[r], &lo[r]);
@@ -351,7 +353,7 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
 template <int X>
 __device__ __forceinline__ int active_waves(int ntiles)
 {
-    if (X == 3) return ntiles < Form<X>::NW ? ntiles : Form<X>::NW;
+    if (X >= 3) return ntiles < Form<X>::NW ? ntiles : Form<X>::NW;
     return ntiles <= 8 ? 2 : Form<X>::NW;
 }
 
@@ -511,7 +513,7 @@ k_net_cone(ConeJobs jobs)
                 uint16_t *cdst = COMMIT ? wcache_s + (gy * L + gx) * F::SITE + (m >> 2) * 8 +
                                               (m & 3) * 2
                                         : nullptr;
-                if (X == 3) {
+                if (X >= 3) {
                     uint16_t h0u, l0u, h1u, l1u;
                     mf::split_bf16(mf::ln_cosh_x3(z0), &h0u, &l0u);
                     mf::split_bf16(mf::ln_cosh_x3(z1), &h1u, &l1u);
@@ -794,7 +796,7 @@ k_net_cone_ls(LsJobs jobs)
             // R_1 sits at frame (K + u, K + v)
             unsigned char *dst =
                 lds + i * FB + (m >> 2) * PB + ((K + v) * FW + K + u) * kChunk + (m & 3) * 4;
-            if (X == 3) {
+            if (X >= 3) {
                 uint16_t h0u, l0u, h1u, l1u;
                 mf::split_bf16(mf::ln_cosh_x3(z0), &h0u, &l0u);
                 mf::split_bf16(mf::ln_cosh_x3(z1), &h1u, &l1u);
@@ -899,7 +901,7 @@ k_net_cone_ls(LsJobs jobs)
 #pragma unroll
             for (int hh = 0; hh < NH; ++hh) {
                 ah[hh] = wbase[hh * 64];
-                if (X == 3) al[hh] = lbase[hh * 64];
+                if (X >= 3) al[hh] = lbase[hh * 64];
             }
 #pragma unroll
             for (int j = 0; j < KS; ++j) {
@@ -907,7 +909,7 @@ k_net_cone_ls(LsJobs jobs)
 #pragma unroll
                     for (int hh = 0; hh < NH; ++hh) {
                         nh[hh] = wbase[((j + 1) * NH + hh) * 64];
-                        if (X == 3) nl[hh] = lbase[((j + 1) * NH + hh) * 64];
+                        if (X >= 3) nl[hh] = lbase[((j + 1) * NH + hh) * 64];
                     }
                 }
                 const int toff = ((j / 3) * FW + (j % 3)) * kChunk;
@@ -916,7 +918,7 @@ k_net_cone_ls(LsJobs jobs)
                     if (wave + n * NW >= ntiles) continue;     // uniform
                     const unsigned char *ap = lds + a0[n] + toff;
                     const bf16x8 bv = *(const bf16x8 *)ap;
-                    if (X == 3) {
+                    if (X >= 3) {
                         const bf16x8 bl = *(const bf16x8 *)(ap + 4 * PB);
 #pragma unroll
                         for (int hh = 0; hh < NH; ++hh) {
@@ -937,13 +939,13 @@ k_net_cone_ls(LsJobs jobs)
 #pragma unroll
                     for (int hh = 0; hh < NH; ++hh) {
                         ah[hh] = nh[hh];
-                        if (X == 3) al[hh] = nl[hh];
+                        if (X >= 3) al[hh] = nl[hh];
                     }
                 }
             }
             // epilogue: ln cosh, then BF16 (split: hi and lo) held for the
             // in-place store, or the last layer's site sums
-            u32x4 oh[S::MAXT], ol[X == 3 ? S::MAXT : 1];
+            u32x4 oh[S::MAXT], ol[X >= 3 ? S::MAXT : 1];
 #pragma unroll
             for (int n = 0; n < S::MAXT; ++n) {
                 if (wave + n * NW >= ntiles) continue;         // uniform
@@ -952,18 +954,18 @@ k_net_cone_ls(LsJobs jobs)
                 for (int hh = 0; hh < NH; ++hh)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) zv[hh * 4 + r] = acc[n][hh][r];
-                if (X == 3)
+                if (X >= 3)
                     mf::ln_cosh_x3_n<8>(zv, hv);
                 else
                     mf::ln_cosh_n<8>(zv, hv);
                 if (!last) {
-                    if (X == 3) {
+                    if (X >= 3) {
                         uint16_t hi[8], lo[8];
 #pragma unroll
                         for (int r = 0; r < 8; ++r) mf::split_bf16(hv[r], &hi[r], &lo[r]);
                         oh[n] = u32x4{pack_u16(hi[0], hi[1]), pack_u16(hi[2], hi[3]),
                                       pack_u16(hi[4], hi[5]), pack_u16(hi[6], hi[7])};
-                        ol[X == 3 ? n : 0] = u32x4{pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
+                        ol[X >= 3 ? n : 0] = u32x4{pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
                                                    pack_u16(lo[4], lo[5]), pack_u16(lo[6], lo[7])};
                     } else {
                         oh[n] = u32x4{pack_bf16(hv[0], hv[1]), pack_bf16(hv[2], hv[3]),
@@ -990,7 +992,7 @@ k_net_cone_ls(LsJobs jobs)
                 for (int n = 0; n < S::MAXT; ++n)
                     if (oaddr[n] >= 0) {
                         *(u32x4 *)(lds + oaddr[n]) = oh[n];
-                        if (X == 3) *(u32x4 *)(lds + oaddr[n] + 4 * PB) = ol[X == 3 ? n : 0];
+                        if (X >= 3) *(u32x4 *)(lds + oaddr[n] + 4 * PB) = ol[X >= 3 ? n : 0];
                     }
 #pragma unroll
                 for (int r = 0; r < S::MAXR; ++r)
@@ -1267,6 +1269,17 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
     // launches of one or two lattices use the two-job instantiation (fewer
     // scalar registers; a one-job instantiation spills)
     if (c0->dtype == NQS_BF16X3) {
+        // two four-wave workgroups per CU where their LDS (with the wave sums)
+        // fits, else one of eight
+        if (2 * (lds + Form<4>::NW * sizeof(double)) <= 160 * 1024) {
+            if (commit)
+                cone_launch_x<2, true, 4>(jp, c0, lds, s);
+            else if (n > 2)
+                cone_launch_x<kMaxJobs, false, 4>(jp, c0, lds, s);
+            else
+                cone_launch_x<2, false, 4>(jp, c0, lds, s);
+            return;
+        }
         if (commit)
             cone_launch_x<2, true, 3>(jp, c0, lds, s);
         else if (n > 2)

@@ -31,6 +31,7 @@ ETA_X3 = 2e-6
 CONE_CASES = [
     ("36x36 K8", 36, 0.5, 8, 1.26, 2),
     ("20x20 K6 J2=0.55", 20, 0.55, 6, 1.1, 3),
+    ("18x18 K7 (deepest with two workgroups per CU)", 18, 0.5, 7, 1.1, 3),
     ("16x16 K6", 16, 0.5, 6, 1.1, 4),
     ("12x12 K4 J2=0", 12, 0.0, 4, 1.0, 6),
     ("8x8 K2 (smallest unwrapped)", 8, 0.5, 2, 1.0, 8),
