@@ -1,7 +1,8 @@
 // k_net_cone64.hip -- the exchanged-configuration pass of the ln cosh CNN in
 // FP64 by the receptive cone [Sec. 5.4.1: the forwards of the O(L^2)
-// exchanged configurations are the hot spot; Sec. 4: the network's
-// arithmetic is FP64], on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// exchanged configurations are the hot spot; Sec. 6.3 and Sec. 8: faithful
+// ground-state energies need double precision], on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).
 //
 // Exchanging the pair (q_i, q_j) changes the spins of a w0 x h0 box, and
 // layer k's output (a 3x3 circular convolution and ln cosh) only on R_k, the

@@ -1,5 +1,5 @@
 """The FP64 receptive-cone pass of the ln cosh CNN [Sec. 5.4.1: the forwards of
-the exchanged configurations; Sec. 4: FP64 arithmetic] on the GPU: INCREMENTAL
+the exchanged configurations; Sec. 6.3: double precision] on the GPU: INCREMENTAL
 mode of an FP64 context with 16 or 32 channels, 2 <= K <= 8 and L >= 2K + 4,
 against the oracle and the full recomputation.
 
