@@ -16,7 +16,7 @@ N C terms, the bound is 1e-11 + 64 eps sqrt(N C) (|f(S)| + |f(S')|).
 * every item's log ratio against the oracle's two forwards on the smallest
   lattices served at K = 2, 3, 4 (J1-J2, J1 only; 16 and 32 channels, stress
   weights), sampled items at K = 8 on 20x20 (the smallest lattice at the
-  paper's depth);
+  paper's depth) with 32 and 16 channels;
 * 36x36, K = 8, C = 32 (the paper's largest lattice and depth): every item of
   two samples against the full pass, at the workload's weights and at stress
   weights, sampled items against the oracle, E_loc against the full pass;
@@ -99,10 +99,11 @@ def test_cone64_items_match_oracle(L, J2, K, C, gain, B):
     assert ctx.get_error() == 0
 
 
-def test_cone64_deep_small_lattice_sampled_items():
-    """K = 8 on 20x20 (L = 2K + 4): every item against the full pass, 24
-    sampled items against the oracle."""
-    L, J2, K, C = 20, 0.5, 8, 32
+@pytest.mark.parametrize("C", [32, 16])
+def test_cone64_deep_small_lattice_sampled_items(C):
+    """K = 8 on 20x20 (L = 2K + 4), both channel counts: every item against
+    the full pass, 24 sampled items against the oracle."""
+    L, J2, K = 20, 0.5, 8
     w = inputs.stress_weights(K, C, 0.5, seed=311)
     sp = inputs.spins_sz0(L, 2, 312)
     ctx = make_ctx(L, J2, K, C, w)
@@ -113,7 +114,7 @@ def test_cone64_deep_small_lattice_sampled_items():
     n = len(sample)
     la, _ = ctx.log_psi(d)
     f0 = la.cpu().numpy()[sample]
-    say("20x20 K8 items", n, "max |inc - full|", np.abs(inc[:n] - full[:n]).max())
+    say("20x20 K8 C", C, "items", n, "max |inc - full|", np.abs(inc[:n] - full[:n]).max())
     assert np.all(np.abs(inc[:n] - full[:n]) <= full_tol(K, f0, full[:n]))
     pick = np.random.default_rng(313).choice(n, size=24, replace=False)
     g0, g1 = oracle_f(L, K, C, w, sp, sample[pick], bond[pick])
