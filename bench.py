@@ -25,8 +25,9 @@ neuron bit-identical to the full pass).  Further non-gating rows: the mixed-latt
 20x20) through one multi-lattice call, SR at 24x24 (P = 46,560, B = 4096, 100
 iterations), SR with O recomputed, Metropolis steps, a graph-replayed VMC
 iteration, the t-J local energy (12x12, hole doping 1/8), the CNN1
-network (10x10, FP64; 36x36 by full recomputation and by the receptive cone)
-and CNN2 (t-J 12x12).  The FP64 CPU oracle is timed on the host cores on a
+network (10x10, FP64; 36x36 by full recomputation and by the receptive cone),
+CNN2 (t-J 12x12), and the split-form cone at K = 6 and 7 (two workgroups per
+CU).  The FP64 CPU oracle is timed on the host cores on a
 bounded sample.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -432,6 +433,48 @@ def cnn1_36_row(dev, reps=2):
     return out
 
 
+def split_depths_row(dev, depths=(6, 7), reps=2):
+    """Non-gating row: the split-BF16 cone kernel on the 36x36 workload's 1024
+    configurations (weights N(0, 0.02^2)) at shallower depths.  Up to K = 7 the
+    windows of two workgroups fit a CU's LDS and the kernel runs two of four
+    waves per CU (two configurations in flight); at K = 8 one of eight."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07816_amd import inputs, nqs
+    L, J2, _, C, _, sp = inputs.config_inputs("full36")
+    B = sp.shape[0]
+    spd = torch.as_tensor(sp).to(dev)
+    out = {}
+    for K in depths:
+        w = inputs.weights(K, C, 0.02, 1004)
+        ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16x3")
+        ctx.reserve(B, "incremental")
+        e = torch.empty(B, dtype=torch.float64, device=dev)
+        ctx.local_energy(spd, mode="incremental", out=e)
+        torch.cuda.synchronize()
+        ctx.kernel_time()
+        ctx.enable_timing(True)
+        for _ in range(reps):
+            ctx.local_energy(spd, mode="incremental", out=e)
+        torch.cuda.synchronize()
+        ctx.enable_timing(False)
+        k_ms, k_n = ctx.kernel_time()
+        _, offs, bonds, _, _ = ctx.connected(spd)
+        b = bonds[:int(offs[-1].item())].cpu().numpy()
+        nd = int(np.sum(b % 4 >= 2))
+        fl = (b.shape[0] - nd) * item_flops(L, K, C, False) + nd * item_flops(L, K, C, True)
+        ms = k_ms / max(k_n, 1)
+        tf = fl / (ms * 1e-3) / 1e12
+        out[f"K{K}"] = {"cone_ms": ms, "items": int(b.shape[0]), "tflops": tf,
+                        "frac": tf / form_peak("bf16x3"),
+                        "shape": "2 workgroups x 4 waves per CU" if K <= 7 else
+                                 "1 workgroup x 8 waves per CU"}
+        assert ctx.get_error() == 0
+        ctx.close()
+    return out
+
+
 def cmp10_row(dev, reps=3):
     """Non-gating row: the precision comparison workload (10x10 J1-J2, J2 =
     0.5, CNN 4x3x3x16, weights N(0, 0.02^2), 8192 configurations): E_loc per
@@ -543,6 +586,7 @@ def main():
     ap.add_argument("--no-cnn1-36", action="store_true")
     ap.add_argument("--no-cnn2", action="store_true")
     ap.add_argument("--no-cmp10", action="store_true")
+    ap.add_argument("--no-depths", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--no-cpu", action="store_true")
@@ -553,12 +597,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
     ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "eloc64", "tj", "cnn1", "cnn1_36",
-                                                     "cnn2", "sr24", "cmp10"],
+                                                     "cnn2", "sr24", "cmp10", "depths"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); "
                          "oderiv likewise the FP32 log-derivative call; eloc64 likewise the "
                          "FP64 local-energy call in --mode; tj runs only the t-J "
-                         "row and prints it; cnn1, cnn2, sr24 and cmp10 likewise their rows")
+                         "row and prints it; cnn1, cnn2, sr24, cmp10 and depths likewise their rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -597,6 +641,9 @@ def main():
         return
     if args.only == "cmp10":
         print(json.dumps(cmp10_row(dev)), flush=True)
+        return
+    if args.only == "depths":
+        print(json.dumps(split_depths_row(dev)), flush=True)
         return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
@@ -953,6 +1000,12 @@ def main():
             f"{cnn1_36['incremental']['samples_per_s']:.1f} samples/s, cone kernel "
             f"{cnn1_36['cone_kernel']['tflops']:.2f} TFLOP/s FP64")
 
+    depths = None
+    if not args.no_depths:
+        depths = split_depths_row(dev)
+        log("split cone by depth: " + ", ".join(f"{k} {v['cone_ms']:.1f} ms ({v['frac']:.3f})"
+                                                 for k, v in depths.items()))
+
     cnn2 = None
     if not args.no_cnn2:
         cnn2 = cnn2_row(dev)
@@ -999,6 +1052,7 @@ def main():
         "tj_nongating": tj,
         "cnn1_nongating": cnn1,
         "cnn1_36x36_nongating": cnn1_36,
+        "split_cone_depths_nongating": depths,
         "cnn2_tj_nongating": cnn2,
         "cmp10_nongating": cmp10,
         "roofline": roofline,
