@@ -15,7 +15,7 @@
 // input; layer k reads it on R_{k+1} and forms R_k as tiles of 16 sites x C
 // channels, with the operand layout and MFMA order of the full pass's
 // k_conv_mma (K-blocks of 16 channels per tap, 4 channels per K-step), the
-// layer's packed taps streamed from memory as B operands one K-block ahead.
+// layer's packed taps streamed from memory as B operands two K-blocks ahead.
 // The results wait in registers until every wave has read the frame, then
 // replace R_k in place, and the ring R_{k+2} \ R_k is filled from the
 // sample's activations of layer k, kept by the base pass (cache: h_1 ..
