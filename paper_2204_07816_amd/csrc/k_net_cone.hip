@@ -60,7 +60,12 @@ struct Form {
     static constexpr int CH = X >= 3 ? 8 : 4;          // 16-byte chunks (planes) per site
     static constexpr int SITE = CH * 8;                // BF16 values per cached site
     static constexpr int WPE = X >= 3 ? 2 : 3;         // waves per SIMD
+    // X = 5: the split form in one frame of side 2K + 4 updated in place
+    // (outputs staged in registers) with the lo parts of the layer's weights in
+    // LDS, so that two workgroups of four waves fit a CU at K <= 8
+    static constexpr bool FRAME = X == 5;
 };
+constexpr int kFrameMaxT = 4;   // tiles per wave of an inner layer in the frame form (K <= 8)
 constexpr int kMaxK = 16;
 constexpr int kMaxJobs = kMaxConnJobs;
 // layer-1 weights in LDS: for each of the 16 channel pairs a thread can own,
@@ -203,7 +208,7 @@ __device__ __forceinline__ void ring_store(const Ring &r, const ConeParams &p, i
 template <int X>
 struct Weights {
     bf16x8 hi[KS][NH];
-    bf16x8 lo[X >= 3 ? KS : 1][NH];
+    bf16x8 lo[X >= 3 && X != 5 ? KS : 1][NH];     // the frame form reads them from LDS
 };
 
 template <int X>
@@ -214,12 +219,13 @@ __device__ __forceinline__ void load_layer(Weights<X> &wt, const ConeParams &p, 
     for (int j = 0; j < KS; ++j)
 #pragma unroll
         for (int hh = 0; hh < NH; ++hh) wt.hi[j][hh] = base[(j * NH + hh) * 64 + lane];
-    if (X >= 3) {
+    if (X >= 3 && X != 5) {
         const bf16x8 *bl = p.wl + (int64_t)(k - 2) * KS * NH * 64;
 #pragma unroll
         for (int j = 0; j < KS; ++j)
 #pragma unroll
-            for (int hh = 0; hh < NH; ++hh) wt.lo[X >= 3 ? j : 0][hh] = bl[(j * NH + hh) * 64 + lane];
+            for (int hh = 0; hh < NH; ++hh)
+                wt.lo[X >= 3 && X != 5 ? j : 0][hh] = bl[(j * NH + hh) * 64 + lane];
     }
 }
 
@@ -241,7 +247,10 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
                                            const unsigned char *cur, unsigned char *nxt,
                                            uint16_t *wcache, double *whsum, int k,
                                            const TileArgs (&ta)[NT], int L, int K, int ax, int ay,
-                                           const double *hsum_s, int g, int n16, double &fsum)
+                                           const double *hsum_s, int g, int n16, double &fsum,
+                                           const unsigned char *wlo = nullptr,
+                                           u32x4 *sh = nullptr, u32x4 *sl = nullptr,
+                                           int *sa = nullptr)
 {
     using F = Form<X>;
     floatx4 acc[NT][NH];
@@ -282,8 +291,13 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
 #pragma unroll
                     for (int hh = 0; hh < NH; ++hh) {
                         floatx4 c0 = j == 0 ? bias[hh] : acc[w][hh];
-                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.lo[X >= 3 ? j : 0][hh],
-                                                                     bv, c0, 0, 0, 0);
+                        bf16x8 wl;
+                        if constexpr (Form<X>::FRAME)
+                            wl = *(const bf16x8 *)(wlo + (((j * NH + hh) << 6) + (g << 4) + n16) *
+                                                             kChunk);
+                        else
+                            wl = wt.lo[X >= 3 && X != 5 ? j : 0][hh];
+                        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bv, c0, 0, 0, 0);
                         c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.hi[j][hh], bl, c0, 0, 0,
                                                                      0);
                         acc[w][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.hi[j][hh], bv,
@@ -314,13 +328,21 @@ __device__ __forceinline__ void cone_group(const Weights<X> &wt, const floatx4 (
                 uint16_t hi[8], lo[8];
 #pragma unroll
                 for (int r = 0; r < 8; ++r) mf::split_bf16(hv[r], &hi[r], &lo[r]);
+                const u32x4 ph = {pack_u16(hi[0], hi[1]), pack_u16(hi[2], hi[3]),
+                                  pack_u16(hi[4], hi[5]), pack_u16(hi[6], hi[7])};
+                const u32x4 pl = {pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
+                                  pack_u16(lo[4], lo[5]), pack_u16(lo[6], lo[7])};
+                if constexpr (Form<X>::FRAME) {
+                    // held until every wave has read the frame
+                    sh[w] = ph;
+                    sl[w] = pl;
+                    sa[w] = valid[w] ? aout[w] : -1;
+                }
                 if (valid[w]) {
-                    const u32x4 ph = {pack_u16(hi[0], hi[1]), pack_u16(hi[2], hi[3]),
-                                      pack_u16(hi[4], hi[5]), pack_u16(hi[6], hi[7])};
-                    const u32x4 pl = {pack_u16(lo[0], lo[1]), pack_u16(lo[2], lo[3]),
-                                      pack_u16(lo[4], lo[5]), pack_u16(lo[6], lo[7])};
-                    *(u32x4 *)(nxt + aout[w]) = ph;
-                    *(u32x4 *)(nxt + aout[w] + 4 * ta[w].psn) = pl;
+                    if constexpr (!Form<X>::FRAME) {
+                        *(u32x4 *)(nxt + aout[w]) = ph;
+                        *(u32x4 *)(nxt + aout[w] + 4 * ta[w].psn) = pl;
+                    }
                     if (COMMIT) {
                         *(u32x4 *)(wcache + site_w[w] * F::SITE + g * 8) = ph;
                         *(u32x4 *)(wcache + site_w[w] * F::SITE + C + g * 8) = pl;
@@ -360,36 +382,60 @@ __device__ __forceinline__ int active_waves(int ntiles)
 // All tiles of layer k owned by this wave (tiles wave, wave + nw, ...), one at
 // a time (the other workgroups / waves of the CU supply the parallelism a
 // second tile in flight would), with the layer's weights in `wt`.
+// Frame form: fw16 is the frame's row pitch in bytes, wlo the layer's lo
+// weights in LDS, and an inner layer's outputs are staged in sh, sl, sa (tile
+// wave + n nw in slot n; sa = -1: nothing to store).
 template <int X, bool last, bool COMMIT>
 __device__ __forceinline__ void cone_layer(const Weights<X> &wt, const float *bs,
                                            const unsigned char *cur, unsigned char *nxt,
                                            uint16_t *wcache, double *whsum, int psc,
                                            int psn, int k, int w0, int h0, int L, int K, int ax,
                                            int ay, const double *hsum_s, int wave, int g, int n16,
-                                           double &fsum)
+                                           double &fsum, int fw16 = 0,
+                                           const unsigned char *wlo = nullptr,
+                                           u32x4 *sh = nullptr, u32x4 *sl = nullptr,
+                                           int *sa = nullptr)
 {
     TileArgs a;
     a.ex = w0 + 2 * k;
     a.npos = a.ex * (h0 + 2 * k);
     a.mul = ((1u << 20) + a.ex - 1) / a.ex;
-    a.p16 = (a.ex + 2) * kChunk;               // W_k = R_{k+1}: width ex + 2
-    a.q16 = (a.ex + 4) * kChunk;               // W_{k+1}: width ex + 4
+    a.p16 = fw16 ? fw16 : (a.ex + 2) * kChunk;     // W_k = R_{k+1}: width ex + 2
+    a.q16 = fw16 ? fw16 : (a.ex + 4) * kChunk;     // W_{k+1}: width ex + 4
     a.psc = psc;
     a.psn = psn;
     const int ntiles = (a.npos + 15) >> 4;
     const int nw = active_waves<X>(ntiles);
+    if constexpr (Form<X>::FRAME && !last) {
+#pragma unroll
+        for (int n = 0; n < kFrameMaxT; ++n) sa[n] = -1;
+    }
     if (wave >= nw) return;
     // bias of this lane's output rows 16 hh + 4 g + r
     floatx4 bias[NH];
 #pragma unroll
     for (int hh = 0; hh < NH; ++hh)
         bias[hh] = *(const floatx4 *)(bs + (k - 2) * C + 16 * hh + 4 * g);
+    if constexpr (Form<X>::FRAME && !last) {
+#pragma unroll
+        for (int n = 0; n < kFrameMaxT; ++n) {
+            const int t = wave + n * nw;
+            if (t < ntiles) {
+                TileArgs ta[1] = {a};
+                ta[0].p0 = t * 16;
+                cone_group<X, last, 1, COMMIT>(wt, bias, cur, nxt, wcache, whsum, k, ta, L, K, ax,
+                                               ay, hsum_s, g, n16, fsum, wlo, sh + n, sl + n,
+                                               sa + n);
+            }
+        }
+        return;
+    }
     int t = wave;
     for (; t < ntiles; t += nw) {
         TileArgs ta[1] = {a};
         ta[0].p0 = t * 16;
         cone_group<X, last, 1, COMMIT>(wt, bias, cur, nxt, wcache, whsum, k, ta, L, K, ax, ay,
-                                       hsum_s, g, n16, fsum);
+                                       hsum_s, g, n16, fsum, wlo);
     }
 }
 
@@ -438,8 +484,30 @@ k_net_cone(ConeJobs jobs)
     };
     Weights<X> wt;
     if (xcd * seg + slot < u_end) load_layer<X>(wt, jobs.job[job_of(xcd * seg + slot)], 2, lane);
-    float *w1s =
-        reinterpret_cast<float *>(lds + F::CH * (jobs.job[0].ps_a + jobs.job[0].ps_b));
+    // frame form: the layer's lo weights in LDS after the frame, the next
+    // layer's on their way in lpf (chunk q = tid + r kThreads of KS NH 64)
+    constexpr int kLoChunks = KS * NH * 64;
+    constexpr int kLoSlots = F::FRAME ? (kLoChunks + kThreads - 1) / kThreads : 1;
+    unsigned char *wlo = lds + F::CH * (jobs.job[0].ps_a + jobs.job[0].ps_b);
+    u32x4 lpf[kLoSlots];
+    auto lo_fetch = [&](const ConeParams &pp, int k) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(pp.wl) + (int64_t)(k - 2) * kLoChunks;
+#pragma unroll
+        for (int r = 0; r < kLoSlots; ++r) {
+            const int q = tid + r * kThreads;
+            lpf[r] = src[q < kLoChunks ? q : 0];
+        }
+    };
+    auto lo_store = [&]() {
+#pragma unroll
+        for (int r = 0; r < kLoSlots; ++r) {
+            const int q = tid + r * kThreads;
+            if (q < kLoChunks) *(u32x4 *)(wlo + q * kChunk) = lpf[r];
+        }
+    };
+    if constexpr (F::FRAME)
+        if (xcd * seg + slot < u_end) lo_fetch(jobs.job[job_of(xcd * seg + slot)], 2);
+    float *w1s = reinterpret_cast<float *>(wlo + (F::FRAME ? kLoChunks * kChunk : 0));
     float *bs = w1s + kW1Floats;   // bias of layer k at bs[(k - 2) C]
     int w1_job = -1;   // job whose layer-1 weights w1s holds
 
@@ -507,9 +575,12 @@ k_net_cone(ConeJobs jobs)
                     z0 = __builtin_fmaf(wm[t], sv[t], z0);
                     z1 = __builtin_fmaf(wm[10 + t], sv[t], z1);
                 }
-                const int p2 = ex1 + 4;                  // pitch of W_2 (its width)
+                // W_2 site (u + 2, v + 2), pitch its width; in the frame form
+                // frame site (K + u, K + v), pitch 2K + 4
+                const int p2 = F::FRAME ? 2 * K + 4 : ex1 + 4;
+                const int o2 = F::FRAME ? K : 2;
                 unsigned char *dst =
-                    lds + (m >> 2) * prm.ps_a + ((v + 2) * p2 + u + 2) * kChunk + (m & 3) * 4;
+                    lds + (m >> 2) * prm.ps_a + ((v + o2) * p2 + u + o2) * kChunk + (m & 3) * 4;
                 uint16_t *cdst = COMMIT ? wcache_s + (gy * L + gx) * F::SITE + (m >> 2) * 8 +
                                               (m & 3) * 2
                                         : nullptr;
@@ -531,14 +602,69 @@ k_net_cone(ConeJobs jobs)
                 }
             }
             ring_store<X>(ring, prm, tid, lds, roff[0], roff[1], ax, ay, L, prm.ps_a, cache_s);
+            if constexpr (F::FRAME) lo_store();          // layer 2's lo weights
         }
         // ring of W_{k+1}, fetched one layer ahead; its table entries two ahead
         Ring ring;
-        ring_fetch<X>(ring, tab, tid, ax, ay, L, prm.ps_b, cache_s + (K >= 3 ? layer_el : 0));
+        ring_fetch<X>(ring, tab, tid, ax, ay, L, F::FRAME ? prm.ps_a : prm.ps_b,
+                      cache_s + (K >= 3 ? layer_el : 0));
         ring_tab_load<X>(tab, prm, K >= 4, roff[K >= 4 ? 2 : 0], roff[K >= 4 ? 3 : 0], tid);
         __syncthreads();
 
         double fsum = 0.0;
+        if constexpr (F::FRAME) {
+            // one frame: W_k is its sub-square from (K - k, K - k), R_k from
+            // (K + 1 - k, K + 1 - k).  A layer's outputs wait in registers
+            // until every wave has read W_k, then replace R_k; the ring
+            // W_{k+1} \ R_k follows from the cache, and the next layer's lo
+            // weights from lpf.
+            const int fw = 2 * K + 4, fw16 = fw * kChunk, ps = prm.ps_a;
+            for (int k = 2; k <= K; ++k) {
+                const unsigned char *cur = lds + (K - k) * (fw + 1) * kChunk;
+                unsigned char *nxt = lds + (K - k - 1) * (fw + 1) * kChunk;
+                uint16_t *wc = COMMIT ? wcache_s + (int64_t)(k - 1) * layer_el : nullptr;
+                if (k < K)
+                    lo_fetch(prm, k + 1);
+                else if (u + per_xcd < u_end)
+                    lo_fetch(jobs.job[job_of(u + per_xcd)], 2);
+                u32x4 sh[kFrameMaxT], sl[kFrameMaxT];
+                int sa[kFrameMaxT];
+                if (k < K)
+                    cone_layer<X, false, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, ps, ps, k, w0, h0,
+                                                 L, K, ax, ay, hsum_s, wave, g, n16, fsum, fw16,
+                                                 wlo, sh, sl, sa);
+                else
+                    cone_layer<X, true, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, ps, ps, k, w0, h0,
+                                                L, K, ax, ay, hsum_s, wave, g, n16, fsum, fw16,
+                                                wlo);
+                if (k < K) {
+                    const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
+                    if (wave < active_waves<X>(nt_next)) load_layer<X>(wt, prm, k + 1, lane);
+                } else if (u + per_xcd < u_end) {
+                    load_layer<X>(wt, jobs.job[job_of(u + per_xcd)], 2, lane);
+                }
+                __syncthreads();                 // every read of W_k and of its weights is done
+                if (k < K) {
+#pragma unroll
+                    for (int n = 0; n < kFrameMaxT; ++n)
+                        if (sa[n] >= 0) {
+                            *(u32x4 *)(nxt + sa[n]) = sh[n];
+                            *(u32x4 *)(nxt + sa[n] + 4 * ps) = sl[n];
+                        }
+                    ring_store<X>(ring, prm, tid, lds, roff[k - 1], roff[k], ax, ay, L, ps,
+                                  cache_s + (int64_t)(k - 1) * layer_el);
+                    lo_store();
+                    if (k + 1 < K) {
+                        ring_fetch<X>(ring, tab, tid, ax, ay, L, ps,
+                                      cache_s + (int64_t)k * layer_el);
+                        const bool more = k + 2 < K;
+                        ring_tab_load<X>(tab, prm, more, roff[more ? k + 1 : 0],
+                                         roff[more ? k + 2 : 0], tid);
+                    }
+                    __syncthreads();             // W_{k+1} and its lo weights are complete
+                }
+            }
+        } else {
         for (int k = 2; k <= K; ++k) {
             unsigned char *cur = lds + ((k & 1) ? prm.buf_b : 0);
             unsigned char *nxt = lds + ((k & 1) ? 0 : prm.buf_b);
@@ -573,6 +699,7 @@ k_net_cone(ConeJobs jobs)
                 load_layer<X>(wt, jobs.job[job_of(u + per_xcd)], 2, lane);
             }
             __syncthreads();
+        }
         }
 
         for (int off = 32; off > 0; off >>= 1) fsum += __shfl_xor(fsum, off);
@@ -1088,9 +1215,45 @@ static void ls_tables(int K, std::vector<int32_t> &ent, std::vector<int> &off)
     }
 }
 
+// Ring tables of the in-place frame form: cone_tab's entries (the sites of
+// W_{k+1} = R_{k+2} outside R_k, with their offsets from the anchor modulo L)
+// with the window index replaced by the frame index (frame of side 2K + 4, the
+// bond box's anchor at frame site (K + 1, K + 1)).
+static void fr_tables(int K, int L, std::vector<int32_t> &ent, std::vector<int> &off)
+{
+    const int FW = 2 * K + 4, F = K + 1;
+    off.assign((size_t)4 * kMaxK, 0);
+    for (int tau = 0; tau < 4; ++tau) {
+        const int w0 = (tau == 1) ? 1 : 2, h0 = (tau == 0) ? 1 : 2;
+        for (int k = 1; k < K; ++k) {
+            off[(size_t)tau * kMaxK + (k - 1)] = (int)ent.size();
+            const int r0 = F - k, w0r = F - k - 2;
+            for (int fy = w0r; fy < w0r + h0 + 2 * k + 4; ++fy)
+                for (int fx = w0r; fx < w0r + w0 + 2 * k + 4; ++fx) {
+                    if (fx >= r0 && fx < r0 + w0 + 2 * k && fy >= r0 && fy < r0 + h0 + 2 * k)
+                        continue;   // R_k
+                    const int du = (((fx - F) % L) + L) % L, dv = (((fy - F) % L) + L) % L;
+                    ent.push_back((fy * FW + fx) | (du << 16) | (dv << 24));
+                }
+        }
+        off[(size_t)tau * kMaxK + (K - 1)] = (int)ent.size();
+    }
+}
+
 nqs_status cone_build_ring_tables(nqs_ctx *c)
 {
     const int L = c->L, K = c->K;
+    if (K <= kLsMaxK) {
+        std::vector<int32_t> fe;
+        fr_tables(K, L, fe, c->fr_off);
+        if (c->fr_tab) (void)hipFree(c->fr_tab);
+        c->fr_tab = nullptr;
+        if (hipMalloc((void **)&c->fr_tab, std::max<size_t>(fe.size(), 1) * 4) != hipSuccess)
+            return NQS_E_NOMEM;
+        if (!fe.empty() &&
+            hipMemcpy(c->fr_tab, fe.data(), fe.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return NQS_E_HIP;
+    }
     if (K <= kLsMaxK) {
         std::vector<int32_t> le;
         ls_tables(K, le, c->ls_off);
@@ -1233,6 +1396,27 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
     // frames fit (K <= 8); write-back launches and deeper networks take the
     // one-configuration kernel
     if (!commit && ls_launch(jobs, n, s)) return;
+    // the split form's shape: two four-wave workgroups per CU with their two
+    // window buffers where those fit (K <= 7), else with one frame updated in
+    // place and the lo weights in LDS where that fits (K <= 8), else one
+    // workgroup of eight waves
+    const nqs_ctx *c0 = jobs[0].c;
+    const size_t tables = sizeof(float) * (kW1Floats + kBiasFloats);
+    const size_t wsums = Form<4>::NW * sizeof(double);
+    const int FW = 2 * c0->K + 4;
+    const size_t frame_ps = (size_t)FW * FW * kChunk;
+    const size_t lo_bytes = (size_t)KS * NH * 64 * kChunk;
+    const size_t frame_lds = Form<5>::CH * frame_ps + lo_bytes + tables;
+    int split_x = 3;
+    if (c0->dtype == NQS_BF16X3) {
+        if (2 * (cone_lds_bytes(c0) + wsums) <= 160 * 1024) {
+            split_x = 4;
+        } else {
+            bool frame = c0->K <= kLsMaxK && 2 * (frame_lds + wsums) <= 160 * 1024;
+            for (int i = 0; i < n; ++i) frame = frame && jobs[i].c->fr_tab != nullptr;
+            if (frame) split_x = 5;
+        }
+    }
     ConeJobs jp{};
     jp.n = n;
     int64_t total_cap = 0;
@@ -1253,25 +1437,41 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
         p.hsum = jobs[i].hsum;
         p.dlog = jobs[i].dlog;
         p.err = c->err;
-        p.ring = c->cone_tab;
-        for (int t = 0; t < 4; ++t)
-            for (int k = 0; k < kMaxK; ++k) jp.ring_off[i][t][k] = c->cone_off[(size_t)t * kMaxK + k];
-        plane_strides(c->K, &p.ps_a, &p.ps_b);
-        p.buf_b = (c->dtype == NQS_BF16X3 ? Form<3>::CH : Form<1>::CH) * p.ps_a;
+        if (split_x == 5) {
+            p.ring = c->fr_tab;
+            for (int t = 0; t < 4; ++t)
+                for (int k = 0; k < kMaxK; ++k) jp.ring_off[i][t][k] = c->fr_off[(size_t)t * kMaxK + k];
+            p.ps_a = (int)frame_ps;              // one frame: plane stride, no second buffer
+            p.ps_b = 0;
+            p.buf_b = 0;
+        } else {
+            p.ring = c->cone_tab;
+            for (int t = 0; t < 4; ++t)
+                for (int k = 0; k < kMaxK; ++k)
+                    jp.ring_off[i][t][k] = c->cone_off[(size_t)t * kMaxK + k];
+            plane_strides(c->K, &p.ps_a, &p.ps_b);
+            p.buf_b = (c->dtype == NQS_BF16X3 ? Form<3>::CH : Form<1>::CH) * p.ps_a;
+        }
         p.commit = commit;
         p.cache_w = (uint16_t *)jobs[i].cache;
         p.hsum_w = const_cast<double *>(jobs[i].hsum);
         total_cap += jobs[i].capacity;
     }
     if (total_cap <= 0) return;
-    const nqs_ctx *c0 = jobs[0].c;
-    const size_t lds = cone_lds_bytes(c0);
+    const size_t lds = split_x == 5 ? frame_lds : cone_lds_bytes(c0);
     // launches of one or two lattices use the two-job instantiation (fewer
     // scalar registers; a one-job instantiation spills)
     if (c0->dtype == NQS_BF16X3) {
-        // two four-wave workgroups per CU where their LDS (with the wave sums)
-        // fits, else one of eight
-        if (2 * (lds + Form<4>::NW * sizeof(double)) <= 160 * 1024) {
+        if (split_x == 5) {
+            if (commit)
+                cone_launch_x<2, true, 5>(jp, c0, lds, s);
+            else if (n > 2)
+                cone_launch_x<kMaxJobs, false, 5>(jp, c0, lds, s);
+            else
+                cone_launch_x<2, false, 5>(jp, c0, lds, s);
+            return;
+        }
+        if (split_x == 4) {
             if (commit)
                 cone_launch_x<2, true, 4>(jp, c0, lds, s);
             else if (n > 2)

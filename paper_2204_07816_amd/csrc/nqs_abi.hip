@@ -790,6 +790,7 @@ nqs_status nqs_destroy(nqs_ctx *c)
     free_dev(c->ring_off);
     free_dev(c->cone_tab);
     free_dev(c->ls_tab);
+    free_dev(c->fr_tab);
     free_dev(c->err);
     for (DevBuf *b : c->ws.all())
         if (b->ptr) (void)hipFree(b->ptr);

@@ -187,6 +187,8 @@ struct nqs_ctx {
     std::vector<int> cone_off;    // [4][16] entry offsets of cone_tab
     int32_t *ls_tab = nullptr;    // frame ring tables of the lockstep cone kernel
     std::vector<int> ls_off;      // [4][16] entry offsets of ls_tab
+    int32_t *fr_tab = nullptr;    // cone_tab's rings in frame coordinates (in-place frame form)
+    std::vector<int> fr_off;      // [4][16] entry offsets of fr_tab
     int cone_variant = -1;        // lockstep shape (items, waves); -1: one-configuration kernel
     // autotuner choice (from nqs_autotune or the tune cache)
     int tuned = 0;
