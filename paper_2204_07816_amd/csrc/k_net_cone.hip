@@ -47,12 +47,13 @@ constexpr int kRingRegs = 2;
 constexpr int kChunk = 16;      // bytes of one 8-channel chunk of a site
 constexpr int kXcd = 8;         // XCDs; workgroup b runs on XCD b % kXcd
 
-// The operand form: X = 1 plain BF16; X = 3, 4 split BF16 (hi + lo of every
-// operand, three products per tap).  The split form's windows and cache hold
-// the lo parts as four more channel planes / chunks, twice the LDS: X = 3
-// runs one workgroup of eight waves per CU, X = 4 (where two workgroups' LDS
-// fits, K <= 7) two of four, which keeps two configurations in flight per CU
-// (1.5x at K = 6).
+// The operand form: X = 1 plain BF16; X = 3, 4, 5 split BF16 (hi + lo of
+// every operand, three products per tap).  The split form's windows and cache
+// hold the lo parts as four more channel planes / chunks, twice the LDS.  Two
+// workgroups of four waves per CU keep two configurations in flight (1.5x at
+// K = 6 against one of eight): X = 4 where two workgroups' windows fit (K <=
+// 7), X = 5 (one frame updated in place, the lo weights in LDS) where two of
+// its frames fit (K <= 8), else X = 3, one workgroup of eight waves.
 template <int X>
 struct Form {
     static constexpr int NW = X == 3 ? 8 : 4;          // waves per workgroup
@@ -440,8 +441,8 @@ __device__ __forceinline__ void cone_layer(const Weights<X> &wt, const float *bs
 }
 
 // Plain form: three workgroups per CU, 166 VGPRs and 46 KB of LDS (K = 8)
-// each.  Split form: one workgroup of eight waves per CU (93 KB of LDS at
-// K = 8).
+// each.  Split form: two workgroups of four waves per CU (windows, K <= 7; the
+// frame form, 73 KB, at K = 8), else one of eight waves.
 // NJ: the number of jobs the launch can hold.  COMMIT: write-back launch (one
 // job): items whose chain is flagged in commit[] store the activations of
 // their cone into the cache and their site sums into hsum, so that the cache
