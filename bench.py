@@ -760,16 +760,23 @@ def main():
         per_item = L * L * C * 9 * 2 + (K - 1) * L * L * C * 9 * C * 2
         flops_launch = float(allb.shape[0]) * per_item
 
+    # the split form's shape at C = 32: two workgroups' compact windows fit a
+    # CU's LDS up to K = 7; deeper cones take the frame form (one frame per
+    # configuration, updated in place)
+    split_label = ("k_net_cone<2, false, %d> (split BF16: hi*hi + hi*lo + lo*hi per "
+                   "multiply-add, so the peak is the 2.5 PFLOP/s BF16 MFMA rate / 3), "
+                   "exchanged configurations, incremental cone, %s"
+                   % ((5, "frame form") if K >= 8 else (4, "compact windows")))
+
     def roofline_of(form, kms, kn):
         avg = kms / max(kn, 1)
         ach = flops_launch / (avg * 1e-3) / 1e12
         peak = form_peak(form)
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": traffic_from_profile(form),
-                "kernel": ("k_net_cone<.., 3> (split BF16: hi*hi + hi*lo + lo*hi per "
-                           "multiply-add, so the peak is the 2.5 PFLOP/s BF16 MFMA rate / 3)"
-                           if form == "bf16x3" else "k_net_cone<.., 1> (plain BF16)")
-                + ", exchanged configurations, incremental cone, unwrapped windows",
+                "kernel": split_label if form == "bf16x3" else
+                          "k_net_cone<2, false, 1> (plain BF16), exchanged configurations, "
+                          "incremental cone, compact windows",
                 "avg_launch_ms": avg, "launches": kn, "flops_per_launch": flops_launch,
                 "items_per_launch": int(allb.shape[0]),
                 "mfma_instruction_tflops": ach * (3 if form == "bf16x3" else 1),
