@@ -1157,13 +1157,19 @@ inline int win_pitch(int w0, int k) { return w0 + 2 * k + 2; }
 // bytes of one channel plane of window W_k for the largest bond box (2 x 2)
 inline int plane_bytes(int k) { return (2 * k + 4) * win_pitch(2, k) * kChunk; }
 
+// One chunk added to every plane stride.  A stride that is a multiple of 256
+// bytes (every even layer's, and the frame's, 16 (K + 2)^2 bytes) puts the
+// eight chunks of a site, which eight neighbouring lanes store together, and
+// the four lane groups' planes of an operand fetch into the same LDS banks.
+constexpr int kPlanePad = kChunk;
+
 // plane strides of the even- and odd-layer buffers
 inline void plane_strides(int K, int *ps_a, int *ps_b)
 {
     *ps_a = *ps_b = 0;
     for (int k = 2; k <= K; ++k) {
         int &ps = (k & 1) ? *ps_b : *ps_a;
-        ps = std::max(ps, plane_bytes(k));
+        ps = std::max(ps, plane_bytes(k) + kPlanePad);
     }
 }
 
@@ -1405,7 +1411,7 @@ static void cone_launch(const ConnJob *jobs, int n, const int32_t *commit, hipSt
     const size_t tables = sizeof(float) * (kW1Floats + kBiasFloats);
     const size_t wsums = Form<4>::NW * sizeof(double);
     const int FW = 2 * c0->K + 4;
-    const size_t frame_ps = (size_t)FW * FW * kChunk;
+    const size_t frame_ps = (size_t)FW * FW * kChunk + kPlanePad;
     const size_t lo_bytes = (size_t)KS * NH * 64 * kChunk;
     const size_t frame_lds = Form<5>::CH * frame_ps + lo_bytes + tables;
     int split_x = 3;
