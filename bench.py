@@ -26,8 +26,8 @@ neuron bit-identical to the full pass).  Further non-gating rows: the mixed-latt
 iterations), SR with O recomputed, Metropolis steps, a graph-replayed VMC
 iteration, the t-J local energy (12x12, hole doping 1/8), the CNN1
 network (10x10, FP64; 36x36 by full recomputation and by the receptive cone),
-CNN2 (t-J 12x12), and the split-form cone at K = 6 and 7 (two workgroups per
-CU).  The FP64 CPU oracle is timed on the host cores on a
+CNN2 (t-J 12x12), the split-form cone at K = 6 and 7 (two workgroups per
+CU), and at K = 8 at the stress weights.  The FP64 CPU oracle is timed on the host cores on a
 bounded sample.  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -433,11 +433,13 @@ def cnn1_36_row(dev, reps=2):
     return out
 
 
-def split_depths_row(dev, depths=(6, 7), reps=2):
+def split_depths_row(dev, depths=(6, 7), reps=2, gain=None):
     """Non-gating row: the split-BF16 cone kernel on the 36x36 workload's 1024
-    configurations (weights N(0, 0.02^2)) at shallower depths.  Up to K = 7 the
+    configurations (weights N(0, 0.02^2), or the stress weights of the
+    precision gate when `gain` is given) at the given depths.  Up to K = 7 the
     windows of two workgroups fit a CU's LDS and the kernel runs two of four
-    waves per CU (two configurations in flight); at K = 8 one of eight."""
+    waves per CU (two configurations in flight); at K = 8 it runs the frame
+    form, also two workgroups of four waves per CU."""
     import numpy as np
     import torch
 
@@ -447,7 +449,8 @@ def split_depths_row(dev, depths=(6, 7), reps=2):
     spd = torch.as_tensor(sp).to(dev)
     out = {}
     for K in depths:
-        w = inputs.weights(K, C, 0.02, 1004)
+        w = inputs.weights(K, C, 0.02, 1004) if gain is None else \
+            inputs.stress_weights(K, C, gain, 77)
         ctx = nqs.Context(L, 1.0, J2, K, C, w, dtype="bf16x3")
         ctx.reserve(B, "incremental")
         e = torch.empty(B, dtype=torch.float64, device=dev)
@@ -468,8 +471,10 @@ def split_depths_row(dev, depths=(6, 7), reps=2):
         tf = fl / (ms * 1e-3) / 1e12
         out[f"K{K}"] = {"cone_ms": ms, "items": int(b.shape[0]), "tflops": tf,
                         "frac": tf / form_peak("bf16x3"),
-                        "shape": "2 workgroups x 4 waves per CU" if K <= 7 else
-                                 "1 workgroup x 8 waves per CU"}
+                        "shape": "2 workgroups x 4 waves per CU" + ("" if K <= 7 else
+                                                                     ", frame form")}
+        if gain is not None:
+            out[f"K{K}"]["weights"] = f"stress (gain {gain}, seed 77)"
         assert ctx.get_error() == 0
         ctx.close()
     return out
@@ -597,7 +602,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain BF16 row")
     ap.add_argument("--no-sr24", action="store_true")
     ap.add_argument("--only", default=None, choices=["eloc", "oderiv", "eloc64", "tj", "cnn1", "cnn1_36",
-                                                     "cnn2", "sr24", "cmp10", "depths"],
+                                                     "cnn2", "sr24", "cmp10", "depths",
+                                                     "stress_cone"],
                     help="profiling aid: eloc runs only the local-energy call --steps times, "
                          "then a 1 GiB device copy (reference for the HBM byte counters); "
                          "oderiv likewise the FP32 log-derivative call; eloc64 likewise the "
@@ -644,6 +650,9 @@ def main():
         return
     if args.only == "depths":
         print(json.dumps(split_depths_row(dev)), flush=True)
+        return
+    if args.only == "stress_cone":
+        print(json.dumps(split_depths_row(dev, depths=(8,), gain=STRESS_GAIN_K8)), flush=True)
         return
     L, J2, K, C, w, sp = inputs.config_inputs("full36")
     B = sp.shape[0]
@@ -1012,6 +1021,10 @@ def main():
         depths = split_depths_row(dev)
         log("split cone by depth: " + ", ".join(f"{k} {v['cone_ms']:.1f} ms ({v['frac']:.3f})"
                                                  for k, v in depths.items()))
+        # the headline depth at the precision gate's stress weights, where most
+        # pre-activations take ln cosh's exponential branch
+        depths["K8_stress"] = split_depths_row(dev, depths=(8,), gain=STRESS_GAIN_K8)["K8"]
+        log(f"split cone at stress weights, K = 8: {depths['K8_stress']['cone_ms']:.1f} ms")
 
     cnn2 = None
     if not args.no_cnn2:

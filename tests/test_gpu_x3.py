@@ -28,6 +28,38 @@ W_X3 = 2.0 * 2.0 ** -16
 ETA_X3 = 2e-6
 
 
+def test_x3_ln_cosh_relative_error():
+    """The split form's FP32 ln cosh itself.  With zero taps in both layers of
+    a K = 2, C = 32 network and every layer-2 bias b, z = b (in FP32) at every
+    site and channel, so log|psi| = N C ln cosh(b) exactly (equal values sum
+    exactly in FP64).  Against an 80-bit long-double evaluation of
+    |b| + log1p(expm1(-2|b|)/2) at b = float32(b), every b from 1e-3 to 60
+    (both signs, the 0.5 switch between the polynomial and the exponential
+    branch) lies within 6.4e-7 relative: the bound of the branch built on the
+    hardware base-2 exp and log within 1 ulp, under the 2e-6 that the rounding
+    bound of the other tests allows."""
+    L, K, C = 8, 2, 32
+    bs = np.concatenate([np.geomspace(1e-3, 60.0, 240), -np.geomspace(2e-3, 30.0, 60),
+                         [0.4999999, 0.5, 0.5000001, 0.55, 1.0, 2.0, 9.0]])
+    sp = to_dev(inputs.spins_sz0(L, 1, 91))
+    w = np.zeros(inputs.num_params(K, C))
+    ctx = make_ctx(L, 0.5, K, C, w, dtype="bf16x3")
+    got = np.empty(len(bs))
+    for i, b in enumerate(bs):
+        w[C * 9 + C + C * C * 9:] = b
+        ctx.set_weights(w)
+        la, _ = ctx.log_psi(sp)
+        got[i] = la.cpu().numpy()[0] / (L * L * C)
+    assert ctx.get_error() == 0
+    ctx.close()
+    a = np.abs(bs.astype(np.float32)).astype(np.longdouble)
+    ref = (a + np.log1p(np.expm1(-2 * a) / 2)).astype(np.float64)
+    rel = np.abs(got - ref) / ref
+    say("split ln cosh: max rel err", rel.max(), "at b =", bs[np.argmax(rel)],
+        "; max over |b| >= 0.5:", rel[np.abs(bs) >= 0.5].max())
+    assert rel.max() <= 6.4e-7
+
+
 CONE_CASES = [
     ("36x36 K8", 36, 0.5, 8, 1.26, 2),
     ("20x20 K6 J2=0.55", 20, 0.55, 6, 1.1, 3),
