@@ -630,6 +630,10 @@ k_net_cone(ConeJobs jobs)
                     lo_fetch(jobs.job[job_of(u + per_xcd)], 2);
                 u32x4 sh[kFrameMaxT], sl[kFrameMaxT];
                 int sa[kFrameMaxT];
+                // the tiles run at a raised wave priority, so that when the
+                // CU's two workgroups compete for instruction issue, tile work
+                // goes first (1% faster at K = 8, bit-identical)
+                __builtin_amdgcn_s_setprio(1);
                 if (k < K)
                     cone_layer<X, false, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, ps, ps, k, w0, h0,
                                                  L, K, ax, ay, hsum_s, wave, g, n16, fsum, fw16,
@@ -638,6 +642,7 @@ k_net_cone(ConeJobs jobs)
                     cone_layer<X, true, COMMIT>(wt, bs, cur, nxt, wc, whsum_s, ps, ps, k, w0, h0,
                                                 L, K, ax, ay, hsum_s, wave, g, n16, fsum, fw16,
                                                 wlo);
+                __builtin_amdgcn_s_setprio(0);
                 if (k < K) {
                     const int nt_next = ((w0 + 2 * k + 2) * (h0 + 2 * k + 2) + 15) >> 4;
                     if (wave < active_waves<X>(nt_next)) load_layer<X>(wt, prm, k + 1, lane);
